@@ -1,0 +1,371 @@
+"""NumPy FP64 oracle of the even/odd staggered operator, its normal operator and CG.
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the CPU
+baseline leg of the benchmark, never by the GPU library.  It shares no code with
+the GPU path.  It is the second, independent implementation of the same
+definitions as ``stag_oracle.c`` (N-version check), plus the brute-force dense
+constructions and the closed forms that pin both.
+
+Paper: Bonati et al., arXiv:1701.00426.
+  * Sec. 4.1, Eq. lexicographic_eo -- half-lattice index h = floor(lex/2), x0
+    fastest, all extents even (applied to both parities).
+  * Sec. 4.1 -- vec3_soa field layout [3][Vh]; gauge field as an array of 8
+    su3_soa, layout here [8][3][3][Vh], slot 2*mu + parity of the link's start.
+  * Sec. 2.2, Eq. diracblock -- M = m + [[0, D_oe], [D_eo, 0]], D_oe^dag = -D_eo.
+  * Sec. 2.2, Eq. lineqeo -- (m^2 - D_eo D_oe) phi_e = b_e, Hermitian positive
+    definite, solved by CG.
+  * Sec. 2.2, Eq. shlineq -- shifted systems (M + sigma_i) phi_i = b.
+  * Sec. 4.3, deo listing -- the operator takes links, in, out and a real
+    per-link "backfield" array; here that array carries the staggered phases.
+
+Everything takes the arrays as given; random inputs come from the seeded
+generators, which hold none of this arithmetic.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# --------------------------------------------------------------------------
+# Geometry (Sec. 4.1, Eq. lexicographic_eo)
+# --------------------------------------------------------------------------
+
+
+def volume(dims) -> int:
+    n0, n1, n2, n3 = dims
+    return n0 * n1 * n2 * n3
+
+
+def half_volume(dims) -> int:
+    return volume(dims) // 2
+
+
+def check_dims(dims):
+    if len(dims) != 4 or any(int(n) < 2 or int(n) % 2 for n in dims):
+        raise ValueError(f"every lattice extent must be even and >= 2, got {dims}")
+
+
+def lex_index(dims, x):
+    """lex(x) = x0 + N0 (x1 + N1 (x2 + N2 x3)); x is (4, ...) integer array."""
+    n0, n1, n2, _ = dims
+    return x[0] + n0 * (x[1] + n1 * (x[2] + n2 * x[3]))
+
+
+def half_index(dims, x):
+    """h(x) = floor(lex(x) / 2) (Eq. lexicographic_eo)."""
+    return lex_index(dims, x) // 2
+
+
+def site_parity(x):
+    return (x[0] + x[1] + x[2] + x[3]) & 1
+
+
+def coords(dims, parity: int):
+    """Coordinates (4, Vh) of the sites of one parity, in half-index order."""
+    n0, n1, n2, _ = dims
+    h = np.arange(half_volume(dims), dtype=np.int64)
+    nh0 = n0 // 2
+    x0half = h % nh0
+    rest = h // nh0
+    x1 = rest % n1
+    rest = rest // n1
+    x2 = rest % n2
+    x3 = rest // n2
+    x0 = 2 * x0half + ((parity + x1 + x2 + x3) & 1)
+    return np.stack([x0, x1, x2, x3])
+
+
+def shifted(dims, x, mu: int, step: int):
+    """x + step*mu_hat with periodic wrap of the index."""
+    y = x.copy()
+    y[mu] = (x[mu] + step) % dims[mu]
+    return y
+
+
+# --------------------------------------------------------------------------
+# Phases
+# --------------------------------------------------------------------------
+
+
+def eta(x, mu: int):
+    """Staggered phase eta_mu(x) = (-1)^(x0 + ... + x_{mu-1})."""
+    s = np.zeros_like(x[0])
+    for nu in range(mu):
+        s = s + x[nu]
+    return np.where(s & 1, -1.0, 1.0)
+
+
+def standard_phases(dims):
+    """phases[2*mu + parity, h] = eta_mu(x) * s_mu(x), antiperiodic in x3.
+
+    s_3(x) = -1 on the link leaving x3 = N3 - 1 (time = x3), else +1.
+    """
+    vh = half_volume(dims)
+    ph = np.empty((8, vh), dtype=np.float64)
+    for parity in (0, 1):
+        x = coords(dims, parity)
+        for mu in range(4):
+            bc = np.where((x[3] == dims[3] - 1), -1.0, 1.0) if mu == 3 else 1.0
+            ph[2 * mu + parity] = eta(x, mu) * bc
+    return ph
+
+
+# --------------------------------------------------------------------------
+# The hop (Sec. 2.2 Eq. diracblock; explicit textbook form)
+# --------------------------------------------------------------------------
+
+
+def dslash(dims, links, phases, out_parity: int, vin):
+    """D restricted to output parity ``out_parity`` (0: D_eo, 1: D_oe).
+
+    (D psi)(x) = 1/2 sum_mu [ phi_mu(x) U_mu(x) psi(x+mu)
+                             - phi_mu(x-mu) U_mu(x-mu)^dag psi(x-mu) ]
+
+    links (8, 3, 3, Vh) complex; phases (8, Vh) real; vin (..., 3, Vh) on the
+    other parity.  Returns (..., 3, Vh).
+    """
+    x = coords(dims, out_parity)
+    in_parity = 1 - out_parity
+    out = np.zeros(vin.shape, dtype=np.complex128)
+    for mu in range(4):
+        hf = half_index(dims, shifted(dims, x, mu, +1))
+        hb = half_index(dims, shifted(dims, x, mu, -1))
+        uf = links[2 * mu + out_parity]                     # U_mu(x), (3,3,Vh)
+        ub = links[2 * mu + in_parity][:, :, hb]            # U_mu(x-mu)
+        pf = phases[2 * mu + out_parity]
+        pb = phases[2 * mu + in_parity][hb]
+        fwd = np.einsum("abh,...bh->...ah", uf, vin[..., :, hf])
+        bwd = np.einsum("bah,...bh->...ah", np.conj(ub), vin[..., :, hb])
+        out += pf * fwd - pb * bwd
+    return 0.5 * out
+
+
+def d_eo(dims, links, phases, v_odd):
+    return dslash(dims, links, phases, 0, v_odd)
+
+
+def d_oe(dims, links, phases, v_even):
+    return dslash(dims, links, phases, 1, v_even)
+
+
+def apply_normal(dims, links, phases, mass, v_even, sigma=0.0):
+    """(m^2 + sigma - D_eo D_oe) v (Eq. lineqeo, shifted as in Eq. shlineq)."""
+    t = d_oe(dims, links, phases, v_even)
+    return (mass * mass + sigma) * v_even - d_eo(dims, links, phases, t)
+
+
+# --------------------------------------------------------------------------
+# CG (Sec. 2.2): textbook Hestenes-Stiefel
+# --------------------------------------------------------------------------
+
+
+def _re_dot(a, b):
+    return float(np.real(np.vdot(a, b)))
+
+
+def cg(dims, links, phases, mass, b, tol=1e-12, max_iter=100000, sigma=0.0, x0=None):
+    """Returns (x, iterations, true relative residual)."""
+    x = np.zeros_like(b) if x0 is None else x0.astype(np.complex128).copy()
+    r = b - apply_normal(dims, links, phases, mass, x, sigma)
+    p = r.copy()
+    bb = _re_dot(b, b)
+    rr = _re_dot(r, r)
+    it = 0
+    while rr > tol * tol * bb and it < max_iter:
+        q = apply_normal(dims, links, phases, mass, p, sigma)
+        alpha = rr / _re_dot(p, q)
+        x = x + alpha * p
+        r = r - alpha * q
+        rr_new = _re_dot(r, r)
+        it += 1
+        if rr_new <= tol * tol * bb:
+            break
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    res = b - apply_normal(dims, links, phases, mass, x, sigma)
+    return x, it, math.sqrt(_re_dot(res, res) / bb)
+
+
+def true_relative_residual(dims, links, phases, mass, b, x, sigma=0.0):
+    res = b - apply_normal(dims, links, phases, mass, x, sigma)
+    return math.sqrt(_re_dot(res, res) / _re_dot(b, b))
+
+
+# --------------------------------------------------------------------------
+# Brute force: the full-lattice operator as a dense matrix
+# --------------------------------------------------------------------------
+
+
+def dense_full_operator(dims, links, phases):
+    """Dense D on all V sites, 3V x 3V, filled entry by entry from the definition.
+
+    Rows/columns are ordered (site lex index, colour).  Independent of
+    ``dslash``: it walks every site and direction once and adds the two hopping
+    terms into the matrix.
+    """
+    n0, n1, n2, n3 = dims
+    v = volume(dims)
+    vh = v // 2
+    d = np.zeros((3 * v, 3 * v), dtype=np.complex128)
+    for x3 in range(n3):
+        for x2 in range(n2):
+            for x1 in range(n1):
+                for x0 in range(n0):
+                    x = np.array([x0, x1, x2, x3])
+                    lx = int(lex_index(dims, x))
+                    px = int(site_parity(x))
+                    hx = lx // 2
+                    for mu in range(4):
+                        xf = x.copy()
+                        xf[mu] = (x[mu] + 1) % dims[mu]
+                        xb = x.copy()
+                        xb[mu] = (x[mu] - 1) % dims[mu]
+                        lf = int(lex_index(dims, xf))
+                        lb = int(lex_index(dims, xb))
+                        hb = lb // 2
+                        uf = links[2 * mu + px, :, :, hx]
+                        ub = links[2 * mu + (1 - px), :, :, hb]
+                        pf = phases[2 * mu + px, hx]
+                        pb = phases[2 * mu + (1 - px), hb]
+                        d[3 * lx:3 * lx + 3, 3 * lf:3 * lf + 3] += 0.5 * pf * uf
+                        d[3 * lx:3 * lx + 3, 3 * lb:3 * lb + 3] -= 0.5 * pb * ub.conj().T
+    assert vh * 2 == v
+    return d
+
+
+def parity_permutation(dims):
+    """Indices into the (lex, colour) ordering giving (parity, colour, h) order.
+
+    Maps the dense full operator onto the [3][Vh] field layout of each parity:
+    perm[parity*3*Vh + c*Vh + h] = 3*lex(x(parity, h)) + c.
+    """
+    vh = half_volume(dims)
+    perm = np.empty(6 * vh, dtype=np.int64)
+    for parity in (0, 1):
+        lx = lex_index(dims, coords(dims, parity))
+        for c in range(3):
+            perm[parity * 3 * vh + c * vh: parity * 3 * vh + (c + 1) * vh] = 3 * lx + c
+    return perm
+
+
+def dense_blocks(dims, links, phases):
+    """(D_ee, D_eo, D_oe, D_oo) dense blocks in the [3][Vh] layout of each parity."""
+    d = dense_full_operator(dims, links, phases)
+    perm = parity_permutation(dims)
+    dp = d[np.ix_(perm, perm)]
+    n = 3 * half_volume(dims)
+    return dp[:n, :n], dp[:n, n:], dp[n:, :n], dp[n:, n:]
+
+
+# --------------------------------------------------------------------------
+# Closed forms and constructions used by the pins
+# --------------------------------------------------------------------------
+
+
+def unit_links(dims):
+    vh = half_volume(dims)
+    u = np.zeros((8, 3, 3, vh), dtype=np.complex128)
+    for a in range(3):
+        u[:, a, a, :] = 1.0
+    return u
+
+
+def momenta(dims, n):
+    """p_mu = 2 pi n_mu / N_mu (mu < 3), p_3 = pi (2 n_3 + 1) / N_3 (antiperiodic)."""
+    p = [2.0 * math.pi * n[mu] / dims[mu] for mu in range(3)]
+    p.append(math.pi * (2 * n[3] + 1) / dims[3])
+    return p
+
+
+def plane_wave(dims, parity, p, colour_vec):
+    """psi(x) = c e^{i p.x} on the sites of one parity, shape (3, Vh)."""
+    x = coords(dims, parity)
+    phase = np.exp(1j * sum(p[mu] * x[mu] for mu in range(4)))
+    return np.asarray(colour_vec, dtype=np.complex128)[:, None] * phase[None, :]
+
+
+def free_doe_plane_wave(dims, p, colour_vec):
+    """Closed form of D_oe on a plane wave with unit links and standard phases.
+
+    (D_oe psi)(x) = i c e^{i p.x} sum_mu eta_mu(x) sin p_mu on odd x.
+    """
+    x = coords(dims, 1)
+    s = sum(eta(x, mu) * math.sin(p[mu]) for mu in range(4))
+    phase = np.exp(1j * sum(p[mu] * x[mu] for mu in range(4)))
+    return 1j * np.asarray(colour_vec, dtype=np.complex128)[:, None] * (s * phase)[None, :]
+
+
+def free_eigenvalue(mass, p, sigma=0.0):
+    """Eigenvalue of m^2 + sigma - D_eo D_oe on a plane wave: m^2 + sigma + sum sin^2 p."""
+    return mass * mass + sigma + sum(math.sin(q) ** 2 for q in p)
+
+
+def free_spectrum(dims, mass):
+    """All 3*Vh eigenvalues of the free normal operator, from the closed form.
+
+    On even sites p and p + (pi,pi,pi,pi) give the same function, so each class
+    is taken once: n_0 runs over half of its range.
+    """
+    vals = []
+    n0, n1, n2, n3 = dims
+    for a in range(n0 // 2):
+        for b in range(n1):
+            for c in range(n2):
+                for d in range(n3):
+                    lam = free_eigenvalue(mass, momenta(dims, (a, b, c, d)))
+                    vals.extend([lam, lam, lam])
+    return np.sort(np.array(vals))
+
+
+def site_matrices_apply(g, v):
+    """(g v)(x) = g(x) v(x); g (3,3,Vh), v (...,3,Vh)."""
+    return np.einsum("abh,...bh->...ah", g, v)
+
+
+def gauge_transform_links(dims, links, g_even, g_odd):
+    """U^g_mu(x) = g(x) U_mu(x) g(x+mu)^dag for every link."""
+    g = (g_even, g_odd)
+    out = np.empty_like(links)
+    for parity in (0, 1):
+        x = coords(dims, parity)
+        for mu in range(4):
+            hf = half_index(dims, shifted(dims, x, mu, +1))
+            gx = g[parity]
+            gf = g[1 - parity][:, :, hf]
+            u = links[2 * mu + parity]
+            out[2 * mu + parity] = np.einsum(
+                "abh,bch,dch->adh", gx, u, np.conj(gf))
+    return out
+
+
+def pure_gauge_links(dims, g_even, g_odd):
+    """U_mu(x) = g(x) g(x+mu)^dag: the gauge transform of the unit field."""
+    return gauge_transform_links(dims, unit_links(dims), g_even, g_odd)
+
+
+def translate_field(dims, v, parity, shift_vec):
+    """Field on one parity translated by an even shift: w(x) = v(x - s).
+
+    Returns the field on the same parity (the shift is even in every
+    component that is nonzero, so parity is preserved when sum(s) is even).
+    """
+    x = coords(dims, parity)
+    src = x.copy()
+    for mu in range(4):
+        src[mu] = (x[mu] - shift_vec[mu]) % dims[mu]
+    hsrc = half_index(dims, src)
+    return v[..., hsrc]
+
+
+def translate_links(dims, links, shift_vec):
+    out = np.empty_like(links)
+    for parity in (0, 1):
+        x = coords(dims, parity)
+        src = x.copy()
+        for mu in range(4):
+            src[mu] = (x[mu] - shift_vec[mu]) % dims[mu]
+        hsrc = half_index(dims, src)
+        for mu in range(4):
+            out[2 * mu + parity] = links[2 * mu + parity][:, :, hsrc]
+    return out

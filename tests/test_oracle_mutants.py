@@ -1,0 +1,106 @@
+"""Planted mistakes in a copy of the NumPy oracle must each fail at least one pin.
+
+This shows the pins are strong enough that a plausible slip in the oracle (a
+dropped term, a wrong sign or index, a transposed operand, a wrong phase or
+boundary sign, a wrong normalisation) cannot pass unnoticed.  CPU only.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle_np as on
+
+import pins
+
+
+def make_dslash(mutation):
+    def dslash(dims, links, phases, out_parity, vin):
+        x = on.coords(dims, out_parity)
+        in_parity = 1 - out_parity
+        out = np.zeros(vin.shape, dtype=np.complex128)
+        for mu in range(4):
+            if mutation == "drop_direction" and mu == 2:
+                continue
+            step_f = 1
+            if mutation == "wrong_neighbour" and mu == 1:
+                step_f = -1 if out_parity == 0 else 1
+            hf = on.half_index(dims, on.shifted(dims, x, mu, step_f))
+            hb = on.half_index(dims, on.shifted(dims, x, mu, -1))
+            uf = links[2 * mu + out_parity]
+            ub = links[2 * mu + in_parity][:, :, hb]
+            if mutation == "wrong_slot":
+                ub = links[2 * mu + out_parity][:, :, hb]
+            pf = phases[2 * mu + out_parity]
+            pb = phases[2 * mu + in_parity][hb]
+            if mutation == "backward_phase_at_x":
+                pb = phases[2 * mu + out_parity]
+            if mutation == "transposed_forward":
+                fwd = np.einsum("bah,...bh->...ah", uf, vin[..., :, hf])
+            else:
+                fwd = np.einsum("abh,...bh->...ah", uf, vin[..., :, hf])
+            if mutation == "no_dagger":
+                bwd = np.einsum("abh,...bh->...ah", ub, vin[..., :, hb])
+            elif mutation == "transpose_no_conj":
+                bwd = np.einsum("bah,...bh->...ah", ub, vin[..., :, hb])
+            else:
+                bwd = np.einsum("bah,...bh->...ah", np.conj(ub), vin[..., :, hb])
+            if mutation == "plus_backward":
+                out += pf * fwd + pb * bwd
+            else:
+                out += pf * fwd - pb * bwd
+        scale = 1.0 if mutation == "no_half" else 0.5
+        return scale * out
+    return dslash
+
+
+def make_phases(mutation):
+    def phases_fn(dims):
+        ph = on.standard_phases(dims)
+        if mutation == "periodic_time":
+            for parity in (0, 1):
+                x = on.coords(dims, parity)
+                ph[6 + parity] = on.eta(x, 3)
+        elif mutation == "eta_inclusive":
+            for parity in (0, 1):
+                x = on.coords(dims, parity)
+                for mu in range(4):
+                    s = sum(x[nu] for nu in range(mu + 1))
+                    e = np.where(s & 1, -1.0, 1.0)
+                    if mu == 3:
+                        e = e * np.where(x[3] == dims[3] - 1, -1.0, 1.0)
+                    ph[2 * mu + parity] = e
+        elif mutation == "no_phases":
+            ph[:] = 1.0
+        elif mutation == "boundary_on_x2":
+            for parity in (0, 1):
+                x = on.coords(dims, parity)
+                ph[6 + parity] = on.eta(x, 3)
+                ph[4 + parity] = on.eta(x, 2) * np.where(x[2] == dims[2] - 1, -1.0, 1.0)
+        return ph
+    return phases_fn
+
+
+OPERATOR_MUTANTS = ["drop_direction", "wrong_neighbour", "wrong_slot", "backward_phase_at_x",
+                    "transposed_forward", "no_dagger", "transpose_no_conj", "plus_backward",
+                    "no_half"]
+PHASE_MUTANTS = ["periodic_time", "eta_inclusive", "no_phases", "boundary_on_x2"]
+
+
+def _failed(res):
+    return [name for name, (err, tol) in res.items() if not err <= tol]
+
+
+def test_unmutated_copy_passes():
+    res = pins.run_operator_pins(make_dslash(None), make_phases(None))
+    assert _failed(res) == []
+
+
+@pytest.mark.parametrize("mutation", OPERATOR_MUTANTS)
+def test_operator_mutant_detected(mutation):
+    res = pins.run_operator_pins(make_dslash(mutation), on.standard_phases)
+    assert _failed(res), f"planted mistake {mutation} passed every pin"
+
+
+@pytest.mark.parametrize("mutation", PHASE_MUTANTS)
+def test_phase_mutant_detected(mutation):
+    res = pins.run_operator_pins(on.dslash, make_phases(mutation))
+    assert _failed(res), f"planted phase mistake {mutation} passed every pin"

@@ -1,0 +1,166 @@
+"""Pins of the two FP64 oracles (NumPy and C) against what the theory fixes.
+
+CPU only.  The oracle is trusted by the GPU parity tests only because of these.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import oracle_np as on
+
+import pins
+
+
+@pytest.fixture(scope="module")
+def impls(corc):
+    return {"numpy": (on.dslash, on.standard_phases),
+            "c": (corc.dslash, corc.standard_phases)}
+
+
+@pytest.mark.parametrize("which", ["numpy", "c"])
+def test_operator_pins(impls, which):
+    dslash, phases_fn = impls[which]
+    res = pins.run_operator_pins(dslash, phases_fn)
+    for name, (err, tol) in res.items():
+        assert err <= tol, f"{which}: pin {name} error {err:.3e} > {tol:.1e}"
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 4, 4), (2, 4, 6, 4)])
+def test_normal_operator_hermitian_positive(dims):
+    herm, gap = pins.hermitian_positive(on.dslash, dims, mass=0.1)
+    assert herm < 1e-14
+    assert gap >= -1e-12
+
+
+def test_free_spectrum_full_4444():
+    """All 384 eigenvalues of the free 4^4 normal operator match the closed form."""
+    err = pins.free_spectrum(on.dslash, on.standard_phases, (4, 4, 4, 4), mass=0.05)
+    assert err < 1e-12
+
+
+def test_antiperiodic_boundary_matters():
+    """Periodic-in-time momenta are not eigenvectors: the boundary sign is present."""
+    dims = (4, 4, 4, 4)
+    p = [0.0, 0.0, 0.0, 2 * math.pi / 4]
+    pw = on.plane_wave(dims, 0, p, [1, 0, 0])
+    a = on.apply_normal(dims, on.unit_links(dims), on.standard_phases(dims), 0.1, pw)
+    assert np.max(np.abs(a - on.free_eigenvalue(0.1, p) * pw)) > 0.1
+
+
+def test_n_version_dslash(corc):
+    """NumPy and C oracles agree on random inputs, several shapes, multi-RHS."""
+    for dims, seed in (((4, 4, 4, 4), 1), ((2, 4, 6, 8), 2), ((6, 2, 4, 4), 3)):
+        links = si.su3_links(dims, seed, 0)
+        phases = si.real_link_field(dims, seed, 1)
+        v = si.gaussian_field(dims, 2, seed, 2)
+        for par in (0, 1):
+            a = on.dslash(dims, links, phases, par, v)
+            b = corc.dslash(dims, links, phases, par, v)
+            assert pins.rel_err(b, a) < 1e-14
+        an = on.apply_normal(dims, links, phases, 0.3, v[0], sigma=0.2)
+        ac = corc.apply_normal(dims, links, phases, 0.3, v[0], sigma=0.2)
+        assert pins.rel_err(ac, an) < 1e-14
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (2, 4, 6, 4)])
+def test_cg_vs_dense_solve(corc, dims):
+    links = si.su3_links(dims, 11, 0)
+    phases = on.standard_phases(dims)
+    b = si.gaussian_field(dims, 1, 11, 1)[0]
+    mass = 0.2
+    a = pins.dense_normal(on.dslash, dims, links, phases, mass)
+    x_dense = np.linalg.solve(a, b.reshape(-1)).reshape(b.shape)
+    x_np, it_np, res_np = on.cg(dims, links, phases, mass, b, tol=1e-13)
+    x_c, it_c, res_c, st = corc.cg(dims, links, phases, mass, b, tol=1e-13)
+    assert st == 0 and res_c < 1e-12 and res_np < 1e-12
+    assert pins.vec_rel(x_np, x_dense) < 1e-11
+    assert pins.vec_rel(x_c, x_dense) < 1e-11
+    # CG on n = 3 Vh unknowns terminates in at most n steps in exact arithmetic
+    assert it_c <= 3 * on.half_volume(dims) + 5
+
+
+def test_cg_pure_gauge_exact(corc):
+    """b = g * plane wave is an exact eigenvector: CG returns b / lambda."""
+    dims = (4, 4, 4, 6)
+    ge = si.su3_site_field(dims, 21, 0)
+    go = si.su3_site_field(dims, 21, 1)
+    links = on.pure_gauge_links(dims, ge, go)
+    phases = on.standard_phases(dims)
+    p = on.momenta(dims, (1, 2, 0, 1))
+    b = on.site_matrices_apply(ge, on.plane_wave(dims, 0, p, [1.0, 0.5j, -0.25]))
+    lam = on.free_eigenvalue(0.1, p)
+    x, it, res, st = corc.cg(dims, links, phases, 0.1, b, tol=1e-12)
+    assert st == 0
+    assert pins.vec_rel(x, b / lam) < 1e-12
+    assert it <= 2  # an eigenvector is solved in one step
+
+
+def test_cg_warm_restart_and_not_converged(corc):
+    dims = (4, 4, 4, 4)
+    links = si.su3_links(dims, 31, 0)
+    phases = on.standard_phases(dims)
+    b = si.gaussian_field(dims, 1, 31, 1)[0]
+    x1, it1, _, st1 = corc.cg(dims, links, phases, 0.1, b, tol=1e-10, max_iter=10)
+    assert st1 == 1 and it1 == 10
+    x2, it2, res2, st2 = corc.cg(dims, links, phases, 0.1, b, tol=1e-10, x0=x1)
+    assert st2 == 0 and res2 < 1e-9
+
+
+def test_cg_iteration_count_random_links(corc):
+    """Random links at m = 0.1 on 8^4: about 300 iterations to 1e-10 (recorded, unpinned
+    by theory; a sanity range only)."""
+    dims = (8, 8, 8, 8)
+    links = si.su3_links(dims, 1701, 0, 0)
+    phases = on.standard_phases(dims)
+    b = si.gaussian_field(dims, 1, 426, 0, 0, 0)[0]
+    x, it, res, st = corc.cg(dims, links, phases, 0.1, b, tol=1e-10)
+    assert st == 0 and res < 2e-10
+    assert 150 < it < 600
+
+
+def test_mscg_vs_independent_cg(corc):
+    """Each multi-shift solution matches an independent CG on its own shifted system."""
+    dims = (4, 4, 4, 4)
+    links = si.su3_links(dims, 41, 0)
+    phases = on.standard_phases(dims)
+    b = si.gaussian_field(dims, 1, 41, 1)[0]
+    shifts = si.log_shifts(6, 1e-4, 10.0)
+    mass = 0.05
+    xs, its, res, st = corc.mscg(dims, links, phases, mass, shifts, b, tol=1e-11)
+    assert st == 0
+    for k, s in enumerate(shifts):
+        assert res[k] < 1e-10
+        xk, _, rk, stk = corc.cg(dims, links, phases, mass, b, tol=1e-12, sigma=s)
+        assert stk == 0
+        assert pins.vec_rel(xs[k], xk) < 1e-9
+        # and against the NumPy oracle's residual on the returned solution
+        assert on.true_relative_residual(dims, links, phases, mass, b, xs[k], sigma=s) < 1e-10
+    # larger shifts converge earlier
+    assert its[-1] < its[0]
+
+
+def test_mscg_single_shift_is_cg(corc):
+    """With one shift the multi-shift recurrences reduce to plain CG (zeta = 1)."""
+    dims = (4, 4, 2, 4)
+    links = si.su3_links(dims, 51, 0)
+    phases = on.standard_phases(dims)
+    b = si.gaussian_field(dims, 1, 51, 1)[0]
+    xs, its, res, st = corc.mscg(dims, links, phases, 0.1, [0.3], b, tol=1e-10)
+    x, it, r, st2 = corc.cg(dims, links, phases, 0.1, b, tol=1e-10, sigma=0.3)
+    assert its[0] == it
+    assert pins.vec_rel(xs[0], x) < 1e-13
+
+
+def test_mscg_shift_order_independent(corc):
+    dims = (4, 2, 4, 4)
+    links = si.su3_links(dims, 61, 0)
+    phases = on.standard_phases(dims)
+    b = si.gaussian_field(dims, 1, 61, 1)[0]
+    sh = np.array([0.5, 0.01, 2.0])
+    x1, _, r1, _ = corc.mscg(dims, links, phases, 0.1, sh, b, tol=1e-11)
+    perm = [2, 0, 1]
+    x2, _, r2, _ = corc.mscg(dims, links, phases, 0.1, sh[perm], b, tol=1e-11)
+    for j, k in enumerate(perm):
+        assert pins.vec_rel(x2[j], x1[k]) < 1e-13
