@@ -1,0 +1,275 @@
+"""Benchmark of the even/odd staggered operator and its CG solves on one MI355X.
+
+Workload (the plain FP64 configuration at scale): 32^4 lattice, seeded random
+SU(3) links with standard staggered phases and antiperiodic time boundary,
+m = 0.01, one complex Gaussian even-site right-hand side.
+
+  * value: D_eo apply bandwidth in GB/s at FP64 with 12-real links (the paper's
+    storage), algorithmic bytes / mean kernel duration, measured with HIP events
+    on the library's stream over back-to-back applies that rotate through three
+    link/field copies (1.36 GB working set, above the 256 MB Infinity Cache).
+  * a step: one FP64 CG solve and one mixed-precision CG solve (FP32-12 links,
+    FP64 reliable updates) of (m^2 - D_eo D_oe) x = b to |r|/|b| <= 1e-10.
+  * roofline: the dominant kernel (the hop) against the 8 TB/s HBM peak.
+  * cpu_baseline: the FP64 C oracle's D_eo on the host cores, bounded sample.
+
+Prints one JSON line.  `python bench.py --gpus N` with N > 1 exits with a
+message: the library runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "D_eo apply GB/s (% HBM peak); mixed vs FP64 CG time to |r|/|b|<1e-10 per RHS"
+HBM_PEAK_GBS = 8000.0
+DIMS = (32, 32, 32, 32)
+MASS = 0.01
+TOL = 1e-10
+# algorithmic bytes per output site of one hop: 8 links + 1 input + 1 output vector
+BYTES_PER_SITE = {"c128_18": 8 * 144 + 48 + 48, "c128_12": 8 * 96 + 48 + 48,
+                  "c64_12": 8 * 48 + 24 + 24, "bf16_12": 8 * 24 + 24 + 24}
+FLOPS_PER_SITE = 570  # 8 SU(3) mat-vecs (66) + 7 colour-vector sums (6); reconstruction excluded
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_traffic_32x32x32x32.json")
+KERNEL_SOURCES = ["paper_1701_00426_amd/csrc/hop.hip",
+                  "paper_1701_00426_amd/csrc/device_common.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_applies(stg, torch, gauges, fields, outs, parity, n):
+    """Mean duration (s) of one hop over n back-to-back launches rotating copies."""
+    fn = stg.dirac_apply_eo if parity == 0 else stg.dirac_apply_oe
+    stream = torch.cuda.current_stream()
+    for i in range(3):
+        fn(gauges[i % len(gauges)], fields[i % len(fields)], outs[i % len(outs)])
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for i in range(n):
+        k = i % len(gauges)
+        fn(gauges[k], fields[k % len(fields)], outs[k % len(outs)])
+    t1.record(stream)
+    t1.synchronize()
+    return t0.elapsed_time(t1) * 1e-3 / n
+
+
+def cpu_baseline(links, b, vh, seconds=10.0):
+    """The FP64 C oracle's D_eo on the host cores: bounded sample of applies."""
+    import numpy as np
+    import oracle
+    from oracle import oracle_np as on
+    orc = oracle.COracle()
+    phases = on.standard_phases(DIMS)
+    t = time.perf_counter()
+    orc.d_eo(DIMS, links, phases, b)
+    one = time.perf_counter() - t
+    n = max(1, min(50, int(seconds / max(one, 1e-3))))
+    t = time.perf_counter()
+    for _ in range(n):
+        orc.d_eo(DIMS, links, phases, b)
+    dt = (time.perf_counter() - t) / n
+    gbs = BYTES_PER_SITE["c128_12"] * vh / dt / 1e9
+    del np
+    return {"value": round(gbs, 3), "unit": "GB/s", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"{n} D_eo applies of the FP64 C oracle (OpenMP, full 3x3 links) at 32^4, "
+                      f"{dt * 1e3:.1f} ms each, same byte model as value (864 B/site)",
+            "ms_per_apply": round(dt * 1e3, 3)}
+
+
+def calibrate_copy():
+    """A plain device-to-device copy of 1 GiB, 10 times: FETCH_SIZE / WRITE_SIZE per
+    dispatch of this kernel against the known 1 GiB read and 1 GiB write give the
+    scale factor of the counters."""
+    import torch
+    n = 1 << 30
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 10
+    print(json.dumps({"calibrate_copy_bytes_read": n, "bytes_written": n,
+                      "GBs_read_plus_write": round(2 * n / dt / 1e9, 1)}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--applies", type=int, default=300)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--profile", action="store_true",
+                    help="for rocprofv3: only the dominant kernel's timed loop (FP64-12 D_eo)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="for rocprofv3 --pmc: a plain 1 GiB device copy, to scale byte counters")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(no halo exchange between slabs); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+
+    import numpy as np
+    import torch
+
+    import paper_1701_00426_amd as stg
+    import seeded_inputs as si
+
+    stg.library()
+    dev = torch.device("cuda:0")
+    vh = stg.half_volume(DIMS)
+    log(f"generating 32^4 inputs (Vh={vh})")
+    links_np = si.su3_links(DIMS, 1701, 2, 0)
+    b_np = si.gaussian_field(DIMS, 1, 426, 2, 0, 0)
+    links = torch.from_numpy(links_np).to(dev)
+    b = torch.from_numpy(b_np).to(dev)
+
+    # ---- operator bandwidth (value + roofline) ----------------------------------------
+    variants = {}
+    hop_time = {}
+    fmts = ("c128_12",) if args.profile else ("c128_12", "c128_18", "c64_12", "bf16_12")
+    for fmt in fmts:
+        cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
+        ncopy = 3
+        gauges = [stg.pack_gauge(DIMS, links if i == 0 else links.clone(), fmt)
+                  for i in range(ncopy)]
+        fields = [b.to(cdt).clone() for _ in range(ncopy)]
+        outs = [torch.empty_like(fields[0]) for _ in range(ncopy)]
+        ws_bytes = sum(g.links.numel() * g.links.element_size() for g in gauges) + \
+            2 * ncopy * fields[0].numel() * fields[0].element_size()
+        res = {}
+        pars = ((0, "D_eo"),) if args.profile else ((0, "D_eo"), (1, "D_oe"))
+        for par, name in pars:
+            dt = time_applies(stg, torch, gauges, fields, outs, par, args.applies)
+            gbs = BYTES_PER_SITE[fmt] * vh / dt / 1e9
+            res[name] = {"us": round(dt * 1e6, 2), "GBs": round(gbs, 1),
+                         "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                         "GFLOPs": round(FLOPS_PER_SITE * vh / dt / 1e9, 1),
+                         "ns_per_site": round(dt * 1e9 / vh, 4)}
+            hop_time[(fmt, name)] = dt
+        res["working_set_GB"] = round(ws_bytes / 1e9, 3)
+        res["bytes_per_site"] = BYTES_PER_SITE[fmt]
+        variants[fmt] = res
+        log(f"{fmt}: " + ", ".join(f"{k} {v['us']} us {v['GBs']} GB/s"
+                                   for k, v in res.items() if isinstance(v, dict)))
+        del gauges, fields, outs
+        torch.cuda.empty_cache()
+
+    if args.profile:
+        dt = hop_time[("c128_12", "D_eo")]
+        print(json.dumps({"profile": "hop D_eo FP64-12 32^4", "applies": args.applies,
+                          "mean_launch_us": round(dt * 1e6, 3),
+                          "GBs": round(BYTES_PER_SITE["c128_12"] * vh / dt / 1e9, 1),
+                          "kernel_hash": kernel_hash()}), flush=True)
+        return
+
+    # ---- the steps: FP64 CG and mixed CG to 1e-10 ------------------------------------
+    hi = stg.pack_gauge(DIMS, links, "c128_12")
+    lo = stg.pack_gauge(DIMS, links, "c64_12")
+    ws64 = torch.empty(stg.stg_workspace_bytes(DIMS, 1, 0, stg.STG_CG_F64), dtype=torch.uint8,
+                       device=dev)
+    wsmx = torch.empty(stg.stg_workspace_bytes(DIMS, 1, 0, stg.STG_CG_MIXED),
+                       dtype=torch.uint8, device=dev)
+    x64 = torch.zeros_like(b)
+    xmx = torch.zeros_like(b)
+
+    def step():
+        x64.zero_()
+        xmx.zero_()
+        t0 = time.perf_counter()
+        _, s1, st1 = stg.cg_solve(hi, MASS, b, x=x64, ws=ws64, tol=TOL)
+        t1 = time.perf_counter()
+        _, s2, st2 = stg.cg_solve(hi, MASS, b, x=xmx, lo=lo, ws=wsmx, tol=TOL)
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1, st1[0], st2[0]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    runs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    t64 = min(r[0] for r in runs)
+    tmx = min(r[1] for r in runs)
+    st64, stmx = runs[-1][2], runs[-1][3]
+
+    # ---- dominant kernel roofline --------------------------------------------------
+    dt = hop_time[("c128_12", "D_eo")]
+    achieved = BYTES_PER_SITE["c128_12"] * vh / dt / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_hash") == kernel_hash():
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "hop_kernel<double, FMT_C128_12, std phases, NR=1, EPI_PLAIN> (D_eo)",
+                "algorithmic_bytes_per_launch": BYTES_PER_SITE["c128_12"] * vh,
+                "mean_launch_us": round(dt * 1e6, 2)}
+
+    out = {
+        "metric": METRIC,
+        "value": round(achieved, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total / max(args.steps, 1) * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "32^4 random SU(3), m=0.01, 1 RHS: FP64-12 D_eo apply; "
+                               "FP64 CG and mixed FP32-12 CG to |r|/|b|<=1e-10",
+                   "lattice": list(DIMS), "mass": MASS, "nrhs": 1, "tol": TOL,
+                   "links": "random SU(3) (Haar), standard phases, antiperiodic t"},
+        "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
+        "cg_fp64_s_per_rhs": round(t64, 4),
+        "cg_mixed_s_per_rhs": round(tmx, 4),
+        "mixed_speedup": round(t64 / tmx, 3),
+        "cg_fp64": {"iters": st64["iters"], "true_rel_resid": st64["true_rel_resid"],
+                    "reliable_updates": st64["reliable_updates"]},
+        "cg_mixed": {"iters": stmx["iters"], "true_rel_resid": stmx["true_rel_resid"],
+                     "reliable_updates": stmx["reliable_updates"]},
+        "operator_variants": variants,
+        "roofline": roofline,
+    }
+    if not args.no_cpu and not args.profile:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(links_np, b_np, vh)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    del np
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,232 @@
+/*
+ * stagmi.h -- C ABI of the MI355X (gfx950) staggered-fermion library.
+ *
+ * The library applies the even/odd staggered Dirac operator and solves the
+ * even/odd normal equations with it, on one GPU, in hand-written HIP kernels.
+ *
+ * Paper: C. Bonati et al., "Design and optimization of a portable LQCD Monte
+ * Carlo code using OpenACC", arXiv:1701.00426.
+ *   - Sec. 2.2, Eq. diracblock: M = m + [[0, D_oe], [D_eo, 0]], D_oe^dag = -D_eo;
+ *     the blocks connect only even and odd sites.
+ *   - Sec. 2.2, Eq. lineqeo: (m^2 - D_eo D_oe) phi_e = b_e on even sites, Hermitian
+ *     positive definite, solved by conjugate gradient.
+ *   - Sec. 2.2, Eq. shlineq: shifted systems (M + sigma_i) phi_i = b for the poles
+ *     of the rational approximation, all solved with one operator application
+ *     per iteration (multi-shift CG).
+ *   - Sec. 2.3: SU(3) links stored as their first two rows, the third rebuilt
+ *     as the complex conjugate of the cross product of the first two.
+ *   - Sec. 4.1: structure-of-arrays layouts (vec3_soa fields, gauge field as an
+ *     array of 8 su3_soa), half-lattice site index of Eq. lexicographic_eo.
+ *   - Sec. 4.3, deo listing: the operator reads links, an input field, a real
+ *     per-link factor array ("backfield") and writes an output field.
+ *
+ * Conventions used by every call
+ * ------------------------------
+ *  Lattice: extents N0..N3, each even and >= 2; x0 runs fastest; the time
+ *    direction is x3.  V = N0 N1 N2 N3, Vh = V / 2.  A site x has parity
+ *    (x0+x1+x2+x3) mod 2 (0 = even) and half-lattice index
+ *    h(x) = floor((x0 + N0 (x1 + N1 (x2 + N2 x3))) / 2), a bijection onto
+ *    [0, Vh) for each parity.
+ *  Operator: (D psi)(x) = 1/2 sum_mu [ phi_mu(x) U_mu(x) psi(x+mu)
+ *                                     - phi_mu(x-mu) U_mu(x-mu)^dag psi(x-mu) ]
+ *    with periodic index wrap.  D_eo maps a field on odd sites to even sites,
+ *    D_oe maps even to odd.  The normal operator is
+ *    A_sigma = (m^2 + sigma) - D_eo D_oe on even sites.
+ *  Phases phi_mu(x): real.  With a NULL phase pointer the library uses the
+ *    standard staggered phases eta_mu(x) = (-1)^(x0+...+x_{mu-1}) times -1 on the
+ *    links leaving x3 = N3-1 (antiperiodic time boundary), computed in the
+ *    kernel without reading memory.  Otherwise phases point to a real array
+ *    [8][Vh], entry (2*mu + parity(x))*Vh + h(x) = phi_mu(x); its element type
+ *    is double for STG_LINK_C128_* gauge fields and float for the others.
+ *  Fields: interleaved complex (re, im), layout [nrhs][3][Vh] (colour, then
+ *    site), element complex128 (STG_C128) or complex64 (STG_C64).
+ *  Gauge field formats (slot s = 2*mu + parity of the link's start site x):
+ *    STG_LINK_C128_18  complex128 [8][3][3][Vh]  row, column, site (full matrix)
+ *    STG_LINK_C128_12  complex128 [8][2][3][Vh]  rows 0 and 1 only
+ *    STG_LINK_C64_12   float4     [8][3][Vh]     chunk k of a link holds the
+ *                      complex64 entries 2k and 2k+1 of (U00 U01 U02 U10 U11 U12)
+ *    STG_LINK_BF16_12  [8][Vh] x 16 bytes, then [8][Vh] x 8 bytes: bfloat16
+ *                      (re, im) of U00 U01 U02 U10 in the first array and of
+ *                      U11 U12 in the second
+ *    The 12-real formats rebuild row 2 as conj(row0 x row1): links must be SU(3).
+ *    Only STG_LINK_C128_* may be used with STG_C128 fields and only
+ *    STG_LINK_C64_12 / STG_LINK_BF16_12 with STG_C64 fields (compute in FP32).
+ *
+ * Memory ownership: every buffer argument marked "device" is a device pointer
+ * owned by the caller; the library allocates no device memory and keeps no
+ * pointer after a call returns.  Solvers take a caller-owned device workspace
+ * whose size comes from stg_workspace_bytes.  Arguments marked "host" are host
+ * memory.  Device buffers must be 16-byte aligned; an input and an output
+ * buffer of one call must not overlap.
+ *
+ * Streams: stg_stream_t is a hipStream_t (NULL = the default stream).  The
+ * operator and packing calls only enqueue work and return; the solvers enqueue
+ * on the stream and return after it has drained, because they report
+ * convergence in host memory.
+ *
+ * Errors: every call returns an int status (below).  No call aborts the process
+ * or lets an exception cross the ABI; stg_status_string gives the text.
+ */
+#ifndef STAGMI_H
+#define STAGMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *stg_stream_t; /* a hipStream_t */
+
+enum {
+    STG_OK = 0,
+    STG_NOT_CONVERGED = 1,      /* iteration cap reached; x holds the last iterate */
+    STG_BREAKDOWN = 2,          /* non-finite scalar or <p, A p> <= 0 */
+    STG_INVALID_ARG = -1,       /* bad extent, null or misaligned pointer, overlap, bad count */
+    STG_HIP_ERROR = -2,         /* a HIP runtime call failed */
+    STG_WORKSPACE_TOO_SMALL = -3
+};
+
+typedef struct { int32_t dims[4]; } stg_lattice;
+
+typedef enum {
+    STG_LINK_C128_18 = 0,
+    STG_LINK_C128_12 = 1,
+    STG_LINK_C64_12 = 2,
+    STG_LINK_BF16_12 = 3
+} stg_link_fmt;
+
+typedef enum { STG_C128 = 0, STG_C64 = 1 } stg_field;
+
+typedef struct {
+    const void *links;   /* device, layout given by fmt */
+    stg_link_fmt fmt;
+    const void *phases;  /* device real [8][Vh], or NULL for the standard phases */
+} stg_gauge;
+
+/* Library version, (major << 16) | minor. */
+int stg_version(void);
+
+/* Text of a status code; never NULL. */
+const char *stg_status_string(int status);
+
+/* Last HIP error text seen by the library on this thread (empty if none). */
+const char *stg_last_error(void);
+
+/* Bytes of a gauge field of format fmt on lattice lat, written to *bytes (host). */
+int stg_links_bytes(const stg_lattice *lat, stg_link_fmt fmt, size_t *bytes);
+
+/*
+ * Converts a full complex128 gauge field [8][3][3][Vh] (device) into format
+ * dst_fmt at dst (device, stg_links_bytes bytes).  Conversions round to
+ * nearest even.  Sec. 2.3 / Sec. 4.1: only rows 0 and 1 are kept by the 12-real
+ * formats.  Asynchronous on stream.
+ */
+int stg_pack_links(const stg_lattice *lat, const void *links_c128_18, stg_link_fmt dst_fmt,
+                   void *dst, stg_stream_t stream);
+
+/*
+ * Converts real phases [8][Vh] double (device) to element type dst (STG_C128:
+ * double copy, STG_C64: float) at dst (device).  Asynchronous on stream.
+ */
+int stg_pack_phases(const stg_lattice *lat, const double *phases_f64, stg_field dst, void *dst_ptr,
+                    stg_stream_t stream);
+
+/*
+ * out_even = D_eo in_odd for nrhs fields (Sec. 2.2 Eq. diracblock; Sec. 4.3 deo).
+ * in_odd, out_even: device [nrhs][3][Vh] of element type field.  Asynchronous.
+ */
+int dirac_apply_eo(const stg_lattice *lat, const stg_gauge *gauge, stg_field field, int nrhs,
+                   const void *in_odd, void *out_even, stg_stream_t stream);
+
+/* out_odd = D_oe in_even for nrhs fields (Sec. 2.2 Eq. diracblock).  Asynchronous. */
+int dirac_apply_oe(const stg_lattice *lat, const stg_gauge *gauge, stg_field field, int nrhs,
+                   const void *in_even, void *out_odd, stg_stream_t stream);
+
+/*
+ * out_even = (mass^2 + sigma) in_even - D_eo D_oe in_even (Sec. 2.2 Eq. lineqeo,
+ * shifted as in Eq. shlineq).  tmp_odd: device scratch field of the same shape
+ * as in_even, overwritten with D_oe in_even.  Asynchronous.
+ */
+int stg_apply_normal(const stg_lattice *lat, const stg_gauge *gauge, stg_field field, int nrhs,
+                     double mass, double sigma, const void *in_even, void *out_even,
+                     void *tmp_odd, stg_stream_t stream);
+
+/* Device workspace bytes needed by stg_dot. */
+size_t stg_dot_workspace_bytes(void);
+
+/*
+ * Compensated complex inner products <x_j, y_j> = sum conj(x) y over n complex
+ * entries for j < nvec (x, y device [nvec][n], element type field), accumulated
+ * in FP64 with error-free transformations (TwoSum) and a fixed summation order,
+ * so the result is bitwise reproducible.  These are the dot products of the
+ * Krylov solvers (Sec. 2.3).  result (host) receives nvec (re, im) pairs.
+ * ws (device) has ws_bytes >= stg_dot_workspace_bytes().  Synchronous.
+ */
+int stg_dot(stg_field field, int nvec, size_t n, const void *x, const void *y, double *result,
+            void *ws, size_t ws_bytes, stg_stream_t stream);
+
+/* Solver modes */
+enum {
+    STG_CG_F64 = 0,         /* FP64 operator and vectors on the hi gauge field */
+    STG_CG_MIXED = 1        /* FP32 operator and vectors on the lo gauge field, FP64
+                               reliable updates and true residual on the hi one */
+};
+
+typedef struct {
+    double tol;        /* stop when the FP64 true |b - A x| / |b| <= tol */
+    int max_iter;      /* cap on operator applications of the inner iteration */
+    int mode;          /* STG_CG_F64 or STG_CG_MIXED */
+    double delta;      /* reliable update when |r| < delta * max|r| since the last one (0.1) */
+    int poll_every;    /* iterations enqueued between host convergence checks (0: auto) */
+    int restart;       /* 1: restart p = r at each reliable update, 0: keep p */
+} stg_cg_params;
+
+typedef struct {
+    int iters;              /* iterations of the solve (shared by a batch) */
+    int reliable_updates;   /* FP64 true-residual recomputations */
+    int status;             /* STG_OK / STG_NOT_CONVERGED / STG_BREAKDOWN */
+    int converged_iter;     /* iteration at which this system met its stopping test */
+    double true_rel_resid;  /* FP64 |b - A x| / |b| at return */
+    double seconds;         /* wall time of the call */
+} stg_cg_stats;
+
+/* Fills p with the defaults: tol 1e-10, max_iter 100000, mode F64, delta 0.1,
+   poll_every 0 (auto), restart 0. */
+void stg_cg_default_params(stg_cg_params *p);
+
+/* Device workspace bytes needed by cg_solve (nshift = 0) or multishift_cg_solve. */
+int stg_workspace_bytes(const stg_lattice *lat, int nrhs, int nshift, int mode, size_t *bytes);
+
+/*
+ * Solves (mass^2 - D_eo D_oe) x_j = b_j for j < nrhs by CG (Sec. 2.2 Eq. lineqeo).
+ * hi: FP64 gauge field (STG_LINK_C128_*) used for the operator in mode F64 and
+ * for the true residual and reliable updates in mode MIXED.  lo: FP32 gauge field
+ * (STG_LINK_C64_12 or STG_LINK_BF16_12) for the inner iteration in mode MIXED,
+ * ignored in mode F64.  b_even (device) and x_even (device, initial guess on
+ * entry, solution on exit) are complex128 [nrhs][3][Vh].  ws (device) has
+ * ws_bytes >= stg_workspace_bytes.  stats (host) gets nrhs entries.  Returns
+ * STG_OK when every system converged, else the worst status.
+ */
+int cg_solve(const stg_lattice *lat, const stg_gauge *hi, const stg_gauge *lo, double mass,
+             int nrhs, const void *b_even, void *x_even, const stg_cg_params *params, void *ws,
+             size_t ws_bytes, stg_cg_stats *stats, stg_stream_t stream);
+
+/*
+ * Solves (mass^2 + shifts[k] - D_eo D_oe) x_{k,j} = b_j for k < nshift, j < nrhs
+ * (Sec. 2.2 Eq. shlineq) with one operator application per iteration on the
+ * smallest shift, then refines every (k, j) to the FP64 tolerance.  shifts
+ * (host) >= 0.  x_even (device, output) is complex128 [nshift][nrhs][3][Vh];
+ * stats (host) gets nshift*nrhs entries in the same order.
+ */
+int multishift_cg_solve(const stg_lattice *lat, const stg_gauge *hi, const stg_gauge *lo,
+                        double mass, int nshift, const double *shifts, int nrhs,
+                        const void *b_even, void *x_even, const stg_cg_params *params, void *ws,
+                        size_t ws_bytes, stg_cg_stats *stats, stg_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STAGMI_H */

@@ -60,6 +60,8 @@ class COracle:
         if not os.path.exists(path):
             build()
         lib = ctypes.CDLL(path)
+        lib.orc_num_threads.restype = ctypes.c_int
+        lib.orc_num_threads.argtypes = []
         lib.orc_half_volume.restype = ctypes.c_long
         lib.orc_half_volume.argtypes = [_P]
         lib.orc_standard_phases.argtypes = [_P, _P]
@@ -70,6 +72,9 @@ class COracle:
         lib.orc_mscg.restype = _I
         lib.orc_mscg.argtypes = [_P, _P, _P, _D, _I, _P, _P, _P, _D, _I, _P, _P]
         self.lib = lib
+
+    def num_threads(self) -> int:
+        return int(self.lib.orc_num_threads())
 
     @staticmethod
     def _dims(dims):

@@ -116,24 +116,28 @@ def standard_phases(dims):
 # --------------------------------------------------------------------------
 
 
-def dslash(dims, links, phases, out_parity: int, vin):
+def dslash(dims, links, phases, out_parity: int, vin, hs=None):
     """D restricted to output parity ``out_parity`` (0: D_eo, 1: D_oe).
 
     (D psi)(x) = 1/2 sum_mu [ phi_mu(x) U_mu(x) psi(x+mu)
                              - phi_mu(x-mu) U_mu(x-mu)^dag psi(x-mu) ]
 
     links (8, 3, 3, Vh) complex; phases (8, Vh) real; vin (..., 3, Vh) on the
-    other parity.  Returns (..., 3, Vh).
+    other parity.  Returns (..., 3, Vh), or (..., 3, len(hs)) for the output
+    sites listed in ``hs`` only (sampled checks of large lattices).
     """
     x = coords(dims, out_parity)
+    if hs is not None:
+        x = x[:, np.asarray(hs, dtype=np.int64)]
+    own = half_index(dims, x)
     in_parity = 1 - out_parity
-    out = np.zeros(vin.shape, dtype=np.complex128)
+    out = np.zeros(vin.shape[:-1] + (x.shape[1],), dtype=np.complex128)
     for mu in range(4):
         hf = half_index(dims, shifted(dims, x, mu, +1))
         hb = half_index(dims, shifted(dims, x, mu, -1))
-        uf = links[2 * mu + out_parity]                     # U_mu(x), (3,3,Vh)
+        uf = links[2 * mu + out_parity][:, :, own]          # U_mu(x), (3,3,n)
         ub = links[2 * mu + in_parity][:, :, hb]            # U_mu(x-mu)
-        pf = phases[2 * mu + out_parity]
+        pf = phases[2 * mu + out_parity][own]
         pb = phases[2 * mu + in_parity][hb]
         fwd = np.einsum("abh,...bh->...ah", uf, vin[..., :, hf])
         bwd = np.einsum("bah,...bh->...ah", np.conj(ub), vin[..., :, hb])

@@ -47,12 +47,24 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cplx;
 
 /* ------------------------------------------------------------------------ */
 /* Geometry (Sec. 4.1, Eq. lexicographic_eo)                                 */
 /* ------------------------------------------------------------------------ */
+
+/* threads the OpenMP loops of this library use */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 long orc_half_volume(const int *N) { return (long)N[0] * N[1] * N[2] * N[3] / 2; }
 

@@ -1,0 +1,405 @@
+// blas.hip -- site-local kernels of the Krylov solvers (the paper's "zaxpy-like"
+// functions, Sec. 2.3 and Sec. 4.2), compensated dot products, and the packing of
+// gauge links into the 12-real formats (Sec. 2.3, Sec. 4.1).
+//
+// Every vector kernel fuses the axpy updates with the reduction that follows
+// them (|r|^2 after x += alpha p, r -= alpha q), so a CG iteration reads each
+// vector the minimum number of times.  Reductions: wave64 shuffle, LDS across
+// the four waves, one FP64 partial per block, and the last block to arrive sums
+// the partials with error-free transformations in a fixed order.
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+#include "solver_state.hpp"
+
+namespace stg {
+
+// x += alpha p; r -= alpha q; partial |r|^2; OP_BETA in the last block
+template <typename T, int NR>
+__global__ __launch_bounds__(kBlock) void cg_update_kernel(VecArgs a) {
+    if (a.gate_running && a.ctl->n_running == 0) return;
+    const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+    double ps[NR], pc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        ps[j] = 0.0;
+        pc[j] = 0.0;
+        const SysState &s = a.state[j];
+        if (!(s.flags & SYS_RUNNING) || h >= a.Vh) continue;
+        const T al = (T)s.alpha;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t i = (size_t)j * a.fstride + (size_t)c * a.Vh + h;
+            cpx<T> x = ld_c<T>(a.x, i), p = ld_c<T>(a.p, i), r = ld_c<T>(a.r, i),
+                   q = ld_c<T>(a.q, i);
+            x.re += al * p.re;
+            x.im += al * p.im;
+            r.re -= al * q.re;
+            r.im -= al * q.im;
+            st_c<T>(a.x, i, x);
+            st_c<T>(a.r, i, r);
+            pair_add(ps[j], pc[j], (double)r.re * (double)r.re + (double)r.im * (double)r.im,
+                     0.0);
+        }
+    }
+    reduce_and_finish<NR>(ps, pc, a.partials, a.ctl, OP_BETA, a.state, nullptr);
+}
+
+// p = r + beta p
+template <typename T, int NR>
+__global__ __launch_bounds__(kBlock) void p_update_kernel(VecArgs a) {
+    if (a.gate_running && a.ctl->n_running == 0) return;
+    const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+    if (h >= a.Vh) return;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const SysState &s = a.state[j];
+        if (!(s.flags & SYS_RUNNING)) continue;
+        const T be = (T)s.beta;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t i = (size_t)j * a.fstride + (size_t)c * a.Vh + h;
+            cpx<T> p = ld_c<T>(a.p, i), r = ld_c<T>(a.r, i);
+            p.re = r.re + be * p.re;
+            p.im = r.im + be * p.im;
+            st_c<T>(a.p, i, p);
+        }
+    }
+}
+
+// x64 += x32; x32 = 0 for parked systems
+template <int NR>
+__global__ __launch_bounds__(kBlock) void ru_accumulate_kernel(VecArgs a) {
+    const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+    if (h >= a.Vh) return;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if (!(a.state[j].flags & SYS_RU_PENDING)) continue;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t i = (size_t)j * a.fstride + (size_t)c * a.Vh + h;
+            cpx<float> xs = ld_c<float>(a.x, i);
+            cpx<double> xd = ld_c<double>(a.x64, i);
+            xd.re += (double)xs.re;
+            xd.im += (double)xs.im;
+            st_c<double>(a.x64, i, xd);
+            st_c<float>(a.x, i, cpx<float>{0.0f, 0.0f});
+        }
+    }
+}
+
+// resumed systems: r_inner = r64 (rounded to T); p = r_inner + beta p
+template <typename T, int NR>
+__global__ __launch_bounds__(kBlock) void ru_resume_kernel(VecArgs a) {
+    const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+    if (h >= a.Vh) return;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const SysState &s = a.state[j];
+        if (!(s.flags & SYS_RESUME)) continue;
+        const T be = (T)s.beta;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t i = (size_t)j * a.fstride + (size_t)c * a.Vh + h;
+            cpx<double> rd = ld_c<double>(a.r64, i);
+            cpx<T> r{(T)rd.re, (T)rd.im};
+            if (a.r != a.r64) st_c<T>(a.r, i, r);
+            cpx<T> p = ld_c<T>(a.p, i);
+            p.re = r.re + be * p.re;
+            p.im = r.im + be * p.im;
+            st_c<T>(a.p, i, p);
+        }
+    }
+}
+
+// multi-shift (Sec. 2.2, Eq. shlineq): base residual update fused with the solution
+// step of every active shift; |r|^2 -> OP_MS_BETA
+template <typename T, int NR>
+__global__ __launch_bounds__(kBlock) void ms_r_update_kernel(VecArgs a) {
+    if (a.gate_running && a.ctl->n_running == 0) return;
+    const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+    const Ctl &ctl = *a.ctl;
+    double ps[NR], pc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        ps[j] = 0.0;
+        pc[j] = 0.0;
+        const SysState &s = a.state[j];
+        if (!(s.flags & SYS_RUNNING) || h >= a.Vh) continue;
+        const T al = (T)s.alpha;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t i = (size_t)j * a.fstride + (size_t)c * a.Vh + h;
+            cpx<T> r = ld_c<T>(a.r, i), q = ld_c<T>(a.q, i);
+            r.re -= al * q.re;
+            r.im -= al * q.im;
+            st_c<T>(a.r, i, r);
+            pair_add(ps[j], pc[j], (double)r.re * (double)r.re + (double)r.im * (double)r.im,
+                     0.0);
+        }
+        for (int k = 0; k < a.nshift; ++k) {
+            const ShiftState &z = ctl.ms[k * ctl.nrhs + s.gid];
+            if (!z.active) continue;
+            const T ak = (T)z.alpha;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t i = (size_t)k * a.kstride + (size_t)j * a.fstride +
+                                 (size_t)c * a.Vh + h;
+                cpx<T> x = ld_c<T>(a.xs, i), p = ld_c<T>(a.ps, i);
+                x.re += ak * p.re;
+                x.im += ak * p.im;
+                st_c<T>(a.xs, i, x);
+            }
+        }
+    }
+    reduce_and_finish<NR>(ps, pc, a.partials, a.ctl, OP_MS_BETA, a.state, nullptr);
+}
+
+// multi-shift: p = r + beta p;  p_k = zeta_k r + beta_k p_k for the active shifts
+template <typename T, int NR>
+__global__ __launch_bounds__(kBlock) void ms_p_update_kernel(VecArgs a) {
+    if (a.gate_running && a.ctl->n_running == 0) return;
+    const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+    if (h >= a.Vh) return;
+    const Ctl &ctl = *a.ctl;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const SysState &s = a.state[j];
+        if (!(s.flags & SYS_RUNNING)) continue;
+        const T be = (T)s.beta;
+        cpx<T> r[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t i = (size_t)j * a.fstride + (size_t)c * a.Vh + h;
+            r[c] = ld_c<T>(a.r, i);
+            cpx<T> p = ld_c<T>(a.p, i);
+            p.re = r[c].re + be * p.re;
+            p.im = r[c].im + be * p.im;
+            st_c<T>(a.p, i, p);
+        }
+        for (int k = 0; k < a.nshift; ++k) {
+            const ShiftState &z = ctl.ms[k * ctl.nrhs + s.gid];
+            if (!z.active) continue;
+            const T zk = (T)z.zeta, bk = (T)z.beta;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t i = (size_t)k * a.kstride + (size_t)j * a.fstride +
+                                 (size_t)c * a.Vh + h;
+                cpx<T> p = ld_c<T>(a.ps, i);
+                p.re = zk * r[c].re + bk * p.re;
+                p.im = zk * r[c].im + bk * p.im;
+                st_c<T>(a.ps, i, p);
+            }
+        }
+    }
+}
+
+// one launcher per kernel template: precision and chunk size are compile-time
+#define STG_VEC_LAUNCHER(NAME, KERNEL)                                                   \
+    int NAME(const VecArgs &a, int fp64, int nr, hipStream_t stream) {                  \
+        dim3 grid(site_blocks(a.Vh));                                                    \
+        switch (nr * 2 + (fp64 ? 1 : 0)) {                                               \
+            case 3: KERNEL<double, 1><<<grid, kBlock, 0, stream>>>(a); return 0;        \
+            case 2: KERNEL<float, 1><<<grid, kBlock, 0, stream>>>(a); return 0;         \
+            case 5: KERNEL<double, 2><<<grid, kBlock, 0, stream>>>(a); return 0;        \
+            case 4: KERNEL<float, 2><<<grid, kBlock, 0, stream>>>(a); return 0;         \
+            case 9: KERNEL<double, 4><<<grid, kBlock, 0, stream>>>(a); return 0;        \
+            case 8: KERNEL<float, 4><<<grid, kBlock, 0, stream>>>(a); return 0;         \
+            case 17: KERNEL<double, 8><<<grid, kBlock, 0, stream>>>(a); return 0;       \
+            case 16: KERNEL<float, 8><<<grid, kBlock, 0, stream>>>(a); return 0;        \
+            default: return -1;                                                          \
+        }                                                                                \
+    }
+
+STG_VEC_LAUNCHER(launch_cg_update, cg_update_kernel)
+STG_VEC_LAUNCHER(launch_p_update, p_update_kernel)
+STG_VEC_LAUNCHER(launch_ru_resume, ru_resume_kernel)
+STG_VEC_LAUNCHER(launch_ms_r_update, ms_r_update_kernel)
+STG_VEC_LAUNCHER(launch_ms_p_update, ms_p_update_kernel)
+
+int launch_ru_accumulate(const VecArgs &a, int nr, hipStream_t stream) {
+    dim3 grid(site_blocks(a.Vh));
+    switch (nr) {
+        case 1: ru_accumulate_kernel<1><<<grid, kBlock, 0, stream>>>(a); return 0;
+        case 2: ru_accumulate_kernel<2><<<grid, kBlock, 0, stream>>>(a); return 0;
+        case 4: ru_accumulate_kernel<4><<<grid, kBlock, 0, stream>>>(a); return 0;
+        case 8: ru_accumulate_kernel<8><<<grid, kBlock, 0, stream>>>(a); return 0;
+        default: return -1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// compensated complex dot product of one vector pair
+// ---------------------------------------------------------------------------
+constexpr uint32_t kDotMaxBlocks = 1024;
+
+size_t dot_blocks(size_t n) {
+    size_t b = (n + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    return b > kDotMaxBlocks ? kDotMaxBlocks : b;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void dot_kernel(size_t n, const void *x, const void *y,
+                                                     double *partials, Ctl *ctl, int op,
+                                                     SysState *state, double *out) {
+    // per-thread compensated accumulation of the real and imaginary parts
+    double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * kBlock) {
+        cpx<T> a = ld_c<T>(x, i), b = ld_c<T>(y, i);
+        // conj(a) b; products of two floats are exact in double
+        double pr1 = (double)a.re * (double)b.re, pr2 = (double)a.im * (double)b.im;
+        double pi1 = (double)a.re * (double)b.im, pi2 = -(double)a.im * (double)b.re;
+        double e;
+        two_sum(sr, pr1, sr, e);
+        cr += e;
+        two_sum(sr, pr2, sr, e);
+        cr += e;
+        two_sum(si, pi1, si, e);
+        ci += e;
+        two_sum(si, pi2, si, e);
+        ci += e;
+    }
+    if (op == OP_STORE) {
+        double ps[2] = {sr, si}, pc[2] = {cr, ci};
+        reduce_and_finish<2>(ps, pc, partials, ctl, OP_STORE, state, out);
+    } else {
+        double ps[1] = {sr}, pc[1] = {cr};
+        reduce_and_finish<1>(ps, pc, partials, ctl, op, state, out);
+    }
+}
+
+int launch_dot(int fp64, int nvec, size_t n, const void *x, const void *y, double *partials,
+               Ctl *ctl, int op, SysState *state, double *out, hipStream_t stream) {
+    const size_t esz = fp64 ? 16 : 8;
+    dim3 grid((uint32_t)dot_blocks(n));
+    for (int j = 0; j < nvec; ++j) {
+        const char *xj = reinterpret_cast<const char *>(x) + (size_t)j * n * esz;
+        const char *yj = reinterpret_cast<const char *>(y) + (size_t)j * n * esz;
+        SysState *sj = state ? state + j : nullptr;
+        double *oj = out ? out + 2 * j : nullptr;
+        if (fp64)
+            dot_kernel<double><<<grid, kBlock, 0, stream>>>(n, xj, yj, partials, ctl, op, sj, oj);
+        else
+            dot_kernel<float><<<grid, kBlock, 0, stream>>>(n, xj, yj, partials, ctl, op, sj, oj);
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// packing (Sec. 2.3: keep rows 0 and 1; Sec. 4.1 layouts)
+// ---------------------------------------------------------------------------
+
+// double -> bfloat16, round to nearest even, via round-to-odd float: the float
+// keeps 16 more bits than bfloat16, so the second rounding is the correct one.
+__device__ __forceinline__ uint32_t bf16_rne(double x) {
+    float f = __double2float_rz(x);
+    uint32_t u = __float_as_uint(f);
+    if ((double)f != x) u |= 1u;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+__global__ __launch_bounds__(kBlock) void pack_links_kernel(uint32_t Vh, const double2 *src,
+                                                            int fmt, void *dst) {
+    const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+    const int s = blockIdx.y;
+    if (h >= Vh) return;
+    double2 e[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) e[a][b] = src[((size_t)(s * 3 + a) * 3 + b) * Vh + h];
+    if (fmt == FMT_C128_18) {
+        double2 *d = reinterpret_cast<double2 *>(dst);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) d[((size_t)(s * 3 + a) * 3 + b) * Vh + h] = e[a][b];
+    } else if (fmt == FMT_C128_12) {
+        double2 *d = reinterpret_cast<double2 *>(dst);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) d[((size_t)(s * 2 + a) * 3 + b) * Vh + h] = e[a][b];
+    } else if (fmt == FMT_C64_12) {
+        float4 *d = reinterpret_cast<float4 *>(dst);
+        const double2 *flat = &e[0][0];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double2 u = flat[2 * k], v = flat[2 * k + 1];
+            d[(size_t)(s * 3 + k) * Vh + h] =
+                make_float4((float)u.x, (float)u.y, (float)v.x, (float)v.y);
+        }
+    } else {  // FMT_BF16_12
+        const double2 *flat = &e[0][0];
+        uint32_t w[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) w[k] = bf16_rne(flat[k].x) | (bf16_rne(flat[k].y) << 16);
+        uint4 *da = reinterpret_cast<uint4 *>(dst);
+        uint2 *db = reinterpret_cast<uint2 *>(da + (size_t)8 * Vh);
+        da[(size_t)s * Vh + h] = make_uint4(w[0], w[1], w[2], w[3]);
+        db[(size_t)s * Vh + h] = make_uint2(w[4], w[5]);
+    }
+}
+
+int launch_pack_links(const Geom &g, const void *src, int fmt, void *dst, hipStream_t stream) {
+    dim3 grid(site_blocks(g.Vh), 8);
+    pack_links_kernel<<<grid, kBlock, 0, stream>>>(g.Vh, reinterpret_cast<const double2 *>(src),
+                                                   fmt, dst);
+    return 0;
+}
+
+__global__ __launch_bounds__(kBlock) void f64_to_f32_kernel(size_t n, const double *src,
+                                                            float *dst) {
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * kBlock)
+        dst[i] = (float)src[i];
+}
+
+int launch_pack_phases_f32(size_t n, const double *src, float *dst, hipStream_t stream) {
+    size_t b = (n + kBlock - 1) / kBlock;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    f64_to_f32_kernel<<<dim3((uint32_t)b), kBlock, 0, stream>>>(n, src, dst);
+    return 0;
+}
+
+int launch_c128_to_c64(size_t n, const void *src, void *dst, hipStream_t stream) {
+    return launch_pack_phases_f32(2 * n, reinterpret_cast<const double *>(src),
+                                  reinterpret_cast<float *>(dst), stream);
+}
+
+__global__ __launch_bounds__(kBlock) void f32_to_f64_kernel(size_t n, const float *src,
+                                                            double *dst) {
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * kBlock)
+        dst[i] = (double)src[i];
+}
+
+int launch_c64_to_c128(size_t n, const void *src, void *dst, hipStream_t stream) {
+    size_t b = (2 * n + kBlock - 1) / kBlock;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    f32_to_f64_kernel<<<dim3((uint32_t)b), kBlock, 0, stream>>>(
+        2 * n, reinterpret_cast<const float *>(src), reinterpret_cast<double *>(dst));
+    return 0;
+}
+
+__global__ __launch_bounds__(kBlock) void zero_kernel(size_t n4, uint32_t *dst) {
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n4;
+         i += (size_t)gridDim.x * kBlock)
+        dst[i] = 0u;
+}
+
+int launch_zero(void *dst, size_t bytes, hipStream_t stream) {
+    size_t n4 = bytes / 4;
+    if (n4 == 0) return 0;
+    size_t b = (n4 + kBlock - 1) / kBlock;
+    if (b > 65536) b = 65536;
+    zero_kernel<<<dim3((uint32_t)b), kBlock, 0, stream>>>(n4, reinterpret_cast<uint32_t *>(dst));
+    return 0;
+}
+
+}  // namespace stg

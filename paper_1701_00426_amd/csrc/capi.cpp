@@ -1,0 +1,936 @@
+// capi.cpp -- the C ABI of include/stagmi.h: argument checks, dispatch of the hop
+// and vector kernels, workspace carving, and the host side of the solvers.
+//
+// Paper: arXiv:1701.00426, Sec. 2.2 (Eqs. diracblock, lineqeo, shlineq: the
+// operator, the even/odd normal equations and the shifted systems), Sec. 4.1
+// (layouts), Sec. 4.3 (deo/doe).  The solver loop keeps alpha and beta on the
+// device; the host enqueues a batch of iterations, then reads the per-system
+// flags once, and enqueues the FP64 true-residual update of any parked system.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/stagmi.h"
+#include "kernels.hpp"
+#include "solver_state.hpp"
+
+using namespace stg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int hip_fail(hipError_t e, const char *what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return STG_HIP_ERROR;
+}
+
+#define HIP_TRY(call)                                   \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+int invalid(const char *why) {
+    g_last_error = why;
+    return STG_INVALID_ARG;
+}
+
+bool make_geom(const stg_lattice *lat, Geom &g) {
+    if (!lat) return false;
+    uint64_t v = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        int32_t n = lat->dims[mu];
+        if (n < 2 || (n & 1) || n > 65536) return false;
+        g.N[mu] = (uint32_t)n;
+        v *= (uint64_t)n;
+    }
+    if (v / 2 >= (1ull << 30)) return false;  // half indices and strides stay in 32 bits
+    g.nh0 = g.N[0] / 2;
+    g.Vh = (uint32_t)(v / 2);
+    g.stride[0] = 1;
+    g.stride[1] = g.nh0;
+    g.stride[2] = g.nh0 * g.N[1];
+    g.stride[3] = g.nh0 * g.N[1] * g.N[2];
+    return true;
+}
+
+bool aligned16(const void *p) { return p && (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + nb && b0 < a0 + na;
+}
+
+size_t link_bytes(const Geom &g, int fmt) {
+    const size_t vh = g.Vh;
+    switch (fmt) {
+        case STG_LINK_C128_18: return 8 * 9 * vh * 16;
+        case STG_LINK_C128_12: return 8 * 6 * vh * 16;
+        case STG_LINK_C64_12: return 8 * 3 * vh * 16;
+        case STG_LINK_BF16_12: return 8 * vh * 24;
+        default: return 0;
+    }
+}
+
+bool fmt_matches(int fmt, int field) {
+    if (field == STG_C128) return fmt == STG_LINK_C128_18 || fmt == STG_LINK_C128_12;
+    if (field == STG_C64) return fmt == STG_LINK_C64_12 || fmt == STG_LINK_BF16_12;
+    return false;
+}
+
+size_t field_elem(int field) { return field == STG_C128 ? 16 : 8; }
+
+int check_gauge(const Geom &g, const stg_gauge *gauge, int field) {
+    if (!gauge) return invalid("gauge is NULL");
+    if (!fmt_matches(gauge->fmt, field))
+        return invalid("gauge format does not match the field precision");
+    if (!aligned16(gauge->links)) return invalid("links NULL or not 16-byte aligned");
+    if (gauge->phases && (reinterpret_cast<uintptr_t>(gauge->phases) & 7u))
+        return invalid("phases not 8-byte aligned");
+    (void)g;
+    return STG_OK;
+}
+
+HopArgs base_hop(const Geom &g, const stg_gauge *gauge) {
+    HopArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.geom = g;
+    a.links = gauge->links;
+    a.phases = gauge->phases;
+    a.fstride = (size_t)3 * g.Vh;
+    return a;
+}
+
+// Largest supported chunk of fields for one kernel launch.
+int chunk_of(int remaining) {
+    if (remaining >= 8) return 8;
+    if (remaining >= 4) return 4;
+    if (remaining >= 2) return 2;
+    return 1;
+}
+
+int hop_plain(const Geom &g, const stg_gauge *gauge, int field, int nrhs, const void *in,
+              void *out, int out_parity, hipStream_t stream) {
+    const size_t fb = (size_t)3 * g.Vh * field_elem(field);
+    HopArgs a = base_hop(g, gauge);
+    a.out_parity = out_parity;
+    a.op = OP_NONE;
+    for (int j0 = 0; j0 < nrhs;) {
+        int nr = chunk_of(nrhs - j0);
+        a.in = reinterpret_cast<const char *>(in) + j0 * fb;
+        a.out = reinterpret_cast<char *>(out) + j0 * fb;
+        if (launch_hop(a, gauge->fmt, nr, EPI_PLAIN, stream)) return invalid("unsupported hop");
+        j0 += nr;
+    }
+    HIP_TRY(hipGetLastError());
+    return STG_OK;
+}
+
+int apply_dirac(const stg_lattice *lat, const stg_gauge *gauge, int field, int nrhs,
+                const void *in, void *out, int out_parity, stg_stream_t stream) {
+    Geom g;
+    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
+    if (field != STG_C128 && field != STG_C64) return invalid("unknown field type");
+    int rc = check_gauge(g, gauge, field);
+    if (rc) return rc;
+    if (nrhs < 1) return invalid("nrhs < 1");
+    if (!aligned16(in) || !aligned16(out)) return invalid("field NULL or not 16-byte aligned");
+    const size_t fb = (size_t)nrhs * 3 * g.Vh * field_elem(field);
+    if (overlap(in, fb, out, fb)) return invalid("input and output overlap");
+    return hop_plain(g, gauge, field, nrhs, in, out, out_parity, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    void *take(size_t bytes) {
+        void *p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    }
+};
+
+struct CgWork {
+    Ctl *ctl;
+    SysState *state;
+    double *partials;
+    double *sums;
+    // inner precision (FP64 mode: double fields; MIXED: float fields)
+    void *x_in, *p, *r, *q, *t;
+    // FP64 fields for the true residual (MIXED only; F64 mode aliases r / t)
+    void *r64, *t64;
+    size_t bytes;
+};
+
+size_t partial_count(const Geom &g) {
+    // (sum, error) pairs: NR <= 8 per site-kernel block, 2 per dot block
+    size_t sites = (size_t)2 * 8 * site_blocks(g.Vh);
+    size_t dots = (size_t)2 * 2 * dot_blocks((size_t)3 * g.Vh);
+    return std::max(sites, dots);
+}
+
+CgWork carve_cg(const Geom &g, int nsys, int mode, void *ws) {
+    Carver c{reinterpret_cast<char *>(ws)};
+    CgWork w;
+    const size_t f64 = (size_t)nsys * 3 * g.Vh * 16;
+    const size_t f32 = (size_t)nsys * 3 * g.Vh * 8;
+    w.ctl = (Ctl *)c.take(sizeof(Ctl));
+    w.state = (SysState *)c.take(sizeof(SysState) * (size_t)nsys);
+    w.partials = (double *)c.take(sizeof(double) * partial_count(g));
+    w.sums = (double *)c.take(sizeof(double) * 16);
+    if (mode == STG_CG_F64) {
+        w.x_in = nullptr;  // the caller's x
+        w.p = c.take(f64);
+        w.r = c.take(f64);
+        w.q = c.take(f64);
+        w.t = c.take(f64);
+        w.r64 = w.r;
+        w.t64 = w.t;
+    } else {
+        w.x_in = c.take(f32);
+        w.p = c.take(f32);
+        w.r = c.take(f32);
+        w.q = c.take(f32);
+        w.t = c.take(f32);
+        w.r64 = c.take(f64);
+        w.t64 = c.take(f64);
+    }
+    w.bytes = c.off;
+    return w;
+}
+
+// ---------------------------------------------------------------------------
+// CG driver shared by cg_solve (and the refinement stage of the multi-shift solve)
+// ---------------------------------------------------------------------------
+struct CgProblem {
+    Geom g;
+    const stg_gauge *hi;
+    const stg_gauge *lo;
+    int mode;
+    int nsys;
+    const void *b;     // complex128 [nsys][3][Vh]
+    void *x;           // complex128 [nsys][3][Vh], guess in, solution out
+    std::vector<double> diag;  // m^2 + sigma per system
+    stg_cg_params prm;
+    int group = 0;     // systems s share b[s % group] (multi-shift refinement); 0: group = nsys
+    int chunk(int j0) const {
+        const int g = group > 0 ? group : nsys;
+        return chunk_of(std::min(nsys - j0, g - j0 % g));
+    }
+    const void *b_at(int j0, size_t fb64) const {
+        const int g = group > 0 ? group : nsys;
+        return (const char *)b + (size_t)(j0 % g) * fb64;
+    }
+};
+
+int enqueue_inner_iteration(const CgProblem &P, const CgWork &w, hipStream_t s) {
+    const bool f64 = P.mode == STG_CG_F64;
+    const stg_gauge *gg = f64 ? P.hi : P.lo;
+    const size_t fb = (size_t)3 * P.g.Vh * (f64 ? 16 : 8);
+    void *xin = f64 ? P.x : w.x_in;
+    for (int j0 = 0; j0 < P.nsys;) {
+        const int nr = P.chunk(j0);
+        const size_t o = j0 * fb;
+        HopArgs a = base_hop(P.g, gg);
+        a.gate_running = 1;
+        a.ctl = w.ctl;
+        a.state = w.state + j0;
+        a.partials = w.partials;
+        // t = D_oe p
+        a.out_parity = 1;
+        a.op = OP_NONE;
+        a.in = (const char *)w.p + o;
+        a.out = (char *)w.t + o;
+        launch_hop(a, gg->fmt, nr, EPI_PLAIN, s);
+        // q = diag p - D_eo t ; <p, q> -> alpha
+        a.out_parity = 0;
+        a.op = OP_ALPHA;
+        a.in = (const char *)w.t + o;
+        a.out = (char *)w.q + o;
+        a.aux0 = (const char *)w.p + o;
+        launch_hop(a, gg->fmt, nr, EPI_NORMAL, s);
+        // x += alpha p, r -= alpha q ; |r|^2 -> beta / park
+        VecArgs v;
+        std::memset(&v, 0, sizeof(v));
+        v.Vh = P.g.Vh;
+        v.fstride = (size_t)3 * P.g.Vh;
+        v.x = (char *)xin + o;
+        v.p = (char *)w.p + o;
+        v.r = (char *)w.r + o;
+        v.q = (const char *)w.q + o;
+        v.state = w.state + j0;
+        v.ctl = w.ctl;
+        v.partials = w.partials;
+        v.gate_running = 1;
+        launch_cg_update(v, f64, nr, s);
+        launch_p_update(v, f64, nr, s);
+        j0 += nr;
+    }
+    HIP_TRY(hipGetLastError());
+    return STG_OK;
+}
+
+// FP64 true-residual update of every parked system: x64 += x_inner (MIXED),
+// r64 = b - A x64, then resume from r64 or finish.
+int enqueue_reliable_update(const CgProblem &P, const CgWork &w, hipStream_t s) {
+    const bool f64 = P.mode == STG_CG_F64;
+    const size_t fb64 = (size_t)3 * P.g.Vh * 16;
+    const size_t fbin = (size_t)3 * P.g.Vh * (f64 ? 16 : 8);
+    for (int j0 = 0; j0 < P.nsys;) {
+        const int nr = P.chunk(j0);
+        VecArgs v;
+        std::memset(&v, 0, sizeof(v));
+        v.Vh = P.g.Vh;
+        v.fstride = (size_t)3 * P.g.Vh;
+        v.state = w.state + j0;
+        v.ctl = w.ctl;
+        v.partials = w.partials;
+        v.x64 = (char *)P.x + j0 * fb64;
+        if (!f64) {
+            v.x = (char *)w.x_in + j0 * fbin;
+            launch_ru_accumulate(v, nr, s);
+        }
+        HopArgs a = base_hop(P.g, P.hi);
+        a.ctl = w.ctl;
+        a.state = w.state + j0;
+        a.partials = w.partials;
+        a.out_parity = 1;
+        a.op = OP_NONE;
+        a.in = (const char *)P.x + j0 * fb64;
+        a.out = (char *)w.t64 + j0 * fb64;
+        launch_hop(a, P.hi->fmt, nr, EPI_PLAIN, s);
+        a.out_parity = 0;
+        a.op = OP_RU;
+        a.in = (const char *)w.t64 + j0 * fb64;
+        a.out = (char *)w.r64 + j0 * fb64;
+        a.aux0 = (const char *)P.x + j0 * fb64;
+        a.aux1 = P.b_at(j0, fb64);
+        launch_hop(a, P.hi->fmt, nr, EPI_RESID, s);
+        v.r64 = (const char *)w.r64 + j0 * fb64;
+        v.r = (char *)w.r + j0 * fbin;
+        v.p = (char *)w.p + j0 * fbin;
+        launch_ru_resume(v, f64, nr, s);
+        j0 += nr;
+    }
+    HIP_TRY(hipGetLastError());
+    return STG_OK;
+}
+
+int read_states_n(const SysState *dev, int nsys, std::vector<SysState> &st, hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(st.data(), dev, sizeof(SysState) * nsys, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return STG_OK;
+}
+
+int read_states(const CgWork &w, int nsys, std::vector<SysState> &st, hipStream_t s) {
+    return read_states_n(w.state, nsys, st, s);
+}
+
+int run_cg(const CgProblem &P, const CgWork &w, stg_cg_stats *stats, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int n = P.nsys;
+    const bool f64 = P.mode == STG_CG_F64;
+    const size_t fbin = (size_t)3 * P.g.Vh * (f64 ? 16 : 8);
+    const size_t fb64 = (size_t)3 * P.g.Vh * 16;
+
+    // initial state: every system parked with beta = 0, so the first update
+    // computes r = b - A x0 and sets p = r
+    std::vector<SysState> st(n);
+    for (int j = 0; j < n; ++j) {
+        SysState &q = st[j];
+        std::memset(&q, 0, sizeof(q));
+        q.diag = P.diag[j];
+        q.tol2bb = P.prm.tol * P.prm.tol;  // times |b|^2 on the device
+        q.delta2 = f64 ? 0.0 : P.prm.delta * P.prm.delta;
+        q.flags = SYS_RU_PENDING;
+        q.restart = P.prm.restart;
+        q.gid = j;
+    }
+    Ctl ctl0;
+    std::memset(&ctl0, 0, sizeof(ctl0));
+    HIP_TRY(hipMemcpyAsync(w.ctl, &ctl0, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w.state, st.data(), sizeof(SysState) * n, hipMemcpyHostToDevice, s));
+    launch_zero(w.p, (size_t)n * fbin, s);
+    if (!f64) launch_zero(w.x_in, (size_t)n * fbin, s);
+    for (int j = 0; j < n; ++j) {
+        const void *bj = P.b_at(j, fb64);
+        launch_dot(1, 1, (size_t)3 * P.g.Vh, bj, bj, w.partials, w.ctl, OP_INIT_BB,
+                   w.state + j, nullptr, s);
+    }
+    HIP_TRY(hipGetLastError());
+    int rc = read_states(w, n, st, s);
+    if (rc) return rc;
+    // b = 0: the solution is x = 0;  non-finite |b|^2: breakdown before any iteration
+    bool any_zero = false;
+    for (int j = 0; j < n; ++j) {
+        if (!(st[j].bb < 1.0e300)) {
+            any_zero = true;
+            st[j].flags = SYS_BREAKDOWN;
+            st[j].rr_true = st[j].bb;
+        } else if (!(st[j].bb > 0.0)) {
+            any_zero = true;
+            st[j].flags = SYS_DONE;
+            st[j].rr_true = 0.0;
+            launch_zero((char *)P.x + j * fb64, fb64, s);
+        }
+    }
+    if (any_zero)
+        HIP_TRY(hipMemcpyAsync(w.state, st.data(), sizeof(SysState) * n, hipMemcpyHostToDevice, s));
+    rc = enqueue_reliable_update(P, w, s);
+    if (rc) return rc;
+
+    int poll = P.prm.poll_every;
+    if (poll <= 0) poll = (int)std::min<uint32_t>(64, std::max<uint32_t>(8, (1u << 22) / P.g.Vh));
+    int status_all = STG_OK;
+    for (;;) {
+        rc = read_states(w, n, st, s);
+        if (rc) return rc;
+        int running = 0, pending = 0, max_it = 0;
+        for (int j = 0; j < n; ++j) {
+            if (st[j].flags & SYS_RUNNING) {
+                ++running;
+                max_it = std::max(max_it, st[j].iter);
+            }
+            if (st[j].flags & SYS_RU_PENDING) ++pending;
+        }
+        if (pending) {
+            rc = enqueue_reliable_update(P, w, s);
+            if (rc) return rc;
+            continue;
+        }
+        if (running == 0) break;
+        if (max_it >= P.prm.max_iter) break;
+        const int k = std::min(poll, P.prm.max_iter - max_it);
+        for (int i = 0; i < k; ++i) {
+            rc = enqueue_inner_iteration(P, w, s);
+            if (rc) return rc;
+        }
+    }
+    // systems stopped by the iteration cap: fold the inner solution into x and
+    // compute their true residual
+    bool any_open = false;
+    for (int j = 0; j < n; ++j)
+        if (st[j].flags & SYS_RUNNING) {
+            st[j].flags = SYS_RU_PENDING;
+            st[j].restart = 1;
+            any_open = true;
+        }
+    if (any_open) {
+        HIP_TRY(hipMemcpyAsync(w.state, st.data(), sizeof(SysState) * n, hipMemcpyHostToDevice, s));
+        rc = enqueue_reliable_update(P, w, s);
+        if (rc) return rc;
+        rc = read_states(w, n, st, s);
+        if (rc) return rc;
+    }
+    const double secs =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int j = 0; j < n; ++j) {
+        int stj;
+        if (st[j].flags & SYS_DONE)
+            stj = STG_OK;
+        else if (st[j].flags & SYS_BREAKDOWN)
+            stj = STG_BREAKDOWN;
+        else
+            stj = STG_NOT_CONVERGED;
+        if (stats) {
+            stats[j].iters = st[j].iter;
+            stats[j].reliable_updates = st[j].n_ru;
+            stats[j].status = stj;
+            stats[j].converged_iter = (stj == STG_OK) ? st[j].conv_iter : -1;
+            stats[j].true_rel_resid = st[j].bb > 0.0   ? std::sqrt(st[j].rr_true / st[j].bb)
+                                      : st[j].bb == 0.0 ? 0.0
+                                                        : std::nan("");
+            stats[j].seconds = secs;
+        }
+        if (stj == STG_BREAKDOWN || (stj == STG_NOT_CONVERGED && status_all == STG_OK))
+            status_all = stj;
+    }
+    return status_all;
+}
+
+int check_solver_common(const stg_lattice *lat, Geom &g, const stg_gauge *hi, const stg_gauge *lo,
+                        int mode, int nrhs, const void *b, void *x, const stg_cg_params *prm) {
+    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
+    if (!prm) return invalid("params is NULL");
+    if (mode != STG_CG_F64 && mode != STG_CG_MIXED) return invalid("unknown solver mode");
+    if (!(prm->tol > 0.0) || prm->max_iter < 1) return invalid("tol must be > 0, max_iter >= 1");
+    if (mode == STG_CG_MIXED && !(prm->delta > 0.0 && prm->delta < 1.0))
+        return invalid("delta must be in (0, 1)");
+    if (nrhs < 1) return invalid("nrhs < 1");
+    int rc = check_gauge(g, hi, STG_C128);
+    if (rc) return rc;
+    if (mode == STG_CG_MIXED) {
+        rc = check_gauge(g, lo, STG_C64);
+        if (rc) return rc;
+    }
+    if (!aligned16(b) || !aligned16(x)) return invalid("b or x NULL or not 16-byte aligned");
+    return STG_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// multi-shift CG (Sec. 2.2, Eq. shlineq)
+// ---------------------------------------------------------------------------
+
+// Target of the multi-shift stage in mixed mode: FP32 vectors cannot carry the
+// shifted solutions below about this relative residual; the refinement stage
+// takes every system from there to the FP64 tolerance.
+constexpr double kMsTolMixed = 1e-6;
+
+struct MsWork {
+    Ctl *ctl;
+    SysState *state;      // one per RHS: the base system
+    ShiftState *shift;    // [nshift][nrhs]
+    double *partials;
+    void *p, *r, *q, *t;  // base vectors, inner precision, [nrhs]
+    void *xs, *ps;        // shifted solutions and directions, inner precision, [nshift][nrhs]
+    size_t bytes;
+};
+
+MsWork carve_ms(const Geom &g, int nrhs, int nshift, int mode, void *ws) {
+    Carver c{reinterpret_cast<char *>(ws)};
+    MsWork w;
+    const size_t e = mode == STG_CG_F64 ? 16 : 8;
+    const size_t f1 = (size_t)nrhs * 3 * g.Vh * e;
+    w.ctl = (Ctl *)c.take(sizeof(Ctl));
+    w.state = (SysState *)c.take(sizeof(SysState) * (size_t)nrhs);
+    w.shift = (ShiftState *)c.take(sizeof(ShiftState) * (size_t)nrhs * nshift);
+    w.partials = (double *)c.take(sizeof(double) * partial_count(g));
+    w.p = c.take(f1);
+    w.r = c.take(f1);
+    w.q = c.take(f1);
+    w.t = c.take(f1);
+    w.xs = c.take(f1 * nshift);
+    w.ps = c.take(f1 * nshift);
+    w.bytes = c.off;
+    return w;
+}
+
+size_t ms_workspace(const Geom &g, int nrhs, int nshift, int mode) {
+    return std::max(carve_ms(g, nrhs, nshift, mode, nullptr).bytes,
+                    carve_cg(g, nrhs * nshift, mode, nullptr).bytes);
+}
+
+int enqueue_ms_iteration(const Geom &g, const stg_gauge *gg, int f64, int nrhs, int nshift,
+                         const MsWork &w, hipStream_t s) {
+    const size_t fb = (size_t)3 * g.Vh * (f64 ? 16 : 8);
+    for (int j0 = 0; j0 < nrhs;) {
+        const int nr = chunk_of(nrhs - j0);
+        const size_t o = j0 * fb;
+        HopArgs a = base_hop(g, gg);
+        a.gate_running = 1;
+        a.ctl = w.ctl;
+        a.state = w.state + j0;
+        a.partials = w.partials;
+        a.out_parity = 1;
+        a.op = OP_NONE;
+        a.in = (const char *)w.p + o;
+        a.out = (char *)w.t + o;
+        launch_hop(a, gg->fmt, nr, EPI_PLAIN, s);
+        a.out_parity = 0;
+        a.op = OP_MS_ALPHA;
+        a.in = (const char *)w.t + o;
+        a.out = (char *)w.q + o;
+        a.aux0 = (const char *)w.p + o;
+        launch_hop(a, gg->fmt, nr, EPI_NORMAL, s);
+        VecArgs v;
+        std::memset(&v, 0, sizeof(v));
+        v.Vh = g.Vh;
+        v.fstride = (size_t)3 * g.Vh;
+        v.p = (char *)w.p + o;
+        v.r = (char *)w.r + o;
+        v.q = (const char *)w.q + o;
+        v.xs = (char *)w.xs + o;
+        v.ps = (char *)w.ps + o;
+        v.kstride = (size_t)nrhs * 3 * g.Vh;
+        v.nshift = nshift;
+        v.state = w.state + j0;
+        v.ctl = w.ctl;
+        v.partials = w.partials;
+        v.gate_running = 1;
+        launch_ms_r_update(v, f64, nr, s);
+        launch_ms_p_update(v, f64, nr, s);
+        j0 += nr;
+    }
+    HIP_TRY(hipGetLastError());
+    return STG_OK;
+}
+
+int run_mscg(const Geom &g, const stg_gauge *hi, const stg_gauge *lo, double mass, int nshift,
+             const double *shifts, int nrhs, const void *b, void *x, const stg_cg_params &prm,
+             void *ws, stg_cg_stats *stats, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int mode = prm.mode;
+    const int f64 = mode == STG_CG_F64;
+    const stg_gauge *gg = f64 ? hi : lo;
+    const size_t fb64 = (size_t)3 * g.Vh * 16;
+    const size_t fbin = (size_t)3 * g.Vh * (f64 ? 16 : 8);
+    const size_t n1 = (size_t)3 * g.Vh;  // complex entries per field
+    int k0 = 0;
+    for (int k = 1; k < nshift; ++k)
+        if (shifts[k] < shifts[k0]) k0 = k;
+    const double sigma0 = shifts[k0];
+    const double tol_ms = f64 ? prm.tol : std::max(prm.tol, kMsTolMixed);
+
+    MsWork w = carve_ms(g, nrhs, nshift, mode, ws);
+    // host-side initial state
+    Ctl ctl0;
+    std::memset(&ctl0, 0, sizeof(ctl0));
+    ctl0.n_running = nrhs;
+    ctl0.nshift = nshift;
+    ctl0.nrhs = nrhs;
+    ctl0.ms = w.shift;
+    std::vector<SysState> st(nrhs);
+    for (int j = 0; j < nrhs; ++j) {
+        SysState &q = st[j];
+        std::memset(&q, 0, sizeof(q));
+        q.diag = mass * mass + sigma0;
+        q.tol2bb = tol_ms * tol_ms;
+        q.flags = SYS_RUNNING;
+        q.gid = j;
+        q.alpha_prev = 1.0;
+        q.beta_prev = 0.0;
+    }
+    std::vector<ShiftState> zs((size_t)nshift * nrhs);
+    for (int k = 0; k < nshift; ++k)
+        for (int j = 0; j < nrhs; ++j) {
+            ShiftState &z = zs[(size_t)k * nrhs + j];
+            std::memset(&z, 0, sizeof(z));
+            z.delta = shifts[k] - sigma0;
+            z.zeta = z.zeta_prev = z.zeta_next = 1.0;
+            z.active = 1;
+        }
+    HIP_TRY(hipMemcpyAsync(w.ctl, &ctl0, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w.state, st.data(), sizeof(SysState) * nrhs, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w.shift, zs.data(), sizeof(ShiftState) * zs.size(),
+                           hipMemcpyHostToDevice, s));
+    // r = p = b, p_k = b, x_k = 0  (in the inner precision)
+    if (f64) {
+        HIP_TRY(hipMemcpyAsync(w.r, b, nrhs * fb64, hipMemcpyDeviceToDevice, s));
+    } else {
+        launch_c128_to_c64((size_t)nrhs * n1, b, w.r, s);
+    }
+    HIP_TRY(hipMemcpyAsync(w.p, w.r, nrhs * fbin, hipMemcpyDeviceToDevice, s));
+    for (int k = 0; k < nshift; ++k)
+        HIP_TRY(hipMemcpyAsync((char *)w.ps + (size_t)k * nrhs * fbin, w.r, nrhs * fbin,
+                               hipMemcpyDeviceToDevice, s));
+    launch_zero(w.xs, (size_t)nshift * nrhs * fbin, s);
+    for (int j = 0; j < nrhs; ++j) {
+        const void *bj = (const char *)b + j * fb64;
+        launch_dot(1, 1, n1, bj, bj, w.partials, w.ctl, OP_INIT_BB, w.state + j, nullptr, s);
+    }
+    HIP_TRY(hipGetLastError());
+    int rc = read_states_n(w.state, nrhs, st, s);
+    if (rc) return rc;
+    bool any_zero = false;
+    for (int j = 0; j < nrhs; ++j) {
+        if (!(st[j].bb < 1.0e300)) {
+            // non-finite |b|^2
+            any_zero = true;
+            st[j].flags = SYS_BREAKDOWN;
+        } else if (!(st[j].bb > 0.0)) {
+            // b = 0: every x_k stays 0
+            any_zero = true;
+            st[j].flags = SYS_DONE;
+        }
+    }
+    if (any_zero) {
+        int nrun = 0;
+        for (int j = 0; j < nrhs; ++j) nrun += (st[j].flags & SYS_RUNNING) ? 1 : 0;
+        ctl0.n_running = nrun;
+        HIP_TRY(hipMemcpyAsync(w.ctl, &ctl0, sizeof(Ctl), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(w.state, st.data(), sizeof(SysState) * nrhs, hipMemcpyHostToDevice,
+                               s));
+    }
+    int poll = prm.poll_every;
+    if (poll <= 0) poll = (int)std::min<uint32_t>(64, std::max<uint32_t>(8, (1u << 22) / g.Vh));
+    int ms_iters = 0;
+    for (;;) {
+        rc = read_states_n(w.state, nrhs, st, s);
+        if (rc) return rc;
+        int running = 0, max_it = 0;
+        for (int j = 0; j < nrhs; ++j)
+            if (st[j].flags & SYS_RUNNING) {
+                ++running;
+                max_it = std::max(max_it, st[j].iter);
+            }
+        for (int j = 0; j < nrhs; ++j) ms_iters = std::max(ms_iters, st[j].iter);
+        if (running == 0 || max_it >= prm.max_iter) break;
+        const int k = std::min(poll, prm.max_iter - max_it);
+        for (int i = 0; i < k; ++i) {
+            rc = enqueue_ms_iteration(g, gg, f64, nrhs, nshift, w, s);
+            if (rc) return rc;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(zs.data(), w.shift, sizeof(ShiftState) * zs.size(),
+                           hipMemcpyDeviceToHost, s));
+    // shifted solutions -> x (complex128, [nshift][nrhs])
+    if (f64)
+        HIP_TRY(hipMemcpyAsync(x, w.xs, (size_t)nshift * nrhs * fb64, hipMemcpyDeviceToDevice, s));
+    else
+        launch_c64_to_c128((size_t)nshift * nrhs * n1, w.xs, x, s);
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<SysState> base = st;
+
+    // refinement: every (shift, RHS) system warm-started from its multi-shift
+    // solution, solved to the FP64 tolerance with its own diagonal
+    CgProblem P;
+    P.g = g;
+    P.hi = hi;
+    P.lo = lo;
+    P.mode = mode;
+    P.nsys = nshift * nrhs;
+    P.b = b;
+    P.x = x;
+    P.group = nrhs;
+    P.diag.resize(P.nsys);
+    for (int k = 0; k < nshift; ++k)
+        for (int j = 0; j < nrhs; ++j) P.diag[(size_t)k * nrhs + j] = mass * mass + shifts[k];
+    P.prm = prm;
+    CgWork cw = carve_cg(g, P.nsys, mode, ws);
+    std::vector<stg_cg_stats> rs(P.nsys);
+    const int status = run_cg(P, cw, rs.data(), s);
+    if (status < 0) return status;
+    const double secs =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int k = 0; k < nshift; ++k)
+        for (int j = 0; j < nrhs; ++j) {
+            const size_t i = (size_t)k * nrhs + j;
+            const ShiftState &z = zs[i];
+            const int ms_it = z.active ? base[j].iter : z.conv_iter;
+            stats[i] = rs[i];
+            stats[i].iters = ms_it + rs[i].iters;
+            stats[i].converged_iter =
+                rs[i].status == STG_OK ? ms_it + std::max(0, rs[i].converged_iter) : -1;
+            stats[i].seconds = secs;
+        }
+    (void)ms_iters;
+    return status;
+}
+
+}  // namespace
+
+// ===========================================================================
+// exported
+// ===========================================================================
+extern "C" {
+
+int stg_version(void) { return (1 << 16) | 0; }
+
+const char *stg_status_string(int status) {
+    switch (status) {
+        case STG_OK: return "ok";
+        case STG_NOT_CONVERGED: return "not converged (iteration cap reached)";
+        case STG_BREAKDOWN: return "breakdown (non-finite scalar or <p, A p> <= 0)";
+        case STG_INVALID_ARG: return "invalid argument";
+        case STG_HIP_ERROR: return "HIP runtime error";
+        case STG_WORKSPACE_TOO_SMALL: return "workspace too small";
+        default: return "unknown status";
+    }
+}
+
+const char *stg_last_error(void) { return g_last_error.c_str(); }
+
+int stg_links_bytes(const stg_lattice *lat, stg_link_fmt fmt, size_t *bytes) {
+    Geom g;
+    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
+    if (!bytes) return invalid("bytes is NULL");
+    size_t b = link_bytes(g, fmt);
+    if (!b) return invalid("unknown link format");
+    *bytes = b;
+    return STG_OK;
+}
+
+int stg_pack_links(const stg_lattice *lat, const void *links_c128_18, stg_link_fmt dst_fmt,
+                   void *dst, stg_stream_t stream) {
+    Geom g;
+    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
+    size_t nb = link_bytes(g, dst_fmt);
+    if (!nb) return invalid("unknown link format");
+    if (!aligned16(links_c128_18) || !aligned16(dst)) return invalid("NULL or misaligned links");
+    if (overlap(links_c128_18, link_bytes(g, STG_LINK_C128_18), dst, nb))
+        return invalid("source and destination overlap");
+    launch_pack_links(g, links_c128_18, dst_fmt, dst, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return STG_OK;
+}
+
+int stg_pack_phases(const stg_lattice *lat, const double *phases_f64, stg_field dst,
+                    void *dst_ptr, stg_stream_t stream) {
+    Geom g;
+    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
+    if (!phases_f64 || !dst_ptr) return invalid("NULL phases");
+    const size_t n = (size_t)8 * g.Vh;
+    hipStream_t s = (hipStream_t)stream;
+    if (dst == STG_C128) {
+        if (overlap(phases_f64, n * 8, dst_ptr, n * 8)) return invalid("overlap");
+        HIP_TRY(hipMemcpyAsync(dst_ptr, phases_f64, n * 8, hipMemcpyDeviceToDevice, s));
+    } else if (dst == STG_C64) {
+        if (overlap(phases_f64, n * 8, dst_ptr, n * 4)) return invalid("overlap");
+        launch_pack_phases_f32(n, phases_f64, (float *)dst_ptr, s);
+        HIP_TRY(hipGetLastError());
+    } else {
+        return invalid("unknown field type");
+    }
+    return STG_OK;
+}
+
+int dirac_apply_eo(const stg_lattice *lat, const stg_gauge *gauge, stg_field field, int nrhs,
+                   const void *in_odd, void *out_even, stg_stream_t stream) {
+    return apply_dirac(lat, gauge, field, nrhs, in_odd, out_even, 0, stream);
+}
+
+int dirac_apply_oe(const stg_lattice *lat, const stg_gauge *gauge, stg_field field, int nrhs,
+                   const void *in_even, void *out_odd, stg_stream_t stream) {
+    return apply_dirac(lat, gauge, field, nrhs, in_even, out_odd, 1, stream);
+}
+
+int stg_apply_normal(const stg_lattice *lat, const stg_gauge *gauge, stg_field field, int nrhs,
+                     double mass, double sigma, const void *in_even, void *out_even,
+                     void *tmp_odd, stg_stream_t stream) {
+    Geom g;
+    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
+    if (field != STG_C128 && field != STG_C64) return invalid("unknown field type");
+    int rc = check_gauge(g, gauge, field);
+    if (rc) return rc;
+    if (nrhs < 1) return invalid("nrhs < 1");
+    if (!aligned16(in_even) || !aligned16(out_even) || !aligned16(tmp_odd))
+        return invalid("field NULL or not 16-byte aligned");
+    const size_t fb = (size_t)nrhs * 3 * g.Vh * field_elem(field);
+    if (overlap(in_even, fb, out_even, fb) || overlap(in_even, fb, tmp_odd, fb) ||
+        overlap(out_even, fb, tmp_odd, fb))
+        return invalid("fields overlap");
+    hipStream_t s = (hipStream_t)stream;
+    rc = hop_plain(g, gauge, field, nrhs, in_even, tmp_odd, 1, s);
+    if (rc) return rc;
+    const size_t f1 = (size_t)3 * g.Vh * field_elem(field);
+    HopArgs a = base_hop(g, gauge);
+    a.out_parity = 0;
+    a.op = OP_NONE;
+    a.diag = mass * mass + sigma;
+    for (int j0 = 0; j0 < nrhs;) {
+        int nr = chunk_of(nrhs - j0);
+        a.in = (const char *)tmp_odd + j0 * f1;
+        a.out = (char *)out_even + j0 * f1;
+        a.aux0 = (const char *)in_even + j0 * f1;
+        launch_hop(a, gauge->fmt, nr, EPI_NORMAL, s);
+        j0 += nr;
+    }
+    HIP_TRY(hipGetLastError());
+    return STG_OK;
+}
+
+size_t stg_dot_workspace_bytes(void) {
+    return align_up(sizeof(Ctl)) + align_up(sizeof(double) * 4 * 1024) + align_up(16);
+}
+
+int stg_dot(stg_field field, int nvec, size_t n, const void *x, const void *y, double *result,
+            void *ws, size_t ws_bytes, stg_stream_t stream) {
+    if (field != STG_C128 && field != STG_C64) return invalid("unknown field type");
+    if (nvec < 1 || n < 1) return invalid("nvec and n must be >= 1");
+    if (!aligned16(x) || !aligned16(y) || !result) return invalid("NULL or misaligned argument");
+    if (!aligned16(ws)) return invalid("workspace NULL or misaligned");
+    if (ws_bytes < stg_dot_workspace_bytes()) return STG_WORKSPACE_TOO_SMALL;
+    Carver c{reinterpret_cast<char *>(ws)};
+    Ctl *ctl = (Ctl *)c.take(sizeof(Ctl));
+    double *partials = (double *)c.take(sizeof(double) * 4 * 1024);
+    double *out = (double *)c.take(16);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemsetAsync(ctl, 0, sizeof(Ctl), s));
+    for (int j = 0; j < nvec; ++j) {
+        const size_t off = (size_t)j * n * field_elem(field);
+        launch_dot(field == STG_C128, 1, n, (const char *)x + off, (const char *)y + off,
+                   partials, ctl, OP_STORE, nullptr, out, s);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(result + 2 * j, out, 16, hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return STG_OK;
+}
+
+void stg_cg_default_params(stg_cg_params *p) {
+    if (!p) return;
+    p->tol = 1e-10;
+    p->max_iter = 100000;
+    p->mode = STG_CG_F64;
+    p->delta = 0.1;
+    p->poll_every = 0;
+    p->restart = 0;
+}
+
+int stg_workspace_bytes(const stg_lattice *lat, int nrhs, int nshift, int mode, size_t *bytes) {
+    Geom g;
+    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
+    if (!bytes) return invalid("bytes is NULL");
+    if (nrhs < 1 || nshift < 0) return invalid("nrhs >= 1, nshift >= 0");
+    if (mode != STG_CG_F64 && mode != STG_CG_MIXED) return invalid("unknown solver mode");
+    *bytes = nshift > 0 ? ms_workspace(g, nrhs, nshift, mode) : carve_cg(g, nrhs, mode, nullptr).bytes;
+    return STG_OK;
+}
+
+int cg_solve(const stg_lattice *lat, const stg_gauge *hi, const stg_gauge *lo, double mass,
+             int nrhs, const void *b_even, void *x_even, const stg_cg_params *params, void *ws,
+             size_t ws_bytes, stg_cg_stats *stats, stg_stream_t stream) {
+    Geom g;
+    const int mode = params ? params->mode : -1;
+    int rc = check_solver_common(lat, g, hi, lo, mode, nrhs, b_even, x_even, params);
+    if (rc) return rc;
+    if (!aligned16(ws)) return invalid("workspace NULL or misaligned");
+    const size_t need = carve_cg(g, nrhs, mode, nullptr).bytes;
+    if (ws_bytes < need) return STG_WORKSPACE_TOO_SMALL;
+    const size_t fb = (size_t)nrhs * 3 * g.Vh * 16;
+    if (overlap(b_even, fb, x_even, fb) || overlap(ws, ws_bytes, b_even, fb) ||
+        overlap(ws, ws_bytes, x_even, fb))
+        return invalid("b, x and workspace must not overlap");
+    CgProblem P;
+    P.g = g;
+    P.hi = hi;
+    P.lo = lo;
+    P.mode = mode;
+    P.nsys = nrhs;
+    P.b = b_even;
+    P.x = x_even;
+    P.diag.assign(nrhs, mass * mass);
+    P.prm = *params;
+    CgWork w = carve_cg(g, nrhs, mode, ws);
+    return run_cg(P, w, stats, (hipStream_t)stream);
+}
+
+int multishift_cg_solve(const stg_lattice *lat, const stg_gauge *hi, const stg_gauge *lo,
+                        double mass, int nshift, const double *shifts, int nrhs,
+                        const void *b_even, void *x_even, const stg_cg_params *params, void *ws,
+                        size_t ws_bytes, stg_cg_stats *stats, stg_stream_t stream) {
+    Geom g;
+    const int mode = params ? params->mode : -1;
+    int rc = check_solver_common(lat, g, hi, lo, mode, nrhs, b_even, x_even, params);
+    if (rc) return rc;
+    if (nshift < 1 || !shifts || !stats) return invalid("nshift >= 1, shifts and stats non-NULL");
+    for (int k = 0; k < nshift; ++k)
+        if (!(shifts[k] >= 0.0 && shifts[k] < 1e300)) return invalid("shifts must be >= 0");
+    if (!aligned16(ws)) return invalid("workspace NULL or misaligned");
+    const size_t need = ms_workspace(g, nrhs, nshift, mode);
+    if (ws_bytes < need) return STG_WORKSPACE_TOO_SMALL;
+    const size_t fbb = (size_t)nrhs * 3 * g.Vh * 16;
+    const size_t fbx = fbb * nshift;
+    if (overlap(b_even, fbb, x_even, fbx) || overlap(ws, ws_bytes, b_even, fbb) ||
+        overlap(ws, ws_bytes, x_even, fbx))
+        return invalid("b, x and workspace must not overlap");
+    return run_mscg(g, hi, lo, mass, nshift, shifts, nrhs, b_even, x_even, *params, ws, stats,
+                    (hipStream_t)stream);
+}
+
+}  // extern "C"

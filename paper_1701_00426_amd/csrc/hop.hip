@@ -1,0 +1,171 @@
+// hop.hip -- the even/odd staggered hop D_eo / D_oe on gfx950, with fused epilogues.
+//
+// Paper: arXiv:1701.00426, Sec. 2.2 Eq. diracblock (D connects only even and odd
+// sites; D_oe^dag = -D_eo), Sec. 4.3 deo listing (links, in, out and a real
+// per-link factor array), Sec. 2.3 (12-real links, third row rebuilt on the fly).
+//
+// For every output site x of parity P the kernel forms
+//   (D psi)(x) = 1/2 sum_mu [ phi_mu(x) U_mu(x) psi(x+mu)
+//                            - phi_mu(x-mu) U_mu(x-mu)^dag psi(x-mu) ]
+// for NR fields at once, so that each link read from memory serves NR mat-vecs.
+// One thread owns one output site; consecutive threads own consecutive half
+// indices, so every link, phase and field access of a wave is one coalesced run
+// (forward links at h, backward links at h - stride_mu, neighbours likewise).
+// Links are read with non-temporal loads: they are streamed once per hop and must
+// not evict the neighbour field lines that the surrounding sites re-read from L2.
+//
+// Epilogues (all on the output site):
+//   EPI_PLAIN   out = D in
+//   EPI_NORMAL  out = diag_j * p - D in           with p on the output parity;
+//               block partials of Re<p, out>      (normal operator, CG's <p, A p>)
+//   EPI_RESID   out = b - (diag_j * x - D in)      true residual; block partials of |out|^2
+// Reductions finish in the last block to arrive (fixed-order compensated sum) and
+// the scalar step of solver_state.hpp runs there.
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+#include "solver_state.hpp"
+
+namespace stg {
+
+template <typename T, int FMT, bool STDPH, int NR, int EPI>
+__global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
+    if (a.gate_running && a.ctl->n_running == 0) return;
+
+    const Geom &g = a.geom;
+    const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = h < g.Vh;
+    const int P = a.out_parity;
+
+    double ps[NR], pc[NR];  // compensated per-thread partials of the epilogue sums
+#pragma unroll
+    for (int j = 0; j < NR; ++j) ps[j] = pc[j] = 0.0;
+
+    if (valid) {
+        Site s = site_coords(g, P, h);
+        vec3<T> acc[NR];
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[j].c[c] = {T(0), T(0)};
+
+        // one direction at a time: the loads of two links and 2*NR neighbour
+        // vectors are in flight together, which bounds the register footprint
+#pragma unroll 1
+        for (int mu = 0; mu < 4; ++mu) {
+            const uint32_t hf = nb_fwd(g, s, h, mu);
+            const uint32_t hb = nb_bwd(g, s, h, mu);
+            const int sf = 2 * mu + P;       // U_mu(x) starts at x
+            const int sb = 2 * mu + (1 - P); // U_mu(x - mu) starts at x - mu
+            T pf, pb;
+            if (STDPH) {
+                pf = (T)std_phase(g, s, mu, false);
+                pb = (T)std_phase(g, s, mu, true);
+            } else {
+                const T *ph = reinterpret_cast<const T *>(a.phases);
+                pf = ph[(size_t)sf * g.Vh + h];
+                pb = ph[(size_t)sb * g.Vh + hb];
+            }
+            su3<T> uf = link_loader<T, FMT>::load(a.links, g.Vh, sf, h);
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                vec3<T> v = ld_v<T>(a.in, a.fstride, g.Vh, j, hf);
+                acc_mv(acc[j], pf, uf, v);
+            }
+            su3<T> ub = link_loader<T, FMT>::load(a.links, g.Vh, sb, hb);
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                vec3<T> v = ld_v<T>(a.in, a.fstride, g.Vh, j, hb);
+                acc_mdv(acc[j], -pb, ub, v);
+            }
+        }
+
+        const T half = T(0.5);
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            vec3<T> o;
+            if (EPI == EPI_PLAIN) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) o.c[c] = cscale(half, acc[j].c[c]);
+            } else if (EPI == EPI_NORMAL) {
+                const T d = (T)a.st_diag(j);
+                vec3<T> p = ld_v<T>(a.aux0, a.fstride, g.Vh, j, h);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    o.c[c].re = d * p.c[c].re - half * acc[j].c[c].re;
+                    o.c[c].im = d * p.c[c].im - half * acc[j].c[c].im;
+                    pair_add(ps[j], pc[j], (double)p.c[c].re * (double)o.c[c].re, 0.0);
+                    pair_add(ps[j], pc[j], (double)p.c[c].im * (double)o.c[c].im, 0.0);
+                }
+            } else {  // EPI_RESID
+                if (!a.st_pending(j)) continue;
+                const T d = (T)a.st_diag(j);
+                vec3<T> x = ld_v<T>(a.aux0, a.fstride, g.Vh, j, h);
+                vec3<T> b = ld_v<T>(a.aux1, a.fstride, g.Vh, j, h);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    o.c[c].re = b.c[c].re - (d * x.c[c].re - half * acc[j].c[c].re);
+                    o.c[c].im = b.c[c].im - (d * x.c[c].im - half * acc[j].c[c].im);
+                    pair_add(ps[j], pc[j], (double)o.c[c].re * (double)o.c[c].re +
+                                               (double)o.c[c].im * (double)o.c[c].im,
+                             0.0);
+                }
+            }
+            st_v<T>(a.out, a.fstride, g.Vh, j, h, o);
+        }
+    }
+
+    if (EPI == EPI_PLAIN || a.op == OP_NONE) return;
+
+    reduce_and_finish<NR>(ps, pc, a.partials, a.ctl, a.op, a.state, a.out_sums);
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+template <typename T, int FMT, bool STDPH, int NR>
+static void launch_nr(const HopArgs &a, int epi, hipStream_t stream) {
+    dim3 grid((a.geom.Vh + kBlock - 1) / kBlock);
+    switch (epi) {
+        case EPI_PLAIN:
+            hop_kernel<T, FMT, STDPH, NR, EPI_PLAIN><<<grid, kBlock, 0, stream>>>(a);
+            break;
+        case EPI_NORMAL:
+            hop_kernel<T, FMT, STDPH, NR, EPI_NORMAL><<<grid, kBlock, 0, stream>>>(a);
+            break;
+        default:
+            hop_kernel<T, FMT, STDPH, NR, EPI_RESID><<<grid, kBlock, 0, stream>>>(a);
+            break;
+    }
+}
+
+template <typename T, int FMT, bool STDPH>
+static int launch_fmt(const HopArgs &a, int nr, int epi, hipStream_t stream) {
+    switch (nr) {
+        case 1: launch_nr<T, FMT, STDPH, 1>(a, epi, stream); return 0;
+        case 2: launch_nr<T, FMT, STDPH, 2>(a, epi, stream); return 0;
+        case 4: launch_nr<T, FMT, STDPH, 4>(a, epi, stream); return 0;
+        case 8: launch_nr<T, FMT, STDPH, 8>(a, epi, stream); return 0;
+        default: return -1;
+    }
+}
+
+template <typename T, int FMT>
+static int launch_ph(const HopArgs &a, int nr, int epi, hipStream_t stream) {
+    return a.phases ? launch_fmt<T, FMT, false>(a, nr, epi, stream)
+                    : launch_fmt<T, FMT, true>(a, nr, epi, stream);
+}
+
+// Launches one hop over NR in {1, 2, 4, 8} fields.  Returns 0, or -1 for an
+// unsupported combination (checked by the caller beforehand).
+int launch_hop(const HopArgs &a, int fmt, int nr, int epi, hipStream_t stream) {
+    switch (fmt) {
+        case FMT_C128_18: return launch_ph<double, FMT_C128_18>(a, nr, epi, stream);
+        case FMT_C128_12: return launch_ph<double, FMT_C128_12>(a, nr, epi, stream);
+        case FMT_C64_12: return launch_ph<float, FMT_C64_12>(a, nr, epi, stream);
+        case FMT_BF16_12: return launch_ph<float, FMT_BF16_12>(a, nr, epi, stream);
+        default: return -1;
+    }
+}
+
+}  // namespace stg

@@ -1,0 +1,139 @@
+// kernels.hpp -- argument blocks and host launchers of the library's kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "device_common.hpp"
+#include "solver_state.hpp"
+
+namespace stg {
+
+enum Epilogue { EPI_PLAIN = 0, EPI_NORMAL = 1, EPI_RESID = 2 };
+
+struct HopArgs {
+    Geom geom;
+    const void *links;
+    const void *phases;   // nullptr: standard phases computed in the kernel
+    const void *in;       // field on the input parity, [NR][3][Vh]
+    void *out;            // field on the output parity, [NR][3][Vh]
+    const void *aux0;     // EPI_NORMAL: p;  EPI_RESID: x
+    const void *aux1;     // EPI_RESID: b
+    size_t fstride;       // complex elements between consecutive fields
+    int out_parity;       // 0: D_eo (even outputs), 1: D_oe (odd outputs)
+    int op;               // FinOp of the reduction (OP_NONE: no reduction)
+    int gate_running;     // exit at once when ctl->n_running == 0
+    int pad_;
+    double diag;          // m^2 + sigma when state == nullptr
+    SysState *state;      // per-field solver state, or nullptr
+    Ctl *ctl;
+    double *partials;     // [NR][grid] block partials
+    double *out_sums;     // OP_STORE destination [NR]
+
+    __device__ __forceinline__ double st_diag(int j) const {
+        return state ? state[j].diag : diag;
+    }
+    __device__ __forceinline__ bool st_pending(int j) const {
+        return state ? (state[j].flags & SYS_RU_PENDING) != 0 : true;
+    }
+};
+
+// Tail of every reduction kernel: per-thread compensated partials (s[j], c[j]) of
+// NR sums -> one (sum, error) pair per block in `partials` ([NR][grid][2]) -> the
+// last block to arrive adds the pairs in a fixed order and runs the scalar step
+// `op` of solver_state.hpp for each of the NR systems.
+template <int NR>
+__device__ __forceinline__ void reduce_and_finish(double (&s)[NR], double (&c)[NR],
+                                                  double *partials, Ctl *ctl, int op,
+                                                  SysState *state, double *out) {
+    __shared__ double sh_red[2 * kWaves];
+    __shared__ double sh_s[kBlock];
+    __shared__ double sh_e[kBlock];
+    __shared__ int sh_last;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        block_sum_pair(s[j], c[j], sh_red);
+        if (threadIdx.x == 0) {
+            double *pj = partials + 2 * ((size_t)j * gridDim.x + blockIdx.x);
+            pj[0] = s[j];
+            pj[1] = c[j];
+        }
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        int prev = atomicAdd(&ctl->counter, 1);
+        sh_last = (prev == (int)gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!sh_last) return;
+    __threadfence();
+#pragma unroll 1
+    for (int j = 0; j < NR; ++j) {
+        double tot = block_sum2_pairs(partials + 2 * (size_t)j * gridDim.x, gridDim.x, sh_s, sh_e);
+        if (threadIdx.x == 0) finalize_one(op, ctl, state, out, j, tot);
+    }
+    if (threadIdx.x == 0) ctl->counter = 0;
+}
+
+// Blocks of kBlock threads needed to cover Vh sites.
+inline uint32_t site_blocks(uint32_t Vh) { return (Vh + kBlock - 1) / kBlock; }
+
+int launch_hop(const HopArgs &a, int fmt, int nr, int epi, hipStream_t stream);
+
+// BLAS-1 style site kernels; fields are [NR][3][Vh] with stride fstride.
+struct VecArgs {
+    uint32_t Vh;
+    int pad_;
+    size_t fstride;
+    void *x;              // solution (inner precision)
+    void *p;
+    void *r;
+    const void *q;
+    void *x64;            // FP64 solution (reliable updates)
+    const void *r64;      // FP64 true residual (reliable updates)
+    SysState *state;
+    Ctl *ctl;
+    double *partials;
+    int gate_running;
+    int op;
+    // multi-shift: shifted solutions and directions, [nshift][nrhs][3][Vh]
+    void *xs;
+    void *ps;
+    size_t kstride;       // complex elements between shifts (nrhs * 3 * Vh)
+    int nshift;
+    int pad2_;
+};
+
+// x += alpha p; r -= alpha q; |r|^2 -> OP_BETA  (running systems)
+int launch_cg_update(const VecArgs &a, int fp64, int nr, hipStream_t stream);
+// p = r + beta p  (running systems)
+int launch_p_update(const VecArgs &a, int fp64, int nr, hipStream_t stream);
+// x64 += x32; x32 = 0  (parked systems)
+int launch_ru_accumulate(const VecArgs &a, int nr, hipStream_t stream);
+// r_inner = r64 (rounded); p = r_inner + beta p  (systems just resumed)
+int launch_ru_resume(const VecArgs &a, int fp64, int nr, hipStream_t stream);
+
+// multi-shift: r -= alpha q, x_k += alpha_k p_k; |r|^2 -> OP_MS_BETA
+int launch_ms_r_update(const VecArgs &a, int fp64, int nr, hipStream_t stream);
+// multi-shift: p = r + beta p; p_k = zeta_k r + beta_k p_k
+int launch_ms_p_update(const VecArgs &a, int fp64, int nr, hipStream_t stream);
+// dst (complex128) = src (complex64), n complex entries
+int launch_c64_to_c128(size_t n, const void *src, void *dst, hipStream_t stream);
+
+// sum_i conj(x_i) y_i over n complex entries of nvec vectors; the last block
+// applies op (OP_STORE into out as (re, im) pairs, or OP_INIT_BB on state).
+int launch_dot(int fp64, int nvec, size_t n, const void *x, const void *y, double *partials,
+               Ctl *ctl, int op, SysState *state, double *out, hipStream_t stream);
+size_t dot_blocks(size_t n);
+
+// full complex128 links -> packed format
+int launch_pack_links(const Geom &g, const void *src, int fmt, void *dst, hipStream_t stream);
+// double phases -> float phases (n entries)
+int launch_pack_phases_f32(size_t n, const double *src, float *dst, hipStream_t stream);
+// zero n bytes (multiple of 4) with a kernel
+int launch_zero(void *dst, size_t bytes, hipStream_t stream);
+// dst (complex64) = src (complex128), n complex entries
+int launch_c128_to_c64(size_t n, const void *src, void *dst, hipStream_t stream);
+
+}  // namespace stg

@@ -1,0 +1,204 @@
+// solver_state.hpp -- per-system solver scalars kept on the device, and the scalar
+// step that the last block of a reduction kernel performs on them.
+//
+// The CG scalars alpha = |r|^2 / <p, A p> and beta = |r_new|^2 / |r|^2 (Sec. 2.2,
+// conjugate gradient on Eq. lineqeo) never leave the GPU during the iteration: the
+// block that finishes a reduction last computes them and the next kernel reads
+// them.  The host only polls the flags every few iterations.
+//
+// Reliable updates (mixed precision): the inner recurrence runs until its
+// residual norm has dropped by delta relative to the largest one since the last
+// update, or below the target; the system is then parked (RU_PENDING) until the
+// host has the FP64 true residual b - A x recomputed, which either finishes the
+// system or resumes it from the true residual.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace stg {
+
+enum SysFlags : int {
+    SYS_RUNNING = 1,     // takes part in the inner iteration
+    SYS_RU_PENDING = 2,  // parked, waiting for a true-residual update
+    SYS_DONE = 4,        // true residual met the target
+    SYS_BREAKDOWN = 8,   // non-finite scalar or <p, A p> <= 0
+    SYS_RESUME = 16      // just updated: the resume kernel rebuilds r_inner and p
+};
+
+struct SysState {
+    double diag;     // m^2 + sigma of this system
+    double bb;       // |b|^2
+    double tol2bb;   // tol^2 |b|^2
+    double delta2;   // delta^2; 0 disables the delta-triggered updates
+    double rr;       // |r|^2 of the current inner residual
+    double rr_old;   // |r|^2 before the iteration that parked the system
+    double maxrr;    // largest |r|^2 since the last true-residual update
+    double alpha;
+    double beta;
+    double rr_true;  // last FP64 true |b - A x|^2
+    int iter;        // inner iterations done by this system
+    int n_ru;        // true-residual updates done
+    int flags;
+    int conv_iter;   // iteration at which the system finished
+    int restart;     // 1: p = r after each update
+    int gid;         // index of this system in the solve (multi-shift: the RHS index)
+    double alpha_prev;  // multi-shift base scalars of the previous iteration
+    double beta_prev;
+};
+
+// One shifted system of the multi-shift iteration (Sec. 2.2, Eq. shlineq): its
+// residual stays collinear with the base residual, r_k = zeta r.
+struct ShiftState {
+    double delta;      // sigma_k - sigma_0
+    double zeta;       // zeta at the current iteration
+    double zeta_prev;  // zeta one iteration back
+    double zeta_next;  // zeta of the next iteration (set after alpha is known)
+    double alpha;      // alpha_k of the current iteration
+    double beta;       // beta_k of the current iteration
+    int active;        // 1 running, 0 retired
+    int conv_iter;     // base iteration at which it retired
+};
+
+struct Ctl {
+    int n_running;   // systems with SYS_RUNNING set; kernels of the inner loop exit when 0
+    int counter;     // arrival counter of the last-block reductions (reset by the last block)
+    int nshift;      // multi-shift: shifts per RHS
+    int nrhs;        // multi-shift: right-hand sides
+    ShiftState *ms;  // multi-shift: [nshift][nrhs]
+    int pad_[10];
+};
+
+enum FinOp {
+    OP_NONE = 0,     // no reduction at all
+    OP_STORE = 1,    // sums -> out[j]
+    OP_INIT_BB = 2,  // sums -> bb, tol2bb = tol^2 bb  (tol^2 passed in delta2 slot)
+    OP_ALPHA = 3,    // sums = <p, A p> -> alpha
+    OP_BETA = 4,     // sums = |r_new|^2 -> beta, convergence / park test
+    OP_RU = 5,       // sums = |b - A x|^2 of parked systems -> done or resume
+    OP_MS_ALPHA = 6, // multi-shift: base alpha, then zeta_next and alpha_k of every shift
+    OP_MS_BETA = 7   // multi-shift: base beta, then beta_k, zeta shift and retirement
+};
+
+__device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < 1.0e300; }
+
+// Scalar step for system j after a reduction (one thread).
+__device__ __forceinline__ void finalize_one(int op, Ctl *ctl, SysState *st, double *out, int j,
+                                             double sum) {
+    if (op == OP_STORE) {
+        out[j] = sum;
+        return;
+    }
+    SysState &s = st[j];
+    if (op == OP_INIT_BB) {
+        s.bb = sum;
+        s.rr = sum;
+        s.tol2bb = s.tol2bb * sum;  // tol^2 was stored there by the host
+        return;
+    }
+    if (op == OP_ALPHA) {
+        s.flags &= ~SYS_RESUME;
+        if (!(s.flags & SYS_RUNNING)) return;
+        if (!finite_pos(sum) || !(s.rr >= 0.0 && s.rr < 1.0e300)) {
+            s.flags = SYS_BREAKDOWN;
+            ctl->n_running -= 1;
+            return;
+        }
+        s.alpha = s.rr / sum;
+        return;
+    }
+    if (op == OP_BETA) {
+        if (!(s.flags & SYS_RUNNING)) return;
+        s.iter += 1;
+        if (!(sum >= 0.0 && sum < 1.0e300)) {
+            s.flags = SYS_BREAKDOWN;
+            ctl->n_running -= 1;
+            return;
+        }
+        if (sum > s.maxrr) s.maxrr = sum;
+        if (sum <= s.tol2bb || sum < s.delta2 * s.maxrr) {
+            s.rr_old = s.rr;
+            s.rr = sum;
+            s.flags = SYS_RU_PENDING;
+            ctl->n_running -= 1;
+            return;
+        }
+        s.beta = sum / s.rr;
+        s.rr = sum;
+        return;
+    }
+    if (op == OP_MS_ALPHA) {
+        if (!(s.flags & SYS_RUNNING)) return;
+        if (!finite_pos(sum)) {
+            s.flags = SYS_BREAKDOWN;
+            ctl->n_running -= 1;
+            return;
+        }
+        const double a = s.rr / sum;
+        s.alpha = a;
+        for (int k = 0; k < ctl->nshift; ++k) {
+            ShiftState &z = ctl->ms[k * ctl->nrhs + s.gid];
+            if (!z.active) continue;
+            // three-term recurrence of CG on A + sigma_0 matched on A + sigma_k
+            const double den = a * s.beta_prev * (z.zeta_prev - z.zeta) +
+                               z.zeta_prev * s.alpha_prev * (1.0 + z.delta * a);
+            z.zeta_next = z.zeta * z.zeta_prev * s.alpha_prev / den;
+            z.alpha = a * z.zeta_next / z.zeta;
+        }
+        return;
+    }
+    if (op == OP_MS_BETA) {
+        if (!(s.flags & SYS_RUNNING)) return;
+        s.iter += 1;
+        if (!(sum >= 0.0 && sum < 1.0e300)) {
+            s.flags = SYS_BREAKDOWN;
+            ctl->n_running -= 1;
+            return;
+        }
+        const double b = sum / s.rr;
+        s.beta = b;
+        s.alpha_prev = s.alpha;
+        s.beta_prev = b;
+        s.rr = sum;
+        for (int k = 0; k < ctl->nshift; ++k) {
+            ShiftState &z = ctl->ms[k * ctl->nrhs + s.gid];
+            if (!z.active) continue;
+            const double ratio = z.zeta_next / z.zeta;
+            z.beta = b * ratio * ratio;
+            z.zeta_prev = z.zeta;
+            z.zeta = z.zeta_next;
+            // |r_k| = |zeta| |r|: this shift is solved (its x_k took this step already)
+            if (z.zeta * z.zeta * sum <= s.tol2bb) {
+                z.active = 0;
+                z.conv_iter = s.iter;
+            }
+        }
+        if (sum <= s.tol2bb) {
+            s.flags = SYS_DONE;
+            s.conv_iter = s.iter;
+            ctl->n_running -= 1;
+        }
+        return;
+    }
+    if (op == OP_RU) {
+        if (!(s.flags & SYS_RU_PENDING)) return;
+        s.n_ru += 1;
+        s.rr_true = sum;
+        if (!(sum >= 0.0 && sum < 1.0e300)) {
+            s.flags = SYS_BREAKDOWN;
+            return;
+        }
+        if (sum <= s.tol2bb) {
+            s.flags = SYS_DONE;
+            s.conv_iter = s.iter;
+            return;
+        }
+        s.beta = (s.restart || !(s.rr_old > 0.0)) ? 0.0 : sum / s.rr_old;
+        s.rr = sum;
+        s.maxrr = sum;
+        s.flags = SYS_RUNNING | SYS_RESUME;
+        ctl->n_running += 1;
+        return;
+    }
+}
+
+}  // namespace stg

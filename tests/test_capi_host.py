@@ -1,0 +1,149 @@
+"""The C-ABI library on the host (no GPU): it loads, exports every entry point that
+include/stagmi.h declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1701_00426_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1701_00426_amd import build
+        build.build()
+    return _lib.load()
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "stagmi.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_1701_00426_amd import _lib
+    names = header_functions()
+    assert len(names) >= 14, names
+    for n in names:
+        assert hasattr(lib, n), f"libstagmi.so does not export {n}"
+    # the Python binding declares exactly the header's surface
+    assert sorted(_lib.SIGNATURES) == names
+
+
+def test_version_and_status_strings(lib):
+    assert lib.stg_version() >> 16 == 1
+    for code in (0, 1, 2, -1, -2, -3):
+        assert lib.stg_status_string(code)
+    assert b"unknown" in lib.stg_status_string(12345)
+
+
+def _lat(dims):
+    from paper_1701_00426_amd import _lib
+    return _lib.lattice(dims)
+
+
+@pytest.mark.parametrize("dims,ok", [((4, 4, 4, 4), True), ((32, 32, 32, 32), True),
+                                     ((3, 4, 4, 4), False), ((4, 4, 4, 0), False),
+                                     ((4, 4, 4, -2), False), ((2, 2, 2, 2), True)])
+def test_links_bytes(lib, dims, ok):
+    n = ctypes.c_size_t(0)
+    rc = lib.stg_links_bytes(ctypes.byref(_lat(dims)), 0, ctypes.byref(n))
+    if ok:
+        vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
+        assert rc == 0 and n.value == 8 * 9 * vh * 16
+        for fmt, per in ((1, 96), (2, 48), (3, 24)):
+            assert lib.stg_links_bytes(ctypes.byref(_lat(dims)), fmt, ctypes.byref(n)) == 0
+            assert n.value == 8 * vh * per
+    else:
+        assert rc == -1
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    from paper_1701_00426_amd import _lib
+    lat = _lat((4, 4, 4, 4))
+    g = _lib.StgGauge()
+    g.links = 0x1000
+    g.fmt = 0
+    g.phases = None
+    # null field pointers
+    assert lib.dirac_apply_eo(ctypes.byref(lat), ctypes.byref(g), 0, 1, None, None, None) == -1
+    # misaligned
+    assert lib.dirac_apply_oe(ctypes.byref(lat), ctypes.byref(g), 0, 1, 0x1008, 0x100000,
+                              None) == -1
+    # aliasing input and output
+    assert lib.dirac_apply_oe(ctypes.byref(lat), ctypes.byref(g), 0, 1, 0x200000, 0x200000,
+                              None) == -1
+    # precision mismatch: FP64 links with complex64 fields
+    assert lib.dirac_apply_eo(ctypes.byref(lat), ctypes.byref(g), 1, 1, 0x200000, 0x400000,
+                              None) == -1
+    # nrhs < 1
+    assert lib.dirac_apply_eo(ctypes.byref(lat), ctypes.byref(g), 0, 0, 0x200000, 0x400000,
+                              None) == -1
+    # odd extent
+    bad = _lat((5, 4, 4, 4))
+    assert lib.dirac_apply_eo(ctypes.byref(bad), ctypes.byref(g), 0, 1, 0x200000, 0x400000,
+                              None) == -1
+    assert b"even" in lib.stg_last_error()
+
+
+def test_solver_arguments_rejected_on_host(lib):
+    from paper_1701_00426_amd import _lib
+    lat = _lat((4, 4, 4, 4))
+    g = _lib.StgGauge()
+    g.links = 0x1000
+    g.fmt = 0
+    prm = _lib.StgCgParams()
+    lib.stg_cg_default_params(ctypes.byref(prm))
+    assert prm.tol == 1e-10 and prm.max_iter == 100000 and abs(prm.delta - 0.1) < 1e-15
+    stats = (_lib.StgCgStats * 1)()
+    need = ctypes.c_size_t(0)
+    assert lib.stg_workspace_bytes(ctypes.byref(lat), 1, 0, 0, ctypes.byref(need)) == 0
+    assert need.value > 0
+    # workspace too small
+    rc = lib.cg_solve(ctypes.byref(lat), ctypes.byref(g), None, 0.1, 1, 0x200000, 0x400000,
+                      ctypes.byref(prm), 0x10000000, 16, stats, None)
+    assert rc == -3
+    # mixed mode without a low-precision gauge field
+    prm.mode = 1
+    rc = lib.cg_solve(ctypes.byref(lat), ctypes.byref(g), None, 0.1, 1, 0x200000, 0x400000,
+                      ctypes.byref(prm), 0x10000000, 1 << 30, stats, None)
+    assert rc == -1
+    # bad tolerance
+    prm.mode = 0
+    prm.tol = 0.0
+    rc = lib.cg_solve(ctypes.byref(lat), ctypes.byref(g), None, 0.1, 1, 0x200000, 0x400000,
+                      ctypes.byref(prm), 0x10000000, 1 << 30, stats, None)
+    assert rc == -1
+    # negative shift
+    prm.tol = 1e-10
+    sh = (ctypes.c_double * 2)(0.1, -1.0)
+    rc = lib.multishift_cg_solve(ctypes.byref(lat), ctypes.byref(g), None, 0.1, 2, sh, 1,
+                                 0x200000, 0x400000, ctypes.byref(prm), 0x10000000, 1 << 30,
+                                 stats, None)
+    assert rc == -1
+    # multi-shift workspace is at least the refinement's
+    ms = ctypes.c_size_t(0)
+    assert lib.stg_workspace_bytes(ctypes.byref(lat), 2, 4, 1, ctypes.byref(ms)) == 0
+    cg8 = ctypes.c_size_t(0)
+    assert lib.stg_workspace_bytes(ctypes.byref(lat), 8, 0, 1, ctypes.byref(cg8)) == 0
+    assert ms.value >= cg8.value
+
+
+def test_product_does_not_import_oracle():
+    """The GPU package never imports the oracle; the oracle never imports the package."""
+    pkg = os.path.join(ROOT, "paper_1701_00426_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in text.lower().replace("oracle-free", ""), f
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith((".py", ".c")):
+            text = open(os.path.join(ROOT, "oracle", f)).read()
+            assert "paper_1701_00426_amd" not in text and "stagmi" not in text, f

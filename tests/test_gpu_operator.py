@@ -1,0 +1,219 @@
+"""GPU parity of the staggered hop, the normal operator, link packing and the
+compensated dot products, through the C ABI, against the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1701_00426_amd as stg  # noqa: E402
+import seeded_inputs as si  # noqa: E402
+from oracle import oracle_np as on  # noqa: E402
+
+from gpu_common import DEV, TOL, rel_max, rel_norm, say, to_dev  # noqa: E402
+
+SHAPES = [(2, 2, 2, 2), (4, 4, 4, 4), (8, 8, 8, 8), (4, 6, 8, 10), (6, 4, 2, 10), (2, 8, 2, 6)]
+
+
+def _bf16_bits(x):
+    """Round-to-nearest-even of float64 values to bfloat16 bit patterns (exact)."""
+    m, e = np.frexp(x)
+    y = np.ldexp(np.rint(m * 256.0) / 256.0, e)
+    return (y.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+
+
+@pytest.mark.parametrize("dims", [(4, 6, 4, 8), (2, 2, 2, 2)])
+def test_pack_links_exact(dims, corc):
+    say(f"pack_links {dims}")
+    links = si.su3_links(dims, 5, 5)
+    vh = on.half_volume(dims)
+    dl = to_dev(links)
+    two = links[:, :2]                                     # (8, 2, 3, Vh)
+    got12 = stg.stg_pack_links(dims, dl, "c128_12").cpu().numpy().view(np.complex128)
+    assert np.array_equal(got12.reshape(8, 2, 3, vh), two)
+    got32 = stg.stg_pack_links(dims, dl, "c64_12").cpu().numpy().view(np.float32)
+    e = two.reshape(8, 6, vh).astype(np.complex64)         # RNE per component
+    want32 = np.stack([e[:, 0::2], e[:, 1::2]], axis=-1)   # (8, 3, Vh, 2) complex64
+    assert np.array_equal(got32, want32.view(np.float32).reshape(-1))
+    gotbf = stg.stg_pack_links(dims, dl, "bf16_12").cpu().numpy().view(np.uint16)
+    e6 = two.reshape(8, 6, vh)
+    bits = np.stack([_bf16_bits(e6.real), _bf16_bits(e6.imag)], axis=-1)  # (8, 6, Vh, 2)
+    first = bits[:, :4].transpose(0, 2, 1, 3).reshape(8, vh, 8)
+    second = bits[:, 4:].transpose(0, 2, 1, 3).reshape(8, vh, 4)
+    want = np.concatenate([first.reshape(-1), second.reshape(-1)])
+    assert np.array_equal(gotbf, want)
+
+
+@pytest.mark.parametrize("fmt", ["c128_18", "c128_12", "c64_12", "bf16_12"])
+@pytest.mark.parametrize("dims", SHAPES)
+def test_hop_parity(dims, fmt, corc):
+    """D_eo and D_oe on random SU(3) links, standard phases computed in-kernel."""
+    say(f"hop {fmt} {dims}")
+    links = si.su3_links(dims, 1701, 7, 0)
+    phases = on.standard_phases(dims)
+    g = stg.pack_gauge(dims, to_dev(links), fmt)
+    cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
+    for par, fn, name in ((0, stg.dirac_apply_eo, "eo"), (1, stg.dirac_apply_oe, "oe")):
+        v = si.gaussian_field(dims, 1, 426, 7, par)
+        out = fn(g, to_dev(v).to(cdt))
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().astype(np.complex128)
+        want = corc.dslash(dims, links, phases, par, v)
+        err = rel_max(got, want)
+        say(f"  D_{name} max rel err {err:.2e} (norm {rel_norm(got, want):.2e})")
+        assert err <= TOL[fmt]
+
+
+@pytest.mark.parametrize("fmt", ["c128_12", "c64_12"])
+def test_hop_explicit_phases(fmt, corc):
+    """Arbitrary real per-link phases read from memory (the paper's backfield array)."""
+    dims = (4, 6, 2, 8)
+    say(f"hop explicit phases {fmt} {dims}")
+    links = si.su3_links(dims, 3, 3)
+    phases = si.real_link_field(dims, 3, 4)
+    g = stg.pack_gauge(dims, to_dev(links), fmt, phases_f64=to_dev(phases))
+    cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
+    for par in (0, 1):
+        v = si.gaussian_field(dims, 2, 3, 5 + par)
+        fn = stg.dirac_apply_eo if par == 0 else stg.dirac_apply_oe
+        got = fn(g, to_dev(v).to(cdt)).cpu().numpy().astype(np.complex128)
+        want = corc.dslash(dims, links, phases, par, v)
+        assert rel_max(got, want) <= TOL[fmt]
+
+
+@pytest.mark.parametrize("nrhs", [2, 3, 5, 8, 11])
+@pytest.mark.parametrize("fmt", ["c128_12", "c64_12"])
+def test_hop_multi_rhs(nrhs, fmt, corc):
+    """Several fields per launch (chunks of 8/4/2/1): each equals its own hop."""
+    dims = (4, 4, 6, 4)
+    say(f"hop multi-rhs {fmt} nrhs={nrhs}")
+    links = si.su3_links(dims, 9, nrhs)
+    phases = on.standard_phases(dims)
+    g = stg.pack_gauge(dims, to_dev(links), fmt)
+    cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
+    v = si.gaussian_field(dims, nrhs, 9, 1)
+    got = stg.dirac_apply_oe(g, to_dev(v).to(cdt)).cpu().numpy().astype(np.complex128)
+    want = corc.dslash(dims, links, phases, 1, v)
+    for j in range(nrhs):
+        assert rel_max(got[j], want[j]) <= TOL[fmt]
+    single = stg.dirac_apply_oe(g, to_dev(v[nrhs - 1:]).to(cdt)).cpu().numpy()
+    if fmt == "c128_12":
+        assert np.array_equal(single[0], got[nrhs - 1].astype(single.dtype))
+
+
+@pytest.mark.parametrize("fmt", ["c128_12", "c64_12", "bf16_12"])
+def test_apply_normal(fmt, corc):
+    dims = (4, 6, 4, 6)
+    say(f"apply_normal {fmt}")
+    links = si.su3_links(dims, 11, 0)
+    phases = on.standard_phases(dims)
+    g = stg.pack_gauge(dims, to_dev(links), fmt)
+    cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
+    v = si.gaussian_field(dims, 3, 11, 1)
+    got = stg.stg_apply_normal(g, 0.3, to_dev(v).to(cdt), sigma=0.05).cpu().numpy()
+    for j in range(3):
+        want = corc.apply_normal(dims, links, phases, 0.3, v[j], sigma=0.05)
+        assert rel_max(got[j].astype(np.complex128), want) <= TOL[fmt]
+
+
+def test_anti_hermiticity_full_size():
+    """32^4 FP64-12 (the benchmark configuration): <chi, D_eo psi> = -<D_oe chi, psi>,
+    evaluated with the library's compensated dot products."""
+    dims = (32, 32, 32, 32)
+    say(f"anti-hermiticity {dims}")
+    links = si.su3_links(dims, 1701, 1, 0)
+    g = stg.pack_gauge(dims, to_dev(links), "c128_12")
+    chi = to_dev(si.gaussian_field(dims, 1, 1, 2))
+    psi = to_dev(si.gaussian_field(dims, 1, 1, 3))
+    a = stg.stg_dot(chi, stg.dirac_apply_eo(g, psi))[0]
+    b = stg.stg_dot(stg.dirac_apply_oe(g, chi), psi)[0]
+    nrm = math.sqrt(stg.stg_dot(chi, chi)[0].real * stg.stg_dot(psi, psi)[0].real)
+    say(f"  |a + b| / |chi||psi| = {abs(a + b) / nrm:.2e}")
+    assert abs(a + b) / nrm < 1e-13
+
+
+@pytest.mark.parametrize("fmt", ["c128_12", "c64_12"])
+def test_hop_sampled_full_size(fmt):
+    """32^4 in the launch configuration the benchmark times: 4096 sampled output sites
+    of D_eo and D_oe against the oracle evaluated site by site."""
+    dims = (32, 32, 32, 32)
+    say(f"sampled full size {fmt} {dims}")
+    links = si.su3_links(dims, 1701, 1, 0)
+    phases = on.standard_phases(dims)
+    g = stg.pack_gauge(dims, to_dev(links), fmt)
+    cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
+    vh = on.half_volume(dims)
+    rng = np.random.default_rng(5)
+    hs = np.concatenate([rng.choice(vh, 4000, replace=False),
+                         np.arange(48), vh - 1 - np.arange(48)])
+    for par in (0, 1):
+        v = si.gaussian_field(dims, 1, 426, 1, par)
+        fn = stg.dirac_apply_eo if par == 0 else stg.dirac_apply_oe
+        out = fn(g, to_dev(v).to(cdt)).cpu().numpy().astype(np.complex128)
+        want = on.dslash(dims, links, phases, par, v, hs=hs)
+        err = rel_max(out[..., hs], want)
+        say(f"  parity {par} sampled max rel err {err:.2e}")
+        assert err <= TOL[fmt]
+
+
+def test_pure_gauge_eigenvector_gpu():
+    """U = g(x) g(x+mu)^dag: the GPU normal operator maps g * plane wave to lambda times it."""
+    dims = (4, 6, 4, 8)
+    ge = si.su3_site_field(dims, 4, 0)
+    go = si.su3_site_field(dims, 4, 1)
+    links = on.pure_gauge_links(dims, ge, go)
+    for fmt in ("c128_18", "c128_12", "c64_12"):
+        g = stg.pack_gauge(dims, to_dev(links), fmt)
+        for n in ((1, 2, 0, 3), (0, 0, 0, 0), (1, 5, 3, 7)):
+            p = on.momenta(dims, n)
+            v = on.site_matrices_apply(ge, on.plane_wave(dims, 0, p, [1.0, -0.5j, 0.25]))
+            cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
+            got = stg.stg_apply_normal(g, 0.1, to_dev(v[None]).to(cdt)).cpu().numpy()[0]
+            lam = on.free_eigenvalue(0.1, p)
+            err = float(np.max(np.abs(got - lam * v)))
+            assert err < (1e-12 if fmt.startswith("c128") else 2e-6), (fmt, n, err)
+
+
+def test_dot_compensated_vs_fsum():
+    """Ill-conditioned sums: the library's dot agrees with math.fsum (correctly rounded)."""
+    rng = np.random.default_rng(3)
+    n = 3 * 20000 + 17
+    for trial in range(4):
+        x = rng.standard_normal(n) * np.exp(rng.uniform(-20, 20, n))
+        x = np.concatenate([x, -x[: n // 2]])            # heavy cancellation
+        x[-1] += 1.0
+        xc = (x + 0j).astype(np.complex128)
+        y = np.ones_like(xc)
+        got = stg.stg_dot(to_dev(xc[None]), to_dev(y[None]))[0].real
+        want = math.fsum(x.tolist())
+        say(f"  trial {trial}: dot {got!r} fsum {want!r}")
+        assert abs(got - want) <= 4 * np.spacing(abs(want)) + 1e-300
+
+
+def test_dot_fp32_products_exact():
+    rng = np.random.default_rng(4)
+    x = (rng.standard_normal((2, 3000)) + 1j * rng.standard_normal((2, 3000))).astype(np.complex64)
+    y = (rng.standard_normal((2, 3000)) + 1j * rng.standard_normal((2, 3000))).astype(np.complex64)
+    got = stg.stg_dot(to_dev(x), to_dev(y))
+    for j in range(2):
+        xd = x[j].astype(np.complex128)
+        yd = y[j].astype(np.complex128)
+        prod = np.conj(xd) * yd
+        want = complex(math.fsum(prod.real.tolist()), math.fsum(prod.imag.tolist()))
+        assert abs(got[j] - want) <= 4 * np.spacing(abs(want))
+
+
+def test_deterministic_hop_and_dot():
+    dims = (8, 8, 8, 8)
+    links = si.su3_links(dims, 8, 8)
+    g = stg.pack_gauge(dims, to_dev(links), "c128_12")
+    v = to_dev(si.gaussian_field(dims, 1, 8, 9))
+    a = stg.dirac_apply_eo(g, v)
+    b = stg.dirac_apply_eo(g, v)
+    assert torch.equal(a, b)
+    assert stg.stg_dot(a, v) == stg.stg_dot(b, v)

@@ -1,0 +1,166 @@
+"""GPU solvers through the C ABI: FP64 CG, mixed-precision CG with reliable
+updates (FP32-12 and BF16-12 links), multi-RHS, multi-shift CG with refinement.
+
+Parity bar: every returned solution has an FP64 true relative residual
+|b - A x| / |b| <= 1e-10 recomputed by the oracle, and its distance to the
+oracle's own solution is within the conditioning bound (reported)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1701_00426_amd as stg  # noqa: E402
+import seeded_inputs as si  # noqa: E402
+from oracle import oracle_np as on  # noqa: E402
+
+from gpu_common import rel_norm, say, to_dev  # noqa: E402
+
+TOL = 1e-10
+
+
+def _problem(dims, seed, nrhs=1):
+    links = si.su3_links(dims, 1701, *seed)
+    phases = on.standard_phases(dims)
+    b = si.gaussian_field(dims, nrhs, 426, *seed)
+    return links, phases, b
+
+
+def _check(corc, dims, links, phases, mass, b, x, stats, sigma=0.0, label=""):
+    for j in range(b.shape[0]):
+        res = on.true_relative_residual(dims, links, phases, mass, b[j], x[j], sigma=sigma)
+        xr, it, r0, st = corc.cg(dims, links, phases, mass, b[j], tol=1e-12, sigma=sigma)
+        err = rel_norm(x[j], xr)
+        s = stats[j]
+        say(f"  {label} rhs {j}: iters {s['iters']} RU {s['reliable_updates']} "
+            f"lib resid {s['true_rel_resid']:.2e} oracle resid {res:.2e} |x-x*|/|x*| {err:.2e} "
+            f"(oracle iters {it})")
+        assert s["status"] == 0
+        assert res <= TOL
+        assert abs(s["true_rel_resid"] - res) <= 1e-3 * res + 1e-14
+        # |x - x*| / |x*| <= kappa |r| / |b|, kappa <= (m^2 + 16) / m^2
+        kappa = (mass * mass + sigma + 16.0) / (mass * mass + sigma)
+        assert err <= kappa * 2 * TOL
+
+
+@pytest.mark.parametrize("fmt", ["c128_18", "c128_12"])
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (4, 6, 8, 10), (2, 2, 2, 2)])
+def test_cg_fp64(dims, fmt, corc):
+    say(f"cg fp64 {fmt} {dims}")
+    links, phases, b = _problem(dims, (0, 0))
+    g = stg.pack_gauge(dims, to_dev(links), fmt)
+    x, st, stats = stg.cg_solve(g, 0.1, to_dev(b), tol=TOL)
+    _check(corc, dims, links, phases, 0.1, b, x.cpu().numpy(), stats, label=fmt)
+
+
+@pytest.mark.parametrize("lofmt", ["c64_12", "bf16_12"])
+def test_cg_mixed(lofmt, corc):
+    dims = (8, 8, 8, 8)
+    say(f"cg mixed {lofmt} {dims}")
+    links, phases, b = _problem(dims, (0, 0))
+    dl = to_dev(links)
+    hi = stg.pack_gauge(dims, dl, "c128_12")
+    lo = stg.pack_gauge(dims, dl, lofmt)
+    x, st, stats = stg.cg_solve(hi, 0.1, to_dev(b), lo=lo, tol=TOL)
+    assert stats[0]["reliable_updates"] >= 2
+    _check(corc, dims, links, phases, 0.1, b, x.cpu().numpy(), stats, label=lofmt)
+
+
+@pytest.mark.parametrize("mode", ["f64", "c64_12"])
+def test_cg_multi_rhs(mode, corc):
+    dims = (4, 6, 4, 8)
+    nrhs = 5
+    say(f"cg multi-rhs {mode} nrhs={nrhs}")
+    links, phases, b = _problem(dims, (2, 0), nrhs)
+    dl = to_dev(links)
+    hi = stg.pack_gauge(dims, dl, "c128_12")
+    lo = stg.pack_gauge(dims, dl, mode) if mode != "f64" else None
+    x, st, stats = stg.cg_solve(hi, 0.05, to_dev(b), lo=lo, tol=TOL)
+    _check(corc, dims, links, phases, 0.05, b, x.cpu().numpy(), stats, label=mode)
+
+
+def test_cg_pure_gauge_exact():
+    """b = g * plane wave: the GPU CG returns b / lambda (FP64 path)."""
+    dims = (4, 4, 6, 8)
+    ge = si.su3_site_field(dims, 21, 0)
+    go = si.su3_site_field(dims, 21, 1)
+    links = on.pure_gauge_links(dims, ge, go)
+    p = on.momenta(dims, (1, 2, 0, 1))
+    b = on.site_matrices_apply(ge, on.plane_wave(dims, 0, p, [1.0, 0.5j, -0.25]))[None]
+    lam = on.free_eigenvalue(0.1, p)
+    g = stg.pack_gauge(dims, to_dev(links), "c128_12")
+    x, st, stats = stg.cg_solve(g, 0.1, to_dev(b), tol=1e-12)
+    err = rel_norm(x.cpu().numpy(), b / lam)
+    say(f"pure gauge: iters {stats[0]['iters']} err {err:.2e}")
+    assert err < 1e-12
+    assert stats[0]["iters"] <= 2
+
+
+def test_cg_not_converged_then_warm_restart(corc):
+    dims = (8, 8, 8, 8)
+    links, phases, b = _problem(dims, (3, 0))
+    g = stg.pack_gauge(dims, to_dev(links), "c128_12")
+    bd = to_dev(b)
+    x, st, stats = stg.cg_solve(g, 0.1, bd, tol=TOL, max_iter=10, check_status=False)
+    assert st == 1 and stats[0]["status"] == 1 and stats[0]["iters"] == 10
+    res10 = on.true_relative_residual(dims, links, phases, 0.1, b[0], x.cpu().numpy()[0])
+    assert abs(stats[0]["true_rel_resid"] - res10) < 1e-6 * res10
+    x2, st2, stats2 = stg.cg_solve(g, 0.1, bd, x=x, tol=TOL)
+    assert st2 == 0
+    _check(corc, dims, links, phases, 0.1, b, x2.cpu().numpy(), stats2, label="warm")
+
+
+def test_cg_zero_rhs():
+    dims = (4, 4, 4, 4)
+    links, phases, b = _problem(dims, (4, 0), 2)
+    b[1] = 0
+    g = stg.pack_gauge(dims, to_dev(links), "c128_12")
+    x0 = to_dev(np.ones_like(b))
+    x, st, stats = stg.cg_solve(g, 0.1, to_dev(b), x=x0, tol=TOL)
+    assert st == 0
+    assert torch.count_nonzero(x[1]).item() == 0
+    assert on.true_relative_residual(dims, links, phases, 0.1, b[0], x.cpu().numpy()[0]) <= TOL
+
+
+def test_cg_breakdown_on_nan():
+    dims = (4, 4, 4, 4)
+    links, phases, b = _problem(dims, (5, 0))
+    b[0, 1, 3] = np.nan
+    g = stg.pack_gauge(dims, to_dev(links), "c128_12")
+    x, st, stats = stg.cg_solve(g, 0.1, to_dev(b), tol=TOL, check_status=False)
+    assert st == 2 and stats[0]["status"] == 2
+
+
+def test_cg_bitwise_reproducible():
+    dims = (8, 8, 8, 8)
+    links, phases, b = _problem(dims, (6, 0))
+    dl = to_dev(links)
+    hi = stg.pack_gauge(dims, dl, "c128_12")
+    lo = stg.pack_gauge(dims, dl, "c64_12")
+    bd = to_dev(b)
+    xa, _, sa = stg.cg_solve(hi, 0.1, bd, lo=lo, tol=TOL)
+    xb, _, sb = stg.cg_solve(hi, 0.1, bd, lo=lo, tol=TOL)
+    assert torch.equal(xa, xb) and sa[0]["iters"] == sb[0]["iters"]
+
+
+@pytest.mark.parametrize("mode", ["f64", "c64_12"])
+def test_multishift(mode, corc):
+    dims = (4, 6, 4, 8)
+    nrhs = 2
+    shifts = si.log_shifts(6, 1e-4, 10.0)
+    mass = 0.05
+    say(f"multishift {mode} shifts={len(shifts)} nrhs={nrhs}")
+    links, phases, b = _problem(dims, (7, 0), nrhs)
+    dl = to_dev(links)
+    hi = stg.pack_gauge(dims, dl, "c128_12")
+    lo = stg.pack_gauge(dims, dl, mode) if mode != "f64" else None
+    x, st, stats = stg.multishift_cg_solve(hi, mass, shifts, to_dev(b), lo=lo, tol=TOL)
+    xn = x.cpu().numpy()
+    for k, s in enumerate(shifts):
+        _check(corc, dims, links, phases, mass, b, xn[k], stats[k], sigma=s,
+               label=f"{mode} shift {s:.1e}")
+    # the multi-shift stage retires large shifts earlier
+    assert stats[-1][0]["iters"] <= stats[0][0]["iters"]
