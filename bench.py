@@ -96,6 +96,26 @@ def cpu_baseline(links, b, vh, seconds=10.0):
             "ms_per_apply": round(dt * 1e3, 3)}
 
 
+def copy_ceiling(torch, nbytes=1 << 30, reps=20):
+    """Read + write GB/s of a plain 1 GiB device copy (HIP events): the practical
+    ceiling a streaming kernel reaches on this GPU."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    t1.synchronize()
+    dt = t0.elapsed_time(t1) * 1e-3 / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(2 * nbytes / dt / 1e9, 1)
+
+
 def calibrate_copy():
     """A plain device-to-device copy of 1 GiB, 10 times: FETCH_SIZE / WRITE_SIZE per
     dispatch of this kernel against the known 1 GiB read and 1 GiB write give the
@@ -123,6 +143,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile", action="store_true",
                     help="for rocprofv3: only the dominant kernel's timed loop (FP64-12 D_eo)")
+    ap.add_argument("--profile-cg", action="store_true",
+                    help="for rocprofv3: one FP64 CG and one mixed CG solve only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="for rocprofv3 --pmc: a plain 1 GiB device copy, to scale byte counters")
     args = ap.parse_args()
@@ -153,6 +175,8 @@ def main():
     variants = {}
     hop_time = {}
     fmts = ("c128_12",) if args.profile else ("c128_12", "c128_18", "c64_12", "bf16_12")
+    if args.profile_cg:
+        fmts = ()
     for fmt in fmts:
         cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
         ncopy = 3
@@ -172,6 +196,13 @@ def main():
                          "GFLOPs": round(FLOPS_PER_SITE * vh / dt / 1e9, 1),
                          "ns_per_site": round(dt * 1e9 / vh, 4)}
             hop_time[(fmt, name)] = dt
+        if fmt == "c128_12" and not args.profile:
+            # the same launches with the plain block order, for comparison
+            stg.stg_set_tuning(stg._lib.STG_TUNE_XCD_REMAP, 0)
+            dt0 = time_applies(stg, torch, gauges, fields, outs, 0, args.applies)
+            stg.stg_set_tuning(stg._lib.STG_TUNE_XCD_REMAP, 1)
+            res["D_eo_plain_block_order"] = {"us": round(dt0 * 1e6, 2),
+                                             "GBs": round(BYTES_PER_SITE[fmt] * vh / dt0 / 1e9, 1)}
         res["working_set_GB"] = round(ws_bytes / 1e9, 3)
         res["bytes_per_site"] = BYTES_PER_SITE[fmt]
         variants[fmt] = res
@@ -197,17 +228,34 @@ def main():
                        dtype=torch.uint8, device=dev)
     x64 = torch.zeros_like(b)
     xmx = torch.zeros_like(b)
+    nb = 8
+    b8 = torch.from_numpy(si.gaussian_field(DIMS, nb, 426, 2, 1, 0)).to(dev)
+    x8 = torch.zeros_like(b8)
+    ws8 = torch.empty(stg.stg_workspace_bytes(DIMS, nb, 0, stg.STG_CG_MIXED), dtype=torch.uint8,
+                      device=dev)
 
     def step():
         x64.zero_()
         xmx.zero_()
+        x8.zero_()
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, s1, st1 = stg.cg_solve(hi, MASS, b, x=x64, ws=ws64, tol=TOL)
         t1 = time.perf_counter()
         _, s2, st2 = stg.cg_solve(hi, MASS, b, x=xmx, lo=lo, ws=wsmx, tol=TOL)
         t2 = time.perf_counter()
-        return t1 - t0, t2 - t1, st1[0], st2[0]
+        st3 = None
+        if not args.profile_cg:
+            _, s3, st3 = stg.cg_solve(hi, MASS, b8, x=x8, lo=lo, ws=ws8, tol=TOL)
+        t3 = time.perf_counter()
+        return t1 - t0, t2 - t1, st1[0], st2[0], t3 - t2, st3
 
+    if args.profile_cg:
+        r = step()
+        print(json.dumps({"profile": "CG 32^4", "fp64_s": round(r[0], 4), "mixed_s": round(r[1], 4),
+                          "fp64_iters": r[2]["iters"], "mixed_iters": r[3]["iters"]}), flush=True)
+        return
+    copy_gbs = copy_ceiling(torch)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -217,7 +265,8 @@ def main():
     total = time.perf_counter() - t_start
     t64 = min(r[0] for r in runs)
     tmx = min(r[1] for r in runs)
-    st64, stmx = runs[-1][2], runs[-1][3]
+    t8 = min(r[4] for r in runs)
+    st64, stmx, st8 = runs[-1][2], runs[-1][3], runs[-1][5]
 
     # ---- dominant kernel roofline --------------------------------------------------
     dt = hop_time[("c128_12", "D_eo")]
@@ -252,9 +301,16 @@ def main():
                    "lattice": list(DIMS), "mass": MASS, "nrhs": 1, "tol": TOL,
                    "links": "random SU(3) (Haar), standard phases, antiperiodic t"},
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
+        "copy_ceiling_GBs": copy_gbs,
+        "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),
         "cg_fp64_s_per_rhs": round(t64, 4),
         "cg_mixed_s_per_rhs": round(tmx, 4),
         "mixed_speedup": round(t64 / tmx, 3),
+        "cg_mixed_batch8_s_per_rhs": round(t8 / nb, 4),
+        "batched_mixed_speedup": round(t64 / (t8 / nb), 3),
+        "cg_mixed_batch8": {"iters": max(x["iters"] for x in st8),
+                            "worst_true_rel_resid": max(x["true_rel_resid"] for x in st8),
+                            "reliable_updates": max(x["reliable_updates"] for x in st8)},
         "cg_fp64": {"iters": st64["iters"], "true_rel_resid": st64["true_rel_resid"],
                     "reliable_updates": st64["reliable_updates"]},
         "cg_mixed": {"iters": stmx["iters"], "true_rel_resid": stmx["true_rel_resid"],

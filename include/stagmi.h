@@ -114,6 +114,22 @@ const char *stg_status_string(int status);
 /* Last HIP error text seen by the library on this thread (empty if none). */
 const char *stg_last_error(void);
 
+/*
+ * Launch-shape choices of the hop kernels, process-wide (results do not depend
+ * on them, only the speed).  Set them before launching work; calls that are in
+ * flight keep the choice they were launched with.
+ *   STG_TUNE_XCD_REMAP: 1 (default) maps the blocks that run on one XCD of the
+ *     chip to one contiguous range of sites, so neighbour field lines meet in
+ *     that XCD's L2; 0 keeps the plain block order.
+ *   STG_TUNE_SITES_PER_THREAD: 1 (default), 2, 4 or 8 output sites per thread
+ *     (a block covers that many consecutive 256-site chunks): fewer, longer
+ *     blocks, to balance the last wave of blocks against the chip's capacity.
+ * Returns STG_INVALID_ARG for an unknown key or value.
+ */
+enum { STG_TUNE_XCD_REMAP = 0, STG_TUNE_SITES_PER_THREAD = 1 };
+int stg_set_tuning(int key, int value);
+int stg_get_tuning(int key, int *value);
+
 /* Bytes of a gauge field of format fmt on lattice lat, written to *bytes (host). */
 int stg_links_bytes(const stg_lattice *lat, stg_link_fmt fmt, size_t *bytes);
 

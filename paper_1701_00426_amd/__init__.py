@@ -30,7 +30,7 @@ from ._lib import (STG_C64, STG_C128, STG_CG_F64, STG_CG_MIXED, STG_LINK_BF16_12
 __all__ = [
     "Gauge", "pack_gauge", "stg_links_bytes", "stg_pack_links", "stg_pack_phases",
     "dirac_apply_eo", "dirac_apply_oe", "stg_apply_normal", "stg_dot", "cg_solve",
-    "multishift_cg_solve", "stg_workspace_bytes", "library",
+    "multishift_cg_solve", "stg_workspace_bytes", "library", "stg_set_tuning", "stg_get_tuning",
 ]
 
 FORMAT_NAMES = {"c128_18": STG_LINK_C128_18, "c128_12": STG_LINK_C128_12,
@@ -105,6 +105,17 @@ class Gauge:
     @property
     def field(self) -> int:
         return STG_C128 if self.fmt in (STG_LINK_C128_18, STG_LINK_C128_12) else STG_C64
+
+
+def stg_set_tuning(key: int, value: int) -> None:
+    """Sets a launch-shape choice of the hop kernels (speed only, not results)."""
+    _lib.check("stg_set_tuning", library().stg_set_tuning(int(key), int(value)))
+
+
+def stg_get_tuning(key: int) -> int:
+    v = ctypes.c_int(0)
+    _lib.check("stg_get_tuning", library().stg_get_tuning(int(key), ctypes.byref(v)))
+    return v.value
 
 
 def stg_links_bytes(dims, fmt) -> int:

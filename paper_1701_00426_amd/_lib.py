@@ -28,6 +28,10 @@ STG_LINK_BF16_12 = 3
 STG_C128 = 0
 STG_C64 = 1
 
+# tuning keys
+STG_TUNE_XCD_REMAP = 0
+STG_TUNE_SITES_PER_THREAD = 1
+
 # solver modes
 STG_CG_F64 = 0
 STG_CG_MIXED = 1
@@ -68,6 +72,8 @@ SIGNATURES = {
     "stg_version": (_I, []),
     "stg_status_string": (ctypes.c_char_p, [_I]),
     "stg_last_error": (ctypes.c_char_p, []),
+    "stg_set_tuning": (_I, [_I, _I]),
+    "stg_get_tuning": (_I, [_I, ctypes.POINTER(_I)]),
     "stg_links_bytes": (_I, [_LAT, _I, ctypes.POINTER(_S)]),
     "stg_pack_links": (_I, [_LAT, _P, _I, _P, _P]),
     "stg_pack_phases": (_I, [_LAT, _P, _I, _P, _P]),

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(VecArgs a) {
                      0.0);
         }
     }
-    reduce_and_finish<NR>(ps, pc, a.partials, a.ctl, OP_BETA, a.state, nullptr);
+    block_partials<NR>(ps, pc, a.partials);
 }
 
 // p = r + beta p
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void ms_r_update_kernel(VecArgs a) {
             }
         }
     }
-    reduce_and_finish<NR>(ps, pc, a.partials, a.ctl, OP_MS_BETA, a.state, nullptr);
+    block_partials<NR>(ps, pc, a.partials);
 }
 
 // multi-shift: p = r + beta p;  p_k = zeta_k r + beta_k p_k for the active shifts
@@ -211,11 +211,43 @@ __global__ __launch_bounds__(kBlock) void ms_p_update_kernel(VecArgs a) {
         }                                                                                \
     }
 
-STG_VEC_LAUNCHER(launch_cg_update, cg_update_kernel)
+STG_VEC_LAUNCHER(launch_cg_update_only, cg_update_kernel)
 STG_VEC_LAUNCHER(launch_p_update, p_update_kernel)
 STG_VEC_LAUNCHER(launch_ru_resume, ru_resume_kernel)
-STG_VEC_LAUNCHER(launch_ms_r_update, ms_r_update_kernel)
+STG_VEC_LAUNCHER(launch_ms_r_update_only, ms_r_update_kernel)
 STG_VEC_LAUNCHER(launch_ms_p_update, ms_p_update_kernel)
+
+int launch_cg_update(const VecArgs &a, int fp64, int nr, hipStream_t stream) {
+    if (launch_cg_update_only(a, fp64, nr, stream)) return -1;
+    FinArgs f{a.partials, site_blocks(a.Vh), nr, OP_BETA, a.gate_running, a.ctl, a.state, nullptr};
+    return launch_finalize(f, stream);
+}
+
+int launch_ms_r_update(const VecArgs &a, int fp64, int nr, hipStream_t stream) {
+    if (launch_ms_r_update_only(a, fp64, nr, stream)) return -1;
+    FinArgs f{a.partials, site_blocks(a.Vh), nr, OP_MS_BETA, a.gate_running, a.ctl, a.state,
+              nullptr};
+    return launch_finalize(f, stream);
+}
+
+// ---------------------------------------------------------------------------
+// finishing the reductions: one block, fixed order, compensated
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void finalize_kernel(FinArgs f) {
+    __shared__ double sh_s[kBlock];
+    __shared__ double sh_e[kBlock];
+    if (f.gate_running && f.ctl->n_running == 0) return;
+    for (int j = 0; j < f.nr; ++j) {
+        double tot = block_sum2_pairs(f.partials + 2 * (size_t)j * f.nblocks, (int)f.nblocks,
+                                      sh_s, sh_e);
+        if (threadIdx.x == 0) finalize_one(f.op, f.ctl, f.state, f.out, j, tot);
+    }
+}
+
+int launch_finalize(const FinArgs &f, hipStream_t stream) {
+    finalize_kernel<<<1, kBlock, 0, stream>>>(f);
+    return 0;
+}
 
 int launch_ru_accumulate(const VecArgs &a, int nr, hipStream_t stream) {
     dim3 grid(site_blocks(a.Vh));
@@ -241,8 +273,7 @@ size_t dot_blocks(size_t n) {
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void dot_kernel(size_t n, const void *x, const void *y,
-                                                     double *partials, Ctl *ctl, int op,
-                                                     SysState *state, double *out) {
+                                                     double *partials) {
     // per-thread compensated accumulation of the real and imaginary parts
     double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n;
@@ -261,13 +292,8 @@ __global__ __launch_bounds__(kBlock) void dot_kernel(size_t n, const void *x, co
         two_sum(si, pi2, si, e);
         ci += e;
     }
-    if (op == OP_STORE) {
-        double ps[2] = {sr, si}, pc[2] = {cr, ci};
-        reduce_and_finish<2>(ps, pc, partials, ctl, OP_STORE, state, out);
-    } else {
-        double ps[1] = {sr}, pc[1] = {cr};
-        reduce_and_finish<1>(ps, pc, partials, ctl, op, state, out);
-    }
+    double ps[2] = {sr, si}, pc[2] = {cr, ci};
+    block_partials<2>(ps, pc, partials);
 }
 
 int launch_dot(int fp64, int nvec, size_t n, const void *x, const void *y, double *partials,
@@ -280,9 +306,12 @@ int launch_dot(int fp64, int nvec, size_t n, const void *x, const void *y, doubl
         SysState *sj = state ? state + j : nullptr;
         double *oj = out ? out + 2 * j : nullptr;
         if (fp64)
-            dot_kernel<double><<<grid, kBlock, 0, stream>>>(n, xj, yj, partials, ctl, op, sj, oj);
+            dot_kernel<double><<<grid, kBlock, 0, stream>>>(n, xj, yj, partials);
         else
-            dot_kernel<float><<<grid, kBlock, 0, stream>>>(n, xj, yj, partials, ctl, op, sj, oj);
+            dot_kernel<float><<<grid, kBlock, 0, stream>>>(n, xj, yj, partials);
+        // OP_STORE finishes both parts (re, im); the solver ops use the real part
+        FinArgs f{partials, grid.x, op == OP_STORE ? 2 : 1, op, 0, ctl, sj, oj};
+        launch_finalize(f, stream);
     }
     return 0;
 }

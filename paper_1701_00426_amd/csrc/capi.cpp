@@ -26,6 +26,10 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// launch-shape choice of the hop kernels (stg_set_tuning)
+int g_xcd_remap = 1;
+int g_sites_per_thread = 1;
+
 int hip_fail(hipError_t e, const char *what) {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
     return STG_HIP_ERROR;
@@ -105,6 +109,8 @@ HopArgs base_hop(const Geom &g, const stg_gauge *gauge) {
     a.links = gauge->links;
     a.phases = gauge->phases;
     a.fstride = (size_t)3 * g.Vh;
+    a.xcd_remap = g_xcd_remap;
+    a.sites_per_thread = (uint32_t)g_sites_per_thread;
     return a;
 }
 
@@ -330,6 +336,45 @@ int enqueue_reliable_update(const CgProblem &P, const CgWork &w, hipStream_t s) 
     return STG_OK;
 }
 
+// Pinned host buffers for the pipelined flag snapshots (grown on demand, kept
+// for the life of the thread).
+struct PinnedSnapshots {
+    SysState *buf = nullptr;
+    size_t cap = 0;  // SysState entries per slot
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+thread_local PinnedSnapshots g_snap;
+
+int snapshots_ready(int nsys) {
+    if (!g_snap.ev[0]) {
+        HIP_TRY(hipEventCreateWithFlags(&g_snap.ev[0], hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&g_snap.ev[1], hipEventDisableTiming));
+    }
+    if ((size_t)nsys > g_snap.cap) {
+        if (g_snap.buf) HIP_TRY(hipHostFree(g_snap.buf));
+        g_snap.buf = nullptr;
+        g_snap.cap = 0;
+        size_t cap = std::max<size_t>(64, (size_t)nsys);
+        HIP_TRY(hipHostMalloc((void **)&g_snap.buf, 2 * cap * sizeof(SysState), 0));
+        g_snap.cap = cap;
+    }
+    return STG_OK;
+}
+
+// Queues a copy of the flags into pinned slot `slot` and records its event.
+int snapshot_enqueue(const SysState *dev, int nsys, int slot, hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(g_snap.buf + (size_t)slot * g_snap.cap, dev, sizeof(SysState) * nsys,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(g_snap.ev[slot], s));
+    return STG_OK;
+}
+
+int snapshot_wait(int nsys, int slot, std::vector<SysState> &st) {
+    HIP_TRY(hipEventSynchronize(g_snap.ev[slot]));
+    std::memcpy(st.data(), g_snap.buf + (size_t)slot * g_snap.cap, sizeof(SysState) * nsys);
+    return STG_OK;
+}
+
 int read_states_n(const SysState *dev, int nsys, std::vector<SysState> &st, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(st.data(), dev, sizeof(SysState) * nsys, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -359,6 +404,7 @@ int run_cg(const CgProblem &P, const CgWork &w, stg_cg_stats *stats, hipStream_t
         q.flags = SYS_RU_PENDING;
         q.restart = P.prm.restart;
         q.gid = j;
+        q.max_iter = P.prm.max_iter;
     }
     Ctl ctl0;
     std::memset(&ctl0, 0, sizeof(ctl0));
@@ -396,35 +442,55 @@ int run_cg(const CgProblem &P, const CgWork &w, stg_cg_stats *stats, hipStream_t
     int poll = P.prm.poll_every;
     if (poll <= 0) poll = (int)std::min<uint32_t>(64, std::max<uint32_t>(8, (1u << 22) / P.g.Vh));
     int status_all = STG_OK;
+    rc = snapshots_ready(n);
+    if (rc) return rc;
+    // Pipelined polling: chunk c+1 is queued before the flags copied after chunk c
+    // are read, so the GPU never waits for the host.  A parked system (reliable
+    // update due) sees its update after at most one more chunk, in which it does
+    // not iterate; the update itself drains the stream and restarts the pipeline.
+    rc = read_states(w, n, st, s);
+    if (rc) return rc;
+    int slot = 0, pend = -1;  // pend: slot of a queued snapshot not read yet
     for (;;) {
-        rc = read_states(w, n, st, s);
-        if (rc) return rc;
-        int running = 0, pending = 0, max_it = 0;
+        int running = 0, pending = 0;
         for (int j = 0; j < n; ++j) {
-            if (st[j].flags & SYS_RUNNING) {
-                ++running;
-                max_it = std::max(max_it, st[j].iter);
-            }
+            if (st[j].flags & SYS_RUNNING) ++running;
             if (st[j].flags & SYS_RU_PENDING) ++pending;
         }
         if (pending) {
+            if (pend >= 0) {
+                rc = snapshot_wait(n, pend, st);  // the chunk queued after it: done, unused
+                if (rc) return rc;
+                pend = -1;
+            }
             rc = enqueue_reliable_update(P, w, s);
+            if (rc) return rc;
+            rc = read_states(w, n, st, s);
             if (rc) return rc;
             continue;
         }
         if (running == 0) break;
-        if (max_it >= P.prm.max_iter) break;
-        const int k = std::min(poll, P.prm.max_iter - max_it);
-        for (int i = 0; i < k; ++i) {
+        for (int i = 0; i < poll; ++i) {
             rc = enqueue_inner_iteration(P, w, s);
             if (rc) return rc;
         }
+        rc = snapshot_enqueue(w.state, n, slot, s);
+        if (rc) return rc;
+        if (pend >= 0) {
+            rc = snapshot_wait(n, pend, st);  // flags one chunk behind the queue
+            if (rc) return rc;
+        }
+        pend = slot;
+        slot ^= 1;
     }
+    HIP_TRY(hipStreamSynchronize(s));
+    rc = read_states(w, n, st, s);
+    if (rc) return rc;
     // systems stopped by the iteration cap: fold the inner solution into x and
     // compute their true residual
     bool any_open = false;
     for (int j = 0; j < n; ++j)
-        if (st[j].flags & SYS_RUNNING) {
+        if (st[j].flags & (SYS_RUNNING | SYS_CAPPED)) {
             st[j].flags = SYS_RU_PENDING;
             st[j].restart = 1;
             any_open = true;
@@ -602,6 +668,7 @@ int run_mscg(const Geom &g, const stg_gauge *hi, const stg_gauge *lo, double mas
         q.tol2bb = tol_ms * tol_ms;
         q.flags = SYS_RUNNING;
         q.gid = j;
+        q.max_iter = prm.max_iter;
         q.alpha_prev = 1.0;
         q.beta_prev = 0.0;
     }
@@ -658,24 +725,33 @@ int run_mscg(const Geom &g, const stg_gauge *hi, const stg_gauge *lo, double mas
     }
     int poll = prm.poll_every;
     if (poll <= 0) poll = (int)std::min<uint32_t>(64, std::max<uint32_t>(8, (1u << 22) / g.Vh));
-    int ms_iters = 0;
+    rc = snapshots_ready(nrhs);
+    if (rc) return rc;
+    rc = read_states_n(w.state, nrhs, st, s);
+    if (rc) return rc;
+    // pipelined polling as in the CG loop (no reliable updates in this stage; the
+    // iteration cap is enforced on the device)
+    int slot = 0, pend = -1;
     for (;;) {
-        rc = read_states_n(w.state, nrhs, st, s);
-        if (rc) return rc;
-        int running = 0, max_it = 0;
-        for (int j = 0; j < nrhs; ++j)
-            if (st[j].flags & SYS_RUNNING) {
-                ++running;
-                max_it = std::max(max_it, st[j].iter);
-            }
-        for (int j = 0; j < nrhs; ++j) ms_iters = std::max(ms_iters, st[j].iter);
-        if (running == 0 || max_it >= prm.max_iter) break;
-        const int k = std::min(poll, prm.max_iter - max_it);
-        for (int i = 0; i < k; ++i) {
+        int running = 0;
+        for (int j = 0; j < nrhs; ++j) running += (st[j].flags & SYS_RUNNING) ? 1 : 0;
+        if (running == 0) break;
+        for (int i = 0; i < poll; ++i) {
             rc = enqueue_ms_iteration(g, gg, f64, nrhs, nshift, w, s);
             if (rc) return rc;
         }
+        rc = snapshot_enqueue(w.state, nrhs, slot, s);
+        if (rc) return rc;
+        if (pend >= 0) {
+            rc = snapshot_wait(nrhs, pend, st);
+            if (rc) return rc;
+        }
+        pend = slot;
+        slot ^= 1;
     }
+    HIP_TRY(hipStreamSynchronize(s));
+    rc = read_states_n(w.state, nrhs, st, s);
+    if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(zs.data(), w.shift, sizeof(ShiftState) * zs.size(),
                            hipMemcpyDeviceToHost, s));
     // shifted solutions -> x (complex128, [nshift][nrhs])
@@ -718,7 +794,6 @@ int run_mscg(const Geom &g, const stg_gauge *hi, const stg_gauge *lo, double mas
                 rs[i].status == STG_OK ? ms_it + std::max(0, rs[i].converged_iter) : -1;
             stats[i].seconds = secs;
         }
-    (void)ms_iters;
     return status;
 }
 
@@ -744,6 +819,30 @@ const char *stg_status_string(int status) {
 }
 
 const char *stg_last_error(void) { return g_last_error.c_str(); }
+
+int stg_set_tuning(int key, int value) {
+    switch (key) {
+        case STG_TUNE_XCD_REMAP:
+            if (value != 0 && value != 1) return invalid("XCD remap takes 0 or 1");
+            g_xcd_remap = value;
+            return STG_OK;
+        case STG_TUNE_SITES_PER_THREAD:
+            if (value != 1 && value != 2 && value != 4 && value != 8)
+                return invalid("sites per thread takes 1, 2, 4 or 8");
+            g_sites_per_thread = value;
+            return STG_OK;
+        default: return invalid("unknown tuning key");
+    }
+}
+
+int stg_get_tuning(int key, int *value) {
+    if (!value) return invalid("value is NULL");
+    switch (key) {
+        case STG_TUNE_XCD_REMAP: *value = g_xcd_remap; return STG_OK;
+        case STG_TUNE_SITES_PER_THREAD: *value = g_sites_per_thread; return STG_OK;
+        default: return invalid("unknown tuning key");
+    }
+}
 
 int stg_links_bytes(const stg_lattice *lat, stg_link_fmt fmt, size_t *bytes) {
     Geom g;

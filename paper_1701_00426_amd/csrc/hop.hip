@@ -19,8 +19,9 @@
 //   EPI_NORMAL  out = diag_j * p - D in           with p on the output parity;
 //               block partials of Re<p, out>      (normal operator, CG's <p, A p>)
 //   EPI_RESID   out = b - (diag_j * x - D in)      true residual; block partials of |out|^2
-// Reductions finish in the last block to arrive (fixed-order compensated sum) and
-// the scalar step of solver_state.hpp runs there.
+// Reductions leave one compensated (sum, error) pair per block; a one-block
+// finalize kernel adds them in a fixed order and runs the scalar step of
+// solver_state.hpp.
 
 #include "device_common.hpp"
 #include "kernels.hpp"
@@ -33,15 +34,18 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
     if (a.gate_running && a.ctl->n_running == 0) return;
 
     const Geom &g = a.geom;
-    const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = h < g.Vh;
+    const uint32_t blk = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
     const int P = a.out_parity;
 
     double ps[NR], pc[NR];  // compensated per-thread partials of the epilogue sums
 #pragma unroll
     for (int j = 0; j < NR; ++j) ps[j] = pc[j] = 0.0;
 
-    if (valid) {
+    // the block owns sites_per_thread consecutive chunks of kBlock sites
+#pragma unroll 1
+    for (uint32_t k = 0; k < a.sites_per_thread; ++k) {
+    const uint32_t h = (blk * a.sites_per_thread + k) * kBlock + threadIdx.x;
+    if (h < g.Vh) {
         Site s = site_coords(g, P, h);
         vec3<T> acc[NR];
 #pragma unroll
@@ -114,10 +118,11 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
             st_v<T>(a.out, a.fstride, g.Vh, j, h, o);
         }
     }
+    }
 
     if (EPI == EPI_PLAIN || a.op == OP_NONE) return;
 
-    reduce_and_finish<NR>(ps, pc, a.partials, a.ctl, a.op, a.state, a.out_sums);
+    block_partials<NR>(ps, pc, a.partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -125,17 +130,22 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
 // ---------------------------------------------------------------------------
 template <typename T, int FMT, bool STDPH, int NR>
 static void launch_nr(const HopArgs &a, int epi, hipStream_t stream) {
-    dim3 grid((a.geom.Vh + kBlock - 1) / kBlock);
+    const uint32_t chunk = kBlock * a.sites_per_thread;
+    dim3 grid((a.geom.Vh + chunk - 1) / chunk);
     switch (epi) {
         case EPI_PLAIN:
             hop_kernel<T, FMT, STDPH, NR, EPI_PLAIN><<<grid, kBlock, 0, stream>>>(a);
-            break;
+            return;
         case EPI_NORMAL:
             hop_kernel<T, FMT, STDPH, NR, EPI_NORMAL><<<grid, kBlock, 0, stream>>>(a);
             break;
         default:
             hop_kernel<T, FMT, STDPH, NR, EPI_RESID><<<grid, kBlock, 0, stream>>>(a);
             break;
+    }
+    if (a.op != OP_NONE) {
+        FinArgs f{a.partials, grid.x, NR, a.op, a.gate_running, a.ctl, a.state, a.out_sums};
+        launch_finalize(f, stream);
     }
 }
 

@@ -24,7 +24,9 @@ struct HopArgs {
     int out_parity;       // 0: D_eo (even outputs), 1: D_oe (odd outputs)
     int op;               // FinOp of the reduction (OP_NONE: no reduction)
     int gate_running;     // exit at once when ctl->n_running == 0
-    int pad_;
+    int xcd_remap;        // 1: blocks of one XCD take one contiguous range of sites
+    uint32_t sites_per_thread;  // each block covers this many consecutive kBlock-site chunks
+    uint32_t pad_;
     double diag;          // m^2 + sigma when state == nullptr
     SysState *state;      // per-field solver state, or nullptr
     Ctl *ctl;
@@ -40,17 +42,14 @@ struct HopArgs {
 };
 
 // Tail of every reduction kernel: per-thread compensated partials (s[j], c[j]) of
-// NR sums -> one (sum, error) pair per block in `partials` ([NR][grid][2]) -> the
-// last block to arrive adds the pairs in a fixed order and runs the scalar step
-// `op` of solver_state.hpp for each of the NR systems.
+// NR sums -> one (sum, error) pair per block in `partials` ([NR][grid][2]).  The
+// sums are finished by finalize_kernel, launched right after on the same stream:
+// the kernel boundary makes the partials of every XCD visible without a
+// device-scope fence in each block (which costs an L2 write-back per block).
 template <int NR>
-__device__ __forceinline__ void reduce_and_finish(double (&s)[NR], double (&c)[NR],
-                                                  double *partials, Ctl *ctl, int op,
-                                                  SysState *state, double *out) {
+__device__ __forceinline__ void block_partials(double (&s)[NR], double (&c)[NR],
+                                               double *partials) {
     __shared__ double sh_red[2 * kWaves];
-    __shared__ double sh_s[kBlock];
-    __shared__ double sh_e[kBlock];
-    __shared__ int sh_last;
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         block_sum_pair(s[j], c[j], sh_red);
@@ -60,20 +59,33 @@ __device__ __forceinline__ void reduce_and_finish(double (&s)[NR], double (&c)[N
             pj[1] = c[j];
         }
     }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        int prev = atomicAdd(&ctl->counter, 1);
-        sh_last = (prev == (int)gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!sh_last) return;
-    __threadfence();
-#pragma unroll 1
-    for (int j = 0; j < NR; ++j) {
-        double tot = block_sum2_pairs(partials + 2 * (size_t)j * gridDim.x, gridDim.x, sh_s, sh_e);
-        if (threadIdx.x == 0) finalize_one(op, ctl, state, out, j, tot);
-    }
-    if (threadIdx.x == 0) ctl->counter = 0;
+}
+
+// One block: adds the nblocks pairs of each of nr sums in a fixed order and runs
+// the scalar step `op` (solver_state.hpp) for each of the nr systems.
+struct FinArgs {
+    const double *partials;
+    uint32_t nblocks;
+    int nr;
+    int op;
+    int gate_running;
+    Ctl *ctl;
+    SysState *state;
+    double *out;
+};
+int launch_finalize(const FinArgs &f, hipStream_t stream);
+
+// Workgroups are dispatched to the 8 XCDs of the chip round-robin by block index,
+// and each XCD has its own L2.  This maps the launch's block b to a logical block
+// so that the blocks running on one XCD cover one contiguous range of sites: the
+// neighbour field lines that nearby sites share (x1, x2 and most x3 neighbours)
+// then meet in the same L2.  A bijection of [0, nb) for any nb.
+constexpr uint32_t kXcds = 8;
+
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+    const uint32_t x = b % kXcds, i = b / kXcds;
+    const uint32_t q = nb / kXcds, r = nb % kXcds;
+    return x * q + (x < r ? x : r) + i;
 }
 
 // Blocks of kBlock threads needed to cover Vh sites.

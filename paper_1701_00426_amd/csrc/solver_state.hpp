@@ -22,7 +22,8 @@ enum SysFlags : int {
     SYS_RU_PENDING = 2,  // parked, waiting for a true-residual update
     SYS_DONE = 4,        // true residual met the target
     SYS_BREAKDOWN = 8,   // non-finite scalar or <p, A p> <= 0
-    SYS_RESUME = 16      // just updated: the resume kernel rebuilds r_inner and p
+    SYS_RESUME = 16,     // just updated: the resume kernel rebuilds r_inner and p
+    SYS_CAPPED = 32      // stopped by the iteration cap (not converged)
 };
 
 struct SysState {
@@ -42,6 +43,8 @@ struct SysState {
     int conv_iter;   // iteration at which the system finished
     int restart;     // 1: p = r after each update
     int gid;         // index of this system in the solve (multi-shift: the RHS index)
+    int max_iter;    // iteration cap: the system stops (SYS_CAPPED) when iter reaches it
+    int pad_;
     double alpha_prev;  // multi-shift base scalars of the previous iteration
     double beta_prev;
 };
@@ -61,7 +64,7 @@ struct ShiftState {
 
 struct Ctl {
     int n_running;   // systems with SYS_RUNNING set; kernels of the inner loop exit when 0
-    int counter;     // arrival counter of the last-block reductions (reset by the last block)
+    int pad0_;
     int nshift;      // multi-shift: shifts per RHS
     int nrhs;        // multi-shift: right-hand sides
     ShiftState *ms;  // multi-shift: [nshift][nrhs]
@@ -124,6 +127,10 @@ __device__ __forceinline__ void finalize_one(int op, Ctl *ctl, SysState *st, dou
         }
         s.beta = sum / s.rr;
         s.rr = sum;
+        if (s.iter >= s.max_iter) {
+            s.flags = SYS_CAPPED;
+            ctl->n_running -= 1;
+        }
         return;
     }
     if (op == OP_MS_ALPHA) {
@@ -176,6 +183,9 @@ __device__ __forceinline__ void finalize_one(int op, Ctl *ctl, SysState *st, dou
             s.flags = SYS_DONE;
             s.conv_iter = s.iter;
             ctl->n_running -= 1;
+        } else if (s.iter >= s.max_iter) {
+            s.flags = SYS_CAPPED;
+            ctl->n_running -= 1;
         }
         return;
     }
@@ -190,6 +200,10 @@ __device__ __forceinline__ void finalize_one(int op, Ctl *ctl, SysState *st, dou
         if (sum <= s.tol2bb) {
             s.flags = SYS_DONE;
             s.conv_iter = s.iter;
+            return;
+        }
+        if (s.iter >= s.max_iter) {
+            s.flags = SYS_CAPPED;
             return;
         }
         s.beta = (s.restart || !(s.rr_old > 0.0)) ? 0.0 : sum / s.rr_old;
