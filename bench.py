@@ -40,6 +40,8 @@ BYTES_PER_SITE = {"c128_18": 8 * 144 + 48 + 48, "c128_12": 8 * 96 + 48 + 48,
 FLOPS_PER_SITE = 570  # 8 SU(3) mat-vecs (66) + 7 colour-vector sums (6); reconstruction excluded
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_traffic_32x32x32x32.json")
 KERNEL_SOURCES = ["paper_1701_00426_amd/csrc/hop.hip",
+                  "paper_1701_00426_amd/csrc/hop_core.hpp",
+                  "paper_1701_00426_amd/csrc/kernels.hpp",
                   "paper_1701_00426_amd/csrc/device_common.hpp"]
 
 
@@ -134,6 +136,85 @@ def calibrate_copy():
                       "GBs_read_plus_write": round(2 * n / dt / 1e9, 1)}), flush=True)
 
 
+def bench_multishift():
+    """24^3 x 48, m = 0.005, 16 shifts log-spaced in [1e-4, 10], 8 RHS in one solve:
+    multi-shift stage in FP32 (FP32-12 links) then per-(shift, RHS) mixed refinement to
+    the FP64 true residual 1e-10."""
+    import torch
+    import paper_1701_00426_amd as stg
+    import seeded_inputs as si
+    dims, mass, nrhs = (24, 24, 24, 48), 0.005, 8
+    shifts = si.log_shifts(16, 1e-4, 10.0)
+    dev = torch.device("cuda:0")
+    log("generating 24^3x48 inputs")
+    links = torch.from_numpy(si.su3_links(dims, 1701, 4, 0)).to(dev)
+    b = torch.from_numpy(si.gaussian_field(dims, nrhs, 426, 4, 0)).to(dev)
+    hi = stg.pack_gauge(dims, links, "c128_12")
+    lo = stg.pack_gauge(dims, links, "c64_12")
+    ws = torch.empty(stg.stg_workspace_bytes(dims, nrhs, len(shifts), stg.STG_CG_MIXED),
+                     dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st, stats = stg.multishift_cg_solve(hi, mass, shifts, b, lo=lo, ws=ws,
+                                           tol=TOL)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    flat = [s for row in stats for s in row]
+    out = {"workload": "multishift 24^3x48 m=0.005, 16 shifts in [1e-4, 10], 8 RHS, FP32-12 + "
+                       "FP64 refinement to 1e-10",
+           "status": st, "seconds": round(dt, 3), "s_per_rhs": round(dt / nrhs, 4),
+           "worst_true_rel_resid": max(s["true_rel_resid"] for s in flat),
+           "iters_smallest_shift": max(s["iters"] for s in stats[0]),
+           "iters_largest_shift": max(s["iters"] for s in stats[-1]),
+           "refine_reliable_updates_max": max(s["reliable_updates"] for s in flat),
+           "workspace_GB": round(ws.numel() / 1e9, 2)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch():
+    """12 solves: two each on 8^4, 12^4, 16^4, 16^3x32, 24^4, 32^4 at m = 0.01 and 0.05,
+    nrhs_i = 1 + (i mod 4): one cg_solve_batch (mixed FP32-12) against the same solves
+    launched one after another with cg_solve."""
+    import torch
+    import paper_1701_00426_amd as stg
+    import seeded_inputs as si
+    dev = torch.device("cuda:0")
+    shapes = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16), (16, 16, 16, 32),
+              (24, 24, 24, 24), (32, 32, 32, 32)]
+    solves = []
+    i = 0
+    for dims in shapes:
+        for m in (0.01, 0.05):
+            nrhs = 1 + (i % 4)
+            links = torch.from_numpy(si.su3_links(dims, 1701, 5, i)).to(dev)
+            b = torch.from_numpy(si.gaussian_field(dims, nrhs, 426, 5, i)).to(dev)
+            solves.append(dict(hi=stg.pack_gauge(dims, links, "c128_12"),
+                               lo=stg.pack_gauge(dims, links, "c64_12"), mass=m, b=b))
+            del links
+            i += 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, st, stats = stg.cg_solve_batch(solves, tol=TOL)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    worst_single = 0.0
+    for sv in solves:
+        _, s1, st1 = stg.cg_solve(sv["hi"], sv["mass"], sv["b"], lo=sv["lo"], tol=TOL)
+        worst_single = max(worst_single, max(q["true_rel_resid"] for q in st1))
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t1
+    flat = [q for row in stats for q in row]
+    out = {"workload": "uneven batch: 12 solves (8^4, 12^4, 16^4, 16^3x32, 24^4, 32^4 x m in "
+                       "{0.01, 0.05}), 30 RHS, FP32-12 + FP64 reliable updates, tol 1e-10",
+           "status": st, "makespan_s": round(t_batch, 3), "sequential_cg_solve_s": round(t_seq, 3),
+           "speedup_vs_sequential": round(t_seq / t_batch, 3),
+           "worst_true_rel_resid": max(q["true_rel_resid"] for q in flat),
+           "worst_true_rel_resid_sequential": worst_single,
+           "max_iters": max(q["iters"] for q in flat), "nsys": len(flat)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +226,9 @@ def main():
                     help="for rocprofv3: only the dominant kernel's timed loop (FP64-12 D_eo)")
     ap.add_argument("--profile-cg", action="store_true",
                     help="for rocprofv3: one FP64 CG and one mixed CG solve only")
+    ap.add_argument("--workload", choices=["main", "multishift", "batch"], default="main",
+                    help="main: the 32^4 line; multishift: 24^3x48, 16 shifts x 8 RHS; "
+                         "batch: 12 solves on 8^4 .. 32^4 in one cg_solve_batch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="for rocprofv3 --pmc: a plain 1 GiB device copy, to scale byte counters")
     args = ap.parse_args()
@@ -154,6 +238,12 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.workload == "multishift":
+        bench_multishift()
+        return
+    if args.workload == "batch":
+        bench_batch()
         return
 
     import numpy as np

@@ -130,6 +130,27 @@ enum { STG_TUNE_XCD_REMAP = 0, STG_TUNE_SITES_PER_THREAD = 1 };
 int stg_set_tuning(int key, int value);
 int stg_get_tuning(int key, int *value);
 
+/*
+ * Autotuner of the hop launch shape (the run-time counterpart of the paper's
+ * per-architecture compile-time tile sizes, Sec. 4.3 TILE0..2 and Sec. 5).
+ * stg_autotune times every candidate shape (XCD remap on/off x 1, 2, 4, 8 sites
+ * per thread) of D_eo on the caller's gauge field and fields (in: device
+ * [nrhs][3][Vh] on odd sites; out: device, overwritten), keeps the fastest for
+ * the key (lattice extents, gauge format, fields per launch = the largest chunk
+ * of nrhs among 8, 4, 2, 1) in a process-wide table that every later hop launch
+ * with that key uses, and, when cache_path is not NULL, appends it to that file as
+ * one JSON object per line.  Synchronous.  stg_autotune_load reads such a file
+ * into the table (later lines win) and reports the entries read in *loaded.
+ * stg_autotune_lookup returns STG_OK and the stored choice, or STG_NOT_CONVERGED
+ * when the key has no entry.  stg_autotune_clear empties the table.
+ */
+int stg_autotune(const stg_lattice *lat, const stg_gauge *gauge, stg_field field, int nrhs,
+                 const void *in, void *out, const char *cache_path, stg_stream_t stream);
+int stg_autotune_load(const char *cache_path, int *loaded);
+int stg_autotune_lookup(const stg_lattice *lat, stg_link_fmt fmt, int nr, int *xcd_remap,
+                        int *sites_per_thread, double *us);
+void stg_autotune_clear(void);
+
 /* Bytes of a gauge field of format fmt on lattice lat, written to *bytes (host). */
 int stg_links_bytes(const stg_lattice *lat, stg_link_fmt fmt, size_t *bytes);
 
@@ -240,6 +261,39 @@ int multishift_cg_solve(const stg_lattice *lat, const stg_gauge *hi, const stg_g
                         double mass, int nshift, const double *shifts, int nrhs,
                         const void *b_even, void *x_even, const stg_cg_params *params, void *ws,
                         size_t ws_bytes, stg_cg_stats *stats, stg_stream_t stream);
+
+/*
+ * Uneven batch: independent CG solves on lattices of different sizes, each
+ * (mass^2 - D_eo D_oe) x_j = b_j as in cg_solve (Sec. 2.2 Eq. lineqeo), advanced
+ * together.  Every kernel of a CG step walks one table of tiles spanning all the
+ * lattices (the paper fixes one lattice per compiled kernel, Sec. 4.1), so one
+ * launch serves every solve; the iterations are captured once in a hipGraph and
+ * replayed, with one host flag read per replay.
+ *   lat, hi, lo, mass, nrhs, b, x: as in cg_solve for this solve (b and x device
+ *   complex128 [nrhs][3][Vh]; x holds the guess on entry).  Every hi field must
+ *   have one format, and in mode MIXED every lo field one format.
+ */
+typedef struct {
+    stg_lattice lat;
+    stg_gauge hi;
+    stg_gauge lo;
+    double mass;
+    int nrhs;
+    const void *b;
+    void *x;
+} stg_solve_desc;
+
+/* Device workspace bytes needed by cg_solve_batch for these solves and mode. */
+int stg_batch_workspace_bytes(int nsolve, const stg_solve_desc *descs, int mode, size_t *bytes);
+
+/*
+ * Solves every system of every descriptor.  params->poll_every is the number of
+ * iterations per graph replay (0: 16).  stats (host) receives one entry per
+ * system, descriptors in order and RHS in order within each.  Returns STG_OK when
+ * every system converged, else the worst status.
+ */
+int cg_solve_batch(int nsolve, const stg_solve_desc *descs, const stg_cg_params *params, void *ws,
+                   size_t ws_bytes, stg_cg_stats *stats, stg_stream_t stream);
 
 #ifdef __cplusplus
 }

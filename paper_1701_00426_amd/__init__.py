@@ -31,6 +31,7 @@ __all__ = [
     "Gauge", "pack_gauge", "stg_links_bytes", "stg_pack_links", "stg_pack_phases",
     "dirac_apply_eo", "dirac_apply_oe", "stg_apply_normal", "stg_dot", "cg_solve",
     "multishift_cg_solve", "stg_workspace_bytes", "library", "stg_set_tuning", "stg_get_tuning",
+    "cg_solve_batch", "stg_autotune", "stg_autotune_load", "stg_autotune_lookup",
 ]
 
 FORMAT_NAMES = {"c128_18": STG_LINK_C128_18, "c128_12": STG_LINK_C128_12,
@@ -300,3 +301,95 @@ def multishift_cg_solve(hi: Gauge, mass: float, shifts, b: torch.Tensor,
         _lib.check("multishift_cg_solve", st, ok=(_lib.STG_OK,))
     out = [[stats[k * nrhs + j].as_dict() for j in range(nrhs)] for k in range(ns)]
     return x, st, out
+
+
+def cg_solve_batch(solves, mode=None, ws: Optional[torch.Tensor] = None, stream=None,
+                   check_status: bool = True, **params):
+    """Uneven batch: every entry of ``solves`` is a dict with ``hi`` (Gauge, FP64),
+    ``lo`` (Gauge, FP32 formats; mixed mode), ``mass``, ``b`` (complex128 (nrhs, 3, Vh))
+    and optionally ``x`` (initial guess, receives the solution).
+
+    Returns (list of x, status, list of per-solve lists of per-RHS stats dicts).
+    """
+    n = len(solves)
+    if mode is None:
+        mode = STG_CG_MIXED if all(sv.get("lo") is not None for sv in solves) else STG_CG_F64
+    descs = (_lib.StgSolveDesc * n)()
+    xs = []
+    keep = []
+    nsys = 0
+    for i, sv in enumerate(solves):
+        hi, lo, b = sv["hi"], sv.get("lo"), sv["b"]
+        vh = half_volume(hi.dims)
+        nrhs = _nrhs(b, vh)
+        if b.dtype != torch.complex128:
+            raise ValueError("b must be complex128")
+        x = sv.get("x")
+        if x is None:
+            x = torch.zeros_like(b)
+        xs.append(x)
+        d = descs[i]
+        d.lat = _lib.lattice(hi.dims)
+        d.hi = hi.c()
+        if lo is not None:
+            d.lo = lo.c()
+        d.mass = float(sv["mass"])
+        d.nrhs = nrhs
+        d.b = b.data_ptr()
+        d.x = x.data_ptr()
+        keep.append((b, x))
+        nsys += nrhs
+    params["mode"] = mode
+    prm = cg_params(**params)
+    lib = library()
+    need = ctypes.c_size_t(0)
+    _lib.check("stg_batch_workspace_bytes", lib.stg_batch_workspace_bytes(
+        n, descs, int(mode), ctypes.byref(need)))
+    if ws is None or ws.numel() < need.value:
+        ws = torch.empty(need.value, dtype=torch.uint8, device=solves[0]["b"].device)
+    stats = (_lib.StgCgStats * nsys)()
+    st = lib.cg_solve_batch(n, descs, ctypes.byref(prm), _ptr(ws), ws.numel(), stats,
+                            _stream(stream))
+    if check_status:
+        _lib.check("cg_solve_batch", st, ok=(_lib.STG_OK,))
+    out, k = [], 0
+    for sv in solves:
+        nr = _nrhs(sv["b"], half_volume(sv["hi"].dims))
+        out.append([stats[k + j].as_dict() for j in range(nr)])
+        k += nr
+    return xs, st, out
+
+
+def stg_autotune(gauge: Gauge, nrhs: int = 1, cache_path: Optional[str] = None, stream=None):
+    """Times the hop launch shapes for this gauge field and nrhs fields per launch and
+    keeps the fastest (process-wide; appended to cache_path when given).  Returns the
+    choice as a dict."""
+    vh = half_volume(gauge.dims)
+    cdt = torch.complex128 if gauge.field == STG_C128 else torch.complex64
+    vin = torch.zeros((nrhs, 3, vh), dtype=cdt, device=gauge.links.device)
+    out = torch.empty_like(vin)
+    g = gauge.c()
+    lib = library()
+    _lib.check("stg_autotune", lib.stg_autotune(
+        ctypes.byref(_lib.lattice(gauge.dims)), ctypes.byref(g), int(gauge.field), int(nrhs),
+        _ptr(vin), _ptr(out), cache_path.encode() if cache_path else None, _stream(stream)))
+    nr = 8 if nrhs >= 8 else 4 if nrhs >= 4 else 2 if nrhs >= 2 else 1
+    return stg_autotune_lookup(gauge.dims, gauge.fmt, nr)
+
+
+def stg_autotune_load(cache_path: str) -> int:
+    n = ctypes.c_int(0)
+    _lib.check("stg_autotune_load", library().stg_autotune_load(cache_path.encode(),
+                                                                ctypes.byref(n)))
+    return n.value
+
+
+def stg_autotune_lookup(dims, fmt, nr: int = 1):
+    """The stored launch shape for (dims, fmt, nr), or None."""
+    x, sp, us = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0)
+    st = library().stg_autotune_lookup(ctypes.byref(_lib.lattice(dims)), int(fmt), int(nr),
+                                       ctypes.byref(x), ctypes.byref(sp), ctypes.byref(us))
+    if st == _lib.STG_NOT_CONVERGED:
+        return None
+    _lib.check("stg_autotune_lookup", st)
+    return {"xcd_remap": x.value, "sites_per_thread": sp.value, "us": us.value}

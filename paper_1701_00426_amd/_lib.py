@@ -60,6 +60,11 @@ class StgCgStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class StgSolveDesc(ctypes.Structure):
+    _fields_ = [("lat", StgLattice), ("hi", StgGauge), ("lo", StgGauge), ("mass", ctypes.c_double),
+                ("nrhs", ctypes.c_int), ("b", ctypes.c_void_p), ("x", ctypes.c_void_p)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _D = ctypes.c_double
@@ -74,6 +79,11 @@ SIGNATURES = {
     "stg_last_error": (ctypes.c_char_p, []),
     "stg_set_tuning": (_I, [_I, _I]),
     "stg_get_tuning": (_I, [_I, ctypes.POINTER(_I)]),
+    "stg_autotune": (_I, [_LAT, _G, _I, _I, _P, _P, ctypes.c_char_p, _P]),
+    "stg_autotune_load": (_I, [ctypes.c_char_p, ctypes.POINTER(_I)]),
+    "stg_autotune_lookup": (_I, [_LAT, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                                 ctypes.POINTER(_D)]),
+    "stg_autotune_clear": (None, []),
     "stg_links_bytes": (_I, [_LAT, _I, ctypes.POINTER(_S)]),
     "stg_pack_links": (_I, [_LAT, _P, _I, _P, _P]),
     "stg_pack_phases": (_I, [_LAT, _P, _I, _P, _P]),
@@ -89,6 +99,10 @@ SIGNATURES = {
     "multishift_cg_solve": (_I, [_LAT, _G, _G, _D, _I, ctypes.POINTER(_D), _I, _P, _P,
                                  ctypes.POINTER(StgCgParams), _P, _S,
                                  ctypes.POINTER(StgCgStats), _P]),
+    "stg_batch_workspace_bytes": (_I, [_I, ctypes.POINTER(StgSolveDesc), _I,
+                                       ctypes.POINTER(_S)]),
+    "cg_solve_batch": (_I, [_I, ctypes.POINTER(StgSolveDesc), ctypes.POINTER(StgCgParams), _P,
+                            _S, ctypes.POINTER(StgCgStats), _P]),
 }
 
 _lib = None

@@ -1,0 +1,367 @@
+// batch.hip -- CG on many independent lattices at once (uneven batch).
+//
+// Paper: arXiv:1701.00426, Sec. 2.2 (CG on Eq. lineqeo), Sec. 4.3 (deo/doe); the
+// paper fixes the lattice extents at compile time (Sec. 4.1 LNH_N0..), so one
+// launch serves one lattice.  Here every kernel of a CG step walks a table of
+// tiles that spans all lattices of the batch: a tile is kBlock consecutive sites of
+// one lattice for a chunk of 1, 2 or 4 right-hand sides.  One launch per step
+// therefore serves every solve, small lattices ride along with large ones, and
+// the launch count does not grow with the number of solves.  Blocks walk
+// contiguous tile ranges (persistent grid), in XCD-aware order.  Solves that have
+// converged skip their tiles.
+
+#include "batch.hpp"
+#include "device_common.hpp"
+#include "hop_core.hpp"
+#include "kernels.hpp"
+#include "solver_state.hpp"
+
+namespace stg {
+
+__device__ __forceinline__ bool tile_active(const BArgs &a, const BSolve &S, const BTile &t) {
+    if (!a.gate_running) return true;
+    for (int j = 0; j < t.nr; ++j)
+        if (a.state[S.sys0 + t.j0 + j].flags & SYS_RUNNING) return true;
+    return false;
+}
+
+// Contiguous tile range of this block.
+__device__ __forceinline__ void tile_range(const BArgs &a, uint32_t &t0, uint32_t &t1) {
+    const uint32_t L = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t per = (a.ntiles + gridDim.x - 1) / gridDim.x;
+    t0 = L * per;
+    t1 = t0 + per < a.ntiles ? t0 + per : a.ntiles;
+}
+
+template <typename T, int FMT, bool STDPH, int NR, int EPI>
+__device__ void bhop_tile(const BArgs &a, const BSolve &S, const BTile &t) {
+    const Geom &g = S.g;
+    const size_t fs = (size_t)3 * g.Vh;
+    const size_t e = sizeof(T) * 2;
+    const bool hi = a.use_hi;
+    const void *links = hi ? S.hi_links : S.lo_links;
+    const void *phases = hi ? S.hi_phases : S.lo_phases;
+    const char *in = (const char *)a.field(S, a.f_in) + t.j0 * fs * e;
+    char *out = (char *)a.field(S, a.f_out) + t.j0 * fs * e;
+    const char *aux0 = (const char *)a.field(S, a.f_aux0) + t.j0 * fs * e;
+    const char *aux1 = EPI == EPI_RESID ? (const char *)S.b + t.j0 * fs * 16 : nullptr;
+    const uint32_t h = t.blk * kBlock + threadIdx.x;
+    double ps[NR], pc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) ps[j] = pc[j] = 0.0;
+    if (h < g.Vh) {
+        vec3<T> acc[NR];
+        hop_site<T, FMT, STDPH, NR>(g, a.out_parity, h, links, phases, in, fs, acc);
+        const T half = T(0.5);
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            const SysState &st = a.state[S.sys0 + t.j0 + j];
+            vec3<T> o;
+            if (EPI == EPI_PLAIN) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) o.c[c] = cscale(half, acc[j].c[c]);
+            } else if (EPI == EPI_NORMAL) {
+                const T d = (T)st.diag;
+                vec3<T> p = ld_v<T>(aux0, fs, g.Vh, j, h);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    o.c[c].re = d * p.c[c].re - half * acc[j].c[c].re;
+                    o.c[c].im = d * p.c[c].im - half * acc[j].c[c].im;
+                    pair_add(ps[j], pc[j], (double)p.c[c].re * (double)o.c[c].re, 0.0);
+                    pair_add(ps[j], pc[j], (double)p.c[c].im * (double)o.c[c].im, 0.0);
+                }
+            } else {  // EPI_RESID: FP64 only (aux1 = b, complex128)
+                if (!(st.flags & SYS_RU_PENDING)) continue;
+                const T d = (T)st.diag;
+                vec3<T> x = ld_v<T>(aux0, fs, g.Vh, j, h);
+                vec3<T> b = ld_v<T>(aux1, fs, g.Vh, j, h);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    o.c[c].re = b.c[c].re - (d * x.c[c].re - half * acc[j].c[c].re);
+                    o.c[c].im = b.c[c].im - (d * x.c[c].im - half * acc[j].c[c].im);
+                    pair_add(ps[j], pc[j], (double)o.c[c].re * (double)o.c[c].re +
+                                               (double)o.c[c].im * (double)o.c[c].im,
+                             0.0);
+                }
+            }
+            st_v<T>(out, fs, g.Vh, j, h, o);
+        }
+    }
+    if (EPI != EPI_PLAIN) {
+        __shared__ double sh_red[2 * kWaves];
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            block_sum_pair(ps[j], pc[j], sh_red);
+            if (threadIdx.x == 0) {
+                double *pj = a.partials + 2 * ((size_t)S.part0 + (size_t)(t.j0 + j) * S.nblk + t.blk);
+                pj[0] = ps[j];
+                pj[1] = pc[j];
+            }
+        }
+    }
+}
+
+template <typename T, int FMT, int EPI>
+__global__ __launch_bounds__(kBlock) void bhop_kernel(BArgs a) {
+    if (a.gate_running && a.ctl->n_running == 0) return;
+    uint32_t t0, t1;
+    tile_range(a, t0, t1);
+    for (uint32_t ti = t0; ti < t1; ++ti) {
+        const BTile t = a.tiles[ti];
+        const BSolve &S = a.solves[t.solve];
+        if (!tile_active(a, S, t)) continue;
+        const bool stdph = (a.use_hi ? S.hi_phases : S.lo_phases) == nullptr;
+        switch (t.nr * 2 + (stdph ? 1 : 0)) {
+            case 3: bhop_tile<T, FMT, true, 1, EPI>(a, S, t); break;
+            case 2: bhop_tile<T, FMT, false, 1, EPI>(a, S, t); break;
+            case 5: bhop_tile<T, FMT, true, 2, EPI>(a, S, t); break;
+            case 4: bhop_tile<T, FMT, false, 2, EPI>(a, S, t); break;
+            case 9: bhop_tile<T, FMT, true, 4, EPI>(a, S, t); break;
+            default: bhop_tile<T, FMT, false, 4, EPI>(a, S, t); break;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// vector kernels over tiles
+// ---------------------------------------------------------------------------
+
+// x += alpha p; r -= alpha q; partials of |r|^2  (running systems)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void bcg_update_kernel(BArgs a) {
+    if (a.gate_running && a.ctl->n_running == 0) return;
+    __shared__ double sh_red[2 * kWaves];
+    uint32_t t0, t1;
+    tile_range(a, t0, t1);
+    for (uint32_t ti = t0; ti < t1; ++ti) {
+        const BTile t = a.tiles[ti];
+        const BSolve &S = a.solves[t.solve];
+        if (!tile_active(a, S, t)) continue;
+        const size_t fs = (size_t)3 * S.g.Vh;
+        const uint32_t h = t.blk * kBlock + threadIdx.x;
+        for (int j = 0; j < t.nr; ++j) {
+            const int js = t.j0 + j;
+            const SysState &st = a.state[S.sys0 + js];
+            double ps = 0.0, pc = 0.0;
+            if ((st.flags & SYS_RUNNING) && h < S.g.Vh) {
+                const T al = (T)st.alpha;
+                for (int c = 0; c < 3; ++c) {
+                    const size_t i = js * fs + (size_t)c * S.g.Vh + h;
+                    cpx<T> x = ld_c<T>(S.xin, i), p = ld_c<T>(S.p, i), r = ld_c<T>(S.r, i),
+                           q = ld_c<T>(S.q, i);
+                    x.re += al * p.re;
+                    x.im += al * p.im;
+                    r.re -= al * q.re;
+                    r.im -= al * q.im;
+                    st_c<T>(S.xin, i, x);
+                    st_c<T>(S.r, i, r);
+                    pair_add(ps, pc, (double)r.re * (double)r.re + (double)r.im * (double)r.im,
+                             0.0);
+                }
+            }
+            block_sum_pair(ps, pc, sh_red);
+            if (threadIdx.x == 0) {
+                double *pj = a.partials + 2 * ((size_t)S.part0 + (size_t)js * S.nblk + t.blk);
+                pj[0] = ps;
+                pj[1] = pc;
+            }
+        }
+    }
+}
+
+// p = r + beta p  (running systems)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void bp_update_kernel(BArgs a) {
+    if (a.gate_running && a.ctl->n_running == 0) return;
+    uint32_t t0, t1;
+    tile_range(a, t0, t1);
+    for (uint32_t ti = t0; ti < t1; ++ti) {
+        const BTile t = a.tiles[ti];
+        const BSolve &S = a.solves[t.solve];
+        const size_t fs = (size_t)3 * S.g.Vh;
+        const uint32_t h = t.blk * kBlock + threadIdx.x;
+        if (h >= S.g.Vh) continue;
+        for (int j = 0; j < t.nr; ++j) {
+            const int js = t.j0 + j;
+            const SysState &st = a.state[S.sys0 + js];
+            if (!(st.flags & SYS_RUNNING)) continue;
+            const T be = (T)st.beta;
+            for (int c = 0; c < 3; ++c) {
+                const size_t i = js * fs + (size_t)c * S.g.Vh + h;
+                cpx<T> p = ld_c<T>(S.p, i), r = ld_c<T>(S.r, i);
+                p.re = r.re + be * p.re;
+                p.im = r.im + be * p.im;
+                st_c<T>(S.p, i, p);
+            }
+        }
+    }
+}
+
+// parked systems: x64 += x32, x32 = 0 (mixed mode)
+__global__ __launch_bounds__(kBlock) void bru_accumulate_kernel(BArgs a) {
+    uint32_t t0, t1;
+    tile_range(a, t0, t1);
+    for (uint32_t ti = t0; ti < t1; ++ti) {
+        const BTile t = a.tiles[ti];
+        const BSolve &S = a.solves[t.solve];
+        const size_t fs = (size_t)3 * S.g.Vh;
+        const uint32_t h = t.blk * kBlock + threadIdx.x;
+        if (h >= S.g.Vh) continue;
+        for (int j = 0; j < t.nr; ++j) {
+            const int js = t.j0 + j;
+            if (!(a.state[S.sys0 + js].flags & SYS_RU_PENDING)) continue;
+            for (int c = 0; c < 3; ++c) {
+                const size_t i = js * fs + (size_t)c * S.g.Vh + h;
+                cpx<float> xs = ld_c<float>(S.xin, i);
+                cpx<double> xd = ld_c<double>(S.x64, i);
+                xd.re += (double)xs.re;
+                xd.im += (double)xs.im;
+                st_c<double>(S.x64, i, xd);
+                st_c<float>(S.xin, i, cpx<float>{0.0f, 0.0f});
+            }
+        }
+    }
+}
+
+// resumed systems: r_inner = r64 (rounded); p = r_inner + beta p
+template <typename T>
+__global__ __launch_bounds__(kBlock) void bru_resume_kernel(BArgs a) {
+    uint32_t t0, t1;
+    tile_range(a, t0, t1);
+    for (uint32_t ti = t0; ti < t1; ++ti) {
+        const BTile t = a.tiles[ti];
+        const BSolve &S = a.solves[t.solve];
+        const size_t fs = (size_t)3 * S.g.Vh;
+        const uint32_t h = t.blk * kBlock + threadIdx.x;
+        if (h >= S.g.Vh) continue;
+        for (int j = 0; j < t.nr; ++j) {
+            const int js = t.j0 + j;
+            const SysState &st = a.state[S.sys0 + js];
+            if (!(st.flags & SYS_RESUME)) continue;
+            const T be = (T)st.beta;
+            for (int c = 0; c < 3; ++c) {
+                const size_t i = js * fs + (size_t)c * S.g.Vh + h;
+                cpx<double> rd = ld_c<double>(S.r64, i);
+                cpx<T> r{(T)rd.re, (T)rd.im};
+                if (S.r != S.r64) st_c<T>(S.r, i, r);
+                cpx<T> p = ld_c<T>(S.p, i);
+                p.re = r.re + be * p.re;
+                p.im = r.im + be * p.im;
+                st_c<T>(S.p, i, p);
+            }
+        }
+    }
+}
+
+// |b|^2 partials of every system (complex128 b)
+__global__ __launch_bounds__(kBlock) void bnorm_b_kernel(BArgs a) {
+    __shared__ double sh_red[2 * kWaves];
+    uint32_t t0, t1;
+    tile_range(a, t0, t1);
+    for (uint32_t ti = t0; ti < t1; ++ti) {
+        const BTile t = a.tiles[ti];
+        const BSolve &S = a.solves[t.solve];
+        const size_t fs = (size_t)3 * S.g.Vh;
+        const uint32_t h = t.blk * kBlock + threadIdx.x;
+        for (int j = 0; j < t.nr; ++j) {
+            const int js = t.j0 + j;
+            double ps = 0.0, pc = 0.0;
+            if (h < S.g.Vh)
+                for (int c = 0; c < 3; ++c) {
+                    cpx<double> v = ld_c<double>(S.b, js * fs + (size_t)c * S.g.Vh + h);
+                    pair_add(ps, pc, v.re * v.re, 0.0);
+                    pair_add(ps, pc, v.im * v.im, 0.0);
+                }
+            block_sum_pair(ps, pc, sh_red);
+            if (threadIdx.x == 0) {
+                double *pj = a.partials + 2 * ((size_t)S.part0 + (size_t)js * S.nblk + t.blk);
+                pj[0] = ps;
+                pj[1] = pc;
+            }
+        }
+    }
+}
+
+// One block per system: fixed-order compensated sum of its partials, then op.
+__global__ __launch_bounds__(kBlock) void bfinalize_kernel(BArgs a, int op) {
+    __shared__ double sh_s[kBlock];
+    __shared__ double sh_e[kBlock];
+    if (a.gate_running && a.ctl->n_running == 0) return;
+    const uint32_t sys = blockIdx.x;
+    const BSysRef ref = a.sysref[sys];
+    const BSolve &S = a.solves[ref.solve];
+    double tot = block_sum2_pairs(a.partials + 2 * ((size_t)S.part0 + (size_t)ref.j * S.nblk),
+                                  (int)S.nblk, sh_s, sh_e);
+    if (threadIdx.x == 0) finalize_one(op, a.ctl, a.state, nullptr, (int)sys, tot);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T, int FMT>
+static void bhop_launch(const BArgs &a, int epi, hipStream_t s) {
+    dim3 grid(a.grid);
+    if (epi == EPI_PLAIN)
+        bhop_kernel<T, FMT, EPI_PLAIN><<<grid, kBlock, 0, s>>>(a);
+    else if (epi == EPI_NORMAL)
+        bhop_kernel<T, FMT, EPI_NORMAL><<<grid, kBlock, 0, s>>>(a);
+    else
+        bhop_kernel<T, FMT, EPI_RESID><<<grid, kBlock, 0, s>>>(a);
+}
+
+int launch_bhop(const BArgs &a, int fmt, int epi, hipStream_t s) {
+    switch (fmt) {
+        case FMT_C128_18: bhop_launch<double, FMT_C128_18>(a, epi, s); return 0;
+        case FMT_C128_12: bhop_launch<double, FMT_C128_12>(a, epi, s); return 0;
+        case FMT_C64_12:
+            if (epi == EPI_RESID) return -1;
+            bhop_launch<float, FMT_C64_12>(a, epi, s);
+            return 0;
+        case FMT_BF16_12:
+            if (epi == EPI_RESID) return -1;
+            bhop_launch<float, FMT_BF16_12>(a, epi, s);
+            return 0;
+        default: return -1;
+    }
+}
+
+int launch_bfinalize(const BArgs &a, int op, hipStream_t s) {
+    bfinalize_kernel<<<dim3(a.nsys), kBlock, 0, s>>>(a, op);
+    return 0;
+}
+
+int launch_bcg_update(const BArgs &a, int fp64, hipStream_t s) {
+    if (fp64)
+        bcg_update_kernel<double><<<dim3(a.grid), kBlock, 0, s>>>(a);
+    else
+        bcg_update_kernel<float><<<dim3(a.grid), kBlock, 0, s>>>(a);
+    return 0;
+}
+
+int launch_bp_update(const BArgs &a, int fp64, hipStream_t s) {
+    if (fp64)
+        bp_update_kernel<double><<<dim3(a.grid), kBlock, 0, s>>>(a);
+    else
+        bp_update_kernel<float><<<dim3(a.grid), kBlock, 0, s>>>(a);
+    return 0;
+}
+
+int launch_bru_accumulate(const BArgs &a, hipStream_t s) {
+    bru_accumulate_kernel<<<dim3(a.grid), kBlock, 0, s>>>(a);
+    return 0;
+}
+
+int launch_bru_resume(const BArgs &a, int fp64, hipStream_t s) {
+    if (fp64)
+        bru_resume_kernel<double><<<dim3(a.grid), kBlock, 0, s>>>(a);
+    else
+        bru_resume_kernel<float><<<dim3(a.grid), kBlock, 0, s>>>(a);
+    return 0;
+}
+
+int launch_bnorm_b(const BArgs &a, hipStream_t s) {
+    bnorm_b_kernel<<<dim3(a.grid), kBlock, 0, s>>>(a);
+    return 0;
+}
+
+}  // namespace stg

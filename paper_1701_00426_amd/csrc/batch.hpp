@@ -1,0 +1,83 @@
+// batch.hpp -- tables of the uneven-batch CG (many lattices per launch).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.hpp"
+#include "solver_state.hpp"
+
+namespace stg {
+
+// One solve of the batch: its lattice, gauge fields and Krylov fields.
+struct BSolve {
+    Geom g;
+    const void *hi_links;
+    const void *hi_phases;
+    const void *lo_links;
+    const void *lo_phases;
+    const void *b;   // complex128 [nrhs][3][Vh]
+    void *x64;       // complex128 [nrhs][3][Vh]: the caller's x
+    void *xin;       // inner-precision solution (the caller's x in FP64 mode)
+    void *p, *r, *q, *t;  // inner precision
+    void *r64, *t64;      // FP64 residual and odd temporary (aliases in FP64 mode)
+    uint32_t sys0;   // global index of its first system
+    uint32_t nblk;   // blocks of kBlock sites
+    uint32_t part0;  // first partial pair of this solve: system j uses part0 + j*nblk
+    uint32_t nrhs;
+};
+
+// kBlock consecutive sites (block blk) of one solve for systems j0 .. j0+nr-1.
+struct BTile {
+    uint32_t solve;
+    uint32_t blk;
+    uint16_t j0;
+    uint16_t nr;  // 1, 2 or 4
+};
+
+struct BSysRef {
+    uint32_t solve;
+    uint32_t j;
+};
+
+enum BField { BF_X64 = 0, BF_XIN, BF_P, BF_R, BF_Q, BF_T, BF_R64, BF_T64, BF_B };
+
+struct BArgs {
+    const BSolve *solves;
+    const BTile *tiles;
+    const BSysRef *sysref;
+    SysState *state;  // [nsys]
+    Ctl *ctl;
+    double *partials;
+    uint32_t ntiles;
+    uint32_t nsys;
+    uint32_t grid;    // persistent grid size
+    int out_parity;
+    int use_hi;       // hop on the FP64 gauge field (true residual) or the inner one
+    int gate_running;
+    int f_in, f_out, f_aux0;  // BField selectors of the hop operands
+
+    __device__ __forceinline__ const void *field(const BSolve &S, int f) const {
+        switch (f) {
+            case BF_X64: return S.x64;
+            case BF_XIN: return S.xin;
+            case BF_P: return S.p;
+            case BF_R: return S.r;
+            case BF_Q: return S.q;
+            case BF_T: return S.t;
+            case BF_R64: return S.r64;
+            case BF_T64: return S.t64;
+            default: return S.b;
+        }
+    }
+};
+
+int launch_bhop(const BArgs &a, int fmt, int epi, hipStream_t s);
+int launch_bfinalize(const BArgs &a, int op, hipStream_t s);
+int launch_bcg_update(const BArgs &a, int fp64, hipStream_t s);
+int launch_bp_update(const BArgs &a, int fp64, hipStream_t s);
+int launch_bru_accumulate(const BArgs &a, hipStream_t s);
+int launch_bru_resume(const BArgs &a, int fp64, hipStream_t s);
+int launch_bnorm_b(const BArgs &a, hipStream_t s);
+
+}  // namespace stg

@@ -17,8 +17,10 @@
 #include <vector>
 
 #include "../../include/stagmi.h"
+#include "batch.hpp"
 #include "kernels.hpp"
 #include "solver_state.hpp"
+#include "tune.hpp"
 
 using namespace stg;
 
@@ -114,6 +116,17 @@ HopArgs base_hop(const Geom &g, const stg_gauge *gauge) {
     return a;
 }
 
+// Launches a hop with the launch shape the autotuner chose for this lattice,
+// format and chunk (process-wide defaults when it has not seen the key).
+int hop(HopArgs a, int fmt, int nr, int epi, hipStream_t stream) {
+    TuneChoice c;
+    if (tune_lookup(a.geom, fmt, nr, c)) {
+        a.xcd_remap = c.xcd_remap;
+        a.sites_per_thread = (uint32_t)c.sites_per_thread;
+    }
+    return launch_hop(a, fmt, nr, epi, stream);
+}
+
 // Largest supported chunk of fields for one kernel launch.
 int chunk_of(int remaining) {
     if (remaining >= 8) return 8;
@@ -132,7 +145,7 @@ int hop_plain(const Geom &g, const stg_gauge *gauge, int field, int nrhs, const 
         int nr = chunk_of(nrhs - j0);
         a.in = reinterpret_cast<const char *>(in) + j0 * fb;
         a.out = reinterpret_cast<char *>(out) + j0 * fb;
-        if (launch_hop(a, gauge->fmt, nr, EPI_PLAIN, stream)) return invalid("unsupported hop");
+        if (hop(a, gauge->fmt, nr, EPI_PLAIN, stream)) return invalid("unsupported hop");
         j0 += nr;
     }
     HIP_TRY(hipGetLastError());
@@ -243,13 +256,24 @@ struct CgProblem {
     }
 };
 
-int enqueue_inner_iteration(const CgProblem &P, const CgWork &w, hipStream_t s) {
+// One CG iteration for every chunk of systems that still has a running system in
+// the flags snapshot `st` (systems leave the running state only inside the
+// iteration, and re-enter it only through a reliable update, after which the host
+// reads fresh flags: a snapshot one chunk old never skips a running system).
+int enqueue_inner_iteration(const CgProblem &P, const CgWork &w, const std::vector<SysState> &st,
+                            hipStream_t s) {
     const bool f64 = P.mode == STG_CG_F64;
     const stg_gauge *gg = f64 ? P.hi : P.lo;
     const size_t fb = (size_t)3 * P.g.Vh * (f64 ? 16 : 8);
     void *xin = f64 ? P.x : w.x_in;
     for (int j0 = 0; j0 < P.nsys;) {
         const int nr = P.chunk(j0);
+        bool any = false;
+        for (int j = j0; j < j0 + nr; ++j) any = any || (st[j].flags & SYS_RUNNING);
+        if (!any) {
+            j0 += nr;
+            continue;
+        }
         const size_t o = j0 * fb;
         HopArgs a = base_hop(P.g, gg);
         a.gate_running = 1;
@@ -261,14 +285,14 @@ int enqueue_inner_iteration(const CgProblem &P, const CgWork &w, hipStream_t s) 
         a.op = OP_NONE;
         a.in = (const char *)w.p + o;
         a.out = (char *)w.t + o;
-        launch_hop(a, gg->fmt, nr, EPI_PLAIN, s);
+        hop(a, gg->fmt, nr, EPI_PLAIN, s);
         // q = diag p - D_eo t ; <p, q> -> alpha
         a.out_parity = 0;
         a.op = OP_ALPHA;
         a.in = (const char *)w.t + o;
         a.out = (char *)w.q + o;
         a.aux0 = (const char *)w.p + o;
-        launch_hop(a, gg->fmt, nr, EPI_NORMAL, s);
+        hop(a, gg->fmt, nr, EPI_NORMAL, s);
         // x += alpha p, r -= alpha q ; |r|^2 -> beta / park
         VecArgs v;
         std::memset(&v, 0, sizeof(v));
@@ -318,14 +342,14 @@ int enqueue_reliable_update(const CgProblem &P, const CgWork &w, hipStream_t s) 
         a.op = OP_NONE;
         a.in = (const char *)P.x + j0 * fb64;
         a.out = (char *)w.t64 + j0 * fb64;
-        launch_hop(a, P.hi->fmt, nr, EPI_PLAIN, s);
+        hop(a, P.hi->fmt, nr, EPI_PLAIN, s);
         a.out_parity = 0;
         a.op = OP_RU;
         a.in = (const char *)w.t64 + j0 * fb64;
         a.out = (char *)w.r64 + j0 * fb64;
         a.aux0 = (const char *)P.x + j0 * fb64;
         a.aux1 = P.b_at(j0, fb64);
-        launch_hop(a, P.hi->fmt, nr, EPI_RESID, s);
+        hop(a, P.hi->fmt, nr, EPI_RESID, s);
         v.r64 = (const char *)w.r64 + j0 * fb64;
         v.r = (char *)w.r + j0 * fbin;
         v.p = (char *)w.p + j0 * fbin;
@@ -373,6 +397,29 @@ int snapshot_wait(int nsys, int slot, std::vector<SysState> &st) {
     HIP_TRY(hipEventSynchronize(g_snap.ev[slot]));
     std::memcpy(st.data(), g_snap.buf + (size_t)slot * g_snap.cap, sizeof(SysState) * nsys);
     return STG_OK;
+}
+
+// Guards the host loops against a device state that stops advancing while some
+// system is still marked running (the loops decide from the per-system flags):
+// after kStallSnapshots snapshots without any change of the iteration counts or
+// flags the solve returns an error instead of waiting forever.
+constexpr int kStallSnapshots = 4;
+
+struct StallGuard {
+    long long last = -1;
+    int same = 0;
+    bool stalled(const std::vector<SysState> &st) {
+        long long sig = 0;
+        for (const SysState &q : st) sig = sig * 1000003LL + q.iter * 64LL + q.flags;
+        same = (sig == last) ? same + 1 : 0;
+        last = sig;
+        return same >= kStallSnapshots;
+    }
+};
+
+int stall_error() {
+    g_last_error = "the solver state stopped advancing with systems still running";
+    return STG_HIP_ERROR;
 }
 
 int read_states_n(const SysState *dev, int nsys, std::vector<SysState> &st, hipStream_t s) {
@@ -451,6 +498,7 @@ int run_cg(const CgProblem &P, const CgWork &w, stg_cg_stats *stats, hipStream_t
     rc = read_states(w, n, st, s);
     if (rc) return rc;
     int slot = 0, pend = -1;  // pend: slot of a queued snapshot not read yet
+    StallGuard guard;
     for (;;) {
         int running = 0, pending = 0;
         for (int j = 0; j < n; ++j) {
@@ -470,8 +518,12 @@ int run_cg(const CgProblem &P, const CgWork &w, stg_cg_stats *stats, hipStream_t
             continue;
         }
         if (running == 0) break;
+        if (guard.stalled(st)) {
+            (void)hipStreamSynchronize(s);
+            return stall_error();
+        }
         for (int i = 0; i < poll; ++i) {
-            rc = enqueue_inner_iteration(P, w, s);
+            rc = enqueue_inner_iteration(P, w, st, s);
             if (rc) return rc;
         }
         rc = snapshot_enqueue(w.state, n, slot, s);
@@ -606,13 +658,13 @@ int enqueue_ms_iteration(const Geom &g, const stg_gauge *gg, int f64, int nrhs, 
         a.op = OP_NONE;
         a.in = (const char *)w.p + o;
         a.out = (char *)w.t + o;
-        launch_hop(a, gg->fmt, nr, EPI_PLAIN, s);
+        hop(a, gg->fmt, nr, EPI_PLAIN, s);
         a.out_parity = 0;
         a.op = OP_MS_ALPHA;
         a.in = (const char *)w.t + o;
         a.out = (char *)w.q + o;
         a.aux0 = (const char *)w.p + o;
-        launch_hop(a, gg->fmt, nr, EPI_NORMAL, s);
+        hop(a, gg->fmt, nr, EPI_NORMAL, s);
         VecArgs v;
         std::memset(&v, 0, sizeof(v));
         v.Vh = g.Vh;
@@ -732,10 +784,15 @@ int run_mscg(const Geom &g, const stg_gauge *hi, const stg_gauge *lo, double mas
     // pipelined polling as in the CG loop (no reliable updates in this stage; the
     // iteration cap is enforced on the device)
     int slot = 0, pend = -1;
+    StallGuard guard;
     for (;;) {
         int running = 0;
         for (int j = 0; j < nrhs; ++j) running += (st[j].flags & SYS_RUNNING) ? 1 : 0;
         if (running == 0) break;
+        if (guard.stalled(st)) {
+            (void)hipStreamSynchronize(s);
+            return stall_error();
+        }
         for (int i = 0; i < poll; ++i) {
             rc = enqueue_ms_iteration(g, gg, f64, nrhs, nshift, w, s);
             if (rc) return rc;
@@ -795,6 +852,349 @@ int run_mscg(const Geom &g, const stg_gauge *hi, const stg_gauge *lo, double mas
             stats[i].seconds = secs;
         }
     return status;
+}
+
+
+// ---------------------------------------------------------------------------
+// uneven batch: many lattices per launch, CG iterations replayed from a hipGraph
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+    std::vector<BSolve> solves;
+    std::vector<BTile> tiles;
+    std::vector<BSysRef> sysref;
+    uint32_t nsys = 0, npairs = 0;
+    // device tables and state (in the workspace)
+    Ctl *ctl = nullptr;
+    SysState *state = nullptr;
+    BSolve *d_solves = nullptr;
+    BTile *d_tiles = nullptr;
+    BSysRef *d_sysref = nullptr;
+    double *partials = nullptr;
+    size_t bytes = 0;
+};
+
+// Persistent grid: enough blocks for 8 resident per CU on 256 CUs.
+constexpr uint32_t kBatchGrid = 2048;
+
+// Lays out the batch in ws (ws == nullptr: size only).  Tiles follow the solve
+// order, then the RHS chunks (4, 2, 1) of each solve, then the site blocks.
+int plan_batch(int nsolve, const stg_solve_desc *d, int mode, void *ws, BatchPlan &B) {
+    const bool f64 = mode == STG_CG_F64;
+    Carver c{reinterpret_cast<char *>(ws)};
+    B.solves.assign(nsolve, BSolve{});
+    B.tiles.clear();
+    B.sysref.clear();
+    uint32_t sys = 0, pairs = 0;
+    for (int i = 0; i < nsolve; ++i) {
+        Geom g;
+        if (!make_geom(&d[i].lat, g)) return invalid("batch: lattice extents must be even, >= 2");
+        if (d[i].nrhs < 1) return invalid("batch: nrhs < 1");
+        BSolve &S = B.solves[i];
+        S.g = g;
+        S.nrhs = (uint32_t)d[i].nrhs;
+        S.sys0 = sys;
+        S.nblk = site_blocks(g.Vh);
+        S.part0 = pairs;
+        pairs += S.nblk * S.nrhs;
+        for (int j = 0; j < d[i].nrhs; ++j) B.sysref.push_back(BSysRef{(uint32_t)i, (uint32_t)j});
+        sys += S.nrhs;
+        for (int j0 = 0; j0 < d[i].nrhs;) {
+            int rem = d[i].nrhs - j0;
+            int nr = rem >= 4 ? 4 : (rem >= 2 ? 2 : 1);
+            for (uint32_t blk = 0; blk < S.nblk; ++blk)
+                B.tiles.push_back(BTile{(uint32_t)i, blk, (uint16_t)j0, (uint16_t)nr});
+            j0 += nr;
+        }
+    }
+    B.nsys = sys;
+    B.npairs = pairs;
+    B.ctl = (Ctl *)c.take(sizeof(Ctl));
+    B.state = (SysState *)c.take(sizeof(SysState) * sys);
+    B.d_solves = (BSolve *)c.take(sizeof(BSolve) * nsolve);
+    B.d_tiles = (BTile *)c.take(sizeof(BTile) * B.tiles.size());
+    B.d_sysref = (BSysRef *)c.take(sizeof(BSysRef) * sys);
+    B.partials = (double *)c.take(sizeof(double) * 2 * (size_t)pairs);
+    for (int i = 0; i < nsolve; ++i) {
+        BSolve &S = B.solves[i];
+        const size_t n1 = (size_t)S.nrhs * 3 * S.g.Vh;
+        const size_t fin = n1 * (f64 ? 16 : 8);
+        S.hi_links = d[i].hi.links;
+        S.hi_phases = d[i].hi.phases;
+        S.lo_links = f64 ? nullptr : d[i].lo.links;
+        S.lo_phases = f64 ? nullptr : d[i].lo.phases;
+        S.b = d[i].b;
+        S.x64 = d[i].x;
+        S.p = c.take(fin);
+        S.r = c.take(fin);
+        S.q = c.take(fin);
+        S.t = c.take(fin);
+        if (f64) {
+            S.xin = d[i].x;
+            S.r64 = S.r;
+            S.t64 = S.t;
+        } else {
+            S.xin = c.take(fin);
+            S.r64 = c.take(n1 * 16);
+            S.t64 = c.take(n1 * 16);
+        }
+    }
+    B.bytes = c.off;
+    return STG_OK;
+}
+
+BArgs batch_args(const BatchPlan &B, int gate) {
+    BArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.solves = B.d_solves;
+    a.tiles = B.d_tiles;
+    a.sysref = B.d_sysref;
+    a.state = B.state;
+    a.ctl = B.ctl;
+    a.partials = B.partials;
+    a.ntiles = (uint32_t)B.tiles.size();
+    a.nsys = B.nsys;
+    a.grid = std::min<uint32_t>(kBatchGrid, a.ntiles);
+    a.gate_running = gate;
+    return a;
+}
+
+int enqueue_batch_iteration(const BatchPlan &B, int f64, int fmt_in, hipStream_t s) {
+    BArgs a = batch_args(B, 1);
+    a.use_hi = f64;
+    a.out_parity = 1;  // t = D_oe p
+    a.f_in = BF_P;
+    a.f_out = BF_T;
+    if (launch_bhop(a, fmt_in, EPI_PLAIN, s)) return invalid("batch hop");
+    a.out_parity = 0;  // q = diag p - D_eo t; <p, q>
+    a.f_in = BF_T;
+    a.f_out = BF_Q;
+    a.f_aux0 = BF_P;
+    launch_bhop(a, fmt_in, EPI_NORMAL, s);
+    launch_bfinalize(a, OP_ALPHA, s);
+    launch_bcg_update(a, f64, s);
+    launch_bfinalize(a, OP_BETA, s);
+    launch_bp_update(a, f64, s);
+    HIP_TRY(hipGetLastError());
+    return STG_OK;
+}
+
+int enqueue_batch_update(const BatchPlan &B, int f64, int fmt_hi, hipStream_t s) {
+    BArgs a = batch_args(B, 0);
+    if (!f64) launch_bru_accumulate(a, s);
+    a.use_hi = 1;
+    a.out_parity = 1;
+    a.f_in = BF_X64;
+    a.f_out = BF_T64;
+    launch_bhop(a, fmt_hi, EPI_PLAIN, s);
+    a.out_parity = 0;
+    a.f_in = BF_T64;
+    a.f_out = BF_R64;
+    a.f_aux0 = BF_X64;
+    launch_bhop(a, fmt_hi, EPI_RESID, s);
+    launch_bfinalize(a, OP_RU, s);
+    launch_bru_resume(a, f64, s);
+    HIP_TRY(hipGetLastError());
+    return STG_OK;
+}
+
+thread_local hipStream_t g_capture_stream = nullptr;
+
+int run_cg_batch(int nsolve, const stg_solve_desc *d, const stg_cg_params &prm, void *ws,
+                 stg_cg_stats *stats, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int mode = prm.mode;
+    const int f64 = mode == STG_CG_F64;
+    BatchPlan B;
+    int rc = plan_batch(nsolve, d, mode, ws, B);
+    if (rc) return rc;
+    const int fmt_hi = d[0].hi.fmt;
+    const int fmt_in = f64 ? fmt_hi : d[0].lo.fmt;
+    const int n = (int)B.nsys;
+    HIP_TRY(hipMemcpyAsync(B.d_solves, B.solves.data(), sizeof(BSolve) * nsolve,
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(B.d_tiles, B.tiles.data(), sizeof(BTile) * B.tiles.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(B.d_sysref, B.sysref.data(), sizeof(BSysRef) * n,
+                           hipMemcpyHostToDevice, s));
+    std::vector<SysState> st(n);
+    for (int k = 0; k < n; ++k) {
+        const stg_solve_desc &di = d[B.sysref[k].solve];
+        SysState &q = st[k];
+        std::memset(&q, 0, sizeof(q));
+        q.diag = di.mass * di.mass;
+        q.tol2bb = prm.tol * prm.tol;
+        q.delta2 = f64 ? 0.0 : prm.delta * prm.delta;
+        q.flags = SYS_RU_PENDING;
+        q.restart = prm.restart;
+        q.gid = k;
+        q.max_iter = prm.max_iter;
+    }
+    Ctl ctl0;
+    std::memset(&ctl0, 0, sizeof(ctl0));
+    HIP_TRY(hipMemcpyAsync(B.ctl, &ctl0, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(B.state, st.data(), sizeof(SysState) * n, hipMemcpyHostToDevice, s));
+    for (int i = 0; i < nsolve; ++i) {
+        const BSolve &S = B.solves[i];
+        const size_t fin = (size_t)S.nrhs * 3 * S.g.Vh * (f64 ? 16 : 8);
+        launch_zero(S.p, fin, s);
+        if (!f64) launch_zero(S.xin, fin, s);
+    }
+    {
+        BArgs a = batch_args(B, 0);
+        launch_bnorm_b(a, s);
+        launch_bfinalize(a, OP_INIT_BB, s);
+    }
+    HIP_TRY(hipGetLastError());
+    rc = read_states_n(B.state, n, st, s);
+    if (rc) return rc;
+    bool fix = false;
+    for (int k = 0; k < n; ++k) {
+        const BSolve &S = B.solves[B.sysref[k].solve];
+        const size_t fb = (size_t)3 * S.g.Vh * 16;
+        if (!(st[k].bb < 1.0e300)) {
+            fix = true;
+            st[k].flags = SYS_BREAKDOWN;
+            st[k].rr_true = st[k].bb;
+        } else if (!(st[k].bb > 0.0)) {
+            fix = true;
+            st[k].flags = SYS_DONE;
+            st[k].rr_true = 0.0;
+            launch_zero((char *)S.x64 + B.sysref[k].j * fb, fb, s);
+        }
+    }
+    if (fix) HIP_TRY(hipMemcpyAsync(B.state, st.data(), sizeof(SysState) * n, hipMemcpyHostToDevice, s));
+    rc = enqueue_batch_update(B, f64, fmt_hi, s);
+    if (rc) return rc;
+
+    // K inner iterations of the whole batch, captured once and replayed
+    int K = prm.poll_every > 0 ? prm.poll_every : 16;
+    if (!g_capture_stream) HIP_TRY(hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIP_TRY(hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < K; ++i) {
+        rc = enqueue_batch_iteration(B, f64, fmt_in, g_capture_stream);
+        if (rc) {
+            hipGraph_t junk;
+            (void)hipStreamEndCapture(g_capture_stream, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            return rc;
+        }
+    }
+    HIP_TRY(hipStreamEndCapture(g_capture_stream, &graph));
+    hipError_t ge = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ge != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(ge, "hipGraphInstantiate");
+    }
+    int replays = 0;
+    rc = snapshots_ready(n);
+    if (!rc) rc = read_states_n(B.state, n, st, s);
+    int slot = 0, pend = -1;
+    StallGuard guard;
+    while (!rc) {
+        int running = 0, pending = 0;
+        for (int k = 0; k < n; ++k) {
+            if (st[k].flags & SYS_RUNNING) ++running;
+            if (st[k].flags & SYS_RU_PENDING) ++pending;
+        }
+        if (pending) {
+            if (pend >= 0) {
+                rc = snapshot_wait(n, pend, st);
+                if (rc) break;
+                pend = -1;
+            }
+            rc = enqueue_batch_update(B, f64, fmt_hi, s);
+            if (!rc) rc = read_states_n(B.state, n, st, s);
+            continue;
+        }
+        if (running == 0) break;
+        if (guard.stalled(st)) {
+            rc = stall_error();
+            break;
+        }
+        hipError_t le = hipGraphLaunch(exec, s);
+        if (le != hipSuccess) {
+            rc = hip_fail(le, "hipGraphLaunch");
+            break;
+        }
+        ++replays;
+        rc = snapshot_enqueue(B.state, n, slot, s);
+        if (rc) break;
+        if (pend >= 0) rc = snapshot_wait(n, pend, st);
+        pend = slot;
+        slot ^= 1;
+    }
+    if (!rc) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
+    }
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (rc) return rc;
+    rc = read_states_n(B.state, n, st, s);
+    if (rc) return rc;
+    bool open = false;
+    for (int k = 0; k < n; ++k)
+        if (st[k].flags & (SYS_RUNNING | SYS_CAPPED)) {
+            st[k].flags = SYS_RU_PENDING;
+            st[k].restart = 1;
+            open = true;
+        }
+    if (open) {
+        HIP_TRY(hipMemcpyAsync(B.state, st.data(), sizeof(SysState) * n, hipMemcpyHostToDevice, s));
+        rc = enqueue_batch_update(B, f64, fmt_hi, s);
+        if (rc) return rc;
+        rc = read_states_n(B.state, n, st, s);
+        if (rc) return rc;
+    }
+    const double secs =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int status_all = STG_OK;
+    for (int k = 0; k < n; ++k) {
+        int stk = (st[k].flags & SYS_DONE) ? STG_OK
+                  : (st[k].flags & SYS_BREAKDOWN) ? STG_BREAKDOWN
+                                                  : STG_NOT_CONVERGED;
+        stats[k].iters = st[k].iter;
+        stats[k].reliable_updates = st[k].n_ru;
+        stats[k].status = stk;
+        stats[k].converged_iter = stk == STG_OK ? st[k].conv_iter : -1;
+        stats[k].true_rel_resid = st[k].bb > 0.0   ? std::sqrt(st[k].rr_true / st[k].bb)
+                                  : st[k].bb == 0.0 ? 0.0
+                                                    : std::nan("");
+        stats[k].seconds = secs;
+        if (stk == STG_BREAKDOWN || (stk == STG_NOT_CONVERGED && status_all == STG_OK))
+            status_all = stk;
+    }
+    (void)replays;
+    return status_all;
+}
+
+int check_batch(int nsolve, const stg_solve_desc *d, const stg_cg_params *prm) {
+    if (nsolve < 1 || !d) return invalid("batch: nsolve >= 1 and descs non-NULL");
+    if (!prm) return invalid("params is NULL");
+    if (prm->mode != STG_CG_F64 && prm->mode != STG_CG_MIXED) return invalid("unknown solver mode");
+    if (!(prm->tol > 0.0) || prm->max_iter < 1) return invalid("tol must be > 0, max_iter >= 1");
+    if (prm->mode == STG_CG_MIXED && !(prm->delta > 0.0 && prm->delta < 1.0))
+        return invalid("delta must be in (0, 1)");
+    for (int i = 0; i < nsolve; ++i) {
+        Geom g;
+        if (!make_geom(&d[i].lat, g)) return invalid("batch: lattice extents must be even, >= 2");
+        if (d[i].nrhs < 1) return invalid("batch: nrhs < 1");
+        int rc = check_gauge(g, &d[i].hi, STG_C128);
+        if (rc) return rc;
+        if (d[i].hi.fmt != d[0].hi.fmt) return invalid("batch: every hi gauge field has one format");
+        if (prm->mode == STG_CG_MIXED) {
+            rc = check_gauge(g, &d[i].lo, STG_C64);
+            if (rc) return rc;
+            if (d[i].lo.fmt != d[0].lo.fmt)
+                return invalid("batch: every lo gauge field has one format");
+        }
+        if (!aligned16(d[i].b) || !aligned16(d[i].x)) return invalid("batch: b or x misaligned");
+        const size_t fb = (size_t)d[i].nrhs * 3 * g.Vh * 16;
+        if (overlap(d[i].b, fb, d[i].x, fb)) return invalid("batch: b and x overlap");
+    }
+    return STG_OK;
 }
 
 }  // namespace
@@ -926,7 +1326,7 @@ int stg_apply_normal(const stg_lattice *lat, const stg_gauge *gauge, stg_field f
         a.in = (const char *)tmp_odd + j0 * f1;
         a.out = (char *)out_even + j0 * f1;
         a.aux0 = (const char *)in_even + j0 * f1;
-        launch_hop(a, gauge->fmt, nr, EPI_NORMAL, s);
+        hop(a, gauge->fmt, nr, EPI_NORMAL, s);
         j0 += nr;
     }
     HIP_TRY(hipGetLastError());
@@ -1031,5 +1431,107 @@ int multishift_cg_solve(const stg_lattice *lat, const stg_gauge *hi, const stg_g
     return run_mscg(g, hi, lo, mass, nshift, shifts, nrhs, b_even, x_even, *params, ws, stats,
                     (hipStream_t)stream);
 }
+
+int stg_batch_workspace_bytes(int nsolve, const stg_solve_desc *descs, int mode, size_t *bytes) {
+    if (!bytes) return invalid("bytes is NULL");
+    stg_cg_params prm;
+    stg_cg_default_params(&prm);
+    prm.mode = mode;
+    int rc = check_batch(nsolve, descs, &prm);
+    if (rc) return rc;
+    BatchPlan B;
+    rc = plan_batch(nsolve, descs, mode, nullptr, B);
+    if (rc) return rc;
+    *bytes = B.bytes;
+    return STG_OK;
+}
+
+int cg_solve_batch(int nsolve, const stg_solve_desc *descs, const stg_cg_params *params, void *ws,
+                   size_t ws_bytes, stg_cg_stats *stats, stg_stream_t stream) {
+    int rc = check_batch(nsolve, descs, params);
+    if (rc) return rc;
+    if (!stats) return invalid("stats is NULL");
+    if (!aligned16(ws)) return invalid("workspace NULL or misaligned");
+    BatchPlan B;
+    rc = plan_batch(nsolve, descs, params->mode, nullptr, B);
+    if (rc) return rc;
+    if (ws_bytes < B.bytes) return STG_WORKSPACE_TOO_SMALL;
+    for (int i = 0; i < nsolve; ++i) {
+        const Geom &g = B.solves[i].g;
+        const size_t fb = (size_t)descs[i].nrhs * 3 * g.Vh * 16;
+        if (overlap(ws, ws_bytes, descs[i].b, fb) || overlap(ws, ws_bytes, descs[i].x, fb))
+            return invalid("batch: workspace overlaps b or x");
+    }
+    return run_cg_batch(nsolve, descs, *params, ws, stats, (hipStream_t)stream);
+}
+
+int stg_autotune(const stg_lattice *lat, const stg_gauge *gauge, stg_field field, int nrhs,
+                 const void *in, void *out, const char *cache_path, stg_stream_t stream) {
+    Geom g;
+    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
+    if (field != STG_C128 && field != STG_C64) return invalid("unknown field type");
+    int rc = check_gauge(g, gauge, field);
+    if (rc) return rc;
+    if (nrhs < 1) return invalid("nrhs < 1");
+    if (!aligned16(in) || !aligned16(out)) return invalid("field NULL or not 16-byte aligned");
+    const size_t fb = (size_t)nrhs * 3 * g.Vh * field_elem(field);
+    if (overlap(in, fb, out, fb)) return invalid("input and output overlap");
+    hipStream_t s = (hipStream_t)stream;
+    const int nr = chunk_of(nrhs);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HopArgs a = base_hop(g, gauge);
+    a.out_parity = 0;
+    a.op = OP_NONE;
+    a.in = in;
+    a.out = out;
+    // repetitions: about 20 ms of work per candidate, at least 5
+    const double est_us = 1e-3 * (double)g.Vh * nr;  // ~1 ns per site and field
+    const int reps = (int)std::max(5.0, std::min(200.0, 20000.0 / std::max(est_us, 1.0)));
+    TuneChoice best{1, 1, 1e300};
+    const int spts[4] = {1, 2, 4, 8};
+    for (int xcd = 0; xcd < 2; ++xcd)
+        for (int si = 0; si < 4; ++si) {
+            a.xcd_remap = xcd;
+            a.sites_per_thread = (uint32_t)spts[si];
+            for (int w = 0; w < 2; ++w) launch_hop(a, gauge->fmt, nr, EPI_PLAIN, s);
+            HIP_TRY(hipEventRecord(e0, s));
+            for (int r = 0; r < reps; ++r) launch_hop(a, gauge->fmt, nr, EPI_PLAIN, s);
+            HIP_TRY(hipEventRecord(e1, s));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            const double us = 1e3 * ms / reps;
+            if (us < best.us) best = TuneChoice{xcd, spts[si], us};
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_TRY(hipGetLastError());
+    tune_store(g, gauge->fmt, nr, best);
+    if (cache_path && tune_append_file(cache_path, g, gauge->fmt, nr, best))
+        return invalid("cannot append to the autotune cache file");
+    return STG_OK;
+}
+
+int stg_autotune_load(const char *cache_path, int *loaded) {
+    if (!cache_path) return invalid("cache_path is NULL");
+    if (tune_load_file(cache_path, loaded)) return invalid("cannot read the autotune cache file");
+    return STG_OK;
+}
+
+int stg_autotune_lookup(const stg_lattice *lat, stg_link_fmt fmt, int nr, int *xcd_remap,
+                        int *sites_per_thread, double *us) {
+    Geom g;
+    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
+    TuneChoice c;
+    if (!tune_lookup(g, fmt, nr, c)) return STG_NOT_CONVERGED;
+    if (xcd_remap) *xcd_remap = c.xcd_remap;
+    if (sites_per_thread) *sites_per_thread = c.sites_per_thread;
+    if (us) *us = c.us;
+    return STG_OK;
+}
+
+void stg_autotune_clear(void) { tune_clear(); }
 
 }  // extern "C"

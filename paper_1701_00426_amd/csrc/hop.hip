@@ -24,6 +24,7 @@
 // solver_state.hpp.
 
 #include "device_common.hpp"
+#include "hop_core.hpp"
 #include "kernels.hpp"
 #include "solver_state.hpp"
 
@@ -46,43 +47,8 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
     for (uint32_t k = 0; k < a.sites_per_thread; ++k) {
     const uint32_t h = (blk * a.sites_per_thread + k) * kBlock + threadIdx.x;
     if (h < g.Vh) {
-        Site s = site_coords(g, P, h);
         vec3<T> acc[NR];
-#pragma unroll
-        for (int j = 0; j < NR; ++j)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) acc[j].c[c] = {T(0), T(0)};
-
-        // one direction at a time: the loads of two links and 2*NR neighbour
-        // vectors are in flight together, which bounds the register footprint
-#pragma unroll 1
-        for (int mu = 0; mu < 4; ++mu) {
-            const uint32_t hf = nb_fwd(g, s, h, mu);
-            const uint32_t hb = nb_bwd(g, s, h, mu);
-            const int sf = 2 * mu + P;       // U_mu(x) starts at x
-            const int sb = 2 * mu + (1 - P); // U_mu(x - mu) starts at x - mu
-            T pf, pb;
-            if (STDPH) {
-                pf = (T)std_phase(g, s, mu, false);
-                pb = (T)std_phase(g, s, mu, true);
-            } else {
-                const T *ph = reinterpret_cast<const T *>(a.phases);
-                pf = ph[(size_t)sf * g.Vh + h];
-                pb = ph[(size_t)sb * g.Vh + hb];
-            }
-            su3<T> uf = link_loader<T, FMT>::load(a.links, g.Vh, sf, h);
-#pragma unroll
-            for (int j = 0; j < NR; ++j) {
-                vec3<T> v = ld_v<T>(a.in, a.fstride, g.Vh, j, hf);
-                acc_mv(acc[j], pf, uf, v);
-            }
-            su3<T> ub = link_loader<T, FMT>::load(a.links, g.Vh, sb, hb);
-#pragma unroll
-            for (int j = 0; j < NR; ++j) {
-                vec3<T> v = ld_v<T>(a.in, a.fstride, g.Vh, j, hb);
-                acc_mdv(acc[j], -pb, ub, v);
-            }
-        }
+        hop_site<T, FMT, STDPH, NR>(g, P, h, a.links, a.phases, a.in, a.fstride, acc);
 
         const T half = T(0.5);
 #pragma unroll

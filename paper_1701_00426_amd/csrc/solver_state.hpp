@@ -84,7 +84,9 @@ enum FinOp {
 
 __device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < 1.0e300; }
 
-// Scalar step for system j after a reduction (one thread).
+// Scalar step for system j after a reduction (one thread).  Several blocks may run
+// it at once for different systems (the batched finalize), so the running count is
+// changed with atomics only.
 __device__ __forceinline__ void finalize_one(int op, Ctl *ctl, SysState *st, double *out, int j,
                                              double sum) {
     if (op == OP_STORE) {
@@ -103,7 +105,7 @@ __device__ __forceinline__ void finalize_one(int op, Ctl *ctl, SysState *st, dou
         if (!(s.flags & SYS_RUNNING)) return;
         if (!finite_pos(sum) || !(s.rr >= 0.0 && s.rr < 1.0e300)) {
             s.flags = SYS_BREAKDOWN;
-            ctl->n_running -= 1;
+            atomicAdd(&ctl->n_running, -1);
             return;
         }
         s.alpha = s.rr / sum;
@@ -114,7 +116,7 @@ __device__ __forceinline__ void finalize_one(int op, Ctl *ctl, SysState *st, dou
         s.iter += 1;
         if (!(sum >= 0.0 && sum < 1.0e300)) {
             s.flags = SYS_BREAKDOWN;
-            ctl->n_running -= 1;
+            atomicAdd(&ctl->n_running, -1);
             return;
         }
         if (sum > s.maxrr) s.maxrr = sum;
@@ -122,14 +124,14 @@ __device__ __forceinline__ void finalize_one(int op, Ctl *ctl, SysState *st, dou
             s.rr_old = s.rr;
             s.rr = sum;
             s.flags = SYS_RU_PENDING;
-            ctl->n_running -= 1;
+            atomicAdd(&ctl->n_running, -1);
             return;
         }
         s.beta = sum / s.rr;
         s.rr = sum;
         if (s.iter >= s.max_iter) {
             s.flags = SYS_CAPPED;
-            ctl->n_running -= 1;
+            atomicAdd(&ctl->n_running, -1);
         }
         return;
     }
@@ -137,7 +139,7 @@ __device__ __forceinline__ void finalize_one(int op, Ctl *ctl, SysState *st, dou
         if (!(s.flags & SYS_RUNNING)) return;
         if (!finite_pos(sum)) {
             s.flags = SYS_BREAKDOWN;
-            ctl->n_running -= 1;
+            atomicAdd(&ctl->n_running, -1);
             return;
         }
         const double a = s.rr / sum;
@@ -158,7 +160,7 @@ __device__ __forceinline__ void finalize_one(int op, Ctl *ctl, SysState *st, dou
         s.iter += 1;
         if (!(sum >= 0.0 && sum < 1.0e300)) {
             s.flags = SYS_BREAKDOWN;
-            ctl->n_running -= 1;
+            atomicAdd(&ctl->n_running, -1);
             return;
         }
         const double b = sum / s.rr;
@@ -182,10 +184,10 @@ __device__ __forceinline__ void finalize_one(int op, Ctl *ctl, SysState *st, dou
         if (sum <= s.tol2bb) {
             s.flags = SYS_DONE;
             s.conv_iter = s.iter;
-            ctl->n_running -= 1;
+            atomicAdd(&ctl->n_running, -1);
         } else if (s.iter >= s.max_iter) {
             s.flags = SYS_CAPPED;
-            ctl->n_running -= 1;
+            atomicAdd(&ctl->n_running, -1);
         }
         return;
     }
@@ -210,7 +212,7 @@ __device__ __forceinline__ void finalize_one(int op, Ctl *ctl, SysState *st, dou
         s.rr = sum;
         s.maxrr = sum;
         s.flags = SYS_RUNNING | SYS_RESUME;
-        ctl->n_running += 1;
+        atomicAdd(&ctl->n_running, 1);
         return;
     }
 }

@@ -1,0 +1,94 @@
+// tune.cpp -- launch-shape autotuner of the hop kernels.
+//
+// The paper picks its OpenACC tile sizes per architecture at compile time
+// (Sec. 4.3, TILE0..2; Sec. 5, "the best tile dimensions for each of them").
+// Here the launch shape of the hop is chosen at run time: for a (lattice, link
+// format, fields-per-launch) key the autotuner times every candidate shape on the
+// caller's buffers with HIP events, keeps the fastest in a process-wide table that
+// every hop launch consults, and appends it to a cache file (one JSON object per
+// line) that a later process can load.  Results never depend on the shape.
+
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "tune.hpp"
+
+namespace stg {
+
+namespace {
+
+using Key = std::tuple<uint32_t, uint32_t, uint32_t, uint32_t, int, int>;
+
+std::mutex g_mu;
+std::map<Key, TuneChoice> g_table;
+
+Key make_key(const Geom &g, int fmt, int nr) {
+    return Key(g.N[0], g.N[1], g.N[2], g.N[3], fmt, nr);
+}
+
+}  // namespace
+
+bool tune_lookup(const Geom &g, int fmt, int nr, TuneChoice &c) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_table.find(make_key(g, fmt, nr));
+    if (it == g_table.end()) return false;
+    c = it->second;
+    return true;
+}
+
+void tune_store(const Geom &g, int fmt, int nr, const TuneChoice &c) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table[make_key(g, fmt, nr)] = c;
+}
+
+void tune_clear() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table.clear();
+}
+
+int tune_append_file(const char *path, const Geom &g, int fmt, int nr, const TuneChoice &c) {
+    FILE *f = std::fopen(path, "a");
+    if (!f) return -1;
+    std::fprintf(f,
+                 "{\"arch\": \"gfx950\", \"dims\": [%u, %u, %u, %u], \"fmt\": %d, \"nr\": %d, "
+                 "\"xcd_remap\": %d, \"sites_per_thread\": %d, \"us\": %.3f}\n",
+                 g.N[0], g.N[1], g.N[2], g.N[3], fmt, nr, c.xcd_remap, c.sites_per_thread, c.us);
+    std::fclose(f);
+    return 0;
+}
+
+int tune_load_file(const char *path, int *loaded) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return -1;
+    char line[512];
+    int n = 0;
+    while (std::fgets(line, sizeof line, f)) {
+        unsigned d0, d1, d2, d3;
+        int fmt, nr, xcd, spt;
+        double us;
+        if (std::sscanf(line,
+                        "{\"arch\": \"gfx950\", \"dims\": [%u, %u, %u, %u], \"fmt\": %d, "
+                        "\"nr\": %d, \"xcd_remap\": %d, \"sites_per_thread\": %d, \"us\": %lf}",
+                        &d0, &d1, &d2, &d3, &fmt, &nr, &xcd, &spt, &us) != 9)
+            continue;
+        if ((xcd != 0 && xcd != 1) || (spt != 1 && spt != 2 && spt != 4 && spt != 8)) continue;
+        Geom g;
+        std::memset(&g, 0, sizeof g);
+        g.N[0] = d0;
+        g.N[1] = d1;
+        g.N[2] = d2;
+        g.N[3] = d3;
+        tune_store(g, fmt, nr, TuneChoice{xcd, spt, us});  // later lines win
+        ++n;
+    }
+    std::fclose(f);
+    if (loaded) *loaded = n;
+    return 0;
+}
+
+}  // namespace stg

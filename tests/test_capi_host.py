@@ -147,3 +147,41 @@ def test_product_does_not_import_oracle():
         if f.endswith((".py", ".c")):
             text = open(os.path.join(ROOT, "oracle", f)).read()
             assert "paper_1701_00426_amd" not in text and "stagmi" not in text, f
+
+
+def test_autotune_cache_roundtrip(lib, tmp_path):
+    """The cache file format is read back into the table; unknown keys report 1."""
+    lat = _lat((32, 32, 32, 32))
+    lib.stg_autotune_clear()
+    x, sp, us = ctypes.c_int(-1), ctypes.c_int(-1), ctypes.c_double(-1)
+    assert lib.stg_autotune_lookup(ctypes.byref(lat), 1, 1, ctypes.byref(x), ctypes.byref(sp),
+                                   ctypes.byref(us)) == 1
+    f = tmp_path / "tune.jsonl"
+    f.write_text(
+        '{"arch": "gfx950", "dims": [32, 32, 32, 32], "fmt": 1, "nr": 1, "xcd_remap": 0, '
+        '"sites_per_thread": 2, "us": 87.5}\n'
+        'not a line of the cache\n'
+        '{"arch": "gfx950", "dims": [32, 32, 32, 32], "fmt": 1, "nr": 1, "xcd_remap": 1, '
+        '"sites_per_thread": 4, "us": 80.25}\n'
+        '{"arch": "gfx950", "dims": [8, 8, 8, 8], "fmt": 2, "nr": 4, "xcd_remap": 1, '
+        '"sites_per_thread": 3, "us": 1.0}\n')
+    n = ctypes.c_int(0)
+    assert lib.stg_autotune_load(str(f).encode(), ctypes.byref(n)) == 0
+    assert n.value == 2  # the malformed line and the invalid sites-per-thread are skipped
+    assert lib.stg_autotune_lookup(ctypes.byref(lat), 1, 1, ctypes.byref(x), ctypes.byref(sp),
+                                   ctypes.byref(us)) == 0
+    assert (x.value, sp.value, us.value) == (1, 4, 80.25)
+    assert lib.stg_autotune_load(b"/nonexistent/file", ctypes.byref(n)) == -1
+    lib.stg_autotune_clear()
+    assert lib.stg_autotune_lookup(ctypes.byref(lat), 1, 1, ctypes.byref(x), ctypes.byref(sp),
+                                   ctypes.byref(us)) == 1
+
+
+def test_tuning_knobs(lib):
+    v = ctypes.c_int(-1)
+    assert lib.stg_get_tuning(0, ctypes.byref(v)) == 0 and v.value == 1
+    assert lib.stg_set_tuning(1, 3) == -1
+    assert lib.stg_set_tuning(1, 2) == 0
+    assert lib.stg_get_tuning(1, ctypes.byref(v)) == 0 and v.value == 2
+    assert lib.stg_set_tuning(1, 1) == 0
+    assert lib.stg_set_tuning(7, 1) == -1
