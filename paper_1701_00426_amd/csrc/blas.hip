@@ -4,9 +4,9 @@
 //
 // Every vector kernel fuses the axpy updates with the reduction that follows
 // them (|r|^2 after x += alpha p, r -= alpha q), so a CG iteration reads each
-// vector the minimum number of times.  Reductions: wave64 shuffle, LDS across
-// the four waves, one FP64 partial per block, and the last block to arrive sums
-// the partials with error-free transformations in a fixed order.
+// vector the minimum number of times.  Reductions: TwoSum per thread, wave64
+// shuffle and LDS pair tree, one (sum, error) pair per block, and a one-block
+// finalize kernel that adds the pairs in a fixed order and runs the scalar step.
 
 #include "device_common.hpp"
 #include "kernels.hpp"
@@ -14,7 +14,7 @@
 
 namespace stg {
 
-// x += alpha p; r -= alpha q; partial |r|^2; OP_BETA in the last block
+// x += alpha p; r -= alpha q; block partials of |r|^2 (OP_BETA in the finalize kernel)
 template <typename T, int NR>
 __global__ __launch_bounds__(kBlock) void cg_update_kernel(VecArgs a) {
     if (a.gate_running && a.ctl->n_running == 0) return;

@@ -187,7 +187,6 @@ struct CgWork {
     Ctl *ctl;
     SysState *state;
     double *partials;
-    double *sums;
     // inner precision (FP64 mode: double fields; MIXED: float fields)
     void *x_in, *p, *r, *q, *t;
     // FP64 fields for the true residual (MIXED only; F64 mode aliases r / t)
@@ -210,7 +209,6 @@ CgWork carve_cg(const Geom &g, int nsys, int mode, void *ws) {
     w.ctl = (Ctl *)c.take(sizeof(Ctl));
     w.state = (SysState *)c.take(sizeof(SysState) * (size_t)nsys);
     w.partials = (double *)c.take(sizeof(double) * partial_count(g));
-    w.sums = (double *)c.take(sizeof(double) * 16);
     if (mode == STG_CG_F64) {
         w.x_in = nullptr;  // the caller's x
         w.p = c.take(f64);

@@ -133,7 +133,7 @@ int launch_ms_p_update(const VecArgs &a, int fp64, int nr, hipStream_t stream);
 // dst (complex128) = src (complex64), n complex entries
 int launch_c64_to_c128(size_t n, const void *src, void *dst, hipStream_t stream);
 
-// sum_i conj(x_i) y_i over n complex entries of nvec vectors; the last block
+// sum_i conj(x_i) y_i over n complex entries of nvec vectors; the finalize kernel
 // applies op (OP_STORE into out as (re, im) pairs, or OP_INIT_BB on state).
 int launch_dot(int fp64, int nvec, size_t n, const void *x, const void *y, double *partials,
                Ctl *ctl, int op, SysState *state, double *out, hipStream_t stream);

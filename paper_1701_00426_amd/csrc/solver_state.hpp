@@ -1,10 +1,10 @@
 // solver_state.hpp -- per-system solver scalars kept on the device, and the scalar
-// step that the last block of a reduction kernel performs on them.
+// step that the finalize kernel of a reduction performs on them.
 //
 // The CG scalars alpha = |r|^2 / <p, A p> and beta = |r_new|^2 / |r|^2 (Sec. 2.2,
 // conjugate gradient on Eq. lineqeo) never leave the GPU during the iteration: the
-// block that finishes a reduction last computes them and the next kernel reads
-// them.  The host only polls the flags every few iterations.
+// finalize kernel that completes a reduction computes them and the next kernel
+// reads them.  The host only polls the flags every few iterations.
 //
 // Reliable updates (mixed precision): the inner recurrence runs until its
 // residual norm has dropped by delta relative to the largest one since the last

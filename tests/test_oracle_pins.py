@@ -164,3 +164,29 @@ def test_mscg_shift_order_independent(corc):
     x2, _, r2, _ = corc.mscg(dims, links, phases, 0.1, sh[perm], b, tol=1e-11)
     for j, k in enumerate(perm):
         assert pins.vec_rel(x2[j], x1[k]) < 1e-13
+
+
+try:
+    from hypothesis import given, settings
+    from hypothesis import strategies as hs
+except ImportError:  # pragma: no cover
+    given = None
+
+if given is not None:
+    _even = hs.sampled_from([2, 4, 6])
+
+    @settings(max_examples=25, deadline=None)
+    @given(n0=_even, n1=_even, n2=_even, n3=_even, seed=hs.integers(0, 2**31 - 1))
+    def test_random_shapes_anti_hermitian_and_n_version(corc, n0, n1, n2, n3, seed):
+        """Any even shape, any seed: anti-Hermiticity, gauge covariance on the NumPy
+        oracle, and NumPy == C oracle."""
+        dims = (n0, n1, n2, n3)
+        assert pins.anti_hermiticity(on.dslash, dims, seed=seed % 1000,
+                                     phases=on.standard_phases(dims)) < 1e-14
+        links = si.su3_links(dims, seed, 1)
+        phases = si.real_link_field(dims, seed, 2)
+        v = si.gaussian_field(dims, 1, seed, 3)[0]
+        for par in (0, 1):
+            assert pins.rel_err(corc.dslash(dims, links, phases, par, v),
+                                on.dslash(dims, links, phases, par, v)) < 1e-14
+        assert pins.gauge_covariance(on.dslash, dims, seed=seed % 997) < 1e-13
