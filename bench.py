@@ -215,6 +215,55 @@ def bench_batch():
     print(json.dumps(out), flush=True)
 
 
+# The paper's Table 3 lattices, written N0 x N1 x N2 x N3 with time last, and its
+# per-site times on other hardware [ns]: (K80 GPU SP, DP, P100 SP, DP).
+PAPER_TABLE3 = {(32, 32, 8, 32): (4.19, 8.51, 1.77, 3.07), (32, 32, 32, 8): (4.15, 8.39, 1.22, 2.48),
+                (24, 24, 24, 24): (4.43, 8.62, 1.58, 2.90), (32, 32, 32, 32): (4.02, 9.54, 1.32, 2.40),
+                (32, 32, 32, 36): (4.03, 8.48, 1.46, 2.54)}
+
+
+def bench_shapes():
+    """D_eo on the paper's Table 3 lattice shapes at FP64-12 and FP32-12: default launch
+    shape and the autotuner's choice; ns per site as (t(D_eo) + t(D_oe)) / V."""
+    import torch
+    import paper_1701_00426_amd as stg
+    import seeded_inputs as si
+    dev = torch.device("cuda:0")
+    rows = []
+    for dims, paper in PAPER_TABLE3.items():
+        vh = stg.half_volume(dims)
+        links = torch.from_numpy(si.su3_links(dims, 1701, 6, 0)).to(dev)
+        b = torch.from_numpy(si.gaussian_field(dims, 1, 426, 6, 0)).to(dev)
+        for fmt in ("c128_12", "c64_12"):
+            cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
+            gauges = [stg.pack_gauge(dims, links if i == 0 else links.clone(), fmt)
+                      for i in range(3)]
+            fields = [b.to(cdt).clone() for _ in range(3)]
+            outs = [torch.empty_like(fields[0]) for _ in range(3)]
+            stg.library().stg_autotune_clear()
+            t_def = time_applies(stg, torch, gauges, fields, outs, 0, 200)
+            t_def_oe = time_applies(stg, torch, gauges, fields, outs, 1, 200)
+            choice = stg.stg_autotune(gauges[0], 1)
+            t_tun = time_applies(stg, torch, gauges, fields, outs, 0, 200)
+            t_tun_oe = time_applies(stg, torch, gauges, fields, outs, 1, 200)
+            bps = BYTES_PER_SITE[fmt]
+            rows.append({"lattice": "x".join(map(str, dims)), "format": fmt,
+                         "deo_us_default": round(t_def * 1e6, 2),
+                         "GBs_default": round(bps * vh / t_def / 1e9, 1),
+                         "deo_us_tuned": round(t_tun * 1e6, 2),
+                         "GBs_tuned": round(bps * vh / t_tun / 1e9, 1),
+                         "tuned": {k: choice[k] for k in ("xcd_remap", "sites_per_thread")},
+                         "ns_per_site": round((t_tun + t_tun_oe) * 1e9 / (2 * vh), 4),
+                         "paper_ns_per_site_K80_P100": paper[1::2] if fmt == "c128_12"
+                         else paper[0::2]})
+            log(json.dumps(rows[-1]))
+            del gauges, fields, outs
+        del links
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": "paper Table 3 shapes, D_eo FP64-12 / FP32-12", "rows": rows}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,7 +275,8 @@ def main():
                     help="for rocprofv3: only the dominant kernel's timed loop (FP64-12 D_eo)")
     ap.add_argument("--profile-cg", action="store_true",
                     help="for rocprofv3: one FP64 CG and one mixed CG solve only")
-    ap.add_argument("--workload", choices=["main", "multishift", "batch"], default="main",
+    ap.add_argument("--workload", choices=["main", "multishift", "batch", "shapes"],
+                    default="main",
                     help="main: the 32^4 line; multishift: 24^3x48, 16 shifts x 8 RHS; "
                          "batch: 12 solves on 8^4 .. 32^4 in one cg_solve_batch")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -244,6 +294,9 @@ def main():
         return
     if args.workload == "batch":
         bench_batch()
+        return
+    if args.workload == "shapes":
+        bench_shapes()
         return
 
     import numpy as np

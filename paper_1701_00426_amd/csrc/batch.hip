@@ -6,9 +6,9 @@
 // tiles that spans all lattices of the batch: a tile is kBlock consecutive sites of
 // one lattice for a chunk of 1, 2 or 4 right-hand sides.  One launch per step
 // therefore serves every solve, small lattices ride along with large ones, and
-// the launch count does not grow with the number of solves.  Blocks walk
-// contiguous tile ranges (persistent grid), in XCD-aware order.  Solves that have
-// converged skip their tiles.
+// the launch count does not grow with the number of solves.  A persistent grid
+// deals the tiles round-robin in XCD-aware order; each kernel only touches tiles
+// holding a system in the state it acts on (running, parked or resumed).
 
 #include "batch.hpp"
 #include "device_common.hpp"
@@ -18,20 +18,21 @@
 
 namespace stg {
 
+// A tile is worked on when one of its systems has a flag of a.tile_mask (0: always).
 __device__ __forceinline__ bool tile_active(const BArgs &a, const BSolve &S, const BTile &t) {
-    if (!a.gate_running) return true;
+    if (!a.tile_mask) return true;
     for (int j = 0; j < t.nr; ++j)
-        if (a.state[S.sys0 + t.j0 + j].flags & SYS_RUNNING) return true;
+        if (a.state[S.sys0 + t.j0 + j].flags & a.tile_mask) return true;
     return false;
 }
 
-// Contiguous tile range of this block.
-__device__ __forceinline__ void tile_range(const BArgs &a, uint32_t &t0, uint32_t &t1) {
-    const uint32_t L = xcd_block(blockIdx.x, gridDim.x);
-    const uint32_t per = (a.ntiles + gridDim.x - 1) / gridDim.x;
-    t0 = L * per;
-    t1 = t0 + per < a.ntiles ? t0 + per : a.ntiles;
-}
+// Tiles are dealt to the blocks round-robin from the XCD-ordered logical block
+// index: in every round the blocks of one XCD take one contiguous run of tiles
+// (neighbour lines meet in that XCD's L2), and every block gets about the same
+// share of every solve, so the work stays balanced as solves finish.
+#define FOR_EACH_TILE(a, ti)                                              \
+    for (uint32_t ti = xcd_block(blockIdx.x, gridDim.x); ti < (a).ntiles; \
+         ti += gridDim.x)
 
 template <typename T, int FMT, bool STDPH, int NR, int EPI>
 __device__ void bhop_tile(const BArgs &a, const BSolve &S, const BTile &t) {
@@ -104,9 +105,7 @@ __device__ void bhop_tile(const BArgs &a, const BSolve &S, const BTile &t) {
 template <typename T, int FMT, int EPI>
 __global__ __launch_bounds__(kBlock) void bhop_kernel(BArgs a) {
     if (a.gate_running && a.ctl->n_running == 0) return;
-    uint32_t t0, t1;
-    tile_range(a, t0, t1);
-    for (uint32_t ti = t0; ti < t1; ++ti) {
+    FOR_EACH_TILE(a, ti) {
         const BTile t = a.tiles[ti];
         const BSolve &S = a.solves[t.solve];
         if (!tile_active(a, S, t)) continue;
@@ -131,9 +130,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void bcg_update_kernel(BArgs a) {
     if (a.gate_running && a.ctl->n_running == 0) return;
     __shared__ double sh_red[2 * kWaves];
-    uint32_t t0, t1;
-    tile_range(a, t0, t1);
-    for (uint32_t ti = t0; ti < t1; ++ti) {
+    FOR_EACH_TILE(a, ti) {
         const BTile t = a.tiles[ti];
         const BSolve &S = a.solves[t.solve];
         if (!tile_active(a, S, t)) continue;
@@ -173,14 +170,12 @@ __global__ __launch_bounds__(kBlock) void bcg_update_kernel(BArgs a) {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void bp_update_kernel(BArgs a) {
     if (a.gate_running && a.ctl->n_running == 0) return;
-    uint32_t t0, t1;
-    tile_range(a, t0, t1);
-    for (uint32_t ti = t0; ti < t1; ++ti) {
+    FOR_EACH_TILE(a, ti) {
         const BTile t = a.tiles[ti];
         const BSolve &S = a.solves[t.solve];
         const size_t fs = (size_t)3 * S.g.Vh;
         const uint32_t h = t.blk * kBlock + threadIdx.x;
-        if (h >= S.g.Vh) continue;
+        if (h >= S.g.Vh || !tile_active(a, S, t)) continue;
         for (int j = 0; j < t.nr; ++j) {
             const int js = t.j0 + j;
             const SysState &st = a.state[S.sys0 + js];
@@ -199,14 +194,12 @@ __global__ __launch_bounds__(kBlock) void bp_update_kernel(BArgs a) {
 
 // parked systems: x64 += x32, x32 = 0 (mixed mode)
 __global__ __launch_bounds__(kBlock) void bru_accumulate_kernel(BArgs a) {
-    uint32_t t0, t1;
-    tile_range(a, t0, t1);
-    for (uint32_t ti = t0; ti < t1; ++ti) {
+    FOR_EACH_TILE(a, ti) {
         const BTile t = a.tiles[ti];
         const BSolve &S = a.solves[t.solve];
         const size_t fs = (size_t)3 * S.g.Vh;
         const uint32_t h = t.blk * kBlock + threadIdx.x;
-        if (h >= S.g.Vh) continue;
+        if (h >= S.g.Vh || !tile_active(a, S, t)) continue;
         for (int j = 0; j < t.nr; ++j) {
             const int js = t.j0 + j;
             if (!(a.state[S.sys0 + js].flags & SYS_RU_PENDING)) continue;
@@ -226,14 +219,12 @@ __global__ __launch_bounds__(kBlock) void bru_accumulate_kernel(BArgs a) {
 // resumed systems: r_inner = r64 (rounded); p = r_inner + beta p
 template <typename T>
 __global__ __launch_bounds__(kBlock) void bru_resume_kernel(BArgs a) {
-    uint32_t t0, t1;
-    tile_range(a, t0, t1);
-    for (uint32_t ti = t0; ti < t1; ++ti) {
+    FOR_EACH_TILE(a, ti) {
         const BTile t = a.tiles[ti];
         const BSolve &S = a.solves[t.solve];
         const size_t fs = (size_t)3 * S.g.Vh;
         const uint32_t h = t.blk * kBlock + threadIdx.x;
-        if (h >= S.g.Vh) continue;
+        if (h >= S.g.Vh || !tile_active(a, S, t)) continue;
         for (int j = 0; j < t.nr; ++j) {
             const int js = t.j0 + j;
             const SysState &st = a.state[S.sys0 + js];
@@ -256,9 +247,7 @@ __global__ __launch_bounds__(kBlock) void bru_resume_kernel(BArgs a) {
 // |b|^2 partials of every system (complex128 b)
 __global__ __launch_bounds__(kBlock) void bnorm_b_kernel(BArgs a) {
     __shared__ double sh_red[2 * kWaves];
-    uint32_t t0, t1;
-    tile_range(a, t0, t1);
-    for (uint32_t ti = t0; ti < t1; ++ti) {
+    FOR_EACH_TILE(a, ti) {
         const BTile t = a.tiles[ti];
         const BSolve &S = a.solves[t.solve];
         const size_t fs = (size_t)3 * S.g.Vh;

@@ -54,7 +54,8 @@ struct BArgs {
     uint32_t grid;    // persistent grid size
     int out_parity;
     int use_hi;       // hop on the FP64 gauge field (true residual) or the inner one
-    int gate_running;
+    int gate_running;     // exit at once when ctl->n_running == 0
+    int tile_mask;        // work on a tile only when one of its systems has one of these flags
     int f_in, f_out, f_aux0;  // BField selectors of the hop operands
 
     __device__ __forceinline__ const void *field(const BSolve &S, int f) const {

@@ -940,7 +940,7 @@ int plan_batch(int nsolve, const stg_solve_desc *d, int mode, void *ws, BatchPla
     return STG_OK;
 }
 
-BArgs batch_args(const BatchPlan &B, int gate) {
+BArgs batch_args(const BatchPlan &B, int gate, int tile_mask) {
     BArgs a;
     std::memset(&a, 0, sizeof(a));
     a.solves = B.d_solves;
@@ -953,11 +953,12 @@ BArgs batch_args(const BatchPlan &B, int gate) {
     a.nsys = B.nsys;
     a.grid = std::min<uint32_t>(kBatchGrid, a.ntiles);
     a.gate_running = gate;
+    a.tile_mask = tile_mask;
     return a;
 }
 
 int enqueue_batch_iteration(const BatchPlan &B, int f64, int fmt_in, hipStream_t s) {
-    BArgs a = batch_args(B, 1);
+    BArgs a = batch_args(B, 1, SYS_RUNNING);
     a.use_hi = f64;
     a.out_parity = 1;  // t = D_oe p
     a.f_in = BF_P;
@@ -977,7 +978,7 @@ int enqueue_batch_iteration(const BatchPlan &B, int f64, int fmt_in, hipStream_t
 }
 
 int enqueue_batch_update(const BatchPlan &B, int f64, int fmt_hi, hipStream_t s) {
-    BArgs a = batch_args(B, 0);
+    BArgs a = batch_args(B, 0, SYS_RU_PENDING);
     if (!f64) launch_bru_accumulate(a, s);
     a.use_hi = 1;
     a.out_parity = 1;
@@ -990,6 +991,7 @@ int enqueue_batch_update(const BatchPlan &B, int f64, int fmt_hi, hipStream_t s)
     a.f_aux0 = BF_X64;
     launch_bhop(a, fmt_hi, EPI_RESID, s);
     launch_bfinalize(a, OP_RU, s);
+    a.tile_mask = SYS_RESUME;
     launch_bru_resume(a, f64, s);
     HIP_TRY(hipGetLastError());
     return STG_OK;
@@ -1038,7 +1040,7 @@ int run_cg_batch(int nsolve, const stg_solve_desc *d, const stg_cg_params &prm, 
         if (!f64) launch_zero(S.xin, fin, s);
     }
     {
-        BArgs a = batch_args(B, 0);
+        BArgs a = batch_args(B, 0, 0);
         launch_bnorm_b(a, s);
         launch_bfinalize(a, OP_INIT_BB, s);
     }
