@@ -124,9 +124,12 @@ const char *stg_last_error(void);
  *   STG_TUNE_SITES_PER_THREAD: 1 (default), 2, 4 or 8 output sites per thread
  *     (a block covers that many consecutive 256-site chunks): fewer, longer
  *     blocks, to balance the last wave of blocks against the chip's capacity.
+ *   STG_TUNE_STAGE_NEIGHBOURS: 0 (default) or 1: each block first copies the input
+ *     field over its sites and one x1 row on either side into LDS and reads the x0
+ *     and x1 neighbours from there (one or two fields per launch, N0 <= 128).
  * Returns STG_INVALID_ARG for an unknown key or value.
  */
-enum { STG_TUNE_XCD_REMAP = 0, STG_TUNE_SITES_PER_THREAD = 1 };
+enum { STG_TUNE_XCD_REMAP = 0, STG_TUNE_SITES_PER_THREAD = 1, STG_TUNE_STAGE_NEIGHBOURS = 2 };
 int stg_set_tuning(int key, int value);
 int stg_get_tuning(int key, int *value);
 
@@ -217,7 +220,8 @@ typedef struct {
     int mode;          /* STG_CG_F64 or STG_CG_MIXED */
     double delta;      /* reliable update when |r| < delta * max|r| since the last one (0.1) */
     int poll_every;    /* iterations enqueued between host convergence checks (0: auto) */
-    int restart;       /* 1: restart p = r at each reliable update, 0: keep p */
+    int restart;       /* 1: restart p = r at each reliable update, 0: keep p, -1: auto
+                          (restart when the lo gauge field is BF16-12, else keep p) */
 } stg_cg_params;
 
 typedef struct {
@@ -230,7 +234,7 @@ typedef struct {
 } stg_cg_stats;
 
 /* Fills p with the defaults: tol 1e-10, max_iter 100000, mode F64, delta 0.1,
-   poll_every 0 (auto), restart 0. */
+   poll_every 0 (auto), restart -1 (auto). */
 void stg_cg_default_params(stg_cg_params *p);
 
 /* Device workspace bytes needed by cg_solve (nshift = 0) or multishift_cg_solve. */

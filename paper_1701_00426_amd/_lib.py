@@ -31,6 +31,7 @@ STG_C64 = 1
 # tuning keys
 STG_TUNE_XCD_REMAP = 0
 STG_TUNE_SITES_PER_THREAD = 1
+STG_TUNE_STAGE_NEIGHBOURS = 2
 
 # solver modes
 STG_CG_F64 = 0

@@ -273,14 +273,13 @@ __global__ __launch_bounds__(kBlock) void bnorm_b_kernel(BArgs a) {
 
 // One block per system: fixed-order compensated sum of its partials, then op.
 __global__ __launch_bounds__(kBlock) void bfinalize_kernel(BArgs a, int op) {
-    __shared__ double sh_s[kBlock];
-    __shared__ double sh_e[kBlock];
-    if (a.gate_running && a.ctl->n_running == 0) return;
+    __shared__ double sh_red[2 * kWaves];
+    if (block_gate_closed(a.ctl, a.gate_running)) return;
     const uint32_t sys = blockIdx.x;
     const BSysRef ref = a.sysref[sys];
     const BSolve &S = a.solves[ref.solve];
     double tot = block_sum2_pairs(a.partials + 2 * ((size_t)S.part0 + (size_t)ref.j * S.nblk),
-                                  (int)S.nblk, sh_s, sh_e);
+                                  (int)S.nblk, sh_red);
     if (threadIdx.x == 0) finalize_one(op, a.ctl, a.state, nullptr, (int)sys, tot);
 }
 

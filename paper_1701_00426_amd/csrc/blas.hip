@@ -112,13 +112,11 @@ __global__ __launch_bounds__(kBlock) void ru_resume_kernel(VecArgs a) {
     }
 }
 
-// multi-shift (Sec. 2.2, Eq. shlineq): base residual update fused with the solution
-// step of every active shift; |r|^2 -> OP_MS_BETA
+// multi-shift (Sec. 2.2, Eq. shlineq): base residual r -= alpha q; |r|^2 -> OP_MS_BETA
 template <typename T, int NR>
 __global__ __launch_bounds__(kBlock) void ms_r_update_kernel(VecArgs a) {
     if (a.gate_running && a.ctl->n_running == 0) return;
     const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
-    const Ctl &ctl = *a.ctl;
     double ps[NR], pc[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
@@ -137,25 +135,13 @@ __global__ __launch_bounds__(kBlock) void ms_r_update_kernel(VecArgs a) {
             pair_add(ps[j], pc[j], (double)r.re * (double)r.re + (double)r.im * (double)r.im,
                      0.0);
         }
-        for (int k = 0; k < a.nshift; ++k) {
-            const ShiftState &z = ctl.ms[k * ctl.nrhs + s.gid];
-            if (!z.active) continue;
-            const T ak = (T)z.alpha;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const size_t i = (size_t)k * a.kstride + (size_t)j * a.fstride +
-                                 (size_t)c * a.Vh + h;
-                cpx<T> x = ld_c<T>(a.xs, i), p = ld_c<T>(a.ps, i);
-                x.re += ak * p.re;
-                x.im += ak * p.im;
-                st_c<T>(a.xs, i, x);
-            }
-        }
     }
     block_partials<NR>(ps, pc, a.partials);
 }
 
-// multi-shift: p = r + beta p;  p_k = zeta_k r + beta_k p_k for the active shifts
+// multi-shift, after beta: every shift that took part in this iteration steps
+// x_k += alpha_k p_k with its old p_k, then the still active ones p_k = zeta_k r +
+// beta_k p_k (one read of p_k for both); the base p = r + beta p.
 template <typename T, int NR>
 __global__ __launch_bounds__(kBlock) void ms_p_update_kernel(VecArgs a) {
     if (a.gate_running && a.ctl->n_running == 0) return;
@@ -165,30 +151,39 @@ __global__ __launch_bounds__(kBlock) void ms_p_update_kernel(VecArgs a) {
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         const SysState &s = a.state[j];
-        if (!(s.flags & SYS_RUNNING)) continue;
+        const bool running = (s.flags & SYS_RUNNING) != 0;
+        if (!running && !(s.flags & SYS_FINISHING)) continue;
         const T be = (T)s.beta;
         cpx<T> r[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const size_t i = (size_t)j * a.fstride + (size_t)c * a.Vh + h;
             r[c] = ld_c<T>(a.r, i);
-            cpx<T> p = ld_c<T>(a.p, i);
-            p.re = r[c].re + be * p.re;
-            p.im = r[c].im + be * p.im;
-            st_c<T>(a.p, i, p);
+            if (running) {
+                cpx<T> p = ld_c<T>(a.p, i);
+                p.re = r[c].re + be * p.re;
+                p.im = r[c].im + be * p.im;
+                st_c<T>(a.p, i, p);
+            }
         }
         for (int k = 0; k < a.nshift; ++k) {
             const ShiftState &z = ctl.ms[k * ctl.nrhs + s.gid];
             if (!z.active) continue;
-            const T zk = (T)z.zeta, bk = (T)z.beta;
+            const bool more = running && z.active == 1;
+            const T ak = (T)z.alpha, zk = (T)z.zeta, bk = (T)z.beta;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const size_t i = (size_t)k * a.kstride + (size_t)j * a.fstride +
                                  (size_t)c * a.Vh + h;
-                cpx<T> p = ld_c<T>(a.ps, i);
-                p.re = zk * r[c].re + bk * p.re;
-                p.im = zk * r[c].im + bk * p.im;
-                st_c<T>(a.ps, i, p);
+                cpx<T> p = ld_c<T>(a.ps, i), x = ld_c<T>(a.xs, i);
+                x.re += ak * p.re;
+                x.im += ak * p.im;
+                st_c<T>(a.xs, i, x);
+                if (more) {
+                    p.re = zk * r[c].re + bk * p.re;
+                    p.im = zk * r[c].im + bk * p.im;
+                    st_c<T>(a.ps, i, p);
+                }
             }
         }
     }
@@ -231,21 +226,21 @@ int launch_ms_r_update(const VecArgs &a, int fp64, int nr, hipStream_t stream) {
 }
 
 // ---------------------------------------------------------------------------
-// finishing the reductions: one block, fixed order, compensated
+// finishing the reductions: one block per system, fixed order, compensated
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void finalize_kernel(FinArgs f) {
-    __shared__ double sh_s[kBlock];
-    __shared__ double sh_e[kBlock];
-    if (f.gate_running && f.ctl->n_running == 0) return;
-    for (int j = 0; j < f.nr; ++j) {
-        double tot = block_sum2_pairs(f.partials + 2 * (size_t)j * f.nblocks, (int)f.nblocks,
-                                      sh_s, sh_e);
-        if (threadIdx.x == 0) finalize_one(f.op, f.ctl, f.state, f.out, j, tot);
-    }
+    __shared__ double sh_red[2 * kWaves];
+    if (block_gate_closed(f.ctl, f.gate_running)) return;
+    const int j = blockIdx.x;
+    double tot = block_sum2_pairs(f.partials + 2 * (size_t)j * f.nblocks, (int)f.nblocks, sh_red);
+    if (f.op == OP_MS_ALPHA || f.op == OP_MS_BETA)
+        finalize_ms_block(f.op, f.ctl, f.state, j, tot);
+    else if (threadIdx.x == 0)
+        finalize_one(f.op, f.ctl, f.state, f.out, j, tot);
 }
 
 int launch_finalize(const FinArgs &f, hipStream_t stream) {
-    finalize_kernel<<<1, kBlock, 0, stream>>>(f);
+    finalize_kernel<<<f.nr, kBlock, 0, stream>>>(f);
     return 0;
 }
 

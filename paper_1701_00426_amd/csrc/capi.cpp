@@ -31,6 +31,7 @@ thread_local std::string g_last_error;
 // launch-shape choice of the hop kernels (stg_set_tuning)
 int g_xcd_remap = 1;
 int g_sites_per_thread = 1;
+int g_stage_neighbours = 0;
 
 int hip_fail(hipError_t e, const char *what) {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
@@ -113,6 +114,7 @@ HopArgs base_hop(const Geom &g, const stg_gauge *gauge) {
     a.fstride = (size_t)3 * g.Vh;
     a.xcd_remap = g_xcd_remap;
     a.sites_per_thread = (uint32_t)g_sites_per_thread;
+    a.stage_neighbours = (uint32_t)g_stage_neighbours;
     return a;
 }
 
@@ -233,6 +235,15 @@ CgWork carve_cg(const Geom &g, int nsys, int mode, void *ws) {
 // ---------------------------------------------------------------------------
 // CG driver shared by cg_solve (and the refinement stage of the multi-shift solve)
 // ---------------------------------------------------------------------------
+// Restart choice of the reliable update: -1 (auto) restarts the search direction
+// when the inner operator stores its links in BF16, whose rounding error is large
+// enough that the kept direction loses conjugacy and stalls the iteration at small
+// mass; FP32 links keep the direction.
+int resolve_restart(int restart, int mode, const stg_gauge *lo) {
+    if (restart >= 0) return restart ? 1 : 0;
+    return (mode == STG_CG_MIXED && lo && lo->fmt == STG_LINK_BF16_12) ? 1 : 0;
+}
+
 struct CgProblem {
     Geom g;
     const stg_gauge *hi;
@@ -447,7 +458,7 @@ int run_cg(const CgProblem &P, const CgWork &w, stg_cg_stats *stats, hipStream_t
         q.tol2bb = P.prm.tol * P.prm.tol;  // times |b|^2 on the device
         q.delta2 = f64 ? 0.0 : P.prm.delta * P.prm.delta;
         q.flags = SYS_RU_PENDING;
-        q.restart = P.prm.restart;
+        q.restart = resolve_restart(P.prm.restart, P.mode, P.lo);
         q.gid = j;
         q.max_iter = P.prm.max_iter;
     }
@@ -785,7 +796,8 @@ int run_mscg(const Geom &g, const stg_gauge *hi, const stg_gauge *lo, double mas
     StallGuard guard;
     for (;;) {
         int running = 0;
-        for (int j = 0; j < nrhs; ++j) running += (st[j].flags & SYS_RUNNING) ? 1 : 0;
+        for (int j = 0; j < nrhs; ++j)
+            running += (st[j].flags & (SYS_RUNNING | SYS_FINISHING)) ? 1 : 0;
         if (running == 0) break;
         if (guard.stalled(st)) {
             (void)hipStreamSynchronize(s);
@@ -1025,7 +1037,7 @@ int run_cg_batch(int nsolve, const stg_solve_desc *d, const stg_cg_params &prm, 
         q.tol2bb = prm.tol * prm.tol;
         q.delta2 = f64 ? 0.0 : prm.delta * prm.delta;
         q.flags = SYS_RU_PENDING;
-        q.restart = prm.restart;
+        q.restart = resolve_restart(prm.restart, prm.mode, f64 ? nullptr : &di.lo);
         q.gid = k;
         q.max_iter = prm.max_iter;
     }
@@ -1231,6 +1243,10 @@ int stg_set_tuning(int key, int value) {
                 return invalid("sites per thread takes 1, 2, 4 or 8");
             g_sites_per_thread = value;
             return STG_OK;
+        case STG_TUNE_STAGE_NEIGHBOURS:
+            if (value != 0 && value != 1) return invalid("neighbour staging takes 0 or 1");
+            g_stage_neighbours = value;
+            return STG_OK;
         default: return invalid("unknown tuning key");
     }
 }
@@ -1240,6 +1256,7 @@ int stg_get_tuning(int key, int *value) {
     switch (key) {
         case STG_TUNE_XCD_REMAP: *value = g_xcd_remap; return STG_OK;
         case STG_TUNE_SITES_PER_THREAD: *value = g_sites_per_thread; return STG_OK;
+        case STG_TUNE_STAGE_NEIGHBOURS: *value = g_stage_neighbours; return STG_OK;
         default: return invalid("unknown tuning key");
     }
 }
@@ -1368,7 +1385,7 @@ void stg_cg_default_params(stg_cg_params *p) {
     p->mode = STG_CG_F64;
     p->delta = 0.1;
     p->poll_every = 0;
-    p->restart = 0;
+    p->restart = -1;
 }
 
 int stg_workspace_bytes(const stg_lattice *lat, int nrhs, int nshift, int mode, size_t *bytes) {

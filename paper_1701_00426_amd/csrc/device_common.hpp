@@ -366,25 +366,14 @@ __device__ __forceinline__ void block_sum_pair(double &s, double &c, double *scr
 
 // Compensated sum (Ogita-Rump-Oishi Sum2 order) of n (sum, error) pairs stored
 // interleaved at x, by the whole block; result valid in thread 0.  Fixed order:
-// thread t takes pairs t, t+B, ...; then a fixed pairwise tree in shared memory.
-__device__ double block_sum2_pairs(const double *x, int n, double *sh_s, double *sh_e) {
+// thread t takes pairs t, t+B, ... (loads unrolled so several are in flight),
+// then the fixed tree of block_sum_pair.  scratch: 2 * kWaves doubles of LDS.
+__device__ __forceinline__ double block_sum2_pairs(const double *x, int n, double *scratch) {
     double s = 0.0, c = 0.0;
+#pragma unroll 8
     for (int i = threadIdx.x; i < n; i += kBlock) pair_add(s, c, x[2 * i], x[2 * i + 1]);
-    sh_s[threadIdx.x] = s;
-    sh_e[threadIdx.x] = c;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            double a = sh_s[threadIdx.x], ca = sh_e[threadIdx.x];
-            pair_add(a, ca, sh_s[threadIdx.x + w], sh_e[threadIdx.x + w]);
-            sh_s[threadIdx.x] = a;
-            sh_e[threadIdx.x] = ca;
-        }
-        __syncthreads();
-    }
-    double r = sh_s[0] + sh_e[0];
-    __syncthreads();
-    return r;
+    block_sum_pair(s, c, scratch);
+    return s + c;
 }
 
 }  // namespace stg

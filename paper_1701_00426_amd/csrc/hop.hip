@@ -30,7 +30,7 @@
 
 namespace stg {
 
-template <typename T, int FMT, bool STDPH, int NR, int EPI>
+template <typename T, int FMT, bool STDPH, int NR, int EPI, bool STAGE>
 __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
     if (a.gate_running && a.ctl->n_running == 0) return;
 
@@ -45,10 +45,24 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
     // the block owns sites_per_thread consecutive chunks of kBlock sites
 #pragma unroll 1
     for (uint32_t k = 0; k < a.sites_per_thread; ++k) {
-    const uint32_t h = (blk * a.sites_per_thread + k) * kBlock + threadIdx.x;
-    if (h < g.Vh) {
-        vec3<T> acc[NR];
+    const uint32_t chunk0 = (blk * a.sites_per_thread + k) * kBlock;
+    const uint32_t h = chunk0 + threadIdx.x;
+    vec3<T> acc[NR];
+    if constexpr (STAGE) {
+        // the block's sites and one x1 row on either side, staged in LDS
+        __shared__ cpx<T> tile[NR][3][kStageMax];
+        const int64_t s0 = (int64_t)chunk0 - (int64_t)g.nh0;
+        const uint32_t len = kBlock + 2 * g.nh0;
+        if (k > 0) __syncthreads();  // the previous chunk's reads are done
+        stage_fill<T, NR>(tile, a.in, a.fstride, g.Vh, s0, len);
+        if (h < g.Vh) {
+            StagedNb<T, NR> nb{tile, s0, len, GlobalNb<T>{a.in, a.fstride, g.Vh}};
+            hop_site_nb<T, FMT, STDPH, NR>(g, P, h, a.links, a.phases, nb, acc);
+        }
+    } else if (h < g.Vh) {
         hop_site<T, FMT, STDPH, NR>(g, P, h, a.links, a.phases, a.in, a.fstride, acc);
+    }
+    if (h < g.Vh) {
 
         const T half = T(0.5);
 #pragma unroll
@@ -94,21 +108,31 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
+template <typename T, int FMT, bool STDPH, int NR, bool STAGE>
+static void launch_epi(const HopArgs &a, int epi, dim3 grid, hipStream_t stream) {
+    switch (epi) {
+        case EPI_PLAIN:
+            hop_kernel<T, FMT, STDPH, NR, EPI_PLAIN, STAGE><<<grid, kBlock, 0, stream>>>(a);
+            return;
+        case EPI_NORMAL:
+            hop_kernel<T, FMT, STDPH, NR, EPI_NORMAL, STAGE><<<grid, kBlock, 0, stream>>>(a);
+            return;
+        default:
+            hop_kernel<T, FMT, STDPH, NR, EPI_RESID, STAGE><<<grid, kBlock, 0, stream>>>(a);
+            return;
+    }
+}
+
 template <typename T, int FMT, bool STDPH, int NR>
 static void launch_nr(const HopArgs &a, int epi, hipStream_t stream) {
     const uint32_t chunk = kBlock * a.sites_per_thread;
     dim3 grid((a.geom.Vh + chunk - 1) / chunk);
-    switch (epi) {
-        case EPI_PLAIN:
-            hop_kernel<T, FMT, STDPH, NR, EPI_PLAIN><<<grid, kBlock, 0, stream>>>(a);
-            return;
-        case EPI_NORMAL:
-            hop_kernel<T, FMT, STDPH, NR, EPI_NORMAL><<<grid, kBlock, 0, stream>>>(a);
-            break;
-        default:
-            hop_kernel<T, FMT, STDPH, NR, EPI_RESID><<<grid, kBlock, 0, stream>>>(a);
-            break;
-    }
+    // LDS staging of the x0/x1 neighbours: one or two fields, rows of <= 64 half-sites
+    if (NR <= 2 && a.stage_neighbours && a.geom.nh0 <= (kStageMax - kBlock) / 2)
+        launch_epi<T, FMT, STDPH, NR, (NR <= 2)>(a, epi, grid, stream);
+    else
+        launch_epi<T, FMT, STDPH, NR, false>(a, epi, grid, stream);
+    if (epi == EPI_PLAIN) return;
     if (a.op != OP_NONE) {
         FinArgs f{a.partials, grid.x, NR, a.op, a.gate_running, a.ctl, a.state, a.out_sums};
         launch_finalize(f, stream);

@@ -24,10 +24,61 @@ struct HopUnroll {
 // acc[j] = sum_mu [ phi_mu(x) U_mu(x) in_j(x+mu) - phi_mu(x-mu) U_mu(x-mu)^dag in_j(x-mu) ]
 // for the output site x of parity P with half index h, and NR fields in_j stored
 // [NR][3][Vh] with stride fstride (the factor 1/2 is left to the caller).
-template <typename T, int FMT, bool STDPH, int NR>
-__device__ __forceinline__ void hop_site(const Geom &g, int P, uint32_t h, const void *links,
-                                         const void *phases, const void *in, size_t fstride,
-                                         vec3<T> (&acc)[NR]) {
+// Neighbour-field reads straight from global memory (L1/L2 serve the re-reads).
+template <typename T>
+struct GlobalNb {
+    const void *in;
+    size_t fstride;
+    uint32_t Vh;
+    __device__ __forceinline__ vec3<T> operator()(int j, uint32_t n) const {
+        return ld_v<T>(in, fstride, Vh, j, n);
+    }
+};
+
+// Neighbour-field reads from an LDS copy of the global index range [s0, s0 + len)
+// (the block's own sites and one x1 row on each side: every x0 and most x1
+// neighbours), from global memory outside it.
+constexpr uint32_t kStageMax = 384;  // staged sites per block: kBlock + 2 * nh0, nh0 <= 64
+
+template <typename T, int NR>
+struct StagedNb {
+    const cpx<T> (*tile)[3][kStageMax];
+    int64_t s0;
+    uint32_t len;
+    GlobalNb<T> glob;
+    __device__ __forceinline__ vec3<T> operator()(int j, uint32_t n) const {
+        const int64_t i = (int64_t)n - s0;
+        if (i >= 0 && i < (int64_t)len) {
+            vec3<T> v;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v.c[c] = tile[j][c][i];
+            return v;
+        }
+        return glob(j, n);
+    }
+};
+
+// Cooperative fill of the LDS copy by the whole block (followed by a barrier).
+template <typename T, int NR>
+__device__ __forceinline__ void stage_fill(cpx<T> (*tile)[3][kStageMax], const void *in,
+                                           size_t fstride, uint32_t Vh, int64_t s0,
+                                           uint32_t len) {
+    for (uint32_t i = threadIdx.x; i < len; i += kBlock) {
+        const int64_t n = s0 + (int64_t)i;
+        if (n < 0 || n >= (int64_t)Vh) continue;
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                tile[j][c][i] = ld_c<T>(in, (size_t)j * fstride + (size_t)c * Vh + (uint32_t)n);
+    }
+    __syncthreads();
+}
+
+template <typename T, int FMT, bool STDPH, int NR, typename NB>
+__device__ __forceinline__ void hop_site_nb(const Geom &g, int P, uint32_t h, const void *links,
+                                            const void *phases, const NB &nb,
+                                            vec3<T> (&acc)[NR]) {
     Site s = site_coords(g, P, h);
 #pragma unroll
     for (int j = 0; j < NR; ++j)
@@ -53,16 +104,23 @@ __device__ __forceinline__ void hop_site(const Geom &g, int P, uint32_t h, const
         su3<T> uf = link_loader<T, FMT>::load(links, g.Vh, sf, h);
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
-            vec3<T> v = ld_v<T>(in, fstride, g.Vh, j, hf);
+            vec3<T> v = nb(j, hf);
             acc_mv(acc[j], pf, uf, v);
         }
         su3<T> ub = link_loader<T, FMT>::load(links, g.Vh, sb, hb);
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
-            vec3<T> v = ld_v<T>(in, fstride, g.Vh, j, hb);
+            vec3<T> v = nb(j, hb);
             acc_mdv(acc[j], -pb, ub, v);
         }
     }
+}
+
+template <typename T, int FMT, bool STDPH, int NR>
+__device__ __forceinline__ void hop_site(const Geom &g, int P, uint32_t h, const void *links,
+                                         const void *phases, const void *in, size_t fstride,
+                                         vec3<T> (&acc)[NR]) {
+    hop_site_nb<T, FMT, STDPH, NR>(g, P, h, links, phases, GlobalNb<T>{in, fstride, g.Vh}, acc);
 }
 
 }  // namespace stg

@@ -26,7 +26,7 @@ struct HopArgs {
     int gate_running;     // exit at once when ctl->n_running == 0
     int xcd_remap;        // 1: blocks of one XCD take one contiguous range of sites
     uint32_t sites_per_thread;  // each block covers this many consecutive kBlock-site chunks
-    uint32_t pad_;
+    uint32_t stage_neighbours;  // 1: x0/x1 neighbour fields read from an LDS copy
     double diag;          // m^2 + sigma when state == nullptr
     SysState *state;      // per-field solver state, or nullptr
     Ctl *ctl;
@@ -126,9 +126,9 @@ int launch_ru_accumulate(const VecArgs &a, int nr, hipStream_t stream);
 // r_inner = r64 (rounded); p = r_inner + beta p  (systems just resumed)
 int launch_ru_resume(const VecArgs &a, int fp64, int nr, hipStream_t stream);
 
-// multi-shift: r -= alpha q, x_k += alpha_k p_k; |r|^2 -> OP_MS_BETA
+// multi-shift: r -= alpha q; |r|^2 -> OP_MS_BETA
 int launch_ms_r_update(const VecArgs &a, int fp64, int nr, hipStream_t stream);
-// multi-shift: p = r + beta p; p_k = zeta_k r + beta_k p_k
+// multi-shift: x_k += alpha_k p_k; p = r + beta p; p_k = zeta_k r + beta_k p_k
 int launch_ms_p_update(const VecArgs &a, int fp64, int nr, hipStream_t stream);
 // dst (complex128) = src (complex64), n complex entries
 int launch_c64_to_c128(size_t n, const void *src, void *dst, hipStream_t stream);

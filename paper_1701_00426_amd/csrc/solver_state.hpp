@@ -23,7 +23,9 @@ enum SysFlags : int {
     SYS_DONE = 4,        // true residual met the target
     SYS_BREAKDOWN = 8,   // non-finite scalar or <p, A p> <= 0
     SYS_RESUME = 16,     // just updated: the resume kernel rebuilds r_inner and p
-    SYS_CAPPED = 32      // stopped by the iteration cap (not converged)
+    SYS_CAPPED = 32,     // stopped by the iteration cap (not converged)
+    SYS_FINISHING = 64   // multi-shift base: stopped this iteration, the shifted solutions
+                         // still take this iteration's step; final_flags follows
 };
 
 struct SysState {
@@ -44,7 +46,7 @@ struct SysState {
     int restart;     // 1: p = r after each update
     int gid;         // index of this system in the solve (multi-shift: the RHS index)
     int max_iter;    // iteration cap: the system stops (SYS_CAPPED) when iter reaches it
-    int pad_;
+    int final_flags; // multi-shift: flags a finishing base system takes next
     double alpha_prev;  // multi-shift base scalars of the previous iteration
     double beta_prev;
 };
@@ -58,7 +60,8 @@ struct ShiftState {
     double zeta_next;  // zeta of the next iteration (set after alpha is known)
     double alpha;      // alpha_k of the current iteration
     double beta;       // beta_k of the current iteration
-    int active;        // 1 running, 0 retired
+    int active;        // 1 running, 2 retired this iteration (its x_k still takes the
+                       // step), 0 retired
     int conv_iter;     // base iteration at which it retired
 };
 
@@ -81,6 +84,17 @@ enum FinOp {
     OP_MS_ALPHA = 6, // multi-shift: base alpha, then zeta_next and alpha_k of every shift
     OP_MS_BETA = 7   // multi-shift: base beta, then beta_k, zeta shift and retirement
 };
+
+// Gate of the kernels that finish reductions: other blocks of the same launch may
+// change the running count meanwhile, so one thread reads it and the whole block
+// takes the same branch (every wave then reaches the same barriers).  A block whose
+// system is still counted as running always finds the count above zero.
+__device__ __forceinline__ bool block_gate_closed(const Ctl *ctl, int gate) {
+    __shared__ int closed;
+    if (threadIdx.x == 0) closed = (gate && ctl->n_running == 0) ? 1 : 0;
+    __syncthreads();
+    return closed != 0;
+}
 
 __device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < 1.0e300; }
 
@@ -135,62 +149,6 @@ __device__ __forceinline__ void finalize_one(int op, Ctl *ctl, SysState *st, dou
         }
         return;
     }
-    if (op == OP_MS_ALPHA) {
-        if (!(s.flags & SYS_RUNNING)) return;
-        if (!finite_pos(sum)) {
-            s.flags = SYS_BREAKDOWN;
-            atomicAdd(&ctl->n_running, -1);
-            return;
-        }
-        const double a = s.rr / sum;
-        s.alpha = a;
-        for (int k = 0; k < ctl->nshift; ++k) {
-            ShiftState &z = ctl->ms[k * ctl->nrhs + s.gid];
-            if (!z.active) continue;
-            // three-term recurrence of CG on A + sigma_0 matched on A + sigma_k
-            const double den = a * s.beta_prev * (z.zeta_prev - z.zeta) +
-                               z.zeta_prev * s.alpha_prev * (1.0 + z.delta * a);
-            z.zeta_next = z.zeta * z.zeta_prev * s.alpha_prev / den;
-            z.alpha = a * z.zeta_next / z.zeta;
-        }
-        return;
-    }
-    if (op == OP_MS_BETA) {
-        if (!(s.flags & SYS_RUNNING)) return;
-        s.iter += 1;
-        if (!(sum >= 0.0 && sum < 1.0e300)) {
-            s.flags = SYS_BREAKDOWN;
-            atomicAdd(&ctl->n_running, -1);
-            return;
-        }
-        const double b = sum / s.rr;
-        s.beta = b;
-        s.alpha_prev = s.alpha;
-        s.beta_prev = b;
-        s.rr = sum;
-        for (int k = 0; k < ctl->nshift; ++k) {
-            ShiftState &z = ctl->ms[k * ctl->nrhs + s.gid];
-            if (!z.active) continue;
-            const double ratio = z.zeta_next / z.zeta;
-            z.beta = b * ratio * ratio;
-            z.zeta_prev = z.zeta;
-            z.zeta = z.zeta_next;
-            // |r_k| = |zeta| |r|: this shift is solved (its x_k took this step already)
-            if (z.zeta * z.zeta * sum <= s.tol2bb) {
-                z.active = 0;
-                z.conv_iter = s.iter;
-            }
-        }
-        if (sum <= s.tol2bb) {
-            s.flags = SYS_DONE;
-            s.conv_iter = s.iter;
-            atomicAdd(&ctl->n_running, -1);
-        } else if (s.iter >= s.max_iter) {
-            s.flags = SYS_CAPPED;
-            atomicAdd(&ctl->n_running, -1);
-        }
-        return;
-    }
     if (op == OP_RU) {
         if (!(s.flags & SYS_RU_PENDING)) return;
         s.n_ru += 1;
@@ -214,6 +172,84 @@ __device__ __forceinline__ void finalize_one(int op, Ctl *ctl, SysState *st, dou
         s.flags = SYS_RUNNING | SYS_RESUME;
         atomicAdd(&ctl->n_running, 1);
         return;
+    }
+}
+
+// Multi-shift scalar steps for system j, by the whole block: thread 0 takes the
+// base system's step, then thread k < nshift that of shift k (the recurrences of
+// different shifts are independent).  Every thread of the block must call it;
+// sum is read in thread 0 only.
+enum MsMode { MS_SKIP = 0, MS_RUN = 1, MS_FINISH = 2 };
+
+__device__ __forceinline__ void finalize_ms_block(int op, Ctl *ctl, SysState *st, int j,
+                                                  double sum) {
+    __shared__ int mode;
+    __shared__ double sh_sum;
+    SysState &s = st[j];
+    if (threadIdx.x == 0) {
+        sh_sum = sum;
+        mode = MS_SKIP;
+        if (op == OP_MS_ALPHA) {
+            if (s.flags & SYS_FINISHING) {
+                // the base stopped last iteration and every x_k took its last step
+                s.flags = s.final_flags;
+                atomicAdd(&ctl->n_running, -1);
+                mode = MS_FINISH;
+            } else if (s.flags & SYS_RUNNING) {
+                if (!finite_pos(sum)) {
+                    s.flags = SYS_BREAKDOWN;
+                    atomicAdd(&ctl->n_running, -1);
+                } else {
+                    s.alpha = s.rr / sum;
+                    mode = MS_RUN;
+                }
+            }
+        } else if (s.flags & SYS_RUNNING) {  // OP_MS_BETA
+            s.iter += 1;
+            if (!(sum >= 0.0 && sum < 1.0e300)) {
+                s.flags = SYS_BREAKDOWN;
+                atomicAdd(&ctl->n_running, -1);
+            } else {
+                const double b = sum / s.rr;
+                s.beta = b;
+                s.alpha_prev = s.alpha;
+                s.beta_prev = b;
+                s.rr = sum;
+                if (sum <= s.tol2bb || s.iter >= s.max_iter) {
+                    s.final_flags = sum <= s.tol2bb ? SYS_DONE : SYS_CAPPED;
+                    if (sum <= s.tol2bb) s.conv_iter = s.iter;
+                    s.flags = SYS_FINISHING;  // still counted as running until the next alpha
+                }
+                mode = MS_RUN;
+            }
+        }
+    }
+    __syncthreads();  // also makes thread 0's state writes visible to the block
+    const int m = mode;
+    sum = sh_sum;
+    for (int k = threadIdx.x; k < ctl->nshift && m != MS_SKIP; k += blockDim.x) {
+        ShiftState &z = ctl->ms[k * ctl->nrhs + s.gid];
+        if (op == OP_MS_ALPHA) {
+            if (z.active == 2) z.active = 0;
+            if (m != MS_RUN || z.active != 1) continue;
+            // three-term recurrence of CG on A + sigma_0 matched on A + sigma_k
+            const double a = s.alpha;
+            const double den = a * s.beta_prev * (z.zeta_prev - z.zeta) +
+                               z.zeta_prev * s.alpha_prev * (1.0 + z.delta * a);
+            z.zeta_next = z.zeta * z.zeta_prev * s.alpha_prev / den;
+            z.alpha = a * z.zeta_next / z.zeta;
+        } else {
+            if (z.active != 1) continue;
+            const double ratio = z.zeta_next / z.zeta;
+            z.beta = s.beta * ratio * ratio;
+            z.zeta_prev = z.zeta;
+            z.zeta = z.zeta_next;
+            // |r_k| = |zeta| |r|: solved; x_k still takes this iteration's step
+            if (z.zeta * z.zeta * sum <= s.tol2bb) {
+                z.active = 2;
+                z.conv_iter = s.iter;
+            }
+        }
     }
 }
 

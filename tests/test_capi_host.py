@@ -185,3 +185,17 @@ def test_tuning_knobs(lib):
     assert lib.stg_get_tuning(1, ctypes.byref(v)) == 0 and v.value == 2
     assert lib.stg_set_tuning(1, 1) == 0
     assert lib.stg_set_tuning(7, 1) == -1
+    # neighbour staging: 0 or 1, off by default
+    assert lib.stg_get_tuning(2, ctypes.byref(v)) == 0 and v.value == 0
+    assert lib.stg_set_tuning(2, 2) == -1
+    assert lib.stg_set_tuning(2, 1) == 0
+    assert lib.stg_get_tuning(2, ctypes.byref(v)) == 0 and v.value == 1
+    assert lib.stg_set_tuning(2, 0) == 0
+
+
+def test_cg_default_params(lib):
+    from paper_1701_00426_amd import _lib
+    p = _lib.StgCgParams()
+    lib.stg_cg_default_params(ctypes.byref(p))
+    assert p.tol == 1e-10 and p.max_iter == 100000 and p.mode == 0
+    assert p.delta == 0.1 and p.poll_every == 0 and p.restart == -1

@@ -69,6 +69,43 @@ def test_hop_parity(dims, fmt, corc):
         assert err <= TOL[fmt]
 
 
+@pytest.fixture
+def staged_neighbours():
+    key = stg._lib.STG_TUNE_STAGE_NEIGHBOURS
+    old = stg.stg_get_tuning(key)
+    stg.stg_set_tuning(key, 1)
+    yield
+    stg.stg_set_tuning(key, old)
+
+
+@pytest.mark.parametrize("spt", [1, 2])
+@pytest.mark.parametrize("nrhs", [1, 2, 3])
+@pytest.mark.parametrize("fmt", ["c128_18", "c128_12", "c64_12", "bf16_12"])
+@pytest.mark.parametrize("dims", [(4, 6, 8, 10), (6, 4, 2, 10), (2, 2, 2, 2), (16, 2, 18, 2),
+                                  (128, 2, 2, 4), (132, 2, 2, 2)])
+def test_hop_staged_neighbours(dims, fmt, nrhs, spt, corc, staged_neighbours):
+    """The hop with x0/x1 neighbours read from an LDS copy of the block's rows
+    (one or two fields per launch, N0 <= 128; wider rows fall back to the plain
+    kernel) against the oracle, with one and two chunks of sites per block."""
+    say(f"hop staged {fmt} {dims} nrhs={nrhs} spt={spt}")
+    key = stg._lib.STG_TUNE_SITES_PER_THREAD
+    old = stg.stg_get_tuning(key)
+    stg.stg_set_tuning(key, spt)
+    try:
+        links = si.su3_links(dims, 1701, 8, 0)
+        phases = on.standard_phases(dims)
+        g = stg.pack_gauge(dims, to_dev(links), fmt)
+        cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
+        for par, fn in ((0, stg.dirac_apply_eo), (1, stg.dirac_apply_oe)):
+            v = si.gaussian_field(dims, nrhs, 426, 8, par)
+            got = fn(g, to_dev(v).to(cdt)).cpu().numpy().astype(np.complex128)
+            want = corc.dslash(dims, links, phases, par, v)
+            for j in range(nrhs):
+                assert rel_max(got[j], want[j]) <= TOL[fmt]
+    finally:
+        stg.stg_set_tuning(key, old)
+
+
 @pytest.mark.parametrize("fmt", ["c128_12", "c64_12"])
 def test_hop_explicit_phases(fmt, corc):
     """Arbitrary real per-link phases read from memory (the paper's backfield array)."""
