@@ -8,8 +8,9 @@ m = 0.01, one complex Gaussian even-site right-hand side.
     storage), algorithmic bytes / mean kernel duration, measured with HIP events
     on the library's stream over back-to-back applies that rotate through three
     link/field copies (1.36 GB working set, above the 256 MB Infinity Cache).
-  * a step: one FP64 CG solve and one mixed-precision CG solve (FP32-12 links,
-    FP64 reliable updates) of (m^2 - D_eo D_oe) x = b to |r|/|b| <= 1e-10.
+  * a step: CG solves of (m^2 - D_eo D_oe) x = b to |r|/|b| <= 1e-10: FP64; mixed
+    precision with FP32-12 inner links and FP64 reliable updates, for one RHS and
+    for eight RHS in one call; mixed precision with BF16-12 inner links.
   * roofline: the dominant kernel (the hop) against the 8 TB/s HBM peak.
   * cpu_baseline: the FP64 C oracle's D_eo on the host cores, bounded sample.
 
@@ -252,7 +253,7 @@ def bench_shapes():
                          "GBs_default": round(bps * vh / t_def / 1e9, 1),
                          "deo_us_tuned": round(t_tun * 1e6, 2),
                          "GBs_tuned": round(bps * vh / t_tun / 1e9, 1),
-                         "tuned": {k: choice[k] for k in ("xcd_remap", "sites_per_thread")},
+                         "tuned": {k: v for k, v in choice.items() if k != "us"},
                          "ns_per_site": round((t_tun + t_tun_oe) * 1e9 / (2 * vh), 4),
                          "paper_ns_per_site_K80_P100": paper[1::2] if fmt == "c128_12"
                          else paper[0::2]})
@@ -369,8 +370,11 @@ def main():
                        device=dev)
     wsmx = torch.empty(stg.stg_workspace_bytes(DIMS, 1, 0, stg.STG_CG_MIXED),
                        dtype=torch.uint8, device=dev)
+    lo16 = stg.pack_gauge(DIMS, links, "bf16_12")
+    wsbf = torch.empty_like(wsmx)
     x64 = torch.zeros_like(b)
     xmx = torch.zeros_like(b)
+    xbf = torch.zeros_like(b)
     nb = 8
     b8 = torch.from_numpy(si.gaussian_field(DIMS, nb, 426, 2, 1, 0)).to(dev)
     x8 = torch.zeros_like(b8)
@@ -380,6 +384,7 @@ def main():
     def step():
         x64.zero_()
         xmx.zero_()
+        xbf.zero_()
         x8.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -387,11 +392,14 @@ def main():
         t1 = time.perf_counter()
         _, s2, st2 = stg.cg_solve(hi, MASS, b, x=xmx, lo=lo, ws=wsmx, tol=TOL)
         t2 = time.perf_counter()
-        st3 = None
+        st3 = st4 = None
         if not args.profile_cg:
             _, s3, st3 = stg.cg_solve(hi, MASS, b8, x=x8, lo=lo, ws=ws8, tol=TOL)
         t3 = time.perf_counter()
-        return t1 - t0, t2 - t1, st1[0], st2[0], t3 - t2, st3
+        if not args.profile_cg:
+            _, s4, st4 = stg.cg_solve(hi, MASS, b, x=xbf, lo=lo16, ws=wsbf, tol=TOL)
+        t4 = time.perf_counter()
+        return t1 - t0, t2 - t1, st1[0], st2[0], t3 - t2, st3, t4 - t3, st4
 
     if args.profile_cg:
         r = step()
@@ -409,7 +417,8 @@ def main():
     t64 = min(r[0] for r in runs)
     tmx = min(r[1] for r in runs)
     t8 = min(r[4] for r in runs)
-    st64, stmx, st8 = runs[-1][2], runs[-1][3], runs[-1][5]
+    tbf = min(r[6] for r in runs)
+    st64, stmx, st8, stbf = runs[-1][2], runs[-1][3], runs[-1][5], runs[-1][7][0]
 
     # ---- dominant kernel roofline --------------------------------------------------
     dt = hop_time[("c128_12", "D_eo")]
@@ -439,8 +448,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "32^4 random SU(3), m=0.01, 1 RHS: FP64-12 D_eo apply; "
-                               "FP64 CG and mixed FP32-12 CG to |r|/|b|<=1e-10",
+        "config": {"workload": "32^4 random SU(3), m=0.01: FP64-12 D_eo apply; FP64 CG, "
+                               "mixed FP32-12 CG (1 and 8 RHS) and mixed BF16-12 CG "
+                               "to |r|/|b|<=1e-10",
                    "lattice": list(DIMS), "mass": MASS, "nrhs": 1, "tol": TOL,
                    "links": "random SU(3) (Haar), standard phases, antiperiodic t"},
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -454,6 +464,10 @@ def main():
         "cg_mixed_batch8": {"iters": max(x["iters"] for x in st8),
                             "worst_true_rel_resid": max(x["true_rel_resid"] for x in st8),
                             "reliable_updates": max(x["reliable_updates"] for x in st8)},
+        "cg_mixed_bf16_s_per_rhs": round(tbf, 4),
+        "mixed_bf16_speedup": round(t64 / tbf, 3),
+        "cg_mixed_bf16": {"iters": stbf["iters"], "true_rel_resid": stbf["true_rel_resid"],
+                          "reliable_updates": stbf["reliable_updates"]},
         "cg_fp64": {"iters": st64["iters"], "true_rel_resid": st64["true_rel_resid"],
                     "reliable_updates": st64["reliable_updates"]},
         "cg_mixed": {"iters": stmx["iters"], "true_rel_resid": stmx["true_rel_resid"],

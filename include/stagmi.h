@@ -127,17 +127,34 @@ const char *stg_last_error(void);
  *   STG_TUNE_STAGE_NEIGHBOURS: 0 (default) or 1: each block first copies the input
  *     field over its sites and one x1 row on either side into LDS and reads the x0
  *     and x1 neighbours from there (one or two fields per launch, N0 <= 128).
+ *   STG_TUNE_THREADS_PER_SITE: 0 (default: automatic), 1, 2 or 4: the four
+ *     directions of a site are shared by that many threads, whose partial sums
+ *     meet in LDS (with 2 or 4, sites per thread and staging do not apply; 4 is
+ *     not built for FP64 links with 8 fields per launch, which then take one
+ *     thread per site).  Automatic: by link format, fields per launch and
+ *     epilogue (one field: 1, or 4 for the plain FP32 / BF16 hop; two or four
+ *     fields: 4; eight fields: 4 for the plain FP32 / BF16 hop, else 2).  An
+ *     autotuned shape sets it for the plain hop only.  The choice changes the
+ *     order of floating-point additions, so results may differ in the last bits
+ *     between choices (each choice is deterministic).
  * Returns STG_INVALID_ARG for an unknown key or value.
  */
-enum { STG_TUNE_XCD_REMAP = 0, STG_TUNE_SITES_PER_THREAD = 1, STG_TUNE_STAGE_NEIGHBOURS = 2 };
+enum {
+    STG_TUNE_XCD_REMAP = 0,
+    STG_TUNE_SITES_PER_THREAD = 1,
+    STG_TUNE_STAGE_NEIGHBOURS = 2,
+    STG_TUNE_THREADS_PER_SITE = 3
+};
 int stg_set_tuning(int key, int value);
 int stg_get_tuning(int key, int *value);
 
 /*
  * Autotuner of the hop launch shape (the run-time counterpart of the paper's
  * per-architecture compile-time tile sizes, Sec. 4.3 TILE0..2 and Sec. 5).
- * stg_autotune times every candidate shape (XCD remap on/off x 1, 2, 4, 8 sites
- * per thread) of D_eo on the caller's gauge field and fields (in: device
+ * stg_autotune times every candidate shape (XCD remap on/off x [one thread per
+ * site with 1, 2, 4, 8 chunks per block and LDS neighbour staging off/on where it
+ * applies, or 2 / 4 threads per site]) of D_eo on the caller's gauge field and
+ * fields (in: device
  * [nrhs][3][Vh] on odd sites; out: device, overwritten), keeps the fastest for
  * the key (lattice extents, gauge format, fields per launch = the largest chunk
  * of nrhs among 8, 4, 2, 1) in a process-wide table that every later hop launch
@@ -150,8 +167,15 @@ int stg_get_tuning(int key, int *value);
 int stg_autotune(const stg_lattice *lat, const stg_gauge *gauge, stg_field field, int nrhs,
                  const void *in, void *out, const char *cache_path, stg_stream_t stream);
 int stg_autotune_load(const char *cache_path, int *loaded);
-int stg_autotune_lookup(const stg_lattice *lat, stg_link_fmt fmt, int nr, int *xcd_remap,
-                        int *sites_per_thread, double *us);
+typedef struct {
+    int xcd_remap;
+    int sites_per_thread;
+    int stage_neighbours;
+    int threads_per_site;
+    double us;          /* measured duration of one D_eo with this shape */
+} stg_tune_choice;
+int stg_autotune_lookup(const stg_lattice *lat, stg_link_fmt fmt, int nr,
+                        stg_tune_choice *choice);
 void stg_autotune_clear(void);
 
 /* Bytes of a gauge field of format fmt on lattice lat, written to *bytes (host). */

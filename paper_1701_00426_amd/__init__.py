@@ -386,10 +386,10 @@ def stg_autotune_load(cache_path: str) -> int:
 
 def stg_autotune_lookup(dims, fmt, nr: int = 1):
     """The stored launch shape for (dims, fmt, nr), or None."""
-    x, sp, us = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0)
+    c = _lib.StgTuneChoice()
     st = library().stg_autotune_lookup(ctypes.byref(_lib.lattice(dims)), int(fmt), int(nr),
-                                       ctypes.byref(x), ctypes.byref(sp), ctypes.byref(us))
+                                       ctypes.byref(c))
     if st == _lib.STG_NOT_CONVERGED:
         return None
     _lib.check("stg_autotune_lookup", st)
-    return {"xcd_remap": x.value, "sites_per_thread": sp.value, "us": us.value}
+    return c.as_dict()

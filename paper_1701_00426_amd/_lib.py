@@ -32,6 +32,7 @@ STG_C64 = 1
 STG_TUNE_XCD_REMAP = 0
 STG_TUNE_SITES_PER_THREAD = 1
 STG_TUNE_STAGE_NEIGHBOURS = 2
+STG_TUNE_THREADS_PER_SITE = 3
 
 # solver modes
 STG_CG_F64 = 0
@@ -61,6 +62,15 @@ class StgCgStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class StgTuneChoice(ctypes.Structure):
+    _fields_ = [("xcd_remap", ctypes.c_int), ("sites_per_thread", ctypes.c_int),
+                ("stage_neighbours", ctypes.c_int), ("threads_per_site", ctypes.c_int),
+                ("us", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class StgSolveDesc(ctypes.Structure):
     _fields_ = [("lat", StgLattice), ("hi", StgGauge), ("lo", StgGauge), ("mass", ctypes.c_double),
                 ("nrhs", ctypes.c_int), ("b", ctypes.c_void_p), ("x", ctypes.c_void_p)]
@@ -82,8 +92,7 @@ SIGNATURES = {
     "stg_get_tuning": (_I, [_I, ctypes.POINTER(_I)]),
     "stg_autotune": (_I, [_LAT, _G, _I, _I, _P, _P, ctypes.c_char_p, _P]),
     "stg_autotune_load": (_I, [ctypes.c_char_p, ctypes.POINTER(_I)]),
-    "stg_autotune_lookup": (_I, [_LAT, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
-                                 ctypes.POINTER(_D)]),
+    "stg_autotune_lookup": (_I, [_LAT, _I, _I, ctypes.POINTER(StgTuneChoice)]),
     "stg_autotune_clear": (None, []),
     "stg_links_bytes": (_I, [_LAT, _I, ctypes.POINTER(_S)]),
     "stg_pack_links": (_I, [_LAT, _P, _I, _P, _P]),

@@ -32,6 +32,7 @@ thread_local std::string g_last_error;
 int g_xcd_remap = 1;
 int g_sites_per_thread = 1;
 int g_stage_neighbours = 0;
+int g_threads_per_site = 0;  // 0: by format and fields
 
 int hip_fail(hipError_t e, const char *what) {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
@@ -48,6 +49,17 @@ int invalid(const char *why) {
     g_last_error = why;
     return STG_INVALID_ARG;
 }
+
+// A launch the library itself set up wrongly (never the caller's arguments).
+int internal(const char *why) {
+    g_last_error = why;
+    return STG_HIP_ERROR;
+}
+
+#define HOP_TRY(call)                                                  \
+    do {                                                               \
+        if ((call) != 0) return internal("hop launch refused: " #call); \
+    } while (0)
 
 bool make_geom(const stg_lattice *lat, Geom &g) {
     if (!lat) return false;
@@ -115,6 +127,7 @@ HopArgs base_hop(const Geom &g, const stg_gauge *gauge) {
     a.xcd_remap = g_xcd_remap;
     a.sites_per_thread = (uint32_t)g_sites_per_thread;
     a.stage_neighbours = (uint32_t)g_stage_neighbours;
+    a.threads_per_site = (uint32_t)g_threads_per_site;
     return a;
 }
 
@@ -125,6 +138,9 @@ int hop(HopArgs a, int fmt, int nr, int epi, hipStream_t stream) {
     if (tune_lookup(a.geom, fmt, nr, c)) {
         a.xcd_remap = c.xcd_remap;
         a.sites_per_thread = (uint32_t)c.sites_per_thread;
+        a.stage_neighbours = (uint32_t)c.stage_neighbours;
+        // the autotuner times the plain hop; epilogues keep their own default
+        if (epi == EPI_PLAIN) a.threads_per_site = (uint32_t)c.threads_per_site;
     }
     return launch_hop(a, fmt, nr, epi, stream);
 }
@@ -197,8 +213,9 @@ struct CgWork {
 };
 
 size_t partial_count(const Geom &g) {
-    // (sum, error) pairs: NR <= 8 per site-kernel block, 2 per dot block
-    size_t sites = (size_t)2 * 8 * site_blocks(g.Vh);
+    // doubles for the (sum, error) pairs: NR <= 8 per block of the site kernels (the
+    // hop with 4 threads per site has the most blocks), 2 per dot block
+    size_t sites = (size_t)2 * 8 * hop_max_blocks(g.Vh);
     size_t dots = (size_t)2 * 2 * dot_blocks((size_t)3 * g.Vh);
     return std::max(sites, dots);
 }
@@ -289,19 +306,20 @@ int enqueue_inner_iteration(const CgProblem &P, const CgWork &w, const std::vect
         a.ctl = w.ctl;
         a.state = w.state + j0;
         a.partials = w.partials;
+        a.partial_pairs = partial_count(P.g) / 2;
         // t = D_oe p
         a.out_parity = 1;
         a.op = OP_NONE;
         a.in = (const char *)w.p + o;
         a.out = (char *)w.t + o;
-        hop(a, gg->fmt, nr, EPI_PLAIN, s);
+        HOP_TRY(hop(a, gg->fmt, nr, EPI_PLAIN, s));
         // q = diag p - D_eo t ; <p, q> -> alpha
         a.out_parity = 0;
         a.op = OP_ALPHA;
         a.in = (const char *)w.t + o;
         a.out = (char *)w.q + o;
         a.aux0 = (const char *)w.p + o;
-        hop(a, gg->fmt, nr, EPI_NORMAL, s);
+        HOP_TRY(hop(a, gg->fmt, nr, EPI_NORMAL, s));
         // x += alpha p, r -= alpha q ; |r|^2 -> beta / park
         VecArgs v;
         std::memset(&v, 0, sizeof(v));
@@ -347,18 +365,19 @@ int enqueue_reliable_update(const CgProblem &P, const CgWork &w, hipStream_t s) 
         a.ctl = w.ctl;
         a.state = w.state + j0;
         a.partials = w.partials;
+        a.partial_pairs = partial_count(P.g) / 2;
         a.out_parity = 1;
         a.op = OP_NONE;
         a.in = (const char *)P.x + j0 * fb64;
         a.out = (char *)w.t64 + j0 * fb64;
-        hop(a, P.hi->fmt, nr, EPI_PLAIN, s);
+        HOP_TRY(hop(a, P.hi->fmt, nr, EPI_PLAIN, s));
         a.out_parity = 0;
         a.op = OP_RU;
         a.in = (const char *)w.t64 + j0 * fb64;
         a.out = (char *)w.r64 + j0 * fb64;
         a.aux0 = (const char *)P.x + j0 * fb64;
         a.aux1 = P.b_at(j0, fb64);
-        hop(a, P.hi->fmt, nr, EPI_RESID, s);
+        HOP_TRY(hop(a, P.hi->fmt, nr, EPI_RESID, s));
         v.r64 = (const char *)w.r64 + j0 * fb64;
         v.r = (char *)w.r + j0 * fbin;
         v.p = (char *)w.p + j0 * fbin;
@@ -663,17 +682,18 @@ int enqueue_ms_iteration(const Geom &g, const stg_gauge *gg, int f64, int nrhs, 
         a.ctl = w.ctl;
         a.state = w.state + j0;
         a.partials = w.partials;
+        a.partial_pairs = partial_count(g) / 2;
         a.out_parity = 1;
         a.op = OP_NONE;
         a.in = (const char *)w.p + o;
         a.out = (char *)w.t + o;
-        hop(a, gg->fmt, nr, EPI_PLAIN, s);
+        HOP_TRY(hop(a, gg->fmt, nr, EPI_PLAIN, s));
         a.out_parity = 0;
         a.op = OP_MS_ALPHA;
         a.in = (const char *)w.t + o;
         a.out = (char *)w.q + o;
         a.aux0 = (const char *)w.p + o;
-        hop(a, gg->fmt, nr, EPI_NORMAL, s);
+        HOP_TRY(hop(a, gg->fmt, nr, EPI_NORMAL, s));
         VecArgs v;
         std::memset(&v, 0, sizeof(v));
         v.Vh = g.Vh;
@@ -1247,6 +1267,11 @@ int stg_set_tuning(int key, int value) {
             if (value != 0 && value != 1) return invalid("neighbour staging takes 0 or 1");
             g_stage_neighbours = value;
             return STG_OK;
+        case STG_TUNE_THREADS_PER_SITE:
+            if (value != 0 && value != 1 && value != 2 && value != 4)
+                return invalid("threads per site takes 0 (automatic), 1, 2 or 4");
+            g_threads_per_site = value;
+            return STG_OK;
         default: return invalid("unknown tuning key");
     }
 }
@@ -1257,6 +1282,7 @@ int stg_get_tuning(int key, int *value) {
         case STG_TUNE_XCD_REMAP: *value = g_xcd_remap; return STG_OK;
         case STG_TUNE_SITES_PER_THREAD: *value = g_sites_per_thread; return STG_OK;
         case STG_TUNE_STAGE_NEIGHBOURS: *value = g_stage_neighbours; return STG_OK;
+        case STG_TUNE_THREADS_PER_SITE: *value = g_threads_per_site; return STG_OK;
         default: return invalid("unknown tuning key");
     }
 }
@@ -1343,7 +1369,7 @@ int stg_apply_normal(const stg_lattice *lat, const stg_gauge *gauge, stg_field f
         a.in = (const char *)tmp_odd + j0 * f1;
         a.out = (char *)out_even + j0 * f1;
         a.aux0 = (const char *)in_even + j0 * f1;
-        hop(a, gauge->fmt, nr, EPI_NORMAL, s);
+        HOP_TRY(hop(a, gauge->fmt, nr, EPI_NORMAL, s));
         j0 += nr;
     }
     HIP_TRY(hipGetLastError());
@@ -1506,22 +1532,41 @@ int stg_autotune(const stg_lattice *lat, const stg_gauge *gauge, stg_field field
     // repetitions: about 20 ms of work per candidate, at least 5
     const double est_us = 1e-3 * (double)g.Vh * nr;  // ~1 ns per site and field
     const int reps = (int)std::max(5.0, std::min(200.0, 20000.0 / std::max(est_us, 1.0)));
-    TuneChoice best{1, 1, 1e300};
-    const int spts[4] = {1, 2, 4, 8};
-    for (int xcd = 0; xcd < 2; ++xcd)
-        for (int si = 0; si < 4; ++si) {
-            a.xcd_remap = xcd;
-            a.sites_per_thread = (uint32_t)spts[si];
-            for (int w = 0; w < 2; ++w) launch_hop(a, gauge->fmt, nr, EPI_PLAIN, s);
-            HIP_TRY(hipEventRecord(e0, s));
-            for (int r = 0; r < reps; ++r) launch_hop(a, gauge->fmt, nr, EPI_PLAIN, s);
-            HIP_TRY(hipEventRecord(e1, s));
-            HIP_TRY(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            const double us = 1e3 * ms / reps;
-            if (us < best.us) best = TuneChoice{xcd, spts[si], us};
+    TuneChoice best{1, 1, 0, 1, 1e300};
+    auto time_shape = [&](const TuneChoice &c) -> int {
+        a.xcd_remap = c.xcd_remap;
+        a.sites_per_thread = (uint32_t)c.sites_per_thread;
+        a.stage_neighbours = (uint32_t)c.stage_neighbours;
+        a.threads_per_site = (uint32_t)c.threads_per_site;
+        for (int w = 0; w < 2; ++w) launch_hop(a, gauge->fmt, nr, EPI_PLAIN, s);
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) launch_hop(a, gauge->fmt, nr, EPI_PLAIN, s);
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        const double us = 1e3 * ms / reps;
+        if (us < best.us) {
+            best = c;
+            best.us = us;
         }
+        return STG_OK;
+    };
+    // one thread per site: block order x chunks per block x LDS staging (where it
+    // applies); several threads per site: block order (one chunk, no staging)
+    const int spts[4] = {1, 2, 4, 8};
+    const int nstage = stage_applies(nr, g.nh0) ? 2 : 1;
+    const size_t elem = gauge->fmt == STG_LINK_C128_18 || gauge->fmt == STG_LINK_C128_12 ? 16 : 8;
+    int rc2 = STG_OK;
+    for (int xcd = 0; xcd < 2 && rc2 == STG_OK; ++xcd) {
+        for (int stage = 0; stage < nstage && rc2 == STG_OK; ++stage)
+            for (int si = 0; si < 4 && rc2 == STG_OK; ++si)
+                rc2 = time_shape(TuneChoice{xcd, spts[si], stage, 1, 0.0});
+        for (int tps = 2; tps <= 4 && rc2 == STG_OK; tps *= 2)
+            if (split_lds_bytes(elem, nr, tps) <= kSplitLdsMax)
+                rc2 = time_shape(TuneChoice{xcd, 1, 0, tps, 0.0});
+    }
+    if (rc2 != STG_OK) return rc2;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIP_TRY(hipGetLastError());
@@ -1537,15 +1582,19 @@ int stg_autotune_load(const char *cache_path, int *loaded) {
     return STG_OK;
 }
 
-int stg_autotune_lookup(const stg_lattice *lat, stg_link_fmt fmt, int nr, int *xcd_remap,
-                        int *sites_per_thread, double *us) {
+int stg_autotune_lookup(const stg_lattice *lat, stg_link_fmt fmt, int nr,
+                        stg_tune_choice *choice) {
     Geom g;
     if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
     TuneChoice c;
     if (!tune_lookup(g, fmt, nr, c)) return STG_NOT_CONVERGED;
-    if (xcd_remap) *xcd_remap = c.xcd_remap;
-    if (sites_per_thread) *sites_per_thread = c.sites_per_thread;
-    if (us) *us = c.us;
+    if (choice) {
+        choice->xcd_remap = c.xcd_remap;
+        choice->sites_per_thread = c.sites_per_thread;
+        choice->stage_neighbours = c.stage_neighbours;
+        choice->threads_per_site = c.threads_per_site;
+        choice->us = c.us;
+    }
     return STG_OK;
 }
 

@@ -49,18 +49,27 @@ __device__ __forceinline__ cpx<T> cconj(cpx<T> a) { return {a.re, -a.im}; }
 template <typename T>
 __device__ __forceinline__ cpx<T> cscale(T s, cpx<T> a) { return {s * a.re, s * a.im}; }
 
-// acc += a * b
+// fused multiply-add a * b + c with one rounding
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// acc += a * b as four fused multiply-adds into the accumulator (written out: the
+// compiler would otherwise form the product first and add it, six operations)
 template <typename T>
 __device__ __forceinline__ void cfma(cpx<T> &acc, cpx<T> a, cpx<T> b) {
-    acc.re += a.re * b.re - a.im * b.im;
-    acc.im += a.re * b.im + a.im * b.re;
+    acc.re = fmat(a.re, b.re, acc.re);
+    acc.re = fmat(-a.im, b.im, acc.re);
+    acc.im = fmat(a.re, b.im, acc.im);
+    acc.im = fmat(a.im, b.re, acc.im);
 }
 
 // acc += conj(a) * b
 template <typename T>
 __device__ __forceinline__ void cfmac(cpx<T> &acc, cpx<T> a, cpx<T> b) {
-    acc.re += a.re * b.re + a.im * b.im;
-    acc.im += a.re * b.im - a.im * b.re;
+    acc.re = fmat(a.re, b.re, acc.re);
+    acc.re = fmat(a.im, b.im, acc.re);
+    acc.im = fmat(a.re, b.im, acc.im);
+    acc.im = fmat(-a.im, b.re, acc.im);
 }
 
 template <typename T>
@@ -238,8 +247,8 @@ __device__ __forceinline__ void acc_mv(vec3<T> &y, T s, const su3<T> &u, const v
         cpx<T> t = cmul(u.e[a][0], v.c[0]);
         cfma(t, u.e[a][1], v.c[1]);
         cfma(t, u.e[a][2], v.c[2]);
-        y.c[a].re += s * t.re;
-        y.c[a].im += s * t.im;
+        y.c[a].re = fmat(s, t.re, y.c[a].re);
+        y.c[a].im = fmat(s, t.im, y.c[a].im);
     }
 }
 
@@ -251,8 +260,8 @@ __device__ __forceinline__ void acc_mdv(vec3<T> &y, T s, const su3<T> &u, const 
         cpx<T> t = cmulc(u.e[0][a], v.c[0]);
         cfmac(t, u.e[1][a], v.c[1]);
         cfmac(t, u.e[2][a], v.c[2]);
-        y.c[a].re += s * t.re;
-        y.c[a].im += s * t.im;
+        y.c[a].re = fmat(s, t.re, y.c[a].re);
+        y.c[a].im = fmat(s, t.im, y.c[a].im);
     }
 }
 

@@ -30,7 +30,7 @@
 
 namespace stg {
 
-template <typename T, int FMT, bool STDPH, int NR, int EPI, bool STAGE>
+template <typename T, int FMT, bool STDPH, int NR, int EPI, bool STAGE, bool MULTI>
 __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
     if (a.gate_running && a.ctl->n_running == 0) return;
 
@@ -42,9 +42,11 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
 #pragma unroll
     for (int j = 0; j < NR; ++j) ps[j] = pc[j] = 0.0;
 
-    // the block owns sites_per_thread consecutive chunks of kBlock sites
+    // the block owns sites_per_thread consecutive chunks of kBlock sites; with one
+    // chunk (MULTI false) the loop disappears, which saves registers
+    const uint32_t nchunk = MULTI ? a.sites_per_thread : 1u;
 #pragma unroll 1
-    for (uint32_t k = 0; k < a.sites_per_thread; ++k) {
+    for (uint32_t k = 0; k < nchunk; ++k) {
     const uint32_t chunk0 = (blk * a.sites_per_thread + k) * kBlock;
     const uint32_t h = chunk0 + threadIdx.x;
     vec3<T> acc[NR];
@@ -62,42 +64,7 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
     } else if (h < g.Vh) {
         hop_site<T, FMT, STDPH, NR>(g, P, h, a.links, a.phases, a.in, a.fstride, acc);
     }
-    if (h < g.Vh) {
-
-        const T half = T(0.5);
-#pragma unroll
-        for (int j = 0; j < NR; ++j) {
-            vec3<T> o;
-            if (EPI == EPI_PLAIN) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) o.c[c] = cscale(half, acc[j].c[c]);
-            } else if (EPI == EPI_NORMAL) {
-                const T d = (T)a.st_diag(j);
-                vec3<T> p = ld_v<T>(a.aux0, a.fstride, g.Vh, j, h);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    o.c[c].re = d * p.c[c].re - half * acc[j].c[c].re;
-                    o.c[c].im = d * p.c[c].im - half * acc[j].c[c].im;
-                    pair_add(ps[j], pc[j], (double)p.c[c].re * (double)o.c[c].re, 0.0);
-                    pair_add(ps[j], pc[j], (double)p.c[c].im * (double)o.c[c].im, 0.0);
-                }
-            } else {  // EPI_RESID
-                if (!a.st_pending(j)) continue;
-                const T d = (T)a.st_diag(j);
-                vec3<T> x = ld_v<T>(a.aux0, a.fstride, g.Vh, j, h);
-                vec3<T> b = ld_v<T>(a.aux1, a.fstride, g.Vh, j, h);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    o.c[c].re = b.c[c].re - (d * x.c[c].re - half * acc[j].c[c].re);
-                    o.c[c].im = b.c[c].im - (d * x.c[c].im - half * acc[j].c[c].im);
-                    pair_add(ps[j], pc[j], (double)o.c[c].re * (double)o.c[c].re +
-                                               (double)o.c[c].im * (double)o.c[c].im,
-                             0.0);
-                }
-            }
-            st_v<T>(a.out, a.fstride, g.Vh, j, h, o);
-        }
-    }
+    if (h < g.Vh) hop_epilogue<T, NR, EPI>(a, h, acc, ps, pc);
     }
 
     if (EPI == EPI_PLAIN || a.op == OP_NONE) return;
@@ -108,44 +75,54 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
-template <typename T, int FMT, bool STDPH, int NR, bool STAGE>
+template <typename T, int FMT, bool STDPH, int NR, bool STAGE, bool MULTI>
 static void launch_epi(const HopArgs &a, int epi, dim3 grid, hipStream_t stream) {
     switch (epi) {
         case EPI_PLAIN:
-            hop_kernel<T, FMT, STDPH, NR, EPI_PLAIN, STAGE><<<grid, kBlock, 0, stream>>>(a);
+            hop_kernel<T, FMT, STDPH, NR, EPI_PLAIN, STAGE, MULTI><<<grid, kBlock, 0, stream>>>(a);
             return;
         case EPI_NORMAL:
-            hop_kernel<T, FMT, STDPH, NR, EPI_NORMAL, STAGE><<<grid, kBlock, 0, stream>>>(a);
+            hop_kernel<T, FMT, STDPH, NR, EPI_NORMAL, STAGE, MULTI><<<grid, kBlock, 0, stream>>>(a);
             return;
         default:
-            hop_kernel<T, FMT, STDPH, NR, EPI_RESID, STAGE><<<grid, kBlock, 0, stream>>>(a);
+            hop_kernel<T, FMT, STDPH, NR, EPI_RESID, STAGE, MULTI><<<grid, kBlock, 0, stream>>>(a);
             return;
     }
 }
 
+template <typename T, int FMT, bool STDPH, int NR, bool STAGE>
+static void launch_multi(const HopArgs &a, int epi, dim3 grid, hipStream_t stream) {
+    if (a.sites_per_thread > 1)
+        launch_epi<T, FMT, STDPH, NR, STAGE, true>(a, epi, grid, stream);
+    else
+        launch_epi<T, FMT, STDPH, NR, STAGE, false>(a, epi, grid, stream);
+}
+
 template <typename T, int FMT, bool STDPH, int NR>
-static void launch_nr(const HopArgs &a, int epi, hipStream_t stream) {
+static int launch_nr(const HopArgs &a, int epi, hipStream_t stream) {
     const uint32_t chunk = kBlock * a.sites_per_thread;
     dim3 grid((a.geom.Vh + chunk - 1) / chunk);
+    const bool reduce = epi != EPI_PLAIN && a.op != OP_NONE;
+    if (reduce && (size_t)NR * grid.x > a.partial_pairs) return -1;
     // LDS staging of the x0/x1 neighbours: one or two fields, rows of <= 64 half-sites
-    if (NR <= 2 && a.stage_neighbours && a.geom.nh0 <= (kStageMax - kBlock) / 2)
-        launch_epi<T, FMT, STDPH, NR, (NR <= 2)>(a, epi, grid, stream);
+    if (a.stage_neighbours && stage_applies(NR, a.geom.nh0))
+        launch_multi<T, FMT, STDPH, NR, (NR <= 2)>(a, epi, grid, stream);
     else
-        launch_epi<T, FMT, STDPH, NR, false>(a, epi, grid, stream);
-    if (epi == EPI_PLAIN) return;
-    if (a.op != OP_NONE) {
+        launch_multi<T, FMT, STDPH, NR, false>(a, epi, grid, stream);
+    if (reduce) {
         FinArgs f{a.partials, grid.x, NR, a.op, a.gate_running, a.ctl, a.state, a.out_sums};
         launch_finalize(f, stream);
     }
+    return 0;
 }
 
 template <typename T, int FMT, bool STDPH>
 static int launch_fmt(const HopArgs &a, int nr, int epi, hipStream_t stream) {
     switch (nr) {
-        case 1: launch_nr<T, FMT, STDPH, 1>(a, epi, stream); return 0;
-        case 2: launch_nr<T, FMT, STDPH, 2>(a, epi, stream); return 0;
-        case 4: launch_nr<T, FMT, STDPH, 4>(a, epi, stream); return 0;
-        case 8: launch_nr<T, FMT, STDPH, 8>(a, epi, stream); return 0;
+        case 1: return launch_nr<T, FMT, STDPH, 1>(a, epi, stream);
+        case 2: return launch_nr<T, FMT, STDPH, 2>(a, epi, stream);
+        case 4: return launch_nr<T, FMT, STDPH, 4>(a, epi, stream);
+        case 8: return launch_nr<T, FMT, STDPH, 8>(a, epi, stream);
         default: return -1;
     }
 }
@@ -156,9 +133,19 @@ static int launch_ph(const HopArgs &a, int nr, int epi, hipStream_t stream) {
                     : launch_fmt<T, FMT, true>(a, nr, epi, stream);
 }
 
-// Launches one hop over NR in {1, 2, 4, 8} fields.  Returns 0, or -1 for an
-// unsupported combination (checked by the caller beforehand).
+// Launches one hop over NR in {1, 2, 4, 8} fields.  Returns 0, or nonzero without
+// launching for an unsupported combination (checked by the caller beforehand) or
+// when a reduction needs more (sum, error) pairs than a.partial_pairs.
 int launch_hop(const HopArgs &a, int fmt, int nr, int epi, hipStream_t stream) {
+    // several threads per site where that variant is built, else one
+    const uint32_t tps = a.threads_per_site ? a.threads_per_site
+                                            : (uint32_t)default_threads_per_site(fmt, nr, epi);
+    if (tps > 1) {
+        HopArgs b = a;
+        b.threads_per_site = tps;
+        const int rc = launch_hop_split(b, fmt, nr, epi, stream);
+        if (rc != -1) return rc;  // launched, or refused for lack of partials
+    }
     switch (fmt) {
         case FMT_C128_18: return launch_ph<double, FMT_C128_18>(a, nr, epi, stream);
         case FMT_C128_12: return launch_ph<double, FMT_C128_12>(a, nr, epi, stream);

@@ -7,6 +7,7 @@
 #pragma once
 
 #include "device_common.hpp"
+#include "kernels.hpp"
 
 namespace stg {
 
@@ -38,7 +39,6 @@ struct GlobalNb {
 // Neighbour-field reads from an LDS copy of the global index range [s0, s0 + len)
 // (the block's own sites and one x1 row on each side: every x0 and most x1
 // neighbours), from global memory outside it.
-constexpr uint32_t kStageMax = 384;  // staged sites per block: kBlock + 2 * nh0, nh0 <= 64
 
 template <typename T, int NR>
 struct StagedNb {
@@ -75,19 +75,17 @@ __device__ __forceinline__ void stage_fill(cpx<T> (*tile)[3][kStageMax], const v
     __syncthreads();
 }
 
-template <typename T, int FMT, bool STDPH, int NR, typename NB>
-__device__ __forceinline__ void hop_site_nb(const Geom &g, int P, uint32_t h, const void *links,
-                                            const void *phases, const NB &nb,
-                                            vec3<T> (&acc)[NR]) {
-    Site s = site_coords(g, P, h);
-#pragma unroll
-    for (int j = 0; j < NR; ++j)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) acc[j].c[c] = {T(0), T(0)};
-
-    constexpr int kUnroll = HopUnroll<T, NR>::value;
+// Adds the terms of directions MU0 .. MU0 + ND - 1 at output site h (parity P) to
+// acc[j] for the NR fields: forward link U_mu(x) and neighbour x + mu, backward
+// link U_mu(x - mu)^dag and neighbour x - mu, each times its phase.
+template <typename T, int FMT, bool STDPH, int NR, int MU0, int ND, typename NB>
+__device__ __forceinline__ void hop_dirs(const Geom &g, int P, uint32_t h, const Site &s,
+                                         const void *links, const void *phases, const NB &nb,
+                                         vec3<T> (&acc)[NR]) {
+    constexpr int kUnroll = HopUnroll<T, NR>::value < ND ? HopUnroll<T, NR>::value : ND;
 #pragma unroll kUnroll
-    for (int mu = 0; mu < 4; ++mu) {
+    for (int d = 0; d < ND; ++d) {
+        const int mu = MU0 + d;
         const uint32_t hf = nb_fwd(g, s, h, mu);
         const uint32_t hb = nb_bwd(g, s, h, mu);
         const int sf = 2 * mu + P;        // U_mu(x) starts at x
@@ -116,11 +114,77 @@ __device__ __forceinline__ void hop_site_nb(const Geom &g, int P, uint32_t h, co
     }
 }
 
+template <typename T, int NR>
+__device__ __forceinline__ void zero_acc(vec3<T> (&acc)[NR]) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[j].c[c] = {T(0), T(0)};
+}
+
+template <typename T, int FMT, bool STDPH, int NR, typename NB>
+__device__ __forceinline__ void hop_site_nb(const Geom &g, int P, uint32_t h, const void *links,
+                                            const void *phases, const NB &nb,
+                                            vec3<T> (&acc)[NR]) {
+    Site s = site_coords(g, P, h);
+    zero_acc<T, NR>(acc);
+    hop_dirs<T, FMT, STDPH, NR, 0, 4>(g, P, h, s, links, phases, nb, acc);
+}
+
 template <typename T, int FMT, bool STDPH, int NR>
 __device__ __forceinline__ void hop_site(const Geom &g, int P, uint32_t h, const void *links,
                                          const void *phases, const void *in, size_t fstride,
                                          vec3<T> (&acc)[NR]) {
     hop_site_nb<T, FMT, STDPH, NR>(g, P, h, links, phases, GlobalNb<T>{in, fstride, g.Vh}, acc);
+}
+
+// Epilogue at output site h from acc = sum_mu [...] (twice the hop):
+//   EPI_PLAIN   out = acc / 2
+//   EPI_NORMAL  out = diag_j p - acc / 2, and Re<p, out> into the partials (ps, pc)
+//   EPI_RESID   out = b - (diag_j x - acc / 2), and |out|^2 into the partials, for
+//               the fields whose system waits for a true residual
+template <typename T, int EPI>
+__device__ __forceinline__ void hop_epilogue_field(const HopArgs &a, uint32_t h, int j,
+                                                   const vec3<T> &acc, double &ps, double &pc) {
+    const Geom &g = a.geom;
+    const T half = T(0.5);
+    vec3<T> o;
+    if (EPI == EPI_PLAIN) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) o.c[c] = cscale(half, acc.c[c]);
+    } else if (EPI == EPI_NORMAL) {
+        const T d = (T)a.st_diag(j);
+        vec3<T> p = ld_v<T>(a.aux0, a.fstride, g.Vh, j, h);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            o.c[c].re = d * p.c[c].re - half * acc.c[c].re;
+            o.c[c].im = d * p.c[c].im - half * acc.c[c].im;
+            pair_add(ps, pc, (double)p.c[c].re * (double)o.c[c].re, 0.0);
+            pair_add(ps, pc, (double)p.c[c].im * (double)o.c[c].im, 0.0);
+        }
+    } else {  // EPI_RESID
+        if (!a.st_pending(j)) return;
+        const T d = (T)a.st_diag(j);
+        vec3<T> x = ld_v<T>(a.aux0, a.fstride, g.Vh, j, h);
+        vec3<T> b = ld_v<T>(a.aux1, a.fstride, g.Vh, j, h);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            o.c[c].re = b.c[c].re - (d * x.c[c].re - half * acc.c[c].re);
+            o.c[c].im = b.c[c].im - (d * x.c[c].im - half * acc.c[c].im);
+            pair_add(ps, pc, (double)o.c[c].re * (double)o.c[c].re +
+                                 (double)o.c[c].im * (double)o.c[c].im,
+                     0.0);
+        }
+    }
+    st_v<T>(a.out, a.fstride, g.Vh, j, h, o);
+}
+
+template <typename T, int NR, int EPI>
+__device__ __forceinline__ void hop_epilogue(const HopArgs &a, uint32_t h,
+                                             const vec3<T> (&acc)[NR], double (&ps)[NR],
+                                             double (&pc)[NR]) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) hop_epilogue_field<T, EPI>(a, h, j, acc[j], ps[j], pc[j]);
 }
 
 }  // namespace stg

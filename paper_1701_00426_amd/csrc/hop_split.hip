@@ -1,0 +1,152 @@
+// hop_split.hip -- the staggered hop with the four directions of a site shared by
+// 2 or 4 threads.
+//
+// Paper: arXiv:1701.00426, Sec. 2.2 Eq. diracblock and the deo listing of Sec. 4.3
+// (the same operator and epilogues as hop.hip).
+//
+// A block of kBlock threads covers kBlock / TPS consecutive output sites.  Thread
+// group q (threads q * SPB .. (q + 1) * SPB - 1, whole waves) takes directions
+// q * 4/TPS .. (q + 1) * 4/TPS - 1 of every site of the block, so each wave's link
+// and field loads stay single coalesced runs.  Groups q > 0 leave their partial
+// sums in LDS; group 0 adds them in the order q = 1, 2, 3 and runs the epilogue.
+// Each thread holds the loads of one or two directions instead of four: fewer
+// registers, more waves in flight per SIMD, and the same bytes from HBM.
+
+#include "device_common.hpp"
+#include "hop_core.hpp"
+#include "kernels.hpp"
+#include "solver_state.hpp"
+
+namespace stg {
+
+template <typename T, int FMT, bool STDPH, int NR, int DPT, int Q>
+__device__ __forceinline__ void group_dirs(const Geom &g, int P, uint32_t h, const Site &s,
+                                           const void *links, const void *phases,
+                                           const GlobalNb<T> &nb, vec3<T> (&acc)[NR]) {
+    hop_dirs<T, FMT, STDPH, NR, Q * DPT, DPT>(g, P, h, s, links, phases, nb, acc);
+}
+
+template <typename T, int FMT, bool STDPH, int NR, int EPI, int TPS>
+__global__ __launch_bounds__(kBlock) void hop_split_kernel(HopArgs a) {
+    if (a.gate_running && a.ctl->n_running == 0) return;
+    constexpr int SPB = kBlock / TPS;  // sites per block, a multiple of the wave size
+    constexpr int DPT = 4 / TPS;       // directions per thread
+    __shared__ cpx<T> part[TPS - 1][NR][3][SPB];
+
+    const Geom &g = a.geom;
+    const int P = a.out_parity;
+    const uint32_t blk = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int q = threadIdx.x / SPB;  // the same in a whole wave
+    const int l = threadIdx.x % SPB;
+    const uint32_t h = blk * SPB + l;
+
+    vec3<T> acc[NR];
+    zero_acc<T, NR>(acc);
+    if (h < g.Vh) {
+        const Site s = site_coords(g, P, h);
+        const GlobalNb<T> nb{a.in, a.fstride, g.Vh};
+        if (q == 0)
+            group_dirs<T, FMT, STDPH, NR, DPT, 0>(g, P, h, s, a.links, a.phases, nb, acc);
+        else if (q == 1)
+            group_dirs<T, FMT, STDPH, NR, DPT, 1>(g, P, h, s, a.links, a.phases, nb, acc);
+        else if (TPS == 4 && q == 2)
+            group_dirs<T, FMT, STDPH, NR, DPT, (TPS == 4 ? 2 : 0)>(g, P, h, s, a.links,
+                                                                  a.phases, nb, acc);
+        else if (TPS == 4)
+            group_dirs<T, FMT, STDPH, NR, DPT, (TPS == 4 ? 3 : 0)>(g, P, h, s, a.links,
+                                                                  a.phases, nb, acc);
+    }
+    if (q > 0) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) part[q - 1][j][c][l] = acc[j].c[c];
+    }
+    __syncthreads();
+
+    double ps[NR], pc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) ps[j] = pc[j] = 0.0;
+    if (q == 0 && h < g.Vh) {
+#pragma unroll
+        for (int r = 0; r < TPS - 1; ++r)
+#pragma unroll
+            for (int j = 0; j < NR; ++j)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const cpx<T> v = part[r][j][c][l];
+                    acc[j].c[c].re += v.re;
+                    acc[j].c[c].im += v.im;
+                }
+        hop_epilogue<T, NR, EPI>(a, h, acc, ps, pc);
+    }
+    if (EPI == EPI_PLAIN || a.op == OP_NONE) return;
+    block_partials<NR>(ps, pc, a.partials);
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+template <typename T, int FMT, bool STDPH, int NR, int TPS>
+static int launch_tps(const HopArgs &a, int epi, hipStream_t stream) {
+    constexpr int SPB = kBlock / TPS;
+    dim3 grid((a.geom.Vh + SPB - 1) / SPB);
+    const bool reduce = epi != EPI_PLAIN && a.op != OP_NONE;
+    if (reduce && (size_t)NR * grid.x > a.partial_pairs) return -2;
+    switch (epi) {
+        case EPI_PLAIN:
+            hop_split_kernel<T, FMT, STDPH, NR, EPI_PLAIN, TPS><<<grid, kBlock, 0, stream>>>(a);
+            break;
+        case EPI_NORMAL:
+            hop_split_kernel<T, FMT, STDPH, NR, EPI_NORMAL, TPS><<<grid, kBlock, 0, stream>>>(a);
+            break;
+        default:
+            hop_split_kernel<T, FMT, STDPH, NR, EPI_RESID, TPS><<<grid, kBlock, 0, stream>>>(a);
+            break;
+    }
+    if (reduce) {
+        FinArgs f{a.partials, grid.x, NR, a.op, a.gate_running, a.ctl, a.state, a.out_sums};
+        launch_finalize(f, stream);
+    }
+    return 0;
+}
+
+template <typename T, int FMT, bool STDPH, int NR>
+static int launch_nr_split(const HopArgs &a, int epi, hipStream_t stream) {
+    if (a.threads_per_site == 2) return launch_tps<T, FMT, STDPH, NR, 2>(a, epi, stream);
+    if constexpr (split_lds_bytes(sizeof(cpx<T>), NR, 4) <= kSplitLdsMax) {
+        if (a.threads_per_site == 4) return launch_tps<T, FMT, STDPH, NR, 4>(a, epi, stream);
+    }
+    return -1;
+}
+
+template <typename T, int FMT, bool STDPH>
+static int launch_fmt_split(const HopArgs &a, int nr, int epi, hipStream_t stream) {
+    switch (nr) {
+        case 1: return launch_nr_split<T, FMT, STDPH, 1>(a, epi, stream);
+        case 2: return launch_nr_split<T, FMT, STDPH, 2>(a, epi, stream);
+        case 4: return launch_nr_split<T, FMT, STDPH, 4>(a, epi, stream);
+        case 8: return launch_nr_split<T, FMT, STDPH, 8>(a, epi, stream);
+        default: return -1;
+    }
+}
+
+template <typename T, int FMT>
+static int launch_ph_split(const HopArgs &a, int nr, int epi, hipStream_t stream) {
+    return a.phases ? launch_fmt_split<T, FMT, false>(a, nr, epi, stream)
+                    : launch_fmt_split<T, FMT, true>(a, nr, epi, stream);
+}
+
+// 0: launched; -1: this (format, fields, threads per site) is not built; -2: the
+// partials buffer is too small for the reduction (nothing launched).
+int launch_hop_split(const HopArgs &a, int fmt, int nr, int epi, hipStream_t stream) {
+    switch (fmt) {
+        case FMT_C128_18: return launch_ph_split<double, FMT_C128_18>(a, nr, epi, stream);
+        case FMT_C128_12: return launch_ph_split<double, FMT_C128_12>(a, nr, epi, stream);
+        case FMT_C64_12: return launch_ph_split<float, FMT_C64_12>(a, nr, epi, stream);
+        case FMT_BF16_12: return launch_ph_split<float, FMT_BF16_12>(a, nr, epi, stream);
+        default: return -1;
+    }
+}
+
+}  // namespace stg

@@ -27,10 +27,14 @@ struct HopArgs {
     int xcd_remap;        // 1: blocks of one XCD take one contiguous range of sites
     uint32_t sites_per_thread;  // each block covers this many consecutive kBlock-site chunks
     uint32_t stage_neighbours;  // 1: x0/x1 neighbour fields read from an LDS copy
+    uint32_t threads_per_site;  // 0: by format and fields (default_threads_per_site),
+                                // 1, or 2 / 4 threads sharing the directions of a site
     double diag;          // m^2 + sigma when state == nullptr
     SysState *state;      // per-field solver state, or nullptr
     Ctl *ctl;
     double *partials;     // [NR][grid] block partials
+    size_t partial_pairs; // (sum, error) pairs that fit in partials; a launch with a
+                          // reduction that needs more is refused
     double *out_sums;     // OP_STORE destination [NR]
 
     __device__ __forceinline__ double st_diag(int j) const {
@@ -75,6 +79,14 @@ struct FinArgs {
 };
 int launch_finalize(const FinArgs &f, hipStream_t stream);
 
+// LDS staging of the x0/x1 neighbours: the block's kBlock sites plus one x1 row
+// (nh0 half-sites) on either side, for one or two fields per launch.
+constexpr uint32_t kStageMax = 384;  // staged sites per block: kBlock + 2 * nh0, nh0 <= 64
+
+__host__ __device__ __forceinline__ bool stage_applies(int nr, uint32_t nh0) {
+    return nr <= 2 && nh0 <= (kStageMax - kBlock) / 2;
+}
+
 // Workgroups are dispatched to the 8 XCDs of the chip round-robin by block index,
 // and each XCD has its own L2.  This maps the launch's block b to a logical block
 // so that the blocks running on one XCD cover one contiguous range of sites: the
@@ -91,7 +103,31 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
 // Blocks of kBlock threads needed to cover Vh sites.
 inline uint32_t site_blocks(uint32_t Vh) { return (Vh + kBlock - 1) / kBlock; }
 
+// Most blocks any hop launch uses: 4 threads per site leave kBlock / 4 sites per block.
+inline uint32_t hop_max_blocks(uint32_t Vh) { return (Vh + kBlock / 4 - 1) / (kBlock / 4); }
+
 int launch_hop(const HopArgs &a, int fmt, int nr, int epi, hipStream_t stream);
+
+// The hop with 2 or 4 threads per site (hop_split.hip): LDS for the partial sums
+// of the helper threads, elem_bytes per complex entry.  Returns -1 when the
+// combination is not built (more LDS than kSplitLdsMax).
+constexpr size_t kSplitLdsMax = 48 * 1024;
+constexpr size_t split_lds_bytes(size_t elem_bytes, int nr, int tps) {
+    return (size_t)(tps - 1) * nr * 3 * elem_bytes * (kBlock / tps);
+}
+int launch_hop_split(const HopArgs &a, int fmt, int nr, int epi, hipStream_t stream);  // -1: not built, -2: partials too small
+
+// Threads per site when the caller leaves the choice open, from hop timings at 32^4
+// on MI355X (one thread per site for one field: the same speed or faster, and the
+// profiled FP64-12 configuration; 4 for two or four fields; with 8 fields 4 for the
+// plain hop in FP32 / BF16, and 2 otherwise: group 0 runs the whole epilogue, which
+// for 8 fields costs more than the extra waves gain, and FP64 at 4 needs 72 KB LDS).
+inline int default_threads_per_site(int fmt, int nr, int epi) {
+    const bool fp64 = fmt == FMT_C128_18 || fmt == FMT_C128_12;
+    if (nr == 1) return (epi == EPI_PLAIN && !fp64) ? 4 : 1;
+    if (nr <= 4) return 4;
+    return (epi == EPI_PLAIN && !fp64) ? 4 : 2;
+}
 
 // BLAS-1 style site kernels; fields are [NR][3][Vh] with stride fstride.
 struct VecArgs {

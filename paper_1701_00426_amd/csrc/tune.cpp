@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -56,11 +57,35 @@ int tune_append_file(const char *path, const Geom &g, int fmt, int nr, const Tun
     if (!f) return -1;
     std::fprintf(f,
                  "{\"arch\": \"gfx950\", \"dims\": [%u, %u, %u, %u], \"fmt\": %d, \"nr\": %d, "
-                 "\"xcd_remap\": %d, \"sites_per_thread\": %d, \"us\": %.3f}\n",
-                 g.N[0], g.N[1], g.N[2], g.N[3], fmt, nr, c.xcd_remap, c.sites_per_thread, c.us);
+                 "\"xcd_remap\": %d, \"sites_per_thread\": %d, \"stage_neighbours\": %d, "
+                 "\"threads_per_site\": %d, \"us\": %.3f}\n",
+                 g.N[0], g.N[1], g.N[2], g.N[3], fmt, nr, c.xcd_remap, c.sites_per_thread,
+                 c.stage_neighbours, c.threads_per_site, c.us);
     std::fclose(f);
     return 0;
 }
+
+namespace {
+
+// Value of "key": <number> in one cache line; false when the key is absent.
+bool find_num(const char *line, const char *key, double &v) {
+    char pat[64];
+    std::snprintf(pat, sizeof pat, "\"%s\": ", key);
+    const char *p = std::strstr(line, pat);
+    if (!p) return false;
+    char *end = nullptr;
+    v = std::strtod(p + std::strlen(pat), &end);
+    return end != p + std::strlen(pat);
+}
+
+bool find_int(const char *line, const char *key, int &v) {
+    double d;
+    if (!find_num(line, key, d) || d != (double)(int)d) return false;
+    v = (int)d;
+    return true;
+}
+
+}  // namespace
 
 int tune_load_file(const char *path, int *loaded) {
     FILE *f = std::fopen(path, "r");
@@ -68,22 +93,29 @@ int tune_load_file(const char *path, int *loaded) {
     char line[512];
     int n = 0;
     while (std::fgets(line, sizeof line, f)) {
-        unsigned d0, d1, d2, d3;
-        int fmt, nr, xcd, spt;
+        unsigned d[4];
+        int fmt, nr, xcd, spt, stage = 0, tps = 1;
         double us;
-        if (std::sscanf(line,
-                        "{\"arch\": \"gfx950\", \"dims\": [%u, %u, %u, %u], \"fmt\": %d, "
-                        "\"nr\": %d, \"xcd_remap\": %d, \"sites_per_thread\": %d, \"us\": %lf}",
-                        &d0, &d1, &d2, &d3, &fmt, &nr, &xcd, &spt, &us) != 9)
+        if (!std::strstr(line, "\"arch\": \"gfx950\"")) continue;
+        const char *dims = std::strstr(line, "\"dims\": [");
+        if (!dims || std::sscanf(dims, "\"dims\": [%u, %u, %u, %u]", &d[0], &d[1], &d[2], &d[3]) != 4)
             continue;
-        if ((xcd != 0 && xcd != 1) || (spt != 1 && spt != 2 && spt != 4 && spt != 8)) continue;
+        if (!find_int(line, "fmt", fmt) || !find_int(line, "nr", nr) ||
+            !find_int(line, "xcd_remap", xcd) || !find_int(line, "sites_per_thread", spt) ||
+            !find_num(line, "us", us))
+            continue;
+        // fields added later are optional: lines without them read as their defaults
+        if (std::strstr(line, "\"stage_neighbours\"") && !find_int(line, "stage_neighbours", stage))
+            continue;
+        if (std::strstr(line, "\"threads_per_site\"") && !find_int(line, "threads_per_site", tps))
+            continue;
+        if ((xcd != 0 && xcd != 1) || (spt != 1 && spt != 2 && spt != 4 && spt != 8) ||
+            (stage != 0 && stage != 1) || (tps != 1 && tps != 2 && tps != 4))
+            continue;
         Geom g;
         std::memset(&g, 0, sizeof g);
-        g.N[0] = d0;
-        g.N[1] = d1;
-        g.N[2] = d2;
-        g.N[3] = d3;
-        tune_store(g, fmt, nr, TuneChoice{xcd, spt, us});  // later lines win
+        for (int k = 0; k < 4; ++k) g.N[k] = d[k];
+        tune_store(g, fmt, nr, TuneChoice{xcd, spt, stage, tps, us});  // later lines win
         ++n;
     }
     std::fclose(f);

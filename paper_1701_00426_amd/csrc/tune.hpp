@@ -8,6 +8,8 @@ namespace stg {
 struct TuneChoice {
     int xcd_remap;
     int sites_per_thread;
+    int stage_neighbours;
+    int threads_per_site;
     double us;  // measured duration of one hop with this shape
 };
 

@@ -150,31 +150,52 @@ def test_product_does_not_import_oracle():
 
 
 def test_autotune_cache_roundtrip(lib, tmp_path):
-    """The cache file format is read back into the table; unknown keys report 1."""
+    """The cache file format is read back into the table; unknown keys report 1.
+    Lines written before a field existed read as that field's default."""
+    from paper_1701_00426_amd import _lib
     lat = _lat((32, 32, 32, 32))
+    lat8 = _lat((8, 8, 8, 8))
     lib.stg_autotune_clear()
-    x, sp, us = ctypes.c_int(-1), ctypes.c_int(-1), ctypes.c_double(-1)
-    assert lib.stg_autotune_lookup(ctypes.byref(lat), 1, 1, ctypes.byref(x), ctypes.byref(sp),
-                                   ctypes.byref(us)) == 1
+    c = _lib.StgTuneChoice()
+    assert lib.stg_autotune_lookup(ctypes.byref(lat), 1, 1, ctypes.byref(c)) == 1
     f = tmp_path / "tune.jsonl"
+    head = '{"arch": "gfx950", "dims": '
     f.write_text(
-        '{"arch": "gfx950", "dims": [32, 32, 32, 32], "fmt": 1, "nr": 1, "xcd_remap": 0, '
+        head + '[32, 32, 32, 32], "fmt": 1, "nr": 1, "xcd_remap": 0, '
         '"sites_per_thread": 2, "us": 87.5}\n'
         'not a line of the cache\n'
-        '{"arch": "gfx950", "dims": [32, 32, 32, 32], "fmt": 1, "nr": 1, "xcd_remap": 1, '
-        '"sites_per_thread": 4, "us": 80.25}\n'
-        '{"arch": "gfx950", "dims": [8, 8, 8, 8], "fmt": 2, "nr": 4, "xcd_remap": 1, '
-        '"sites_per_thread": 3, "us": 1.0}\n')
+        + head + '[32, 32, 32, 32], "fmt": 1, "nr": 1, "xcd_remap": 1, '
+        '"sites_per_thread": 4, "stage_neighbours": 1, "threads_per_site": 1, "us": 80.25}\n'
+        + head + '[8, 8, 8, 8], "fmt": 2, "nr": 4, "xcd_remap": 1, '
+        '"sites_per_thread": 3, "us": 1.0}\n'
+        + head + '[8, 8, 8, 8], "fmt": 2, "nr": 2, "xcd_remap": 1, '
+        '"sites_per_thread": 1, "stage_neighbours": 2, "us": 1.0}\n'
+        + head + '[8, 8, 8, 8], "fmt": 2, "nr": 8, "xcd_remap": 1, '
+        '"sites_per_thread": 1, "stage_neighbours": 0, "threads_per_site": 3, "us": 1.0}\n'
+        + '{"arch": "gfx942", "dims": [8, 8, 8, 8], "fmt": 2, "nr": 1, "xcd_remap": 1, '
+        '"sites_per_thread": 1, "us": 1.0}\n'
+        + head + '[8, 8, 8, 8], "fmt": 2, "nr": 1, "xcd_remap": 0, '
+        '"sites_per_thread": 2, "us": 3.5}\n'
+        + head + '[8, 8, 8, 8], "fmt": 3, "nr": 2, "xcd_remap": 1, '
+        '"sites_per_thread": 1, "stage_neighbours": 0, "threads_per_site": 4, "us": 2.25}\n')
     n = ctypes.c_int(0)
     assert lib.stg_autotune_load(str(f).encode(), ctypes.byref(n)) == 0
-    assert n.value == 2  # the malformed line and the invalid sites-per-thread are skipped
-    assert lib.stg_autotune_lookup(ctypes.byref(lat), 1, 1, ctypes.byref(x), ctypes.byref(sp),
-                                   ctypes.byref(us)) == 0
-    assert (x.value, sp.value, us.value) == (1, 4, 80.25)
+    # skipped: the malformed line, sites per thread 3, staging 2, threads per site 3,
+    # another architecture
+    assert n.value == 4
+    assert lib.stg_autotune_lookup(ctypes.byref(lat), 1, 1, ctypes.byref(c)) == 0
+    assert (c.xcd_remap, c.sites_per_thread, c.stage_neighbours, c.threads_per_site,
+            c.us) == (1, 4, 1, 1, 80.25)
+    assert lib.stg_autotune_lookup(ctypes.byref(lat8), 2, 1, ctypes.byref(c)) == 0
+    assert (c.xcd_remap, c.sites_per_thread, c.stage_neighbours, c.threads_per_site,
+            c.us) == (0, 2, 0, 1, 3.5)
+    assert lib.stg_autotune_lookup(ctypes.byref(lat8), 3, 2, ctypes.byref(c)) == 0
+    assert (c.threads_per_site, c.us) == (4, 2.25)
+    for fmt, nr in ((2, 4), (2, 2), (2, 8)):
+        assert lib.stg_autotune_lookup(ctypes.byref(lat8), fmt, nr, ctypes.byref(c)) == 1
     assert lib.stg_autotune_load(b"/nonexistent/file", ctypes.byref(n)) == -1
     lib.stg_autotune_clear()
-    assert lib.stg_autotune_lookup(ctypes.byref(lat), 1, 1, ctypes.byref(x), ctypes.byref(sp),
-                                   ctypes.byref(us)) == 1
+    assert lib.stg_autotune_lookup(ctypes.byref(lat), 1, 1, ctypes.byref(c)) == 1
 
 
 def test_tuning_knobs(lib):
@@ -191,6 +212,12 @@ def test_tuning_knobs(lib):
     assert lib.stg_set_tuning(2, 1) == 0
     assert lib.stg_get_tuning(2, ctypes.byref(v)) == 0 and v.value == 1
     assert lib.stg_set_tuning(2, 0) == 0
+    # threads per site: 0 (automatic, the default), 1, 2 or 4
+    assert lib.stg_get_tuning(3, ctypes.byref(v)) == 0 and v.value == 0
+    assert lib.stg_set_tuning(3, 3) == -1
+    assert lib.stg_set_tuning(3, 4) == 0
+    assert lib.stg_get_tuning(3, ctypes.byref(v)) == 0 and v.value == 4
+    assert lib.stg_set_tuning(3, 0) == 0
 
 
 def test_cg_default_params(lib):

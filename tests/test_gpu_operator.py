@@ -49,11 +49,14 @@ def test_pack_links_exact(dims, corc):
     assert np.array_equal(gotbf, want)
 
 
+@pytest.mark.parametrize("tps", [0, 1])
 @pytest.mark.parametrize("fmt", ["c128_18", "c128_12", "c64_12", "bf16_12"])
 @pytest.mark.parametrize("dims", SHAPES)
-def test_hop_parity(dims, fmt, corc):
-    """D_eo and D_oe on random SU(3) links, standard phases computed in-kernel."""
-    say(f"hop {fmt} {dims}")
+def test_hop_parity(dims, fmt, tps, corc, tuning):
+    """D_eo and D_oe on random SU(3) links, standard phases computed in-kernel, with
+    the automatic launch shape and with one thread per site."""
+    say(f"hop {fmt} {dims} tps={tps}")
+    tuning(stg._lib.STG_TUNE_THREADS_PER_SITE, tps)
     links = si.su3_links(dims, 1701, 7, 0)
     phases = on.standard_phases(dims)
     g = stg.pack_gauge(dims, to_dev(links), fmt)
@@ -71,11 +74,14 @@ def test_hop_parity(dims, fmt, corc):
 
 @pytest.fixture
 def staged_neighbours():
-    key = stg._lib.STG_TUNE_STAGE_NEIGHBOURS
-    old = stg.stg_get_tuning(key)
-    stg.stg_set_tuning(key, 1)
+    """Neighbour staging on, with one thread per site (the kernel that stages)."""
+    keys = (stg._lib.STG_TUNE_STAGE_NEIGHBOURS, stg._lib.STG_TUNE_THREADS_PER_SITE)
+    old = [stg.stg_get_tuning(k) for k in keys]
+    stg.stg_set_tuning(keys[0], 1)
+    stg.stg_set_tuning(keys[1], 1)
     yield
-    stg.stg_set_tuning(key, old)
+    for k, v in zip(keys, old):
+        stg.stg_set_tuning(k, v)
 
 
 @pytest.mark.parametrize("spt", [1, 2])
@@ -106,6 +112,63 @@ def test_hop_staged_neighbours(dims, fmt, nrhs, spt, corc, staged_neighbours):
         stg.stg_set_tuning(key, old)
 
 
+@pytest.fixture
+def tuning():
+    """Sets hop tuning knobs for one test and restores them afterwards."""
+    saved = {}
+
+    def set_(key, value):
+        if key not in saved:
+            saved[key] = stg.stg_get_tuning(key)
+        stg.stg_set_tuning(key, value)
+
+    yield set_
+    for key, value in saved.items():
+        stg.stg_set_tuning(key, value)
+
+
+@pytest.mark.parametrize("tps", [2, 4])
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 8, 13])
+@pytest.mark.parametrize("fmt", ["c128_18", "c128_12", "c64_12", "bf16_12"])
+@pytest.mark.parametrize("dims", [(4, 6, 8, 10), (6, 4, 2, 10), (2, 2, 2, 2), (10, 2, 4, 2)])
+def test_hop_threads_per_site(dims, fmt, nrhs, tps, corc, tuning):
+    """The hop with the directions of a site shared by 2 or 4 threads (partials
+    combined in LDS; FP64 with 8 fields at 4 threads falls back to one thread) for
+    both parities, explicit and standard phases, against the oracle."""
+    say(f"hop tps={tps} {fmt} {dims} nrhs={nrhs}")
+    tuning(stg._lib.STG_TUNE_THREADS_PER_SITE, tps)
+    links = si.su3_links(dims, 1701, 9, 0)
+    phases = on.standard_phases(dims)
+    cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
+    for explicit in (False, True):
+        ph = si.real_link_field(dims, 9, 1) if explicit else phases
+        g = stg.pack_gauge(dims, to_dev(links), fmt,
+                           phases_f64=to_dev(ph) if explicit else None)
+        for par, fn in ((0, stg.dirac_apply_eo), (1, stg.dirac_apply_oe)):
+            v = si.gaussian_field(dims, nrhs, 426, 9, par)
+            got = fn(g, to_dev(v).to(cdt)).cpu().numpy().astype(np.complex128)
+            want = corc.dslash(dims, links, ph, par, v)
+            for j in range(nrhs):
+                assert rel_max(got[j], want[j]) <= TOL[fmt]
+
+
+@pytest.mark.parametrize("tps", [2, 4])
+@pytest.mark.parametrize("fmt", ["c128_12", "c64_12"])
+def test_apply_normal_threads_per_site(fmt, tps, corc, tuning):
+    """The normal-operator epilogue (q = diag p - D_eo D_oe p) in the shared-site kernel."""
+    dims = (4, 6, 4, 6)
+    tuning(stg._lib.STG_TUNE_THREADS_PER_SITE, tps)
+    links = si.su3_links(dims, 11, 1)
+    phases = on.standard_phases(dims)
+    g = stg.pack_gauge(dims, to_dev(links), fmt)
+    cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
+    v = si.gaussian_field(dims, 5, 11, 2)
+    got = stg.stg_apply_normal(g, 0.3, to_dev(v).to(cdt), sigma=0.05).cpu().numpy()
+    for j in range(5):
+        want = corc.apply_normal(dims, links, phases, 0.3, v[j], sigma=0.05)
+        assert rel_max(got[j].astype(np.complex128), want) <= TOL[fmt]
+
+
 @pytest.mark.parametrize("fmt", ["c128_12", "c64_12"])
 def test_hop_explicit_phases(fmt, corc):
     """Arbitrary real per-link phases read from memory (the paper's backfield array)."""
@@ -123,12 +186,14 @@ def test_hop_explicit_phases(fmt, corc):
         assert rel_max(got, want) <= TOL[fmt]
 
 
+@pytest.mark.parametrize("tps", [0, 1])
 @pytest.mark.parametrize("nrhs", [2, 3, 5, 8, 11])
 @pytest.mark.parametrize("fmt", ["c128_12", "c64_12"])
-def test_hop_multi_rhs(nrhs, fmt, corc):
+def test_hop_multi_rhs(nrhs, fmt, tps, corc, tuning):
     """Several fields per launch (chunks of 8/4/2/1): each equals its own hop."""
     dims = (4, 4, 6, 4)
-    say(f"hop multi-rhs {fmt} nrhs={nrhs}")
+    say(f"hop multi-rhs {fmt} nrhs={nrhs} tps={tps}")
+    tuning(stg._lib.STG_TUNE_THREADS_PER_SITE, tps)
     links = si.su3_links(dims, 9, nrhs)
     phases = on.standard_phases(dims)
     g = stg.pack_gauge(dims, to_dev(links), fmt)
@@ -138,9 +203,11 @@ def test_hop_multi_rhs(nrhs, fmt, corc):
     want = corc.dslash(dims, links, phases, 1, v)
     for j in range(nrhs):
         assert rel_max(got[j], want[j]) <= TOL[fmt]
+    # the last field alone: the same values up to the order of additions (the
+    # launch shape may differ with the number of fields)
     single = stg.dirac_apply_oe(g, to_dev(v[nrhs - 1:]).to(cdt)).cpu().numpy()
-    if fmt == "c128_12":
-        assert np.array_equal(single[0], got[nrhs - 1].astype(single.dtype))
+    assert rel_max(single[0].astype(np.complex128), got[nrhs - 1]) <= \
+        (1e-14 if fmt == "c128_12" else 1e-6)
 
 
 @pytest.mark.parametrize("fmt", ["c128_12", "c64_12", "bf16_12"])

@@ -69,10 +69,12 @@ def test_cg_mixed(lofmt, corc):
     _check(corc, dims, links, phases, 0.1, b, x.cpu().numpy(), stats, label=lofmt)
 
 
+@pytest.mark.parametrize("nrhs", [5, 8])
 @pytest.mark.parametrize("mode", ["f64", "c64_12"])
-def test_cg_multi_rhs(mode, corc):
+def test_cg_multi_rhs(mode, nrhs, corc):
+    """Chunks of 4 + 1 and 8 fields per launch, with the default launch shapes
+    (several threads per site: the most blocks, so the most reduction partials)."""
     dims = (4, 6, 4, 8)
-    nrhs = 5
     say(f"cg multi-rhs {mode} nrhs={nrhs}")
     links, phases, b = _problem(dims, (2, 0), nrhs)
     dl = to_dev(links)
@@ -171,3 +173,24 @@ def test_multishift(mode, corc):
         rus = [s["reliable_updates"] for row in stats for s in row]
         say(f"  refinement updates per system: {rus}")
         assert max(rus) <= 2 and sum(r == 1 for r in rus) >= len(rus) // 2
+
+
+@pytest.mark.parametrize("tps", [2, 4])
+@pytest.mark.parametrize("mode", ["f64", "c64_12", "bf16_12"])
+def test_cg_threads_per_site(mode, tps, corc):
+    """CG with every hop (plain, normal-operator and true-residual epilogues) in the
+    kernel that shares a site's directions among 2 or 4 threads; 3 RHS."""
+    dims = (8, 4, 6, 8)
+    key = stg._lib.STG_TUNE_THREADS_PER_SITE
+    old = stg.stg_get_tuning(key)
+    stg.stg_set_tuning(key, tps)
+    try:
+        links, phases, b = _problem(dims, (8, tps), 3)
+        dl = to_dev(links)
+        hi = stg.pack_gauge(dims, dl, "c128_12")
+        lo = stg.pack_gauge(dims, dl, mode) if mode != "f64" else None
+        x, st, stats = stg.cg_solve(hi, 0.1, to_dev(b), lo=lo, tol=TOL)
+        _check(corc, dims, links, phases, 0.1, b, x.cpu().numpy(), stats,
+               label=f"{mode} tps={tps}")
+    finally:
+        stg.stg_set_tuning(key, old)
