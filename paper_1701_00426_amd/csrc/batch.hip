@@ -64,26 +64,29 @@ __device__ void bhop_tile(const BArgs &a, const BSolve &S, const BTile &t) {
             } else if (EPI == EPI_NORMAL) {
                 const T d = (T)st.diag;
                 vec3<T> p = ld_v<T>(aux0, fs, g.Vh, j, h);
+                double site = 0.0;  // the site's terms in FP64, then one compensated add
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     o.c[c].re = d * p.c[c].re - half * acc[j].c[c].re;
                     o.c[c].im = d * p.c[c].im - half * acc[j].c[c].im;
-                    pair_add(ps[j], pc[j], (double)p.c[c].re * (double)o.c[c].re, 0.0);
-                    pair_add(ps[j], pc[j], (double)p.c[c].im * (double)o.c[c].im, 0.0);
+                    site = fmat((double)p.c[c].re, (double)o.c[c].re, site);
+                    site = fmat((double)p.c[c].im, (double)o.c[c].im, site);
                 }
+                pair_add(ps[j], pc[j], site, 0.0);
             } else {  // EPI_RESID: FP64 only (aux1 = b, complex128)
                 if (!(st.flags & SYS_RU_PENDING)) continue;
                 const T d = (T)st.diag;
                 vec3<T> x = ld_v<T>(aux0, fs, g.Vh, j, h);
                 vec3<T> b = ld_v<T>(aux1, fs, g.Vh, j, h);
+                double site = 0.0;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     o.c[c].re = b.c[c].re - (d * x.c[c].re - half * acc[j].c[c].re);
                     o.c[c].im = b.c[c].im - (d * x.c[c].im - half * acc[j].c[c].im);
-                    pair_add(ps[j], pc[j], (double)o.c[c].re * (double)o.c[c].re +
-                                               (double)o.c[c].im * (double)o.c[c].im,
-                             0.0);
+                    site = fmat((double)o.c[c].re, (double)o.c[c].re, site);
+                    site = fmat((double)o.c[c].im, (double)o.c[c].im, site);
                 }
+                pair_add(ps[j], pc[j], site, 0.0);
             }
             st_v<T>(out, fs, g.Vh, j, h, o);
         }

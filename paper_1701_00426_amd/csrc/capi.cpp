@@ -1532,43 +1532,48 @@ int stg_autotune(const stg_lattice *lat, const stg_gauge *gauge, stg_field field
     // repetitions: about 20 ms of work per candidate, at least 5
     const double est_us = 1e-3 * (double)g.Vh * nr;  // ~1 ns per site and field
     const int reps = (int)std::max(5.0, std::min(200.0, 20000.0 / std::max(est_us, 1.0)));
-    TuneChoice best{1, 1, 0, 1, 1e300};
-    auto time_shape = [&](const TuneChoice &c) -> int {
-        a.xcd_remap = c.xcd_remap;
-        a.sites_per_thread = (uint32_t)c.sites_per_thread;
-        a.stage_neighbours = (uint32_t)c.stage_neighbours;
-        a.threads_per_site = (uint32_t)c.threads_per_site;
-        for (int w = 0; w < 2; ++w) launch_hop(a, gauge->fmt, nr, EPI_PLAIN, s);
-        HIP_TRY(hipEventRecord(e0, s));
-        for (int r = 0; r < reps; ++r) launch_hop(a, gauge->fmt, nr, EPI_PLAIN, s);
-        HIP_TRY(hipEventRecord(e1, s));
-        HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        const double us = 1e3 * ms / reps;
-        if (us < best.us) {
-            best = c;
-            best.us = us;
-        }
-        return STG_OK;
-    };
-    // one thread per site: block order x chunks per block x LDS staging (where it
-    // applies); several threads per site: block order (one chunk, no staging)
+    // the candidates, timed in two interleaved passes (each keeps its faster pass, so a
+    // clock or power transient during one pass does not decide the choice)
+    std::vector<TuneChoice> cand;
     const int spts[4] = {1, 2, 4, 8};
     const int nstage = stage_applies(nr, g.nh0) ? 2 : 1;
     const size_t elem = gauge->fmt == STG_LINK_C128_18 || gauge->fmt == STG_LINK_C128_12 ? 16 : 8;
-    int rc2 = STG_OK;
-    for (int xcd = 0; xcd < 2 && rc2 == STG_OK; ++xcd) {
-        for (int stage = 0; stage < nstage && rc2 == STG_OK; ++stage)
-            for (int si = 0; si < 4 && rc2 == STG_OK; ++si)
-                rc2 = time_shape(TuneChoice{xcd, spts[si], stage, 1, 0.0});
-        for (int tps = 2; tps <= 4 && rc2 == STG_OK; tps *= 2)
+    for (int xcd = 0; xcd < 2; ++xcd) {
+        // one thread per site: chunks per block x LDS staging (where it applies)
+        for (int stage = 0; stage < nstage; ++stage)
+            for (int si = 0; si < 4; ++si) cand.push_back(TuneChoice{xcd, spts[si], stage, 1, 1e300});
+        // several threads per site (one chunk, no staging)
+        for (int tps = 2; tps <= 4; tps *= 2)
             if (split_lds_bytes(elem, nr, tps) <= kSplitLdsMax)
-                rc2 = time_shape(TuneChoice{xcd, 1, 0, tps, 0.0});
+                cand.push_back(TuneChoice{xcd, 1, 0, tps, 1e300});
     }
-    if (rc2 != STG_OK) return rc2;
+    int rc2 = STG_OK;
+    for (int pass = 0; pass < 2 && rc2 == STG_OK; ++pass)
+        for (size_t k = 0; k < cand.size() && rc2 == STG_OK; ++k) {
+            TuneChoice &c = cand[k];
+            a.xcd_remap = c.xcd_remap;
+            a.sites_per_thread = (uint32_t)c.sites_per_thread;
+            a.stage_neighbours = (uint32_t)c.stage_neighbours;
+            a.threads_per_site = (uint32_t)c.threads_per_site;
+            for (int w = 0; w < 2; ++w) launch_hop(a, gauge->fmt, nr, EPI_PLAIN, s);
+            hipError_t e = hipEventRecord(e0, s);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) launch_hop(a, gauge->fmt, nr, EPI_PLAIN, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc2 = hip_fail(e, "autotune timing");
+                break;
+            }
+            c.us = std::min(c.us, 1e3 * ms / reps);
+        }
+    TuneChoice best{1, 1, 0, 1, 1e300};
+    for (const TuneChoice &c : cand)
+        if (c.us < best.us) best = c;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (rc2 != STG_OK) return rc2;
     HIP_TRY(hipGetLastError());
     tune_store(g, gauge->fmt, nr, best);
     if (cache_path && tune_append_file(cache_path, g, gauge->fmt, nr, best))

@@ -155,26 +155,29 @@ __device__ __forceinline__ void hop_epilogue_field(const HopArgs &a, uint32_t h,
     } else if (EPI == EPI_NORMAL) {
         const T d = (T)a.st_diag(j);
         vec3<T> p = ld_v<T>(a.aux0, a.fstride, g.Vh, j, h);
+        double site = 0.0;  // this site's six terms in FP64, then one compensated add
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             o.c[c].re = d * p.c[c].re - half * acc.c[c].re;
             o.c[c].im = d * p.c[c].im - half * acc.c[c].im;
-            pair_add(ps, pc, (double)p.c[c].re * (double)o.c[c].re, 0.0);
-            pair_add(ps, pc, (double)p.c[c].im * (double)o.c[c].im, 0.0);
+            site = fmat((double)p.c[c].re, (double)o.c[c].re, site);
+            site = fmat((double)p.c[c].im, (double)o.c[c].im, site);
         }
+        pair_add(ps, pc, site, 0.0);
     } else {  // EPI_RESID
         if (!a.st_pending(j)) return;
         const T d = (T)a.st_diag(j);
         vec3<T> x = ld_v<T>(a.aux0, a.fstride, g.Vh, j, h);
         vec3<T> b = ld_v<T>(a.aux1, a.fstride, g.Vh, j, h);
+        double site = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             o.c[c].re = b.c[c].re - (d * x.c[c].re - half * acc.c[c].re);
             o.c[c].im = b.c[c].im - (d * x.c[c].im - half * acc.c[c].im);
-            pair_add(ps, pc, (double)o.c[c].re * (double)o.c[c].re +
-                                 (double)o.c[c].im * (double)o.c[c].im,
-                     0.0);
+            site = fmat((double)o.c[c].re, (double)o.c[c].re, site);
+            site = fmat((double)o.c[c].im, (double)o.c[c].im, site);
         }
+        pair_add(ps, pc, site, 0.0);
     }
     st_v<T>(a.out, a.fstride, g.Vh, j, h, o);
 }
