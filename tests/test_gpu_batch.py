@@ -38,9 +38,20 @@ def _inputs(lofmt):
     return out
 
 
+@pytest.fixture(params=[0, 1], ids=["tps-auto", "tps-1"])
+def batch_tps(request):
+    """Launch shapes of the single solves the batch is compared with: automatic
+    (several threads per site for several fields) and one thread per site."""
+    key = stg._lib.STG_TUNE_THREADS_PER_SITE
+    old = stg.stg_get_tuning(key)
+    stg.stg_set_tuning(key, request.param)
+    yield request.param
+    stg.stg_set_tuning(key, old)
+
+
 @pytest.mark.parametrize("lofmt", [None, "c64_12", "bf16_12"])
-def test_batch_parity_and_equal_to_single(lofmt):
-    say(f"batch {lofmt or 'f64'}: {[s[0] for s in SOLVES]}")
+def test_batch_parity_and_equal_to_single(lofmt, batch_tps):
+    say(f"batch {lofmt or 'f64'} tps={batch_tps}: {[s[0] for s in SOLVES]}")
     inp = _inputs(lofmt)
     solves = [dict(hi=v["hi"], lo=v["lo"], mass=v["mass"], b=v["b"]) for v in inp]
     xs, st, stats = stg.cg_solve_batch(solves, tol=TOL)
