@@ -120,23 +120,32 @@ def copy_ceiling(torch, nbytes=1 << 30, reps=20):
 
 
 def read_ceiling(torch, nbytes=1 << 30, reps=20):
-    """Read GB/s of a plain sum over three rotating 1 GiB device buffers (beyond the
-    Infinity Cache; HIP events): the practical ceiling of a read-dominated stream."""
+    """Read GB/s of the fastest of a few plain read-only library reductions over three
+    rotating 1 GiB device buffers (beyond the Infinity Cache; HIP events): a floor on
+    the practical ceiling of a read-dominated stream on this GPU."""
     bufs = [torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0") for _ in range(3)]
-    for b in bufs:
-        b.sum()
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for i in range(reps):
-        bufs[i % 3].sum()
-    t1.record()
-    t1.synchronize()
-    dt = t0.elapsed_time(t1) * 1e-3 / reps
+    ops = {"dot": lambda i: torch.dot(bufs[i % 3], bufs[(i + 1) % 3]),
+           "sum": lambda i: bufs[i % 3].sum(),
+           "rowsum": lambda i: bufs[i % 3].view(-1, 4096).sum(1),
+           "amax": lambda i: bufs[i % 3].amax()}
+    best = {}
+    for name, op in ops.items():
+        for i in range(3):
+            op(i)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for i in range(reps):
+            op(i)
+        t1.record()
+        t1.synchronize()
+        dt = t0.elapsed_time(t1) * 1e-3 / reps
+        read = 2 * nbytes if name == "dot" else nbytes
+        best[name] = round(read / dt / 1e9, 1)
     del bufs
     torch.cuda.empty_cache()
-    return round(nbytes / dt / 1e9, 1)
+    return max(best.values()), best
 
 
 def calibrate_copy():
@@ -427,7 +436,7 @@ def main():
                           "fp64_iters": r[2]["iters"], "mixed_iters": r[3]["iters"]}), flush=True)
         return
     copy_gbs = copy_ceiling(torch)
-    read_gbs = read_ceiling(torch)
+    read_gbs, read_ops = read_ceiling(torch)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -477,6 +486,7 @@ def main():
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
         "copy_ceiling_GBs": copy_gbs,
         "read_ceiling_GBs": read_gbs,
+        "read_ceiling_ops_GBs": read_ops,
         "frac_of_read_ceiling": round(achieved / read_gbs, 4),
         "cg_fp64_s_per_rhs": round(t64, 4),
         "cg_mixed_s_per_rhs": round(tmx, 4),

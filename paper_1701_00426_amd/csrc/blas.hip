@@ -5,8 +5,9 @@
 // Every vector kernel fuses the axpy updates with the reduction that follows
 // them (|r|^2 after x += alpha p, r -= alpha q), so a CG iteration reads each
 // vector the minimum number of times.  Reductions: TwoSum per thread, wave64
-// shuffle and LDS pair tree, one (sum, error) pair per block, and a one-block
-// finalize kernel that adds the pairs in a fixed order and runs the scalar step.
+// shuffle and LDS pair tree, one (sum, error) pair per block, and a finalize
+// kernel (one block per system) that adds the pairs in a fixed order and runs the
+// scalar step.
 
 #include "device_common.hpp"
 #include "kernels.hpp"

@@ -133,6 +133,19 @@ __device__ __forceinline__ void st_v(void *base, size_t fstride, uint32_t Vh, in
     for (int c = 0; c < 3; ++c) st_c<T>(base, o + (size_t)c * Vh, v.c[c]);
 }
 
+// FP64 colour vector stored with non-temporal stores (streamed past the caches):
+// the hop's plain output is not re-read by the same launch.
+__device__ __forceinline__ void st_v_nt(void *base, size_t fstride, uint32_t Vh, int j,
+                                        uint32_t h, const vec3<double> &v) {
+    typedef double sd2 __attribute__((ext_vector_type(2)));
+    sd2 *p = reinterpret_cast<sd2 *>(base) + (size_t)j * fstride + h;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        sd2 w = {v.c[c].re, v.c[c].im};
+        __builtin_nontemporal_store(w, p + (size_t)c * Vh);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // gauge links: formats of the C ABI, slot s = 2*mu + parity
 // ---------------------------------------------------------------------------

@@ -19,8 +19,8 @@
 //   EPI_NORMAL  out = diag_j * p - D in           with p on the output parity;
 //               block partials of Re<p, out>      (normal operator, CG's <p, A p>)
 //   EPI_RESID   out = b - (diag_j * x - D in)      true residual; block partials of |out|^2
-// Reductions leave one compensated (sum, error) pair per block; a one-block
-// finalize kernel adds them in a fixed order and runs the scalar step of
+// Reductions leave one compensated (sum, error) pair per block; a finalize kernel
+// (one block per system) adds them in a fixed order and runs the scalar step of
 // solver_state.hpp.
 
 #include "device_common.hpp"

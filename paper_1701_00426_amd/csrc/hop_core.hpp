@@ -179,7 +179,12 @@ __device__ __forceinline__ void hop_epilogue_field(const HopArgs &a, uint32_t h,
         }
         pair_add(ps, pc, site, 0.0);
     }
-    st_v<T>(a.out, a.fstride, g.Vh, j, h, o);
+    // FP64 plain output streams past the caches (measured 2 % faster at 32^4; the
+    // FP32 hop gains nothing)
+    if constexpr (EPI == EPI_PLAIN && sizeof(T) == 8)
+        st_v_nt(a.out, a.fstride, g.Vh, j, h, o);
+    else
+        st_v<T>(a.out, a.fstride, g.Vh, j, h, o);
 }
 
 template <typename T, int NR, int EPI>

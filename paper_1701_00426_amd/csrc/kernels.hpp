@@ -65,8 +65,8 @@ __device__ __forceinline__ void block_partials(double (&s)[NR], double (&c)[NR],
     }
 }
 
-// One block: adds the nblocks pairs of each of nr sums in a fixed order and runs
-// the scalar step `op` (solver_state.hpp) for each of the nr systems.
+// One block per system j < nr: adds the nblocks pairs of its sum in a fixed order
+// and runs the scalar step `op` (solver_state.hpp) for it.
 struct FinArgs {
     const double *partials;
     uint32_t nblocks;
