@@ -132,7 +132,7 @@ const char *stg_last_error(void);
  *     meet in LDS (with 2 or 4, sites per thread and staging do not apply; 4 is
  *     not built for FP64 links with 8 fields per launch, which then take one
  *     thread per site).  Automatic: by link format, fields per launch and
- *     epilogue (one field: 1, or 4 for the plain FP32 / BF16 hop; two or four
+ *     epilogue (one field: 1, or 4 for the plain BF16-12 hop; two to four
  *     fields: 4; eight fields: 4 for the plain FP32 / BF16 hop, else 2).  An
  *     autotuned shape sets it for the plain hop only.  The choice changes the
  *     order of floating-point additions, so results may differ in the last bits
@@ -157,7 +157,7 @@ int stg_get_tuning(int key, int *value);
  * fields (in: device
  * [nrhs][3][Vh] on odd sites; out: device, overwritten), keeps the fastest for
  * the key (lattice extents, gauge format, fields per launch = the largest chunk
- * of nrhs among 8, 4, 2, 1) in a process-wide table that every later hop launch
+ * of nrhs among 8, 4, 3, 2, 1) in a process-wide table that every later hop launch
  * with that key uses, and, when cache_path is not NULL, appends it to that file as
  * one JSON object per line.  Synchronous.  stg_autotune_load reads such a file
  * into the table (later lines win) and reports the entries read in *loaded.

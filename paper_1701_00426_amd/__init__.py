@@ -373,7 +373,7 @@ def stg_autotune(gauge: Gauge, nrhs: int = 1, cache_path: Optional[str] = None, 
     _lib.check("stg_autotune", lib.stg_autotune(
         ctypes.byref(_lib.lattice(gauge.dims)), ctypes.byref(g), int(gauge.field), int(nrhs),
         _ptr(vin), _ptr(out), cache_path.encode() if cache_path else None, _stream(stream)))
-    nr = 8 if nrhs >= 8 else 4 if nrhs >= 4 else 2 if nrhs >= 2 else 1
+    nr = 8 if nrhs >= 8 else 4 if nrhs >= 4 else nrhs
     return stg_autotune_lookup(gauge.dims, gauge.fmt, nr)
 
 

@@ -4,7 +4,7 @@
 // paper fixes the lattice extents at compile time (Sec. 4.1 LNH_N0..), so one
 // launch serves one lattice.  Here every kernel of a CG step walks a table of
 // tiles that spans all lattices of the batch: a tile is kBlock consecutive sites of
-// one lattice for a chunk of 1, 2 or 4 right-hand sides.  One launch per step
+// one lattice for a chunk of 1 to 4 right-hand sides.  One launch per step
 // therefore serves every solve, small lattices ride along with large ones, and
 // the launch count does not grow with the number of solves.  A persistent grid
 // deals the tiles round-robin in XCD-aware order; each kernel only touches tiles
@@ -34,6 +34,57 @@ __device__ __forceinline__ bool tile_active(const BArgs &a, const BSolve &S, con
     for (uint32_t ti = xcd_block(blockIdx.x, gridDim.x); ti < (a).ntiles; \
          ti += gridDim.x)
 
+// Epilogue of a tile's fields at site h (acc = twice the hop): plain, normal
+// operator with Re<p, q> partials, or true residual with |r|^2 partials.
+template <typename T, int NR, int EPI>
+__device__ __forceinline__ void bhop_epilogue(const BArgs &a, const BSolve &S, const BTile &t,
+                                              uint32_t h, const vec3<T> (&acc)[NR],
+                                              double (&ps)[NR], double (&pc)[NR]) {
+    const Geom &g = S.g;
+    const size_t fs = (size_t)3 * g.Vh;
+    const size_t e = sizeof(T) * 2;
+    char *out = (char *)a.field(S, a.f_out) + t.j0 * fs * e;
+    const char *aux0 = (const char *)a.field(S, a.f_aux0) + t.j0 * fs * e;
+    const char *aux1 = EPI == EPI_RESID ? (const char *)S.b + t.j0 * fs * 16 : nullptr;
+    const T half = T(0.5);
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const SysState &st = a.state[S.sys0 + t.j0 + j];
+        vec3<T> o;
+        if (EPI == EPI_PLAIN) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) o.c[c] = cscale(half, acc[j].c[c]);
+        } else if (EPI == EPI_NORMAL) {
+            const T d = (T)st.diag;
+            vec3<T> p = ld_v<T>(aux0, fs, g.Vh, j, h);
+            double site = 0.0;  // the site's terms in FP64, then one compensated add
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                o.c[c].re = d * p.c[c].re - half * acc[j].c[c].re;
+                o.c[c].im = d * p.c[c].im - half * acc[j].c[c].im;
+                site = fmat((double)p.c[c].re, (double)o.c[c].re, site);
+                site = fmat((double)p.c[c].im, (double)o.c[c].im, site);
+            }
+            pair_add(ps[j], pc[j], site, 0.0);
+        } else {  // EPI_RESID: FP64 only (aux1 = b, complex128)
+            if (!(st.flags & SYS_RU_PENDING)) continue;
+            const T d = (T)st.diag;
+            vec3<T> x = ld_v<T>(aux0, fs, g.Vh, j, h);
+            vec3<T> b = ld_v<T>(aux1, fs, g.Vh, j, h);
+            double site = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                o.c[c].re = b.c[c].re - (d * x.c[c].re - half * acc[j].c[c].re);
+                o.c[c].im = b.c[c].im - (d * x.c[c].im - half * acc[j].c[c].im);
+                site = fmat((double)o.c[c].re, (double)o.c[c].re, site);
+                site = fmat((double)o.c[c].im, (double)o.c[c].im, site);
+            }
+            pair_add(ps[j], pc[j], site, 0.0);
+        }
+        st_v<T>(out, fs, g.Vh, j, h, o);
+    }
+}
+
 template <typename T, int FMT, bool STDPH, int NR, int EPI>
 __device__ void bhop_tile(const BArgs &a, const BSolve &S, const BTile &t) {
     const Geom &g = S.g;
@@ -43,9 +94,6 @@ __device__ void bhop_tile(const BArgs &a, const BSolve &S, const BTile &t) {
     const void *links = hi ? S.hi_links : S.lo_links;
     const void *phases = hi ? S.hi_phases : S.lo_phases;
     const char *in = (const char *)a.field(S, a.f_in) + t.j0 * fs * e;
-    char *out = (char *)a.field(S, a.f_out) + t.j0 * fs * e;
-    const char *aux0 = (const char *)a.field(S, a.f_aux0) + t.j0 * fs * e;
-    const char *aux1 = EPI == EPI_RESID ? (const char *)S.b + t.j0 * fs * 16 : nullptr;
     const uint32_t h = t.blk * kBlock + threadIdx.x;
     double ps[NR], pc[NR];
 #pragma unroll
@@ -53,43 +101,7 @@ __device__ void bhop_tile(const BArgs &a, const BSolve &S, const BTile &t) {
     if (h < g.Vh) {
         vec3<T> acc[NR];
         hop_site<T, FMT, STDPH, NR>(g, a.out_parity, h, links, phases, in, fs, acc);
-        const T half = T(0.5);
-#pragma unroll
-        for (int j = 0; j < NR; ++j) {
-            const SysState &st = a.state[S.sys0 + t.j0 + j];
-            vec3<T> o;
-            if (EPI == EPI_PLAIN) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) o.c[c] = cscale(half, acc[j].c[c]);
-            } else if (EPI == EPI_NORMAL) {
-                const T d = (T)st.diag;
-                vec3<T> p = ld_v<T>(aux0, fs, g.Vh, j, h);
-                double site = 0.0;  // the site's terms in FP64, then one compensated add
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    o.c[c].re = d * p.c[c].re - half * acc[j].c[c].re;
-                    o.c[c].im = d * p.c[c].im - half * acc[j].c[c].im;
-                    site = fmat((double)p.c[c].re, (double)o.c[c].re, site);
-                    site = fmat((double)p.c[c].im, (double)o.c[c].im, site);
-                }
-                pair_add(ps[j], pc[j], site, 0.0);
-            } else {  // EPI_RESID: FP64 only (aux1 = b, complex128)
-                if (!(st.flags & SYS_RU_PENDING)) continue;
-                const T d = (T)st.diag;
-                vec3<T> x = ld_v<T>(aux0, fs, g.Vh, j, h);
-                vec3<T> b = ld_v<T>(aux1, fs, g.Vh, j, h);
-                double site = 0.0;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    o.c[c].re = b.c[c].re - (d * x.c[c].re - half * acc[j].c[c].re);
-                    o.c[c].im = b.c[c].im - (d * x.c[c].im - half * acc[j].c[c].im);
-                    site = fmat((double)o.c[c].re, (double)o.c[c].re, site);
-                    site = fmat((double)o.c[c].im, (double)o.c[c].im, site);
-                }
-                pair_add(ps[j], pc[j], site, 0.0);
-            }
-            st_v<T>(out, fs, g.Vh, j, h, o);
-        }
+        bhop_epilogue<T, NR, EPI>(a, S, t, h, acc, ps, pc);
     }
     if (EPI != EPI_PLAIN) {
         __shared__ double sh_red[2 * kWaves];
@@ -118,6 +130,8 @@ __global__ __launch_bounds__(kBlock) void bhop_kernel(BArgs a) {
             case 2: bhop_tile<T, FMT, false, 1, EPI>(a, S, t); break;
             case 5: bhop_tile<T, FMT, true, 2, EPI>(a, S, t); break;
             case 4: bhop_tile<T, FMT, false, 2, EPI>(a, S, t); break;
+            case 7: bhop_tile<T, FMT, true, 3, EPI>(a, S, t); break;
+            case 6: bhop_tile<T, FMT, false, 3, EPI>(a, S, t); break;
             case 9: bhop_tile<T, FMT, true, 4, EPI>(a, S, t); break;
             default: bhop_tile<T, FMT, false, 4, EPI>(a, S, t); break;
         }

@@ -32,7 +32,7 @@ struct BTile {
     uint32_t solve;
     uint32_t blk;
     uint16_t j0;
-    uint16_t nr;  // 1, 2 or 4
+    uint16_t nr;  // 1 to 4
 };
 
 struct BSysRef {

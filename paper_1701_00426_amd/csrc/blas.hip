@@ -199,6 +199,8 @@ __global__ __launch_bounds__(kBlock) void ms_p_update_kernel(VecArgs a) {
             case 2: KERNEL<float, 1><<<grid, kBlock, 0, stream>>>(a); return 0;         \
             case 5: KERNEL<double, 2><<<grid, kBlock, 0, stream>>>(a); return 0;        \
             case 4: KERNEL<float, 2><<<grid, kBlock, 0, stream>>>(a); return 0;         \
+            case 7: KERNEL<double, 3><<<grid, kBlock, 0, stream>>>(a); return 0;        \
+            case 6: KERNEL<float, 3><<<grid, kBlock, 0, stream>>>(a); return 0;         \
             case 9: KERNEL<double, 4><<<grid, kBlock, 0, stream>>>(a); return 0;        \
             case 8: KERNEL<float, 4><<<grid, kBlock, 0, stream>>>(a); return 0;         \
             case 17: KERNEL<double, 8><<<grid, kBlock, 0, stream>>>(a); return 0;       \
@@ -250,6 +252,7 @@ int launch_ru_accumulate(const VecArgs &a, int nr, hipStream_t stream) {
     switch (nr) {
         case 1: ru_accumulate_kernel<1><<<grid, kBlock, 0, stream>>>(a); return 0;
         case 2: ru_accumulate_kernel<2><<<grid, kBlock, 0, stream>>>(a); return 0;
+        case 3: ru_accumulate_kernel<3><<<grid, kBlock, 0, stream>>>(a); return 0;
         case 4: ru_accumulate_kernel<4><<<grid, kBlock, 0, stream>>>(a); return 0;
         case 8: ru_accumulate_kernel<8><<<grid, kBlock, 0, stream>>>(a); return 0;
         default: return -1;

@@ -145,12 +145,12 @@ int hop(HopArgs a, int fmt, int nr, int epi, hipStream_t stream) {
     return launch_hop(a, fmt, nr, epi, stream);
 }
 
-// Largest supported chunk of fields for one kernel launch.
+// Largest supported chunk of fields for one kernel launch (8, 4, 3, 2 or 1: each
+// launch reads the links once for all its fields).
 int chunk_of(int remaining) {
     if (remaining >= 8) return 8;
     if (remaining >= 4) return 4;
-    if (remaining >= 2) return 2;
-    return 1;
+    return remaining;
 }
 
 int hop_plain(const Geom &g, const stg_gauge *gauge, int field, int nrhs, const void *in,
@@ -907,7 +907,8 @@ struct BatchPlan {
 constexpr uint32_t kBatchGrid = 2048;
 
 // Lays out the batch in ws (ws == nullptr: size only).  Tiles follow the solve
-// order, then the RHS chunks (4, 2, 1) of each solve, then the site blocks.
+// order, then the RHS chunks (4 while at least 4 remain, then the rest) of each
+// solve, then the site blocks.
 int plan_batch(int nsolve, const stg_solve_desc *d, int mode, void *ws, BatchPlan &B) {
     const bool f64 = mode == STG_CG_F64;
     Carver c{reinterpret_cast<char *>(ws)};
@@ -930,7 +931,7 @@ int plan_batch(int nsolve, const stg_solve_desc *d, int mode, void *ws, BatchPla
         sys += S.nrhs;
         for (int j0 = 0; j0 < d[i].nrhs;) {
             int rem = d[i].nrhs - j0;
-            int nr = rem >= 4 ? 4 : (rem >= 2 ? 2 : 1);
+            int nr = rem >= 4 ? 4 : rem;
             for (uint32_t blk = 0; blk < S.nblk; ++blk)
                 B.tiles.push_back(BTile{(uint32_t)i, blk, (uint16_t)j0, (uint16_t)nr});
             j0 += nr;

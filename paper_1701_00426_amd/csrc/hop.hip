@@ -121,6 +121,7 @@ static int launch_fmt(const HopArgs &a, int nr, int epi, hipStream_t stream) {
     switch (nr) {
         case 1: return launch_nr<T, FMT, STDPH, 1>(a, epi, stream);
         case 2: return launch_nr<T, FMT, STDPH, 2>(a, epi, stream);
+        case 3: return launch_nr<T, FMT, STDPH, 3>(a, epi, stream);
         case 4: return launch_nr<T, FMT, STDPH, 4>(a, epi, stream);
         case 8: return launch_nr<T, FMT, STDPH, 8>(a, epi, stream);
         default: return -1;
@@ -133,7 +134,7 @@ static int launch_ph(const HopArgs &a, int nr, int epi, hipStream_t stream) {
                     : launch_fmt<T, FMT, true>(a, nr, epi, stream);
 }
 
-// Launches one hop over NR in {1, 2, 4, 8} fields.  Returns 0, or nonzero without
+// Launches one hop over NR in {1, 2, 3, 4, 8} fields.  Returns 0, or nonzero without
 // launching for an unsupported combination (checked by the caller beforehand) or
 // when a reduction needs more (sum, error) pairs than a.partial_pairs.
 int launch_hop(const HopArgs &a, int fmt, int nr, int epi, hipStream_t stream) {

@@ -125,6 +125,7 @@ static int launch_fmt_split(const HopArgs &a, int nr, int epi, hipStream_t strea
     switch (nr) {
         case 1: return launch_nr_split<T, FMT, STDPH, 1>(a, epi, stream);
         case 2: return launch_nr_split<T, FMT, STDPH, 2>(a, epi, stream);
+        case 3: return launch_nr_split<T, FMT, STDPH, 3>(a, epi, stream);
         case 4: return launch_nr_split<T, FMT, STDPH, 4>(a, epi, stream);
         case 8: return launch_nr_split<T, FMT, STDPH, 8>(a, epi, stream);
         default: return -1;

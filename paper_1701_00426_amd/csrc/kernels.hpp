@@ -118,13 +118,14 @@ constexpr size_t split_lds_bytes(size_t elem_bytes, int nr, int tps) {
 int launch_hop_split(const HopArgs &a, int fmt, int nr, int epi, hipStream_t stream);  // -1: not built, -2: partials too small
 
 // Threads per site when the caller leaves the choice open, from hop timings at 32^4
-// on MI355X (one thread per site for one field: the same speed or faster, and the
-// profiled FP64-12 configuration; 4 for two or four fields; with 8 fields 4 for the
-// plain hop in FP32 / BF16, and 2 otherwise: group 0 runs the whole epilogue, which
-// for 8 fields costs more than the extra waves gain, and FP64 at 4 needs 72 KB LDS).
+// on MI355X: one field: one thread per site (the same speed or faster inside CG,
+// and the profiled FP64-12 configuration), except the plain BF16-12 hop (4: 5 %
+// faster); two to four fields: 4; eight fields: 4 for the plain FP32 / BF16 hop,
+// else 2 (group 0 runs the whole epilogue, which for 8 fields costs more than the
+// extra waves gain, and FP64 at 4 would need 72 KB of LDS per block).
 inline int default_threads_per_site(int fmt, int nr, int epi) {
     const bool fp64 = fmt == FMT_C128_18 || fmt == FMT_C128_12;
-    if (nr == 1) return (epi == EPI_PLAIN && !fp64) ? 4 : 1;
+    if (nr == 1) return (epi == EPI_PLAIN && fmt == FMT_BF16_12) ? 4 : 1;
     if (nr <= 4) return 4;
     return (epi == EPI_PLAIN && !fp64) ? 4 : 2;
 }

@@ -190,7 +190,7 @@ def test_hop_explicit_phases(fmt, corc):
 @pytest.mark.parametrize("nrhs", [2, 3, 5, 8, 11])
 @pytest.mark.parametrize("fmt", ["c128_12", "c64_12"])
 def test_hop_multi_rhs(nrhs, fmt, tps, corc, tuning):
-    """Several fields per launch (chunks of 8/4/2/1): each equals its own hop."""
+    """Several fields per launch (chunks of 8/4/3/2/1): each equals its own hop."""
     dims = (4, 4, 6, 4)
     say(f"hop multi-rhs {fmt} nrhs={nrhs} tps={tps}")
     tuning(stg._lib.STG_TUNE_THREADS_PER_SITE, tps)
