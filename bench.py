@@ -201,27 +201,21 @@ def bench_multishift():
     print(json.dumps(out), flush=True)
 
 
-def bench_batch():
-    """12 solves: two each on 8^4, 12^4, 16^4, 16^3x32, 24^4, 32^4 at m = 0.01 and 0.05,
-    nrhs_i = 1 + (i mod 4): one cg_solve_batch (mixed FP32-12) against the same solves
-    launched one after another with cg_solve."""
+def _batch_run(shapes_masses, label):
+    """One cg_solve_batch (mixed FP32-12) over the solves, against the same solves
+    launched one after another with cg_solve; nrhs_i = 1 + (i mod 4)."""
     import torch
     import paper_1701_00426_amd as stg
     import seeded_inputs as si
     dev = torch.device("cuda:0")
-    shapes = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16), (16, 16, 16, 32),
-              (24, 24, 24, 24), (32, 32, 32, 32)]
     solves = []
-    i = 0
-    for dims in shapes:
-        for m in (0.01, 0.05):
-            nrhs = 1 + (i % 4)
-            links = torch.from_numpy(si.su3_links(dims, 1701, 5, i)).to(dev)
-            b = torch.from_numpy(si.gaussian_field(dims, nrhs, 426, 5, i)).to(dev)
-            solves.append(dict(hi=stg.pack_gauge(dims, links, "c128_12"),
-                               lo=stg.pack_gauge(dims, links, "c64_12"), mass=m, b=b))
-            del links
-            i += 1
+    for i, (dims, m) in enumerate(shapes_masses):
+        nrhs = 1 + (i % 4)
+        links = torch.from_numpy(si.su3_links(dims, 1701, 5, i)).to(dev)
+        b = torch.from_numpy(si.gaussian_field(dims, nrhs, 426, 5, i)).to(dev)
+        solves.append(dict(hi=stg.pack_gauge(dims, links, "c128_12"),
+                           lo=stg.pack_gauge(dims, links, "c64_12"), mass=m, b=b))
+        del links
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     xs, st, stats = stg.cg_solve_batch(solves, tol=TOL)
@@ -235,14 +229,31 @@ def bench_batch():
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t1
     flat = [q for row in stats for q in row]
-    out = {"workload": "uneven batch: 12 solves (8^4, 12^4, 16^4, 16^3x32, 24^4, 32^4 x m in "
-                       "{0.01, 0.05}), 30 RHS, FP32-12 + FP64 reliable updates, tol 1e-10",
-           "status": st, "makespan_s": round(t_batch, 3), "sequential_cg_solve_s": round(t_seq, 3),
+    out = {"workload": label, "status": st, "makespan_s": round(t_batch, 3),
+           "sequential_cg_solve_s": round(t_seq, 3),
            "speedup_vs_sequential": round(t_seq / t_batch, 3),
            "worst_true_rel_resid": max(q["true_rel_resid"] for q in flat),
            "worst_true_rel_resid_sequential": worst_single,
            "max_iters": max(q["iters"] for q in flat), "nsys": len(flat)}
     print(json.dumps(out), flush=True)
+
+
+def bench_batch():
+    """12 solves: two each on 8^4, 12^4, 16^4, 16^3x32, 24^4, 32^4 at m = 0.01 and 0.05."""
+    shapes = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16), (16, 16, 16, 32),
+              (24, 24, 24, 24), (32, 32, 32, 32)]
+    _batch_run([(d, m) for d in shapes for m in (0.01, 0.05)],
+               "uneven batch: 12 solves (8^4, 12^4, 16^4, 16^3x32, 24^4, 32^4 x m in "
+               "{0.01, 0.05}), 30 RHS, FP32-12 + FP64 reliable updates, tol 1e-10")
+
+
+def bench_batch_small():
+    """48 small solves: 16 each on 8^4, 12^4 and 16^4 at m in {0.05, 0.1}: the regime the
+    batch is for, where one launch per kernel and solve is all overhead."""
+    shapes = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16)]
+    _batch_run([(d, (0.05, 0.1)[k % 2]) for d in shapes for k in range(16)],
+               "uneven batch of small lattices: 48 solves (16 each on 8^4, 12^4, 16^4, m in "
+               "{0.05, 0.1}), 120 RHS, FP32-12 + FP64 reliable updates, tol 1e-10")
 
 
 # The paper's Table 3 lattices, written N0 x N1 x N2 x N3 with time last, and its
@@ -305,10 +316,11 @@ def main():
                     help="for rocprofv3: only the dominant kernel's timed loop (FP64-12 D_eo)")
     ap.add_argument("--profile-cg", action="store_true",
                     help="for rocprofv3: one FP64 CG and one mixed CG solve only")
-    ap.add_argument("--workload", choices=["main", "multishift", "batch", "shapes"],
+    ap.add_argument("--workload", choices=["main", "multishift", "batch", "batch-small", "shapes"],
                     default="main",
                     help="main: the 32^4 line; multishift: 24^3x48, 16 shifts x 8 RHS; "
-                         "batch: 12 solves on 8^4 .. 32^4 in one cg_solve_batch")
+                         "batch: 12 solves on 8^4 .. 32^4 in one cg_solve_batch; "
+                         "batch-small: 48 solves on 8^4 .. 16^4")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="for rocprofv3 --pmc: a plain 1 GiB device copy, to scale byte counters")
     args = ap.parse_args()
@@ -324,6 +336,9 @@ def main():
         return
     if args.workload == "batch":
         bench_batch()
+        return
+    if args.workload == "batch-small":
+        bench_batch_small()
         return
     if args.workload == "shapes":
         bench_shapes()

@@ -142,69 +142,102 @@ __global__ __launch_bounds__(kBlock) void bhop_kernel(BArgs a) {
 // vector kernels over tiles
 // ---------------------------------------------------------------------------
 
-// x += alpha p; r -= alpha q; partials of |r|^2  (running systems)
+// x += alpha p; r -= alpha q; partials of |r|^2  (running systems).  Compiled per
+// field count so that the loads of all fields of a tile are issued together and
+// the block reductions follow them.
+template <typename T, int NR>
+__device__ void bcg_update_tile(const BArgs &a, const BSolve &S, const BTile &t,
+                                double *sh_red) {
+    const size_t fs = (size_t)3 * S.g.Vh;
+    const uint32_t h = t.blk * kBlock + threadIdx.x;
+    double ps[NR], pc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        ps[j] = pc[j] = 0.0;
+        const int js = t.j0 + j;
+        const SysState &st = a.state[S.sys0 + js];
+        if (!(st.flags & SYS_RUNNING) || h >= S.g.Vh) continue;
+        const T al = (T)st.alpha;
+        double site = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t i = js * fs + (size_t)c * S.g.Vh + h;
+            cpx<T> x = ld_c<T>(S.xin, i), p = ld_c<T>(S.p, i), r = ld_c<T>(S.r, i),
+                   q = ld_c<T>(S.q, i);
+            x.re += al * p.re;
+            x.im += al * p.im;
+            r.re -= al * q.re;
+            r.im -= al * q.im;
+            st_c<T>(S.xin, i, x);
+            st_c<T>(S.r, i, r);
+            site = fmat((double)r.re, (double)r.re, site);
+            site = fmat((double)r.im, (double)r.im, site);
+        }
+        pair_add(ps[j], pc[j], site, 0.0);
+    }
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        block_sum_pair(ps[j], pc[j], sh_red);
+        if (threadIdx.x == 0) {
+            double *pj = a.partials + 2 * ((size_t)S.part0 + (size_t)(t.j0 + j) * S.nblk + t.blk);
+            pj[0] = ps[j];
+            pj[1] = pc[j];
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void bcg_update_kernel(BArgs a) {
-    if (a.gate_running && a.ctl->n_running == 0) return;
+    if (block_gate_closed(a.ctl, a.gate_running)) return;
     __shared__ double sh_red[2 * kWaves];
     FOR_EACH_TILE(a, ti) {
         const BTile t = a.tiles[ti];
         const BSolve &S = a.solves[t.solve];
         if (!tile_active(a, S, t)) continue;
-        const size_t fs = (size_t)3 * S.g.Vh;
-        const uint32_t h = t.blk * kBlock + threadIdx.x;
-        for (int j = 0; j < t.nr; ++j) {
-            const int js = t.j0 + j;
-            const SysState &st = a.state[S.sys0 + js];
-            double ps = 0.0, pc = 0.0;
-            if ((st.flags & SYS_RUNNING) && h < S.g.Vh) {
-                const T al = (T)st.alpha;
-                for (int c = 0; c < 3; ++c) {
-                    const size_t i = js * fs + (size_t)c * S.g.Vh + h;
-                    cpx<T> x = ld_c<T>(S.xin, i), p = ld_c<T>(S.p, i), r = ld_c<T>(S.r, i),
-                           q = ld_c<T>(S.q, i);
-                    x.re += al * p.re;
-                    x.im += al * p.im;
-                    r.re -= al * q.re;
-                    r.im -= al * q.im;
-                    st_c<T>(S.xin, i, x);
-                    st_c<T>(S.r, i, r);
-                    pair_add(ps, pc, (double)r.re * (double)r.re + (double)r.im * (double)r.im,
-                             0.0);
-                }
-            }
-            block_sum_pair(ps, pc, sh_red);
-            if (threadIdx.x == 0) {
-                double *pj = a.partials + 2 * ((size_t)S.part0 + (size_t)js * S.nblk + t.blk);
-                pj[0] = ps;
-                pj[1] = pc;
-            }
+        switch (t.nr) {
+            case 1: bcg_update_tile<T, 1>(a, S, t, sh_red); break;
+            case 2: bcg_update_tile<T, 2>(a, S, t, sh_red); break;
+            case 3: bcg_update_tile<T, 3>(a, S, t, sh_red); break;
+            default: bcg_update_tile<T, 4>(a, S, t, sh_red); break;
         }
     }
 }
 
 // p = r + beta p  (running systems)
+template <typename T, int NR>
+__device__ __forceinline__ void bp_update_tile(const BArgs &a, const BSolve &S, const BTile &t) {
+    const size_t fs = (size_t)3 * S.g.Vh;
+    const uint32_t h = t.blk * kBlock + threadIdx.x;
+    if (h >= S.g.Vh) return;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const int js = t.j0 + j;
+        const SysState &st = a.state[S.sys0 + js];
+        if (!(st.flags & SYS_RUNNING)) continue;
+        const T be = (T)st.beta;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t i = js * fs + (size_t)c * S.g.Vh + h;
+            cpx<T> p = ld_c<T>(S.p, i), r = ld_c<T>(S.r, i);
+            p.re = r.re + be * p.re;
+            p.im = r.im + be * p.im;
+            st_c<T>(S.p, i, p);
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void bp_update_kernel(BArgs a) {
     if (a.gate_running && a.ctl->n_running == 0) return;
     FOR_EACH_TILE(a, ti) {
         const BTile t = a.tiles[ti];
         const BSolve &S = a.solves[t.solve];
-        const size_t fs = (size_t)3 * S.g.Vh;
-        const uint32_t h = t.blk * kBlock + threadIdx.x;
-        if (h >= S.g.Vh || !tile_active(a, S, t)) continue;
-        for (int j = 0; j < t.nr; ++j) {
-            const int js = t.j0 + j;
-            const SysState &st = a.state[S.sys0 + js];
-            if (!(st.flags & SYS_RUNNING)) continue;
-            const T be = (T)st.beta;
-            for (int c = 0; c < 3; ++c) {
-                const size_t i = js * fs + (size_t)c * S.g.Vh + h;
-                cpx<T> p = ld_c<T>(S.p, i), r = ld_c<T>(S.r, i);
-                p.re = r.re + be * p.re;
-                p.im = r.im + be * p.im;
-                st_c<T>(S.p, i, p);
-            }
+        if (!tile_active(a, S, t)) continue;
+        switch (t.nr) {
+            case 1: bp_update_tile<T, 1>(a, S, t); break;
+            case 2: bp_update_tile<T, 2>(a, S, t); break;
+            case 3: bp_update_tile<T, 3>(a, S, t); break;
+            default: bp_update_tile<T, 4>(a, S, t); break;
         }
     }
 }
