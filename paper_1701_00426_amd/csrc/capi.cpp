@@ -1393,7 +1393,7 @@ int stg_dot(stg_field field, int nvec, size_t n, const void *x, const void *y, d
     double *partials = (double *)c.take(sizeof(double) * 4 * 1024);
     double *out = (double *)c.take(16);
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(hipMemsetAsync(ctl, 0, sizeof(Ctl), s));
+    launch_zero(ctl, sizeof(Ctl), s);  // a fill kernel, not a memset node
     for (int j = 0; j < nvec; ++j) {
         const size_t off = (size_t)j * n * field_elem(field);
         launch_dot(field == STG_C128, 1, n, (const char *)x + off, (const char *)y + off,
