@@ -321,3 +321,49 @@ def test_deterministic_hop_and_dot():
     b = stg.dirac_apply_eo(g, v)
     assert torch.equal(a, b)
     assert stg.stg_dot(a, v) == stg.stg_dot(b, v)
+
+
+@pytest.mark.parametrize("fmt,nrhs", [("c64_12", 1), ("c64_12", 3), ("c128_12", 2),
+                                      ("bf16_12", 1)])
+def test_autotune_choice_and_parity(fmt, nrhs, corc, tmp_path):
+    """stg_autotune times the launch shapes on the caller's buffers, keeps a valid
+    choice in the process-wide table and the cache file (read back by
+    stg_autotune_load), and the hop launched with that shape matches the oracle."""
+    dims = (8, 6, 4, 10)
+    say(f"autotune {fmt} nrhs={nrhs}")
+    links = si.su3_links(dims, 1701, 12, 0)
+    phases = on.standard_phases(dims)
+    g = stg.pack_gauge(dims, to_dev(links), fmt)
+    cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
+    cache = tmp_path / "tune.jsonl"
+    lib = stg.library()
+    lib.stg_autotune_clear()
+    try:
+        choice = stg.stg_autotune(g, nrhs, cache_path=str(cache))
+        say(f"  choice {choice}")
+        assert choice["xcd_remap"] in (0, 1)
+        assert choice["sites_per_thread"] in (1, 2, 4, 8)
+        assert choice["stage_neighbours"] in (0, 1)
+        assert choice["threads_per_site"] in (1, 2, 4)
+        assert choice["us"] > 0
+        if choice["threads_per_site"] > 1:
+            assert choice["sites_per_thread"] == 1 and choice["stage_neighbours"] == 0
+        v = si.gaussian_field(dims, nrhs, 426, 12, 1)
+        got = stg.dirac_apply_eo(g, to_dev(v).to(cdt)).cpu().numpy().astype(np.complex128)
+        want = corc.dslash(dims, links, phases, 0, v)
+        for j in range(nrhs):
+            assert rel_max(got[j], want[j]) <= TOL[fmt]
+        lib.stg_autotune_clear()
+        assert stg.stg_autotune_lookup(dims, g.fmt, choice_nr(nrhs)) is None
+        assert stg.stg_autotune_load(str(cache)) == 1
+        again = stg.stg_autotune_lookup(dims, g.fmt, choice_nr(nrhs))
+        assert {k: again[k] for k in choice if k != "us"} == {k: choice[k] for k in choice
+                                                               if k != "us"}
+        assert abs(again["us"] - choice["us"]) <= 1e-3
+    finally:
+        lib.stg_autotune_clear()
+
+
+def choice_nr(nrhs):
+    """Fields per launch of the first chunk of nrhs fields (8, 4, or nrhs below 4)."""
+    return 8 if nrhs >= 8 else 4 if nrhs >= 4 else nrhs
