@@ -305,6 +305,62 @@ def bench_shapes():
           flush=True)
 
 
+# Launch-shape variants of the hop compared under one kernel trace: (format, fields,
+# knob settings).  Each runs the same number of back-to-back D_eo launches.
+VARIANTS = [
+    ("c128_12", 1, {"tps": 1, "stage": 0, "xcd": 1}, "default"),
+    ("c128_12", 1, {"tps": 1, "stage": 0, "xcd": 0}, "plain block order"),
+    ("c128_12", 1, {"tps": 1, "stage": 1, "xcd": 1}, "LDS neighbour staging"),
+    ("c128_12", 1, {"tps": 4, "stage": 0, "xcd": 1}, "4 threads per site"),
+    ("c64_12", 1, {"tps": 1, "stage": 0, "xcd": 1}, "default"),
+    ("c64_12", 1, {"tps": 1, "stage": 1, "xcd": 1}, "LDS neighbour staging"),
+    ("c64_12", 1, {"tps": 4, "stage": 0, "xcd": 1}, "4 threads per site"),
+    ("c64_12", 8, {"tps": 1, "stage": 0, "xcd": 1}, "1 thread per site"),
+    ("c64_12", 8, {"tps": 2, "stage": 0, "xcd": 1}, "2 threads per site"),
+    ("c64_12", 8, {"tps": 4, "stage": 0, "xcd": 1}, "default (4 threads per site)"),
+    ("bf16_12", 1, {"tps": 1, "stage": 0, "xcd": 1}, "1 thread per site"),
+    ("bf16_12", 1, {"tps": 4, "stage": 0, "xcd": 1}, "default (4 threads per site)"),
+]
+
+
+def profile_variants(applies=100):
+    """For rocprofv3: the hop variants of VARIANTS at 32^4, `applies` D_eo launches each,
+    in order; prints one JSON line per variant with its HIP-event mean."""
+    import torch
+    import paper_1701_00426_amd as stg
+    import seeded_inputs as si
+    dev = torch.device("cuda:0")
+    vh = stg.half_volume(DIMS)
+    links = torch.from_numpy(si.su3_links(DIMS, 1701, 2, 0)).to(dev)
+    b8 = torch.from_numpy(si.gaussian_field(DIMS, 8, 426, 2, 0, 0)).to(dev)
+    L = stg._lib
+    keys = {"tps": L.STG_TUNE_THREADS_PER_SITE, "stage": L.STG_TUNE_STAGE_NEIGHBOURS,
+            "xcd": L.STG_TUNE_XCD_REMAP}
+    cache = {}
+    for fmt, nr, knobs, label in VARIANTS:
+        if fmt not in cache:
+            cache.clear()
+            torch.cuda.empty_cache()
+            cache[fmt] = [stg.pack_gauge(DIMS, links if i == 0 else links.clone(), fmt)
+                          for i in range(3)]
+        gauges = cache[fmt]
+        cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
+        fields = [b8[:nr].to(cdt).clone() for _ in range(3)]
+        outs = [torch.empty_like(fields[0]) for _ in range(3)]
+        for k, v in knobs.items():
+            stg.stg_set_tuning(keys[k], v)
+        dt = time_applies(stg, torch, gauges, fields, outs, 0, applies)
+        stg.stg_set_tuning(keys["tps"], 0)
+        stg.stg_set_tuning(keys["stage"], 0)
+        stg.stg_set_tuning(keys["xcd"], 1)
+        links_b = {"c128_12": 768, "c64_12": 384, "bf16_12": 192}[fmt]
+        field_b = 96 if fmt.startswith("c128") else 48
+        gbs = (links_b + nr * field_b) * vh / dt / 1e9
+        print(json.dumps({"format": fmt, "fields": nr, "variant": label, "knobs": knobs,
+                          "mean_launch_us": round(dt * 1e6, 2), "GBs": round(gbs, 1)}), flush=True)
+        del fields, outs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -321,6 +377,8 @@ def main():
                     help="main: the 32^4 line; multishift: 24^3x48, 16 shifts x 8 RHS; "
                          "batch: 12 solves on 8^4 .. 32^4 in one cg_solve_batch; "
                          "batch-small: 48 solves on 8^4 .. 16^4")
+    ap.add_argument("--profile-variants", action="store_true",
+                    help="for rocprofv3: the hop's launch-shape variants at 32^4, in order")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="for rocprofv3 --pmc: a plain 1 GiB device copy, to scale byte counters")
     args = ap.parse_args()
@@ -330,6 +388,9 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.profile_variants:
+        profile_variants()
         return
     if args.workload == "multishift":
         bench_multishift()
