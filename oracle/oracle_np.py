@@ -14,7 +14,9 @@ Paper: Bonati et al., arXiv:1701.00426.
   * Sec. 2.2, Eq. diracblock -- M = m + [[0, D_oe], [D_eo, 0]], D_oe^dag = -D_eo.
   * Sec. 2.2, Eq. lineqeo -- (m^2 - D_eo D_oe) phi_e = b_e, Hermitian positive
     definite, solved by CG.
-  * Sec. 2.2, Eq. shlineq -- shifted systems (M + sigma_i) phi_i = b.
+  * Sec. 2.2, Eq. shlineq -- shifted systems (M + sigma_i) phi_i = b; with the
+    coefficients of a rational approximation (Eq. rooting, the RHMC algorithm)
+    their solutions combine into r(A) b.
   * Sec. 4.3, deo listing -- the operator takes links, in, out and a real
     per-link "backfield" array; here that array carries the staggered phases.
 
@@ -194,6 +196,23 @@ def cg(dims, links, phases, mass, b, tol=1e-12, max_iter=100000, sigma=0.0, x0=N
 def true_relative_residual(dims, links, phases, mass, b, x, sigma=0.0):
     res = b - apply_normal(dims, links, phases, mass, x, sigma)
     return math.sqrt(_re_dot(res, res) / _re_dot(b, b))
+
+
+def rational_apply(dims, links, phases, mass, shifts, coeffs, a0, b, tol=1e-12):
+    """y = a0 b + sum_k coeffs[k] (m^2 + shifts[k] - D_eo D_oe)^{-1} b.
+
+    The rational function of the normal operator that the RHMC algorithm uses in
+    place of the fractional power of Eq. rooting (Sec. 2.2): its poles are the
+    shifts of Eq. shlineq, whose solutions are combined with the caller's
+    coefficients.  Each shifted system is solved here by plain CG (the definition;
+    no multi-shift recurrence).  Returns (y, worst true relative residual)."""
+    y = a0 * np.asarray(b, dtype=np.complex128)
+    worst = 0.0
+    for s, a in zip(shifts, coeffs):
+        x, _, res = cg(dims, links, phases, mass, b, tol=tol, sigma=s)
+        y = y + a * x
+        worst = max(worst, res)
+    return y, worst
 
 
 # --------------------------------------------------------------------------

@@ -190,3 +190,56 @@ if given is not None:
             assert pins.rel_err(corc.dslash(dims, links, phases, par, v),
                                 on.dslash(dims, links, phases, par, v)) < 1e-14
         assert pins.gauge_covariance(on.dslash, dims, seed=seed % 997) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# rational function of the normal operator (RHMC, Eq. rooting / Eq. shlineq)
+# --------------------------------------------------------------------------
+def test_rational_apply_free_field_closed_form():
+    """Unit links: a plane wave is an eigenvector of A with lambda = m^2 + sum sin^2 p,
+    so r(A) pw = (a0 + sum_k a_k / (lambda + sigma_k)) pw exactly."""
+    dims = (4, 6, 4, 8)
+    links = on.unit_links(dims)
+    phases = on.standard_phases(dims)
+    mass = 0.1
+    shifts = [0.0, 0.03, 0.4, 2.5]
+    coeffs = [0.7, -0.2, 1.3, 0.05]
+    a0 = 0.25
+    for n in ((0, 0, 0, 0), (1, 2, 3, 1), (3, 5, 1, 6)):
+        p = on.momenta(dims, n)
+        pw = on.plane_wave(dims, 0, p, np.array([1.0, 0.5j, -0.25 + 0.1j]))
+        lam = on.free_eigenvalue(mass, p)
+        want = (a0 + sum(a / (lam + s) for a, s in zip(coeffs, shifts))) * pw
+        y, worst = on.rational_apply(dims, links, phases, mass, shifts, coeffs, a0, pw)
+        assert worst <= 1e-12
+        assert np.max(np.abs(y - want)) <= 1e-10 * np.max(np.abs(want))
+
+
+def test_rational_apply_partial_fractions():
+    """1/((x+s1)(x+s2)) = (1/(x+s1) - 1/(x+s2)) / (s2 - s1): with those coefficients
+    (A + s2)(A + s1) y = b, checked with the operator itself on random SU(3) links."""
+    dims = (4, 4, 2, 6)
+    links = si.su3_links(dims, 31, 0)
+    phases = on.standard_phases(dims)
+    mass, s1, s2 = 0.2, 0.01, 0.3
+    b = si.gaussian_field(dims, 1, 31, 1)[0]
+    c = 1.0 / (s2 - s1)
+    y, worst = on.rational_apply(dims, links, phases, mass, [s1, s2], [c, -c], 0.0, b)
+    assert worst <= 1e-12
+    back = on.apply_normal(dims, links, phases, mass,
+                           on.apply_normal(dims, links, phases, mass, y, sigma=s1), sigma=s2)
+    assert np.linalg.norm(back - b) <= 1e-9 * np.linalg.norm(b)
+
+
+def test_rational_apply_linear_in_coefficients():
+    dims = (2, 4, 2, 4)
+    links = si.su3_links(dims, 32, 0)
+    phases = on.standard_phases(dims)
+    b = si.gaussian_field(dims, 1, 32, 1)[0]
+    shifts = [0.0, 0.1, 1.0]
+    ca, cb = [1.0, 2.0, -0.5], [0.3, -1.0, 0.25]
+    ya, _ = on.rational_apply(dims, links, phases, 0.1, shifts, ca, 0.5, b)
+    yb, _ = on.rational_apply(dims, links, phases, 0.1, shifts, cb, -0.2, b)
+    yab, _ = on.rational_apply(dims, links, phases, 0.1, shifts,
+                               [u + v for u, v in zip(ca, cb)], 0.3, b)
+    assert np.max(np.abs(yab - (ya + yb))) <= 1e-10 * np.max(np.abs(yab))
