@@ -201,6 +201,42 @@ def bench_multishift():
     print(json.dumps(out), flush=True)
 
 
+def bench_rational():
+    """The multi-shift workload of bench_multishift combined into a rational function
+    of the normal operator: y = a0 b + sum_k a_k (A + sigma_k)^-1 b with synthetic
+    coefficients a_k = 1 / (1 + k), a0 = 0.5 (a caller's RHMC approximation would
+    supply its own), 8 RHS, FP32-12 multi-shift stage + FP64 refinement to 1e-10."""
+    import torch
+    import paper_1701_00426_amd as stg
+    import seeded_inputs as si
+    dims, mass, nrhs = (24, 24, 24, 48), 0.005, 8
+    shifts = si.log_shifts(16, 1e-4, 10.0)
+    coeffs = [1.0 / (1 + k) for k in range(len(shifts))]
+    dev = torch.device("cuda:0")
+    log("generating 24^3x48 inputs")
+    links = torch.from_numpy(si.su3_links(dims, 1701, 4, 0)).to(dev)
+    b = torch.from_numpy(si.gaussian_field(dims, nrhs, 426, 4, 0)).to(dev)
+    hi = stg.pack_gauge(dims, links, "c128_12")
+    lo = stg.pack_gauge(dims, links, "c64_12")
+    ws = torch.empty(stg.stg_rational_workspace_bytes(dims, nrhs, len(shifts), stg.STG_CG_MIXED),
+                     dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    y, st, stats = stg.rational_apply(hi, mass, shifts, coeffs, 0.5, b, lo=lo, ws=ws, tol=TOL)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    flat = [s for row in stats for s in row]
+    vh = stg.half_volume(dims)
+    out = {"workload": "rational function a0 b + sum_k a_k (A + sigma_k)^-1 b, 24^3x48 "
+                       "m=0.005, 16 poles in [1e-4, 10], 8 RHS, FP32-12 + FP64 refinement "
+                       "to 1e-10",
+           "status": st, "seconds": round(dt, 3), "s_per_rhs": round(dt / nrhs, 4),
+           "worst_true_rel_resid": max(s["true_rel_resid"] for s in flat),
+           "sum_kernel_bytes": (len(shifts) + 2) * 16 * 3 * vh * nrhs,
+           "workspace_GB": round(ws.numel() / 1e9, 2)}
+    print(json.dumps(out), flush=True)
+
+
 def _batch_run(shapes_masses, label):
     """One cg_solve_batch (mixed FP32-12) over the solves, against the same solves
     launched one after another with cg_solve; nrhs_i = 1 + (i mod 4)."""
@@ -372,9 +408,11 @@ def main():
                     help="for rocprofv3: only the dominant kernel's timed loop (FP64-12 D_eo)")
     ap.add_argument("--profile-cg", action="store_true",
                     help="for rocprofv3: one FP64 CG and one mixed CG solve only")
-    ap.add_argument("--workload", choices=["main", "multishift", "batch", "batch-small", "shapes"],
+    ap.add_argument("--workload", choices=["main", "multishift", "rational", "batch",
+                                           "batch-small", "shapes"],
                     default="main",
                     help="main: the 32^4 line; multishift: 24^3x48, 16 shifts x 8 RHS; "
+                         "rational: the same shifts combined into r(A) b; "
                          "batch: 12 solves on 8^4 .. 32^4 in one cg_solve_batch; "
                          "batch-small: 48 solves on 8^4 .. 16^4")
     ap.add_argument("--profile-variants", action="store_true",
@@ -394,6 +432,9 @@ def main():
         return
     if args.workload == "multishift":
         bench_multishift()
+        return
+    if args.workload == "rational":
+        bench_rational()
         return
     if args.workload == "batch":
         bench_batch()

@@ -291,6 +291,27 @@ int multishift_cg_solve(const stg_lattice *lat, const stg_gauge *hi, const stg_g
                         size_t ws_bytes, stg_cg_stats *stats, stg_stream_t stream);
 
 /*
+ * Rational function of the normal operator applied to each RHS (the RHMC use of
+ * Eq. shlineq: the fractional power of Eq. rooting is replaced by a rational
+ * approximation whose poles are the shifts, Sec. 2.2):
+ *   y_j = a0 b_j + sum_k coeffs[k] (mass^2 + shifts[k] - D_eo D_oe)^{-1} b_j,  j < nrhs.
+ * The coefficients and poles are the caller's (the library does not compute
+ * rational approximations).  Solves every shifted system as multishift_cg_solve
+ * does (same params, modes and stopping test) into the workspace, then forms y in
+ * one fused pass.  shifts, coeffs (host) have nshift entries, shifts >= 0.
+ * b_even, y_even (device) are complex128 [nrhs][3][Vh].  ws (device) has
+ * ws_bytes >= stg_rational_workspace_bytes.  stats (host) gets nshift*nrhs entries
+ * ordered as for multishift_cg_solve.  Returns STG_OK when every system converged,
+ * else the worst status (y is then formed from the last iterates).
+ */
+int stg_rational_workspace_bytes(const stg_lattice *lat, int nrhs, int nshift, int mode,
+                                 size_t *bytes);
+int rational_apply(const stg_lattice *lat, const stg_gauge *hi, const stg_gauge *lo, double mass,
+                   int nshift, const double *shifts, const double *coeffs, double a0, int nrhs,
+                   const void *b_even, void *y_even, const stg_cg_params *params, void *ws,
+                   size_t ws_bytes, stg_cg_stats *stats, stg_stream_t stream);
+
+/*
  * Uneven batch: independent CG solves on lattices of different sizes, each
  * (mass^2 - D_eo D_oe) x_j = b_j as in cg_solve (Sec. 2.2 Eq. lineqeo), advanced
  * together.  Every kernel of a CG step walks one table of tiles spanning all the

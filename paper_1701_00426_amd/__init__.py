@@ -31,7 +31,8 @@ __all__ = [
     "Gauge", "pack_gauge", "stg_links_bytes", "stg_pack_links", "stg_pack_phases",
     "dirac_apply_eo", "dirac_apply_oe", "stg_apply_normal", "stg_dot", "cg_solve",
     "multishift_cg_solve", "stg_workspace_bytes", "library", "stg_set_tuning", "stg_get_tuning",
-    "cg_solve_batch", "stg_autotune", "stg_autotune_load", "stg_autotune_lookup",
+    "cg_solve_batch", "rational_apply", "stg_rational_workspace_bytes", "stg_autotune",
+    "stg_autotune_load", "stg_autotune_lookup",
 ]
 
 FORMAT_NAMES = {"c128_18": STG_LINK_C128_18, "c128_12": STG_LINK_C128_12,
@@ -301,6 +302,50 @@ def multishift_cg_solve(hi: Gauge, mass: float, shifts, b: torch.Tensor,
         _lib.check("multishift_cg_solve", st, ok=(_lib.STG_OK,))
     out = [[stats[k * nrhs + j].as_dict() for j in range(nrhs)] for k in range(ns)]
     return x, st, out
+
+
+def stg_rational_workspace_bytes(dims, nrhs: int, nshift: int, mode: int) -> int:
+    n = ctypes.c_size_t(0)
+    _lib.check("stg_rational_workspace_bytes", library().stg_rational_workspace_bytes(
+        ctypes.byref(_lib.lattice(dims)), int(nrhs), int(nshift), int(mode), ctypes.byref(n)))
+    return n.value
+
+
+def rational_apply(hi: Gauge, mass: float, shifts, coeffs, a0: float, b: torch.Tensor,
+                   lo: Optional[Gauge] = None, ws: Optional[torch.Tensor] = None, stream=None,
+                   check_status: bool = True, **params):
+    """y_j = a0 b_j + sum_k coeffs[k] (mass^2 + shifts[k] - D_eo D_oe)^{-1} b_j.
+
+    Returns (y complex128 (nrhs, 3, Vh), status, stats[nshift][nrhs]).
+    """
+    vh = half_volume(hi.dims)
+    if b.dtype != torch.complex128:
+        raise ValueError("b must be complex128")
+    nrhs = _nrhs(b, vh)
+    shifts = [float(s) for s in shifts]
+    coeffs = [float(c) for c in coeffs]
+    if len(coeffs) != len(shifts):
+        raise ValueError("one coefficient per shift")
+    ns = len(shifts)
+    y = torch.empty_like(b)
+    params.setdefault("mode", STG_CG_MIXED if lo is not None else STG_CG_F64)
+    prm = cg_params(**params)
+    need = stg_rational_workspace_bytes(hi.dims, nrhs, ns, prm.mode)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=b.device)
+    stats = (_lib.StgCgStats * (ns * nrhs))()
+    sh = (ctypes.c_double * ns)(*shifts)
+    co = (ctypes.c_double * ns)(*coeffs)
+    g_hi = hi.c()
+    g_lo = lo.c() if lo is not None else None
+    st = library().rational_apply(
+        ctypes.byref(_lib.lattice(hi.dims)), ctypes.byref(g_hi),
+        ctypes.byref(g_lo) if g_lo is not None else None, float(mass), ns, sh, co, float(a0),
+        nrhs, _ptr(b), _ptr(y), ctypes.byref(prm), _ptr(ws), ws.numel(), stats, _stream(stream))
+    if check_status:
+        _lib.check("rational_apply", st, ok=(_lib.STG_OK,))
+    out = [[stats[k * nrhs + j].as_dict() for j in range(nrhs)] for k in range(ns)]
+    return y, st, out
 
 
 def cg_solve_batch(solves, mode=None, ws: Optional[torch.Tensor] = None, stream=None,

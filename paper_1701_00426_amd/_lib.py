@@ -109,6 +109,10 @@ SIGNATURES = {
     "multishift_cg_solve": (_I, [_LAT, _G, _G, _D, _I, ctypes.POINTER(_D), _I, _P, _P,
                                  ctypes.POINTER(StgCgParams), _P, _S,
                                  ctypes.POINTER(StgCgStats), _P]),
+    "stg_rational_workspace_bytes": (_I, [_LAT, _I, _I, _I, ctypes.POINTER(_S)]),
+    "rational_apply": (_I, [_LAT, _G, _G, _D, _I, ctypes.POINTER(_D), ctypes.POINTER(_D), _D,
+                            _I, _P, _P, ctypes.POINTER(StgCgParams), _P, _S,
+                            ctypes.POINTER(StgCgStats), _P]),
     "stg_batch_workspace_bytes": (_I, [_I, ctypes.POINTER(StgSolveDesc), _I,
                                        ctypes.POINTER(_S)]),
     "cg_solve_batch": (_I, [_I, ctypes.POINTER(StgSolveDesc), ctypes.POINTER(StgCgParams), _P,

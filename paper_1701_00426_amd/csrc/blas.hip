@@ -430,4 +430,34 @@ int launch_zero(void *dst, size_t bytes, hipStream_t stream) {
     return 0;
 }
 
+// ---------------------------------------------------------------------------
+// rational function: y = a0 b + sum_k a_k x_k (FP64), one pass over the x_k
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void rational_sum_kernel(size_t n, int nshift, double a0,
+                                                              const double *coeffs, const void *b,
+                                                              const void *xs, void *y) {
+    const size_t stride = (size_t)gridDim.x * kBlock;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        const cpx<double> bi = ld_c<double>(b, i);
+        cpx<double> acc{a0 * bi.re, a0 * bi.im};
+        for (int k = 0; k < nshift; ++k) {
+            const double a = coeffs[k];
+            const cpx<double> x = ld_c<double>(xs, (size_t)k * n + i);
+            acc.re = fmat(a, x.re, acc.re);
+            acc.im = fmat(a, x.im, acc.im);
+        }
+        st_c<double>(y, i, acc);
+    }
+}
+
+int launch_rational_sum(size_t n, int nshift, double a0, const double *coeffs, const void *b,
+                        const void *xs, void *y, hipStream_t stream) {
+    size_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks == 0) return 0;
+    rational_sum_kernel<<<dim3((uint32_t)blocks), kBlock, 0, stream>>>(n, nshift, a0, coeffs, b,
+                                                                      xs, y);
+    return 0;
+}
+
 }  // namespace stg

@@ -1476,6 +1476,60 @@ int multishift_cg_solve(const stg_lattice *lat, const stg_gauge *hi, const stg_g
                     (hipStream_t)stream);
 }
 
+// Rational function: the shifted solutions x_k (complex128 [nshift][nrhs][3][Vh])
+// and the coefficients sit in front of the multi-shift workspace.
+size_t rational_prefix(const Geom &g, int nrhs, int nshift) {
+    return align_up((size_t)nshift * nrhs * 3 * g.Vh * 16) + align_up(sizeof(double) * nshift);
+}
+
+int stg_rational_workspace_bytes(const stg_lattice *lat, int nrhs, int nshift, int mode,
+                                 size_t *bytes) {
+    Geom g;
+    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
+    if (!bytes) return invalid("bytes is NULL");
+    if (nrhs < 1 || nshift < 1) return invalid("nrhs and nshift must be >= 1");
+    if (mode != STG_CG_F64 && mode != STG_CG_MIXED) return invalid("unknown solver mode");
+    *bytes = rational_prefix(g, nrhs, nshift) + ms_workspace(g, nrhs, nshift, mode);
+    return STG_OK;
+}
+
+int rational_apply(const stg_lattice *lat, const stg_gauge *hi, const stg_gauge *lo, double mass,
+                   int nshift, const double *shifts, const double *coeffs, double a0, int nrhs,
+                   const void *b_even, void *y_even, const stg_cg_params *params, void *ws,
+                   size_t ws_bytes, stg_cg_stats *stats, stg_stream_t stream) {
+    Geom g;
+    const int mode = params ? params->mode : -1;
+    int rc = check_solver_common(lat, g, hi, lo, mode, nrhs, b_even, y_even, params);
+    if (rc) return rc;
+    if (nshift < 1 || !shifts || !coeffs || !stats)
+        return invalid("nshift >= 1, shifts, coeffs and stats non-NULL");
+    for (int k = 0; k < nshift; ++k) {
+        if (!(shifts[k] >= 0.0 && shifts[k] < 1e300)) return invalid("shifts must be >= 0");
+        if (!std::isfinite(coeffs[k])) return invalid("coefficients must be finite");
+    }
+    if (!std::isfinite(a0)) return invalid("a0 must be finite");
+    if (!aligned16(ws)) return invalid("workspace NULL or misaligned");
+    const size_t pre = rational_prefix(g, nrhs, nshift);
+    const size_t need = pre + ms_workspace(g, nrhs, nshift, mode);
+    if (ws_bytes < need) return STG_WORKSPACE_TOO_SMALL;
+    const size_t fbb = (size_t)nrhs * 3 * g.Vh * 16;
+    if (overlap(b_even, fbb, y_even, fbb) || overlap(ws, ws_bytes, b_even, fbb) ||
+        overlap(ws, ws_bytes, y_even, fbb))
+        return invalid("b, y and workspace must not overlap");
+    hipStream_t s = (hipStream_t)stream;
+    Carver c{reinterpret_cast<char *>(ws)};
+    void *xs = c.take((size_t)nshift * nrhs * 3 * g.Vh * 16);
+    double *dcoef = (double *)c.take(sizeof(double) * nshift);
+    HIP_TRY(hipMemcpyAsync(dcoef, coeffs, sizeof(double) * nshift, hipMemcpyHostToDevice, s));
+    rc = run_mscg(g, hi, lo, mass, nshift, shifts, nrhs, b_even, xs, *params,
+                  (char *)ws + pre, stats, s);
+    if (rc < 0) return rc;  // argument or HIP error: no result
+    launch_rational_sum(fbb / 16, nshift, a0, dcoef, b_even, xs, y_even, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    return rc;
+}
+
 int stg_batch_workspace_bytes(int nsolve, const stg_solve_desc *descs, int mode, size_t *bytes) {
     if (!bytes) return invalid("bytes is NULL");
     stg_cg_params prm;

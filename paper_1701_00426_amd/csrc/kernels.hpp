@@ -182,6 +182,10 @@ int launch_pack_links(const Geom &g, const void *src, int fmt, void *dst, hipStr
 int launch_pack_phases_f32(size_t n, const double *src, float *dst, hipStream_t stream);
 // zero n bytes (multiple of 4) with a kernel
 int launch_zero(void *dst, size_t bytes, hipStream_t stream);
+// y[i] = a0 b[i] + sum_k coeffs[k] xs[k * n + i] over n complex128 entries;
+// coeffs (device) has nshift entries.
+int launch_rational_sum(size_t n, int nshift, double a0, const double *coeffs, const void *b,
+                        const void *xs, void *y, hipStream_t stream);
 // dst (complex64) = src (complex128), n complex entries
 int launch_c128_to_c64(size_t n, const void *src, void *dst, hipStream_t stream);
 

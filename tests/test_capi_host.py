@@ -135,6 +135,39 @@ def test_solver_arguments_rejected_on_host(lib):
     assert ms.value >= cg8.value
 
 
+def test_rational_arguments_rejected_on_host(lib):
+    """rational_apply checks its arguments before any GPU work."""
+    from paper_1701_00426_amd import _lib
+    lat = _lat((4, 4, 4, 4))
+    g = _lib.StgGauge()
+    g.links = 0x1000
+    g.fmt = 0
+    prm = _lib.StgCgParams()
+    lib.stg_cg_default_params(ctypes.byref(prm))
+    stats = (_lib.StgCgStats * 2)()
+    sh = (ctypes.c_double * 2)(0.1, 1.0)
+    co = (ctypes.c_double * 2)(0.5, 0.25)
+    need = ctypes.c_size_t(0)
+    assert lib.stg_rational_workspace_bytes(ctypes.byref(lat), 1, 2, 0, ctypes.byref(need)) == 0
+    ms = ctypes.c_size_t(0)
+    assert lib.stg_workspace_bytes(ctypes.byref(lat), 1, 2, 0, ctypes.byref(ms)) == 0
+    # the shifted solutions (2 x 128 sites x 3 x 16 B) plus the coefficients come first
+    assert need.value >= ms.value + 2 * 128 * 3 * 16
+    assert lib.stg_rational_workspace_bytes(ctypes.byref(lat), 1, 0, 0, ctypes.byref(need)) == -1
+
+    def call(nshift=2, shifts=sh, coeffs=co, a0=0.5, ws_bytes=1 << 30):
+        return lib.rational_apply(ctypes.byref(lat), ctypes.byref(g), None, 0.1, nshift, shifts,
+                                  coeffs, a0, 1, 0x200000, 0x400000, ctypes.byref(prm),
+                                  0x10000000, ws_bytes, stats, None)
+
+    assert call(nshift=0) == -1
+    assert call(coeffs=None) == -1
+    assert call(shifts=(ctypes.c_double * 2)(0.1, -1.0)) == -1
+    assert call(coeffs=(ctypes.c_double * 2)(0.1, float("nan"))) == -1
+    assert call(a0=float("inf")) == -1
+    assert call(ws_bytes=64) == -3
+
+
 def test_product_does_not_import_oracle():
     """The GPU package never imports the oracle; the oracle never imports the package."""
     pkg = os.path.join(ROOT, "paper_1701_00426_amd")

@@ -194,3 +194,78 @@ def test_cg_threads_per_site(mode, tps, corc):
                label=f"{mode} tps={tps}")
     finally:
         stg.stg_set_tuning(key, old)
+
+
+# --------------------------------------------------------------------------
+# rational function of the normal operator (RHMC: Eq. rooting via Eq. shlineq)
+# --------------------------------------------------------------------------
+def _rational_bound(dims, links, phases, mass, shifts, coeffs, b, y_ref):
+    """|y - y*| <= sum_k |a_k| |x_k - x_k*| <= sum_k |a_k| kappa_k 2 tol |x_k*|."""
+    tot = 0.0
+    for s, a in zip(shifts, coeffs):
+        xk, _, _ = on.cg(dims, links, phases, mass, b, tol=1e-12, sigma=s)
+        kappa = (mass * mass + s + 16.0) / (mass * mass + s)
+        tot += abs(a) * kappa * 2 * TOL * np.linalg.norm(xk)
+    return tot / np.linalg.norm(y_ref)
+
+
+@pytest.mark.parametrize("mode", ["f64", "c64_12", "bf16_12"])
+def test_rational_apply(mode, corc):
+    dims = (4, 6, 4, 8)
+    shifts = [0.0, 0.003, 0.05, 0.8, 6.0]
+    coeffs = [0.11, 0.4, -0.27, 1.9, 7.5]
+    a0, mass, nrhs = 0.35, 0.05, 2
+    say(f"rational {mode} poles={len(shifts)} nrhs={nrhs}")
+    links, phases, b = _problem(dims, (9, 0), nrhs)
+    dl = to_dev(links)
+    hi = stg.pack_gauge(dims, dl, "c128_12")
+    lo = stg.pack_gauge(dims, dl, mode) if mode != "f64" else None
+    y, st, stats = stg.rational_apply(hi, mass, shifts, coeffs, a0, to_dev(b), lo=lo, tol=TOL)
+    assert st == 0
+    yn = y.cpu().numpy()
+    for k in range(len(shifts)):
+        for j in range(nrhs):
+            assert stats[k][j]["status"] == 0 and stats[k][j]["true_rel_resid"] <= TOL
+    for j in range(nrhs):
+        want, worst = on.rational_apply(dims, links, phases, mass, shifts, coeffs, a0, b[j])
+        err = rel_norm(yn[j], want)
+        bound = _rational_bound(dims, links, phases, mass, shifts, coeffs, b[j], want)
+        say(f"  rhs {j}: |y - y*|/|y*| = {err:.2e} (bound {bound:.2e})")
+        assert err <= bound
+
+
+def test_rational_apply_free_field_and_identity():
+    """Unit links: r(A) on a plane wave is the closed-form scalar times the wave; on
+    random links, coefficients of a partial-fraction pair give (A+s1)^-1 (A+s2)^-1 b,
+    checked by applying (A+s2)(A+s1) with the oracle; a0 alone returns a0 b exactly."""
+    dims = (4, 4, 6, 8)
+    mass = 0.1
+    links = on.unit_links(dims)
+    p = on.momenta(dims, (1, 2, 3, 1))
+    pw = on.plane_wave(dims, 0, p, np.array([1.0, 0.5j, -0.25 + 0.1j]))[None]
+    lam = on.free_eigenvalue(mass, p)
+    shifts, coeffs, a0 = [0.0, 0.2, 3.0], [0.5, -0.3, 2.0], 0.125
+    g = stg.pack_gauge(dims, to_dev(links), "c128_12")
+    y, st, _ = stg.rational_apply(g, mass, shifts, coeffs, a0, to_dev(pw), tol=1e-12)
+    want = (a0 + sum(a / (lam + s) for a, s in zip(coeffs, shifts))) * pw
+    err = rel_norm(y.cpu().numpy(), want)
+    say(f"rational free field: err {err:.2e}")
+    assert err <= 1e-10
+    # partial fractions on random SU(3) links
+    links = si.su3_links(dims, 41, 0)
+    phases = on.standard_phases(dims)
+    b = si.gaussian_field(dims, 1, 41, 1)
+    s1, s2 = 0.01, 0.4
+    c = 1.0 / (s2 - s1)
+    g = stg.pack_gauge(dims, to_dev(links), "c128_12")
+    y, st, _ = stg.rational_apply(g, mass, [s1, s2], [c, -c], 0.0, to_dev(b), tol=1e-12)
+    yn = y.cpu().numpy()[0]
+    back = on.apply_normal(dims, links, phases, mass,
+                           on.apply_normal(dims, links, phases, mass, yn, sigma=s1), sigma=s2)
+    ident = np.linalg.norm(back - b[0]) / np.linalg.norm(b[0])
+    say(f"rational partial fractions: |(A+s2)(A+s1) y - b|/|b| = {ident:.2e}")
+    assert ident <= 1e-9
+    # a0 only
+    bd = to_dev(b)
+    y0, st, _ = stg.rational_apply(g, mass, [0.5], [0.0], 0.75, bd, tol=1e-10)
+    assert torch.equal(y0, 0.75 * bd)
