@@ -19,6 +19,9 @@ Paper: Bonati et al., arXiv:1701.00426.
     their solutions combine into r(A) b.
   * Sec. 4.3, deo listing -- the operator takes links, in, out and a real
     per-link "backfield" array; here that array carries the staggered phases.
+  * Sec. 2.1 (tree-level Symanzik gauge action) and Sec. 4.3 (gauge force:
+    staples as products of 3 and 5 links along C-shaped paths) -- Wilson
+    lines, the 1x1 and 1x2 loop sums and the staple sum of every link.
 
 Everything takes the arrays as given; random inputs come from the seeded
 generators, which hold none of this arithmetic.
@@ -392,3 +395,119 @@ def translate_links(dims, links, shift_vec):
         for mu in range(4):
             out[2 * mu + parity] = links[2 * mu + parity][:, :, hsrc]
     return out
+
+
+# --------------------------------------------------------------------------
+# Gauge part: Wilson lines, the loops of the tree-level Symanzik action and
+# the staples of its gauge force (Sec. 2.1: tree-level Symanzik gauge action;
+# Sec. 4.3: staples as products of 3 and 5 links along C-shaped paths).
+# --------------------------------------------------------------------------
+
+# Tree-level Symanzik weights of the 1x1 and 1x2 loops.  The paper names the
+# action and cites its origin without printing the numbers; these are the
+# standard tree-level values, c0 + 8 c1 = 1 (Wilson normalisation).
+SYMANZIK_C1 = -1.0 / 12.0
+SYMANZIK_C0 = 1.0 - 8.0 * SYMANZIK_C1
+
+
+def all_coords(dims):
+    """Coordinates (4, V) of every site: the even sites, then the odd ones."""
+    return np.concatenate([coords(dims, 0), coords(dims, 1)], axis=1)
+
+
+def link_matrices(dims, links, y, mu: int):
+    """U_mu(y), (3, 3, n), for sites y (4, n) of any parity."""
+    u = links[2 * mu + site_parity(y), :, :, half_index(dims, y)]  # (n, 3, 3)
+    return np.transpose(u, (1, 2, 0))
+
+
+def path_product(dims, links, start, steps):
+    """Ordered product of the links met along a lattice path, (3, 3, n).
+
+    steps is a sequence of (mu, +1 | -1) taken from each site of ``start``.  A +1
+    step from y contributes U_mu(y) and moves to y + mu; a -1 step moves to
+    y - mu and contributes U_mu(y - mu)^dag.  Factors multiply from the right in
+    path order (a Wilson line from the start to the end of the path).
+    """
+    y = start.copy()
+    n = start.shape[1]
+    w = np.repeat(np.eye(3, dtype=np.complex128)[:, :, None], n, axis=2)
+    for mu, s in steps:
+        if s > 0:
+            u = link_matrices(dims, links, y, mu)
+            y = shifted(dims, y, mu, +1)
+        else:
+            y = shifted(dims, y, mu, -1)
+            u = np.conj(np.transpose(link_matrices(dims, links, y, mu), (1, 0, 2)))
+        w = np.einsum("abn,bcn->acn", w, u)
+    return w
+
+
+def staple_paths(mu: int, nu: int):
+    """The C-shaped paths in the (mu, nu) plane that lead from x + mu back to x.
+
+    Two 3-link paths (the rest of the 1x1 loops above and below the link) and
+    six 5-link paths (the rest of the 1x2 loops: long side along mu, extended
+    forward or backward, and long side along nu, each above or below the link).
+    U_mu(x) times any of them is a closed loop through x.
+    """
+    fw, bw, up, dn = (mu, +1), (mu, -1), (nu, +1), (nu, -1)
+    three = [[up, bw, dn], [dn, bw, up]]
+    five = [[fw, up, bw, bw, dn], [up, bw, bw, dn, fw], [up, up, bw, dn, dn],
+            [fw, dn, bw, bw, up], [dn, bw, bw, up, fw], [dn, dn, bw, up, up]]
+    return three, five
+
+
+def staples(dims, links, c0=SYMANZIK_C0, c1=SYMANZIK_C1):
+    """Sigma_mu(x) for every link, (8, 3, 3, Vh) in the gauge-field layout.
+
+    Sigma_mu(x) = sum over nu != mu of c0 (the two 3-link paths) + c1 (the six
+    5-link paths) of staple_paths, each a Wilson line from x + mu to x, so that
+    U_mu(x) Sigma_mu(x) is the weighted sum of the closed 1x1 and 1x2 loops that
+    contain the link.  Written out directly as products along each path.
+    """
+    check_dims(dims)
+    out = np.zeros((8, 3, 3, half_volume(dims)), dtype=np.complex128)
+    for parity in (0, 1):
+        x = coords(dims, parity)
+        for mu in range(4):
+            start = shifted(dims, x, mu, +1)
+            acc = out[2 * mu + parity]
+            for nu in range(4):
+                if nu == mu:
+                    continue
+                three, five = staple_paths(mu, nu)
+                for p in three:
+                    acc += c0 * path_product(dims, links, start, p)
+                for p in five:
+                    acc += c1 * path_product(dims, links, start, p)
+    return out
+
+
+def loop_sums(dims, links):
+    """(sum of Re Tr over all 1x1 loops, sum of Re Tr over all 1x2 loops).
+
+    Every unoriented loop counted once: the plaquette U_mu U_nu U_mu^dag U_nu^dag
+    at x for mu < nu, and the rectangle with its long side (two links) along mu
+    and its short side along nu at x for every ordered pair mu != nu.
+    """
+    x = all_coords(dims)
+    plaq = rect = 0.0
+    for mu in range(4):
+        for nu in range(4):
+            if nu == mu:
+                continue
+            if mu < nu:
+                w = path_product(dims, links, x, [(mu, 1), (nu, 1), (mu, -1), (nu, -1)])
+                plaq += float(np.sum(np.real(np.einsum("aan->n", w))))
+            w = path_product(dims, links, x,
+                             [(mu, 1), (mu, 1), (nu, 1), (mu, -1), (mu, -1), (nu, -1)])
+            rect += float(np.sum(np.real(np.einsum("aan->n", w))))
+    return plaq, rect
+
+
+def weighted_loop_sum(dims, links, c0=SYMANZIK_C0, c1=SYMANZIK_C1):
+    """c0 (1x1 loop sum) + c1 (1x2 loop sum): the link-dependent part of the
+    tree-level Symanzik action up to its -beta/3 normalisation and a constant."""
+    plaq, rect = loop_sums(dims, links)
+    return c0 * plaq + c1 * rect

@@ -170,6 +170,145 @@ def run_operator_pins(dslash, phases_fn):
     return out
 
 
+# --------------------------------------------------------------------------
+# Staples of the tree-level Symanzik gauge force (Sec. 2.1 action, Sec. 4.3
+# staples: products of 3 and 5 links on C-shaped paths).  Each check takes
+# ``staples_fn(dims, links, c0, c1) -> (8, 3, 3, Vh)``.  The closed forms are
+# textbook properties of closed Wilson loops: unit and pure-gauge fields make
+# every loop the identity, gauge transformations act on a staple at its two
+# ends, and a loop sum is linear in each link it contains once.
+# --------------------------------------------------------------------------
+
+
+def _mat_rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _site_gauge(dims, seed):
+    return si.su3_site_field(dims, seed, 0), si.su3_site_field(dims, seed, 1)
+
+
+def _g_at(dims, g, y):
+    """g(y), (3, 3, n), for sites y of any parity."""
+    par = on.site_parity(y)
+    h = on.half_index(dims, y)
+    return np.where(par[None, None, :] == 0, g[0][:, :, h], g[1][:, :, h])
+
+
+def staple_unit_links(staples_fn, dims, c0=1.3, c1=-0.35):
+    """Unit links: every loop is 1, so Sigma = (6 c0 + 18 c1) I exactly."""
+    s = staples_fn(dims, on.unit_links(dims), c0, c1)
+    want = np.zeros_like(s)
+    for a in range(3):
+        want[:, a, a, :] = 6 * c0 + 18 * c1
+    return _mat_rel(s, want)
+
+
+def staple_pure_gauge(staples_fn, dims, c0=0.7, c1=0.45, seed=21):
+    """U_mu(x) = g(x) g(x+mu)^dag: a path from x+mu to x multiplies to
+    g(x+mu) g(x)^dag, so Sigma_mu(x) = (6 c0 + 18 c1) g(x+mu) g(x)^dag."""
+    g = _site_gauge(dims, seed)
+    s = staples_fn(dims, on.pure_gauge_links(dims, *g), c0, c1)
+    want = np.empty_like(s)
+    for parity in (0, 1):
+        x = on.coords(dims, parity)
+        for mu in range(4):
+            gf = _g_at(dims, g, on.shifted(dims, x, mu, +1))
+            want[2 * mu + parity] = (6 * c0 + 18 * c1) * np.einsum(
+                "abn,cbn->acn", gf, np.conj(g[parity]))
+    return _mat_rel(s, want)
+
+
+def staple_gauge_covariance(staples_fn, dims, c0=1.1, c1=-0.6, seed=22):
+    """Sigma[U^g]_mu(x) = g(x+mu) Sigma[U]_mu(x) g(x)^dag."""
+    links = si.su3_links(dims, seed, 0)
+    g = _site_gauge(dims, seed + 100)
+    s = staples_fn(dims, links, c0, c1)
+    sg = staples_fn(dims, on.gauge_transform_links(dims, links, *g), c0, c1)
+    want = np.empty_like(s)
+    for parity in (0, 1):
+        x = on.coords(dims, parity)
+        for mu in range(4):
+            gf = _g_at(dims, g, on.shifted(dims, x, mu, +1))
+            want[2 * mu + parity] = np.einsum("abn,bcn,dcn->adn", gf, s[2 * mu + parity],
+                                              np.conj(g[parity]))
+    return _mat_rel(sg, want)
+
+
+def staple_linear_response(staples_fn, dims, c0, c1, seed=23, nlinks=3):
+    """Each 1x1 and 1x2 loop holds a given link at most once (extents >= 3), so
+    replacing U by U + E changes c0 P + c1 R by exactly Re Tr(E Sigma).  With E
+    the 18 real basis directions this reads every entry of Sigma off the loop
+    sums; compared at nlinks links per slot."""
+    links = si.su3_links(dims, seed, 0)
+    s = staples_fn(dims, links, c0, c1)
+    base = on.weighted_loop_sum(dims, links, c0, c1)
+    vh = on.half_volume(dims)
+    pick = si.rng(seed, 1).integers(0, vh, size=(8, nlinks))
+    err = 0.0
+    for slot in range(8):
+        for h in pick[slot]:
+            got = np.empty((3, 3), dtype=np.complex128)
+            for a in range(3):
+                for b in range(3):
+                    d = []
+                    for e in (1.0, 1j):
+                        pert = links.copy()
+                        pert[slot, a, b, h] += e
+                        d.append(on.weighted_loop_sum(dims, pert, c0, c1) - base)
+                    got[b, a] = d[0] - 1j * d[1]
+            err = max(err, _mat_rel(s[slot, :, :, h], got))
+    return err
+
+
+def staple_loop_identity(staples_fn, dims, c0=1.0, c1=1.0, seed=24):
+    """sum over links of Re Tr(U Sigma) = 4 c0 P + 6 c1 R: a 1x1 loop has 4 links
+    and a 1x2 loop 6, and each loop appears once in the staple of each of them."""
+    links = si.su3_links(dims, seed, 0)
+    s = staples_fn(dims, links, c0, c1)
+    lhs = float(np.sum(np.real(np.einsum("sabn,sban->sn", links, s))))
+    plaq, rect = on.loop_sums(dims, links)
+    rhs = 4 * c0 * plaq + 6 * c1 * rect
+    return abs(lhs - rhs) / max(abs(rhs), 1.0)
+
+
+def staple_translation(staples_fn, dims, c0=0.9, c1=0.2, seed=25, shift=(2, 1, 0, 3)):
+    """Staples of a translated field are the translated staples (any shift whose
+    components sum to an even number keeps each parity in place)."""
+    links = si.su3_links(dims, seed, 0)
+    s = staples_fn(dims, links, c0, c1)
+    st = staples_fn(dims, on.translate_links(dims, links, shift), c0, c1)
+    return _mat_rel(st, on.translate_links(dims, s, shift))
+
+
+ALL_STAPLE_PINS = ("unit_links", "pure_gauge", "gauge_covariance", "linear_response_plaq",
+                   "linear_response_rect", "loop_identity", "translation")
+
+
+def run_staple_pins(staples_fn, first_failure=False):
+    """Runs the staple pins on small lattices, cheapest first; returns {name: (error,
+    tolerance)}.  With first_failure it stops after the first pin that fails."""
+    checks = [
+        ("unit_links", lambda: staple_unit_links(staples_fn, (4, 4, 4, 4)), 1e-14),
+        ("pure_gauge", lambda: staple_pure_gauge(staples_fn, (4, 6, 4, 4)), 1e-13),
+        ("gauge_covariance", lambda: staple_gauge_covariance(staples_fn, (4, 4, 6, 4)), 1e-13),
+        ("translation", lambda: staple_translation(staples_fn, (4, 6, 4, 4)), 1e-15),
+        ("loop_identity", lambda: staple_loop_identity(staples_fn, (6, 4, 4, 8)), 1e-13),
+        ("linear_response_plaq",
+         lambda: staple_linear_response(staples_fn, (4, 4, 4, 6), 1.0, 0.0, nlinks=1), 1e-10),
+        ("linear_response_rect",
+         lambda: staple_linear_response(staples_fn, (4, 6, 4, 4), 0.0, 1.0, seed=26, nlinks=1),
+         1e-10),
+    ]
+    out = {}
+    for name, fn, tol in checks:
+        err = fn()
+        out[name] = (err, tol)
+        if first_failure and not err <= tol:
+            break
+    return out
+
+
 def rel_err(a, b):
     return _rel(a, b)
 

@@ -104,3 +104,75 @@ def test_operator_mutant_detected(mutation):
 def test_phase_mutant_detected(mutation):
     res = pins.run_operator_pins(on.dslash, make_phases(mutation))
     assert _failed(res), f"planted phase mistake {mutation} passed every pin"
+
+
+# --------------------------------------------------------------------------
+# Staples: planted mistakes in a copy of the staple sum
+# --------------------------------------------------------------------------
+
+
+def _path_product(dims, links, start, steps, mutation):
+    y = start.copy()
+    w = np.repeat(np.eye(3, dtype=np.complex128)[:, :, None], start.shape[1], axis=2)
+    for mu, s in steps:
+        if s > 0:
+            u = on.link_matrices(dims, links, y, mu)
+            y = on.shifted(dims, y, mu, +1)
+        else:
+            y = on.shifted(dims, y, mu, -1)
+            u = on.link_matrices(dims, links, y, mu)
+            if mutation == "transpose_no_conj":
+                u = np.transpose(u, (1, 0, 2))
+            elif mutation != "no_dagger":
+                u = np.conj(np.transpose(u, (1, 0, 2)))
+        if mutation == "reversed_product":
+            w = np.einsum("abn,bcn->acn", u, w)
+        else:
+            w = np.einsum("abn,bcn->acn", w, u)
+    return w
+
+
+def make_staples(mutation):
+    def staples_fn(dims, links, c0, c1):
+        out = np.zeros((8, 3, 3, on.half_volume(dims)), dtype=np.complex128)
+        for parity in (0, 1):
+            x = on.coords(dims, parity)
+            for mu in range(4):
+                start = x if mutation == "start_at_x" else on.shifted(dims, x, mu, +1)
+                for nu in range(4):
+                    if nu == mu:
+                        continue
+                    three, five = on.staple_paths(mu, nu)
+                    if mutation == "drop_lower_plaquette":
+                        three = three[:1]
+                    if mutation == "drop_tall":
+                        five = [five[0], five[1], five[3], five[4]]
+                    if mutation == "rect_ends_wrong":
+                        five = [p[:-1] + [(mu, -1)] if p[-1] == (mu, 1) else p for p in five]
+                    if mutation == "tall_along_mu":
+                        five = five[:2] + [[(mu, 1), (mu, 1), (nu, 1), (mu, -1), (nu, -1)]] \
+                            + five[3:]
+                    w3, w5 = (c1, c0) if mutation == "swapped_weights" else (c0, c1)
+                    for p in three:
+                        out[2 * mu + parity] += w3 * _path_product(dims, links, start, p,
+                                                                   mutation)
+                    for p in five:
+                        out[2 * mu + parity] += w5 * _path_product(dims, links, start, p,
+                                                                   mutation)
+        return out
+    return staples_fn
+
+
+STAPLE_MUTANTS = ["start_at_x", "drop_lower_plaquette", "drop_tall", "rect_ends_wrong",
+                  "tall_along_mu", "swapped_weights", "no_dagger", "transpose_no_conj",
+                  "reversed_product"]
+
+
+def test_unmutated_staple_copy_passes():
+    assert _failed(pins.run_staple_pins(make_staples(None))) == []
+
+
+@pytest.mark.parametrize("mutation", STAPLE_MUTANTS)
+def test_staple_mutant_detected(mutation):
+    res = pins.run_staple_pins(make_staples(mutation), first_failure=True)
+    assert _failed(res), f"planted staple mistake {mutation} passed every pin"

@@ -243,3 +243,45 @@ def test_rational_apply_linear_in_coefficients():
     yab, _ = on.rational_apply(dims, links, phases, 0.1, shifts,
                                [u + v for u, v in zip(ca, cb)], 0.3, b)
     assert np.max(np.abs(yab - (ya + yb))) <= 1e-10 * np.max(np.abs(yab))
+
+
+# --------------------------------------------------------------------------
+# Staples of the tree-level Symanzik gauge force (Sec. 2.1, Sec. 4.3)
+# --------------------------------------------------------------------------
+
+
+def test_staple_pins():
+    res = pins.run_staple_pins(on.staples)
+    for name, (err, tol) in res.items():
+        assert err <= tol, f"staple pin {name} error {err:.3e} > {tol:.1e}"
+
+
+def test_path_product_pure_gauge():
+    """On U_mu(x) = g(x) g(x+mu)^dag any path from y to z multiplies to g(y) g(z)^dag."""
+    dims = (4, 6, 4, 4)
+    g = (si.su3_site_field(dims, 27, 0), si.su3_site_field(dims, 27, 1))
+    links = on.pure_gauge_links(dims, *g)
+    x = on.all_coords(dims)
+    steps = [(0, 1), (2, -1), (1, 1), (1, 1), (3, -1), (0, -1), (0, -1), (2, 1)]
+    w = on.path_product(dims, links, x, steps)
+    end = x.copy()
+    for mu, s in steps:
+        end = on.shifted(dims, end, mu, s)
+    want = np.einsum("abn,cbn->acn", pins._g_at(dims, g, x), np.conj(pins._g_at(dims, g, end)))
+    assert np.max(np.abs(w - want)) <= 1e-13
+
+
+def test_loop_sums_unit_and_counts():
+    """Unit links: each loop has trace 3; there are 6 V plaquettes and 12 V rectangles."""
+    dims = (4, 4, 6, 4)
+    plaq, rect = on.loop_sums(dims, on.unit_links(dims))
+    v = on.volume(dims)
+    assert plaq == 3.0 * 6 * v and rect == 3.0 * 12 * v
+
+
+def test_staples_tree_level_weights():
+    """Tree-level weights: c1 = -1/12 and c0 + 8 c1 = 1, so the unit-link staple is 8.5 I."""
+    assert on.SYMANZIK_C1 == -1.0 / 12.0 and abs(on.SYMANZIK_C0 - 5.0 / 3.0) < 1e-15
+    dims = (4, 4, 4, 4)
+    s = on.staples(dims, on.unit_links(dims))
+    assert np.allclose(s[5], 8.5 * np.eye(3)[:, :, None], rtol=0, atol=1e-14)
