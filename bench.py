@@ -341,6 +341,109 @@ def bench_shapes():
           flush=True)
 
 
+# Staples of the tree-level Symanzik gauge force.  Flops of the kernel's factored
+# evaluation per link: per neighbouring direction and side, 8 SU(3) products into a
+# fresh matrix (27 complex multiplies + 18 complex adds = 198 flops) and 3 into an
+# accumulator (216 flops) plus the weighting (72 flops): 2304; x 2 sides x 3
+# directions = 13824 (row-2 reconstruction of the 12-real formats not counted).
+STAPLE_FLOPS_PER_LINK = 13824
+# Vector FMA peak without packed-FP32 instructions: 256 CUs x 4 SIMDs x 16 lanes x
+# 2 flops x 2.4 GHz, the same for FP64 and for unpacked FP32.
+ALU_PEAK_TFLOPS = 78.6
+# Paper Table 4: ns per site of the pure-gauge MD step (whose most expensive part is
+# the staples) on NVIDIA GK201 (K80) and P100: context only, a different quantity.
+PAPER_TABLE4 = {(32, 32, 8, 32): (193.79, 51.80), (32, 32, 32, 8): (190.39, 51.69),
+                (24, 24, 24, 24): (212.04, 53.74), (32, 32, 32, 32): (201.82, 51.72),
+                (32, 32, 32, 36): (208.54, 52.62)}
+STAPLE_LINK_BYTES = {"c128_18": 144, "c128_12": 96, "c64_12": 48, "bf16_12": 24}
+
+
+def time_staples(stg, torch, gauges, outs, n):
+    """Mean duration (s) of one gauge_staples launch over n back-to-back launches
+    rotating link copies, HIP events on the launching stream."""
+    stream = torch.cuda.current_stream()
+    for i in range(3):
+        stg.gauge_staples(gauges[i % len(gauges)], out=outs[i % len(outs)])
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for i in range(n):
+        stg.gauge_staples(gauges[i % len(gauges)], out=outs[i % len(outs)])
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / 1e3 / n
+
+
+def staple_cpu_baseline(dims=(8, 8, 8, 8)):
+    """The NumPy oracle's staples of a whole 8^4 lattice (all 4 directions), timed
+    on the host: ns per site."""
+    import seeded_inputs as si
+    from oracle import oracle_np as on
+    links = si.su3_links(dims, 1701, 7, 1)
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        on.staples(dims, links)
+        reps += 1
+        if time.perf_counter() - t0 > 5.0:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    v = 2 * on.half_volume(dims)
+    return {"value": round(dt * 1e9 / v, 1), "unit": "ns/site", "cores": 1, "kind": "oracle",
+            "sample": f"NumPy oracle, whole {'x'.join(map(str, dims))} lattice, {reps} passes"}
+
+
+def bench_staples(profile=False, no_cpu=False, applies=100):
+    """Staples of every link (gauge_staples) on the paper's Table 4 lattice shapes at
+    FP64-12 and FP32-12, and at 32^4 in every format; ns per site = t / V (all four
+    directions in one launch).  The first line printed is the 32^4 FP64-12 one with
+    its ALU roofline."""
+    import torch
+    import paper_1701_00426_amd as stg
+    import seeded_inputs as si
+    dev = torch.device("cuda:0")
+    shapes = [(32, 32, 32, 32)] if profile else list(PAPER_TABLE4)
+    rows = []
+    head = None
+    for dims in shapes:
+        vh = stg.half_volume(dims)
+        links = torch.from_numpy(si.su3_links(dims, 1701, 7, 0)).to(dev)
+        fmts = ["c128_12"] if profile else (
+            ["c128_12", "c128_18", "c64_12", "bf16_12"] if dims == (32, 32, 32, 32)
+            else ["c128_12", "c64_12"])
+        for fmt in fmts:
+            gauges = [stg.pack_gauge(dims, links if i == 0 else links.clone(), fmt)
+                      for i in range(2)]
+            cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
+            outs = [torch.empty((8, 3, 3, vh), dtype=cdt, device=dev) for _ in range(2)]
+            dt = time_staples(stg, torch, gauges, outs, applies)
+            tflops = STAPLE_FLOPS_PER_LINK * 8 * vh / dt / 1e12
+            row = {"lattice": "x".join(map(str, dims)), "format": fmt,
+                   "launch_us": round(dt * 1e6, 2),
+                   "ns_per_site": round(dt * 1e9 / (2 * vh), 4),
+                   "TFLOPs": round(tflops, 2), "frac_alu": round(tflops / ALU_PEAK_TFLOPS, 4),
+                   "algorithmic_GBs": round((STAPLE_LINK_BYTES[fmt] + (144 if cdt ==
+                                             torch.complex128 else 72)) * 8 * vh / dt / 1e9, 1),
+                   "paper_gauge_md_ns_per_site_K80_P100": PAPER_TABLE4[dims]}
+            rows.append(row)
+            log(json.dumps(row))
+            if dims == (32, 32, 32, 32) and fmt == "c128_12":
+                head = row
+            del gauges, outs
+        del links
+        torch.cuda.empty_cache()
+    out = {"workload": "staples of the tree-level Symanzik gauge force, every link, "
+                       "paper Table 4 shapes", "rows": rows}
+    if head is not None:
+        out["roofline"] = {"bound": "alu", "kernel": "staple_kernel<double, FP64-12> 32^4",
+                           "achieved": head["TFLOPs"], "peak": ALU_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": head["frac_alu"], "traffic": None}
+    if not no_cpu and not profile:
+        out["cpu_baseline"] = staple_cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
 # Launch-shape variants of the hop compared under one kernel trace: (format, fields,
 # knob settings).  Each runs the same number of back-to-back D_eo launches.
 VARIANTS = [
@@ -409,12 +512,15 @@ def main():
     ap.add_argument("--profile-cg", action="store_true",
                     help="for rocprofv3: one FP64 CG and one mixed CG solve only")
     ap.add_argument("--workload", choices=["main", "multishift", "rational", "batch",
-                                           "batch-small", "shapes"],
+                                           "batch-small", "shapes", "staples"],
                     default="main",
                     help="main: the 32^4 line; multishift: 24^3x48, 16 shifts x 8 RHS; "
                          "rational: the same shifts combined into r(A) b; "
                          "batch: 12 solves on 8^4 .. 32^4 in one cg_solve_batch; "
-                         "batch-small: 48 solves on 8^4 .. 16^4")
+                         "batch-small: 48 solves on 8^4 .. 16^4; "
+                         "staples: gauge-force staples on the Table 4 shapes")
+    ap.add_argument("--profile-staples", action="store_true",
+                    help="for rocprofv3: only the 32^4 FP64-12 staple loop")
     ap.add_argument("--profile-variants", action="store_true",
                     help="for rocprofv3: the hop's launch-shape variants at 32^4, in order")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -444,6 +550,9 @@ def main():
         return
     if args.workload == "shapes":
         bench_shapes()
+        return
+    if args.workload == "staples" or args.profile_staples:
+        bench_staples(profile=args.profile_staples, no_cpu=args.no_cpu)
         return
 
     import numpy as np

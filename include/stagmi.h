@@ -322,6 +322,28 @@ int rational_apply(const stg_lattice *lat, const stg_gauge *hi, const stg_gauge 
  *   complex128 [nrhs][3][Vh]; x holds the guess on entry).  Every hi field must
  *   have one format, and in mode MIXED every lo field one format.
  */
+/*
+ * Staples of the tree-level Symanzik gauge force (Sec. 2.1: the tree-level
+ * Symanzik improved gauge action, built from 1x1 and 1x2 Wilson loops; Sec. 4.3:
+ * the staples, products of 3 and 5 links along C-shaped paths, are the most
+ * expensive step of the gauge cycle).  For every link U_mu(x), out receives
+ *   Sigma_mu(x) = sum_{nu != mu} ( c0 [2 three-link paths] + c1 [6 five-link paths] ),
+ * each path the ordered product of the links met going from x+mu back to x (a
+ * step from y to y-nu contributes U_nu(y-nu)^dag), so that U_mu(x) Sigma_mu(x) is
+ * the c0/c1-weighted sum of the 1x1 and 1x2 loops through the link.  The
+ * tree-level weights are c1 = -1/12, c0 = 1 - 8 c1 = 5/3.
+ *  gauge: links in any format; its phases are ignored (staples use the bare
+ *    links).  The 12-real formats rebuild row 2, so their links must be SU(3).
+ *  out: device, [8][3][3][Vh] (slot 2*mu + parity of x, row, column, site),
+ *    complex128 for STG_LINK_C128_* (FP64 arithmetic) and complex64 for
+ *    STG_LINK_C64_12 / STG_LINK_BF16_12 (FP32 arithmetic); 16-byte aligned and
+ *    not overlapping the links.  Written entirely.
+ * Errors: STG_INVALID_ARG (bad extents, NULL or misaligned pointer, overlap,
+ * unknown format, non-finite c0 or c1), and nothing is launched.  Asynchronous.
+ */
+int gauge_staples(const stg_lattice *lat, const stg_gauge *gauge, double c0, double c1,
+                  void *out, stg_stream_t stream);
+
 typedef struct {
     stg_lattice lat;
     stg_gauge hi;

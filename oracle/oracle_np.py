@@ -511,3 +511,22 @@ def weighted_loop_sum(dims, links, c0=SYMANZIK_C0, c1=SYMANZIK_C1):
     tree-level Symanzik action up to its -beta/3 normalisation and a constant."""
     plaq, rect = loop_sums(dims, links)
     return c0 * plaq + c1 * rect
+
+
+def staples_at(dims, links, slot: int, hs, c0=SYMANZIK_C0, c1=SYMANZIK_C1):
+    """Sigma_mu(x), (3, 3, n), for the links of one slot (2*mu + parity) at the
+    half indices hs only: the same sum of path products as ``staples``, for
+    spot checks on lattices too large to do whole."""
+    mu, parity = slot // 2, slot % 2
+    x = coords(dims, parity)[:, np.asarray(hs, dtype=np.int64)]
+    start = shifted(dims, x, mu, +1)
+    acc = np.zeros((3, 3, x.shape[1]), dtype=np.complex128)
+    for nu in range(4):
+        if nu == mu:
+            continue
+        three, five = staple_paths(mu, nu)
+        for p in three:
+            acc += c0 * path_product(dims, links, start, p)
+        for p in five:
+            acc += c1 * path_product(dims, links, start, p)
+    return acc

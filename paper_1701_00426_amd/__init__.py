@@ -32,8 +32,12 @@ __all__ = [
     "dirac_apply_eo", "dirac_apply_oe", "stg_apply_normal", "stg_dot", "cg_solve",
     "multishift_cg_solve", "stg_workspace_bytes", "library", "stg_set_tuning", "stg_get_tuning",
     "cg_solve_batch", "rational_apply", "stg_rational_workspace_bytes", "stg_autotune",
-    "stg_autotune_load", "stg_autotune_lookup",
+    "stg_autotune_load", "stg_autotune_lookup", "gauge_staples", "SYMANZIK_C0", "SYMANZIK_C1",
 ]
+
+# tree-level Symanzik weights of the 1x1 and 1x2 loops: c1 = -1/12, c0 + 8 c1 = 1
+SYMANZIK_C1 = -1.0 / 12.0
+SYMANZIK_C0 = 1.0 - 8.0 * SYMANZIK_C1
 
 FORMAT_NAMES = {"c128_18": STG_LINK_C128_18, "c128_12": STG_LINK_C128_12,
                 "c64_12": STG_LINK_C64_12, "bf16_12": STG_LINK_BF16_12}
@@ -191,6 +195,23 @@ def dirac_apply_oe(gauge: Gauge, in_even: torch.Tensor, out_odd: Optional[torch.
                    stream=None) -> torch.Tensor:
     """out_odd = D_oe in_even (asynchronous on the stream)."""
     return _apply("dirac_apply_oe", gauge, in_even, out_odd, stream)
+
+
+def gauge_staples(gauge: Gauge, c0: float = SYMANZIK_C0, c1: float = SYMANZIK_C1,
+                  out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Staples Sigma_mu(x) of every link, (8, 3, 3, Vh): complex128 for the FP64
+    link formats, complex64 for the FP32 ones (asynchronous on the stream)."""
+    vh = half_volume(gauge.dims)
+    dtype = torch.complex128 if gauge.field == STG_C128 else torch.complex64
+    if out is None:
+        out = torch.empty((8, 3, 3, vh), dtype=dtype, device=gauge.links.device)
+    elif out.dtype != dtype or tuple(out.shape) != (8, 3, 3, vh) or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous {dtype} tensor of shape (8, 3, 3, {vh})")
+    g = gauge.c()
+    _lib.check("gauge_staples", library().gauge_staples(
+        ctypes.byref(_lib.lattice(gauge.dims)), ctypes.byref(g), float(c0), float(c1), _ptr(out),
+        _stream(stream)))
+    return out
 
 
 def stg_apply_normal(gauge: Gauge, mass: float, in_even: torch.Tensor, sigma: float = 0.0,

@@ -20,6 +20,7 @@
 #include "batch.hpp"
 #include "kernels.hpp"
 #include "solver_state.hpp"
+#include "staple.hpp"
 #include "tune.hpp"
 
 using namespace stg;
@@ -1329,6 +1330,31 @@ int stg_pack_phases(const stg_lattice *lat, const double *phases_f64, stg_field 
     } else {
         return invalid("unknown field type");
     }
+    return STG_OK;
+}
+
+int gauge_staples(const stg_lattice *lat, const stg_gauge *gauge, double c0, double c1,
+                  void *out, stg_stream_t stream) {
+    Geom g;
+    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
+    if (!gauge) return invalid("gauge is NULL");
+    const size_t lb = link_bytes(g, gauge->fmt);
+    if (!lb) return invalid("unknown link format");
+    if (!aligned16(gauge->links) || !aligned16(out)) return invalid("NULL or misaligned pointer");
+    if (!std::isfinite(c0) || !std::isfinite(c1)) return invalid("c0 and c1 must be finite");
+    const bool fp64 = gauge->fmt == STG_LINK_C128_18 || gauge->fmt == STG_LINK_C128_12;
+    const size_t ob = (size_t)8 * 9 * g.Vh * (fp64 ? 16 : 8);
+    if (overlap(gauge->links, lb, out, ob)) return invalid("links and out overlap");
+    StapleArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.geom = g;
+    a.links = gauge->links;
+    a.out = out;
+    a.c0 = c0;
+    a.c1 = c1;
+    a.xcd_remap = g_xcd_remap;
+    if (launch_staples(a, gauge->fmt, (hipStream_t)stream)) return invalid("unknown link format");
+    HIP_TRY(hipGetLastError());
     return STG_OK;
 }
 

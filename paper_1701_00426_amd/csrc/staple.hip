@@ -1,0 +1,370 @@
+// staple.hip -- staples of the tree-level Symanzik gauge force.
+//
+// Paper: arXiv:1701.00426, Sec. 2.1 (tree-level Symanzik improved gauge action:
+// 1x1 and 1x2 Wilson loops) and Sec. 4.3 (the gauge cycle's most expensive step:
+// staples, products of 3 and 5 SU(3) links along C-shaped paths, computed per
+// link with second-neighbour addressing).
+//
+// For the link U_mu(x) the kernel forms
+//   Sigma_mu(x) = sum_{nu != mu} [ c0 (2 three-link paths) + c1 (6 five-link paths) ],
+// each path a product of links leading from x + mu back to x, so U_mu(x) Sigma_mu(x)
+// is the weighted sum of the closed loops through the link.
+//
+// One thread per link; the link's (mu, parity) is uniform in a block.  Neighbour
+// half indices come from coordinate arithmetic (no index tables).  The 8 paths of
+// each side (above / below the link) share their factors:
+//   above:  A = U_nu(x+mu), W = U_mu(x+nu)^dag U_nu(x)^dag,
+//           D = U_mu(x-mu+nu)^dag U_nu(x-mu)^dag U_mu(x-mu),
+//           T = U_nu(x+mu+nu) U_mu(x+2nu)^dag U_nu(x+nu)^dag,
+//           E = U_mu(x+mu) U_nu(x+2mu) U_mu(x+mu+nu)^dag,
+//   1x1: A W;  1x2: E W (long side forward), A U_mu(x+nu)^dag D (long side
+//   backward), A T U_nu(x)^dag (long side along nu), so the side contributes
+//           A [c0 W + c1 (U_mu(x+nu)^dag D + T U_nu(x)^dag)] + c1 E W,
+// 11 SU(3) products instead of 14 taken path by path; below the link likewise
+// with nu -> -nu.  Products accumulate in the arithmetic type of the format
+// (FP64 for complex128 links, FP32 for the 12-real FP32 / BF16 ones).
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+#include "staple.hpp"
+
+namespace stg {
+
+namespace {
+
+// acc += a * conj(b)
+template <typename T>
+__device__ __forceinline__ void cfma_cb(cpx<T> &acc, cpx<T> a, cpx<T> b) {
+    acc.re = fmat(a.re, b.re, acc.re);
+    acc.re = fmat(a.im, b.im, acc.re);
+    acc.im = fmat(a.im, b.re, acc.im);
+    acc.im = fmat(-a.re, b.im, acc.im);
+}
+
+// C = A B
+template <typename T>
+__device__ __forceinline__ su3<T> mm(const su3<T> &a, const su3<T> &b) {
+    su3<T> c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cpx<T> t = cmul(a.e[i][0], b.e[0][j]);
+            cfma(t, a.e[i][1], b.e[1][j]);
+            cfma(t, a.e[i][2], b.e[2][j]);
+            c.e[i][j] = t;
+        }
+    return c;
+}
+
+// C += A B
+template <typename T>
+__device__ __forceinline__ void mm_acc(su3<T> &c, const su3<T> &a, const su3<T> &b) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cfma(c.e[i][j], a.e[i][k], b.e[k][j]);
+}
+
+// C = A B^dag
+template <typename T>
+__device__ __forceinline__ su3<T> mmd(const su3<T> &a, const su3<T> &b) {
+    su3<T> c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cpx<T> t = {T(0), T(0)};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cfma_cb(t, a.e[i][k], b.e[j][k]);
+            c.e[i][j] = t;
+        }
+    return c;
+}
+
+// C += A B^dag
+template <typename T>
+__device__ __forceinline__ void mmd_acc(su3<T> &c, const su3<T> &a, const su3<T> &b) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cfma_cb(c.e[i][j], a.e[i][k], b.e[j][k]);
+}
+
+// C = A^dag B
+template <typename T>
+__device__ __forceinline__ su3<T> mdm(const su3<T> &a, const su3<T> &b) {
+    su3<T> c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cpx<T> t = cmulc(a.e[0][i], b.e[0][j]);
+            cfmac(t, a.e[1][i], b.e[1][j]);
+            cfmac(t, a.e[2][i], b.e[2][j]);
+            c.e[i][j] = t;
+        }
+    return c;
+}
+
+// C += A^dag B
+template <typename T>
+__device__ __forceinline__ void mdm_acc(su3<T> &c, const su3<T> &a, const su3<T> &b) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cfmac(c.e[i][j], a.e[k][i], b.e[k][j]);
+}
+
+// C = A^dag B^dag = (B A)^dag
+template <typename T>
+__device__ __forceinline__ su3<T> mdmd(const su3<T> &a, const su3<T> &b) {
+    su3<T> c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cpx<T> t = cmul(b.e[j][0], a.e[0][i]);
+            cfma(t, b.e[j][1], a.e[1][i]);
+            cfma(t, b.e[j][2], a.e[2][i]);
+            c.e[i][j] = cconj(t);
+        }
+    return c;
+}
+
+// C = s C + r B
+template <typename T>
+__device__ __forceinline__ void axpby(su3<T> &c, T s, T r, const su3<T> &b) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            c.e[i][j].re = fmat(s, c.e[i][j].re, r * b.e[i][j].re);
+            c.e[i][j].im = fmat(s, c.e[i][j].im, r * b.e[i][j].im);
+        }
+}
+
+template <typename T>
+__device__ __forceinline__ void scale(su3<T> &c, T s) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            c.e[i][j].re *= s;
+            c.e[i][j].im *= s;
+        }
+}
+
+__device__ __forceinline__ uint32_t pick4(uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3,
+                                          int i) {
+    return i == 0 ? v0 : i == 1 ? v1 : i == 2 ? v2 : v3;
+}
+
+// x_d + s with periodic wrap, |s| <= 2 <= N
+__device__ __forceinline__ int wrap_step(int x, int s, int n) {
+    int y = x + s;
+    y += (y < 0) ? n : 0;
+    y -= (y >= n) ? n : 0;
+    return y;
+}
+
+// Lexicographic displacement of the site x when its coordinate x_d (extent n,
+// lexicographic stride st) moves by s.
+__device__ __forceinline__ int lex_step(int x, int s, int n, int st) {
+    return (wrap_step(x, s, n) - x) * st;
+}
+
+// Link loads through the caches: every link is read by about sixty staple
+// computations of nearby links, so these loads must stay cached (the hop's loader
+// streams its links past the caches instead).
+template <typename T, int FMT>
+struct cached_link;
+
+template <>
+struct cached_link<double, FMT_C128_18> {
+    __device__ __forceinline__ static su3<double> load(const void *L, uint32_t Vh, int s,
+                                                        uint32_t h) {
+        const double2 *p = reinterpret_cast<const double2 *>(L) + (size_t)s * 9 * Vh + h;
+        su3<double> u;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const double2 v = p[(size_t)(a * 3 + b) * Vh];
+                u.e[a][b] = {v.x, v.y};
+            }
+        return u;
+    }
+};
+
+template <>
+struct cached_link<double, FMT_C128_12> {
+    __device__ __forceinline__ static su3<double> load(const void *L, uint32_t Vh, int s,
+                                                        uint32_t h) {
+        const double2 *p = reinterpret_cast<const double2 *>(L) + (size_t)s * 6 * Vh + h;
+        su3<double> u;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const double2 v = p[(size_t)(a * 3 + b) * Vh];
+                u.e[a][b] = {v.x, v.y};
+            }
+        rebuild_row2(u);
+        return u;
+    }
+};
+
+template <>
+struct cached_link<float, FMT_C64_12> {
+    __device__ __forceinline__ static su3<float> load(const void *L, uint32_t Vh, int s,
+                                                       uint32_t h) {
+        const float4 *p = reinterpret_cast<const float4 *>(L) + (size_t)s * 3 * Vh + h;
+        const float4 c0 = p[0], c1 = p[Vh], c2 = p[2 * (size_t)Vh];
+        su3<float> u;
+        u.e[0][0] = {c0.x, c0.y};
+        u.e[0][1] = {c0.z, c0.w};
+        u.e[0][2] = {c1.x, c1.y};
+        u.e[1][0] = {c1.z, c1.w};
+        u.e[1][1] = {c2.x, c2.y};
+        u.e[1][2] = {c2.z, c2.w};
+        rebuild_row2(u);
+        return u;
+    }
+};
+
+template <>
+struct cached_link<float, FMT_BF16_12> {
+    __device__ __forceinline__ static su3<float> load(const void *L, uint32_t Vh, int s,
+                                                       uint32_t h) {
+        const uint4 a = reinterpret_cast<const uint4 *>(L)[(size_t)s * Vh + h];
+        const uint2 b = reinterpret_cast<const uint2 *>(
+            reinterpret_cast<const uint4 *>(L) + (size_t)8 * Vh)[(size_t)s * Vh + h];
+        su3<float> u;
+        u.e[0][0] = {bf16_lo(a.x), bf16_hi(a.x)};
+        u.e[0][1] = {bf16_lo(a.y), bf16_hi(a.y)};
+        u.e[0][2] = {bf16_lo(a.z), bf16_hi(a.z)};
+        u.e[1][0] = {bf16_lo(a.w), bf16_hi(a.w)};
+        u.e[1][1] = {bf16_lo(b.x), bf16_hi(b.x)};
+        u.e[1][2] = {bf16_lo(b.y), bf16_hi(b.y)};
+        rebuild_row2(u);
+        return u;
+    }
+};
+
+// The links around one site x: lexicographic index L of x, parity P of x.
+template <typename T, int FMT>
+struct LinkAt {
+    const void *links;
+    uint32_t Vh;
+    int L, P;
+    // U_d(y) for y = x + (displacement dl in lexicographic units, odd-even flip par)
+    __device__ __forceinline__ su3<T> operator()(int d, int dl, int flip) const {
+        const int par = (P + flip) & 1;
+        const uint32_t h = (uint32_t)(L + dl) >> 1;
+        return cached_link<T, FMT>::load(links, Vh, 2 * d + par, h);
+    }
+};
+
+template <typename T, int FMT>
+__global__ __launch_bounds__(kStapleBlock) void staple_kernel(StapleArgs a) {
+    const Geom &g = a.geom;
+    const uint32_t nbx = (g.Vh + kStapleBlock - 1) / kStapleBlock;
+    const uint32_t blk = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int slot = (int)(blk / nbx);
+    const uint32_t h = (blk % nbx) * kStapleBlock + threadIdx.x;
+    if (h >= g.Vh) return;
+    const int mu = slot >> 1, P = slot & 1;
+
+    const Site s = site_coords(g, P, h);
+    const int st[4] = {1, (int)g.N[0], (int)(g.N[0] * g.N[1]), (int)(g.N[0] * g.N[1] * g.N[2])};
+    const int L = (int)s.x[0] + st[1] * (int)s.x[1] + st[2] * (int)s.x[2] + st[3] * (int)s.x[3];
+    const LinkAt<T, FMT> U{a.links, g.Vh, L, P};
+
+    const int xm = (int)pick4(s.x[0], s.x[1], s.x[2], s.x[3], mu);
+    const int nm = (int)pick4(g.N[0], g.N[1], g.N[2], g.N[3], mu);
+    const int sm = (int)pick4(st[0], st[1], st[2], st[3], mu);
+    const int mp1 = lex_step(xm, 1, nm, sm), mm1 = lex_step(xm, -1, nm, sm);
+    const int mp2 = lex_step(xm, 2, nm, sm);
+    const T c0 = (T)a.c0, c1 = (T)a.c1;
+
+    su3<T> acc;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc.e[i][j] = {T(0), T(0)};
+
+#pragma unroll 1
+    for (int k = 1; k < 4; ++k) {
+        const int nu = (mu + k) & 3;
+        const int xn = (int)pick4(s.x[0], s.x[1], s.x[2], s.x[3], nu);
+        const int nn = (int)pick4(g.N[0], g.N[1], g.N[2], g.N[3], nu);
+        const int sn = (int)pick4(st[0], st[1], st[2], st[3], nu);
+        const int np1 = lex_step(xn, 1, nn, sn), nm1 = lex_step(xn, -1, nn, sn);
+        const int np2 = lex_step(xn, 2, nn, sn), nm2 = lex_step(xn, -2, nn, sn);
+
+        // ---- above the link (+nu) ----
+        {
+            // U_mu(x+nu)^dag D + T U_nu(x)^dag, then c0 W + c1 (that)
+            su3<T> y = mm(mdmd(U(mu, mm1 + np1, 0), U(nu, mm1, 1)), U(mu, mm1, 1));  // D
+            su3<T> x = mdm(U(mu, np1, 1), y);
+            y = mmd(mmd(U(nu, mp1 + np1, 0), U(mu, np2, 0)), U(nu, np1, 1));          // T
+            mmd_acc(x, y, U(nu, 0, 0));
+            su3<T> w = mdmd(U(mu, np1, 1), U(nu, 0, 0));  // W = U_mu(x+nu)^dag U_nu(x)^dag
+            axpby(x, c1, c0, w);
+            mm_acc(acc, U(nu, mp1, 1), x);                 // A [...]
+            y = mmd(mm(U(mu, mp1, 1), U(nu, mp2, 0)), U(mu, mp1 + np1, 0));          // E
+            scale(w, c1);
+            mm_acc(acc, y, w);                              // c1 E W
+        }
+        // ---- below the link (-nu) ----
+        {
+            su3<T> y = mm(mdm(U(mu, mm1 + nm1, 0), U(nu, mm1 + nm1, 0)), U(mu, mm1, 1));  // D'
+            su3<T> x = mdm(U(mu, nm1, 1), y);
+            y = mm(mdmd(U(nu, mp1 + nm2, 1), U(mu, nm2, 0)), U(nu, nm2, 0));             // T'
+            mm_acc(x, y, U(nu, nm1, 1));
+            su3<T> w = mdm(U(mu, nm1, 1), U(nu, nm1, 1));  // W' = U_mu(x-nu)^dag U_nu(x-nu)
+            axpby(x, c1, c0, w);
+            mdm_acc(acc, U(nu, mp1 + nm1, 0), x);          // A'^dag [...], A' = U_nu(x+mu-nu)
+            y = mmd(mmd(U(mu, mp1, 1), U(nu, mp2 + nm1, 1)), U(mu, mp1 + nm1, 0));     // E'
+            scale(w, c1);
+            mm_acc(acc, y, w);                              // c1 E' W'
+        }
+    }
+
+    const size_t base = (size_t)slot * 9 * g.Vh + h;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) st_c<T>(a.out, base + (size_t)(i * 3 + j) * g.Vh, acc.e[i][j]);
+}
+
+}  // namespace
+
+int launch_staples(const StapleArgs &a, int fmt, hipStream_t stream) {
+    const dim3 grid(staple_blocks(a.geom.Vh));
+    switch (fmt) {
+        case FMT_C128_18:
+            staple_kernel<double, FMT_C128_18><<<grid, kStapleBlock, 0, stream>>>(a);
+            return 0;
+        case FMT_C128_12:
+            staple_kernel<double, FMT_C128_12><<<grid, kStapleBlock, 0, stream>>>(a);
+            return 0;
+        case FMT_C64_12:
+            staple_kernel<float, FMT_C64_12><<<grid, kStapleBlock, 0, stream>>>(a);
+            return 0;
+        case FMT_BF16_12:
+            staple_kernel<float, FMT_BF16_12><<<grid, kStapleBlock, 0, stream>>>(a);
+            return 0;
+        default:
+            return -1;
+    }
+}
+
+}  // namespace stg

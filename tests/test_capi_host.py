@@ -259,3 +259,29 @@ def test_cg_default_params(lib):
     lib.stg_cg_default_params(ctypes.byref(p))
     assert p.tol == 1e-10 and p.max_iter == 100000 and p.mode == 0
     assert p.delta == 0.1 and p.poll_every == 0 and p.restart == -1
+
+
+def test_staple_arguments_rejected_on_host(lib):
+    """gauge_staples checks its arguments before any GPU work."""
+    from paper_1701_00426_amd import _lib
+    lat = _lat((4, 4, 4, 4))
+    g = _lib.StgGauge()
+    g.links = 0x1000
+    g.fmt = 0
+
+    def call(lattice=lat, gauge=g, c0=5.0 / 3.0, c1=-1.0 / 12.0, out=0x10000000):
+        return lib.gauge_staples(ctypes.byref(lattice), ctypes.byref(gauge) if gauge else None,
+                                 c0, c1, out, None)
+
+    assert call(lattice=_lat((4, 3, 4, 4))) == -1
+    assert call(gauge=None) == -1
+    assert call(out=None) == -1
+    assert call(out=0x10000008) == -1          # not 16-byte aligned
+    assert call(out=0x1000 + 64) == -1         # overlaps the links
+    assert call(c0=float("nan")) == -1
+    assert call(c1=float("inf")) == -1
+    bad = _lib.StgGauge()
+    bad.links = 0x1000
+    bad.fmt = 7
+    assert call(gauge=bad) == -1
+    assert b"format" in lib.stg_last_error()

@@ -285,3 +285,13 @@ def test_staples_tree_level_weights():
     dims = (4, 4, 4, 4)
     s = on.staples(dims, on.unit_links(dims))
     assert np.allclose(s[5], 8.5 * np.eye(3)[:, :, None], rtol=0, atol=1e-14)
+
+
+def test_staples_at_matches_whole_lattice():
+    dims = (4, 6, 2, 4)
+    links = si.su3_links(dims, 28, 0)
+    full = on.staples(dims, links, 0.8, -0.3)
+    hs = [0, 5, 17, 47]
+    for slot in range(8):
+        part = on.staples_at(dims, links, slot, hs, 0.8, -0.3)
+        assert np.array_equal(part, full[slot][:, :, hs])
