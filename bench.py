@@ -46,12 +46,31 @@ KERNEL_SOURCES = ["paper_1701_00426_amd/csrc/hop.hip",
                   "paper_1701_00426_amd/csrc/device_common.hpp"]
 
 
-def kernel_hash() -> str:
+STAPLE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "staples_traffic_32x32x32x32.json")
+STAPLE_SOURCES = ["paper_1701_00426_amd/csrc/staple.hip",
+                  "paper_1701_00426_amd/csrc/staple.hpp",
+                  "paper_1701_00426_amd/csrc/kernels.hpp",
+                  "paper_1701_00426_amd/csrc/device_common.hpp"]
+
+
+def kernel_hash(sources=None) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in (sources or KERNEL_SOURCES):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def measured_traffic(path, sources):
+    """HBM bytes per launch from a committed PMC summary, or None when the kernel
+    sources have changed since the counters were taken."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        tr = json.load(fh)
+    if tr.get("kernel_hash") != kernel_hash(sources):
+        return None
+    return tr.get("bytes_per_launch")
 
 
 def log(*a):
@@ -356,6 +375,8 @@ PAPER_TABLE4 = {(32, 32, 8, 32): (193.79, 51.80), (32, 32, 32, 8): (190.39, 51.6
                 (24, 24, 24, 24): (212.04, 53.74), (32, 32, 32, 32): (201.82, 51.72),
                 (32, 32, 32, 36): (208.54, 52.62)}
 STAPLE_LINK_BYTES = {"c128_18": 144, "c128_12": 96, "c64_12": 48, "bf16_12": 24}
+# threads per link gauge_staples takes by default (2 for FP64 links, 1 for FP32 ones)
+STAPLE_DEFAULT_THREADS = {"c128_18": 2, "c128_12": 2, "c64_12": 1, "bf16_12": 1}
 
 
 def time_staples(stg, torch, gauges, outs, n):
@@ -412,14 +433,25 @@ def bench_staples(profile=False, no_cpu=False, applies=100):
         fmts = ["c128_12"] if profile else (
             ["c128_12", "c128_18", "c64_12", "bf16_12"] if dims == (32, 32, 32, 32)
             else ["c128_12", "c64_12"])
-        for fmt in fmts:
-            gauges = [stg.pack_gauge(dims, links if i == 0 else links.clone(), fmt)
-                      for i in range(2)]
-            cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
-            outs = [torch.empty((8, 3, 3, vh), dtype=cdt, device=dev) for _ in range(2)]
+        key = stg._lib.STG_TUNE_STAPLE_THREADS
+        runs = [(fmt, 0) for fmt in fmts]
+        if dims == (32, 32, 32, 32) and not profile:
+            # the non-default threads per link too, for comparison
+            runs = [(fmt, t) for fmt in fmts for t in (0, 3 - STAPLE_DEFAULT_THREADS[fmt])]
+        cur = None
+        for fmt, threads in runs:
+            if cur != fmt:
+                gauges = [stg.pack_gauge(dims, links if i == 0 else links.clone(), fmt)
+                          for i in range(2)]
+                cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
+                outs = [torch.empty((8, 3, 3, vh), dtype=cdt, device=dev) for _ in range(2)]
+                cur = fmt
+            stg.stg_set_tuning(key, threads)
             dt = time_staples(stg, torch, gauges, outs, applies)
+            stg.stg_set_tuning(key, 0)
             tflops = STAPLE_FLOPS_PER_LINK * 8 * vh / dt / 1e12
             row = {"lattice": "x".join(map(str, dims)), "format": fmt,
+                   "threads_per_link": threads or STAPLE_DEFAULT_THREADS[fmt],
                    "launch_us": round(dt * 1e6, 2),
                    "ns_per_site": round(dt * 1e9 / (2 * vh), 4),
                    "TFLOPs": round(tflops, 2), "frac_alu": round(tflops / ALU_PEAK_TFLOPS, 4),
@@ -428,17 +460,18 @@ def bench_staples(profile=False, no_cpu=False, applies=100):
                    "paper_gauge_md_ns_per_site_K80_P100": PAPER_TABLE4[dims]}
             rows.append(row)
             log(json.dumps(row))
-            if dims == (32, 32, 32, 32) and fmt == "c128_12":
+            if dims == (32, 32, 32, 32) and fmt == "c128_12" and threads == 0:
                 head = row
-            del gauges, outs
-        del links
+        del gauges, outs, links
         torch.cuda.empty_cache()
     out = {"workload": "staples of the tree-level Symanzik gauge force, every link, "
                        "paper Table 4 shapes", "rows": rows}
     if head is not None:
         out["roofline"] = {"bound": "alu", "kernel": "staple_kernel<double, FP64-12> 32^4",
                            "achieved": head["TFLOPs"], "peak": ALU_PEAK_TFLOPS,
-                           "unit": "TFLOP/s", "frac": head["frac_alu"], "traffic": None}
+                           "unit": "TFLOP/s", "frac": head["frac_alu"],
+                           "traffic": measured_traffic(STAPLE_TRAFFIC_FILE, STAPLE_SOURCES),
+                           "kernel_hash": kernel_hash(STAPLE_SOURCES)}
     if not no_cpu and not profile:
         out["cpu_baseline"] = staple_cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -115,7 +115,7 @@ const char *stg_status_string(int status);
 const char *stg_last_error(void);
 
 /*
- * Launch-shape choices of the hop kernels, process-wide (results do not depend
+ * Launch-shape choices of the hop and staple kernels, process-wide (results do not depend
  * on them, only the speed).  Set them before launching work; calls that are in
  * flight keep the choice they were launched with.
  *   STG_TUNE_XCD_REMAP: 1 (default) maps the blocks that run on one XCD of the
@@ -137,13 +137,19 @@ const char *stg_last_error(void);
  *     autotuned shape sets it for the plain hop only.  The choice changes the
  *     order of floating-point additions, so results may differ in the last bits
  *     between choices (each choice is deterministic).
+ *   STG_TUNE_STAPLE_THREADS: 0 (default: automatic), 1 or 2 threads per link in
+ *     gauge_staples; with 2 the paths above and below the link run on separate
+ *     waves and meet in LDS.  Automatic: 2 for FP64 links, 1 for FP32 / BF16
+ *     ones.  Like the threads per site, it changes the order of additions.
+ *     STG_TUNE_XCD_REMAP applies to gauge_staples too.
  * Returns STG_INVALID_ARG for an unknown key or value.
  */
 enum {
     STG_TUNE_XCD_REMAP = 0,
     STG_TUNE_SITES_PER_THREAD = 1,
     STG_TUNE_STAGE_NEIGHBOURS = 2,
-    STG_TUNE_THREADS_PER_SITE = 3
+    STG_TUNE_THREADS_PER_SITE = 3,
+    STG_TUNE_STAPLE_THREADS = 4
 };
 int stg_set_tuning(int key, int value);
 int stg_get_tuning(int key, int *value);

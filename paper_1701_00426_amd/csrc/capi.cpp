@@ -34,6 +34,7 @@ int g_xcd_remap = 1;
 int g_sites_per_thread = 1;
 int g_stage_neighbours = 0;
 int g_threads_per_site = 0;  // 0: by format and fields
+int g_staple_threads = 0;    // 0: by format
 
 int hip_fail(hipError_t e, const char *what) {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
@@ -1274,6 +1275,11 @@ int stg_set_tuning(int key, int value) {
                 return invalid("threads per site takes 0 (automatic), 1, 2 or 4");
             g_threads_per_site = value;
             return STG_OK;
+        case STG_TUNE_STAPLE_THREADS:
+            if (value < 0 || value > 2)
+                return invalid("staple threads per link takes 0 (automatic), 1 or 2");
+            g_staple_threads = value;
+            return STG_OK;
         default: return invalid("unknown tuning key");
     }
 }
@@ -1285,6 +1291,7 @@ int stg_get_tuning(int key, int *value) {
         case STG_TUNE_SITES_PER_THREAD: *value = g_sites_per_thread; return STG_OK;
         case STG_TUNE_STAGE_NEIGHBOURS: *value = g_stage_neighbours; return STG_OK;
         case STG_TUNE_THREADS_PER_SITE: *value = g_threads_per_site; return STG_OK;
+        case STG_TUNE_STAPLE_THREADS: *value = g_staple_threads; return STG_OK;
         default: return invalid("unknown tuning key");
     }
 }
@@ -1348,12 +1355,15 @@ int gauge_staples(const stg_lattice *lat, const stg_gauge *gauge, double c0, dou
     StapleArgs a;
     std::memset(&a, 0, sizeof(a));
     a.geom = g;
+    a.tile = staple_tile(g);
     a.links = gauge->links;
     a.out = out;
     a.c0 = c0;
     a.c1 = c1;
     a.xcd_remap = g_xcd_remap;
-    if (launch_staples(a, gauge->fmt, (hipStream_t)stream)) return invalid("unknown link format");
+    const int threads = g_staple_threads ? g_staple_threads : staple_default_threads(gauge->fmt);
+    if (launch_staples(a, gauge->fmt, threads, (hipStream_t)stream))
+        return invalid("unknown link format");
     HIP_TRY(hipGetLastError());
     return STG_OK;
 }

@@ -272,98 +272,181 @@ struct LinkAt {
     }
 };
 
+// The 1x1 and 1x2 paths on the +nu side of the link: A [c0 W + c1 (U_mu(x+nu)^dag D +
+// T U_nu(x)^dag)] + c1 E W.  mp1 .. np2: lexicographic displacements of x +- mu, x + 2mu,
+// x +- nu, x + 2nu (periodic).
 template <typename T, int FMT>
-__global__ __launch_bounds__(kStapleBlock) void staple_kernel(StapleArgs a) {
+__device__ __forceinline__ void side_above(su3<T> &acc, const LinkAt<T, FMT> &U, int mu, int nu,
+                                           int mp1, int mm1, int mp2, int np1, int np2, T c0,
+                                           T c1) {
+    su3<T> y = mm(mdmd(U(mu, mm1 + np1, 0), U(nu, mm1, 1)), U(mu, mm1, 1));  // D
+    su3<T> x = mdm(U(mu, np1, 1), y);
+    y = mmd(mmd(U(nu, mp1 + np1, 0), U(mu, np2, 0)), U(nu, np1, 1));          // T
+    mmd_acc(x, y, U(nu, 0, 0));
+    su3<T> w = mdmd(U(mu, np1, 1), U(nu, 0, 0));  // W = U_mu(x+nu)^dag U_nu(x)^dag
+    axpby(x, c1, c0, w);                           // c0 W + c1 (...)
+    mm_acc(acc, U(nu, mp1, 1), x);                 // A = U_nu(x+mu)
+    y = mmd(mm(U(mu, mp1, 1), U(nu, mp2, 0)), U(mu, mp1 + np1, 0));          // E
+    scale(w, c1);
+    mm_acc(acc, y, w);
+}
+
+// The same on the -nu side: A' = U_nu(x+mu-nu)^dag, W' = U_mu(x-nu)^dag U_nu(x-nu),
+// D' = U_mu(x-mu-nu)^dag U_nu(x-mu-nu) U_mu(x-mu), T' = U_nu(x+mu-2nu)^dag
+// U_mu(x-2nu)^dag U_nu(x-2nu), E' = U_mu(x+mu) U_nu(x+2mu-nu)^dag U_mu(x+mu-nu)^dag.
+template <typename T, int FMT>
+__device__ __forceinline__ void side_below(su3<T> &acc, const LinkAt<T, FMT> &U, int mu, int nu,
+                                           int mp1, int mm1, int mp2, int nm1, int nm2, T c0,
+                                           T c1) {
+    su3<T> y = mm(mdm(U(mu, mm1 + nm1, 0), U(nu, mm1 + nm1, 0)), U(mu, mm1, 1));  // D'
+    su3<T> x = mdm(U(mu, nm1, 1), y);
+    y = mm(mdmd(U(nu, mp1 + nm2, 1), U(mu, nm2, 0)), U(nu, nm2, 0));             // T'
+    mm_acc(x, y, U(nu, nm1, 1));
+    su3<T> w = mdm(U(mu, nm1, 1), U(nu, nm1, 1));
+    axpby(x, c1, c0, w);
+    mdm_acc(acc, U(nu, mp1 + nm1, 0), x);
+    y = mmd(mmd(U(mu, mp1, 1), U(nu, mp2 + nm1, 1)), U(mu, mp1 + nm1, 0));     // E'
+    scale(w, c1);
+    mm_acc(acc, y, w);
+}
+
+// Half index of the j-th site of one parity in the pencil order of StapleTile.
+__device__ __forceinline__ uint32_t pencil_site(const Geom &g, const StapleTile &t, uint32_t j) {
+    const uint32_t i = j % t.nsl;
+    uint32_t r = j / t.nsl;
+    const uint32_t x3 = r % g.N[3];
+    r /= g.N[3];
+    const uint32_t p0 = r % t.np0;
+    r /= t.np0;
+    const uint32_t p1 = r % t.np1;
+    const uint32_t p2 = r / t.np1;
+    const uint32_t x0h = p0 * t.t0h + i % t.t0h;
+    const uint32_t x1 = p1 * t.t1 + (i / t.t0h) % t.t1;
+    const uint32_t x2 = p2 * t.t2 + i / (t.t0h * t.t1);
+    return x0h + g.nh0 * (x1 + g.N[1] * (x2 + g.N[2] * x3));
+}
+
+// TPL threads per link (1 or 2): a block is TPL waves over the same kStapleLinks
+// links; with 2, wave 0 sums the +nu sides and wave 1 the -nu sides, and wave 0
+// adds wave 1's sums from LDS.  Two waves per SIMD are asked of the FP64 split
+// kernel (it then fits in 256 registers).
+template <typename T, int FMT, int TPL>
+__global__ __launch_bounds__(kStapleLinks * TPL)
+__attribute__((amdgpu_waves_per_eu((TPL == 2 && sizeof(T) == 8) ? 2 : 1)))
+void staple_kernel(StapleArgs a) {
+    __shared__ cpx<T> part[9][kStapleLinks];
     const Geom &g = a.geom;
-    const uint32_t nbx = (g.Vh + kStapleBlock - 1) / kStapleBlock;
     const uint32_t blk = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-    const int slot = (int)(blk / nbx);
-    const uint32_t h = (blk % nbx) * kStapleBlock + threadIdx.x;
-    if (h >= g.Vh) return;
+    const int slot = (int)(blk % 8);
+    const int q = (int)threadIdx.x / kStapleLinks;  // the same in a whole wave
+    const int l = (int)threadIdx.x % kStapleLinks;
+    const uint32_t j = (blk / 8) * kStapleLinks + l;
+    const bool valid = j < g.Vh;
+    const uint32_t h = valid ? pencil_site(g, a.tile, j) : 0;
     const int mu = slot >> 1, P = slot & 1;
-
-    const Site s = site_coords(g, P, h);
-    const int st[4] = {1, (int)g.N[0], (int)(g.N[0] * g.N[1]), (int)(g.N[0] * g.N[1] * g.N[2])};
-    const int L = (int)s.x[0] + st[1] * (int)s.x[1] + st[2] * (int)s.x[2] + st[3] * (int)s.x[3];
-    const LinkAt<T, FMT> U{a.links, g.Vh, L, P};
-
-    const int xm = (int)pick4(s.x[0], s.x[1], s.x[2], s.x[3], mu);
-    const int nm = (int)pick4(g.N[0], g.N[1], g.N[2], g.N[3], mu);
-    const int sm = (int)pick4(st[0], st[1], st[2], st[3], mu);
-    const int mp1 = lex_step(xm, 1, nm, sm), mm1 = lex_step(xm, -1, nm, sm);
-    const int mp2 = lex_step(xm, 2, nm, sm);
-    const T c0 = (T)a.c0, c1 = (T)a.c1;
 
     su3<T> acc;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) acc.e[i][j] = {T(0), T(0)};
+        for (int k = 0; k < 3; ++k) acc.e[i][k] = {T(0), T(0)};
 
+    if (valid) {
+        const Site s = site_coords(g, P, h);
+        const int st[4] = {1, (int)g.N[0], (int)(g.N[0] * g.N[1]),
+                           (int)(g.N[0] * g.N[1] * g.N[2])};
+        const int L = (int)s.x[0] + st[1] * (int)s.x[1] + st[2] * (int)s.x[2] +
+                      st[3] * (int)s.x[3];
+        const LinkAt<T, FMT> U{a.links, g.Vh, L, P};
+        const int xm = (int)pick4(s.x[0], s.x[1], s.x[2], s.x[3], mu);
+        const int nm = (int)pick4(g.N[0], g.N[1], g.N[2], g.N[3], mu);
+        const int sm = (int)pick4(st[0], st[1], st[2], st[3], mu);
+        const int mp1 = lex_step(xm, 1, nm, sm), mm1 = lex_step(xm, -1, nm, sm);
+        const int mp2 = lex_step(xm, 2, nm, sm);
+        const T c0 = (T)a.c0, c1 = (T)a.c1;
 #pragma unroll 1
-    for (int k = 1; k < 4; ++k) {
-        const int nu = (mu + k) & 3;
-        const int xn = (int)pick4(s.x[0], s.x[1], s.x[2], s.x[3], nu);
-        const int nn = (int)pick4(g.N[0], g.N[1], g.N[2], g.N[3], nu);
-        const int sn = (int)pick4(st[0], st[1], st[2], st[3], nu);
-        const int np1 = lex_step(xn, 1, nn, sn), nm1 = lex_step(xn, -1, nn, sn);
-        const int np2 = lex_step(xn, 2, nn, sn), nm2 = lex_step(xn, -2, nn, sn);
-
-        // ---- above the link (+nu) ----
-        {
-            // U_mu(x+nu)^dag D + T U_nu(x)^dag, then c0 W + c1 (that)
-            su3<T> y = mm(mdmd(U(mu, mm1 + np1, 0), U(nu, mm1, 1)), U(mu, mm1, 1));  // D
-            su3<T> x = mdm(U(mu, np1, 1), y);
-            y = mmd(mmd(U(nu, mp1 + np1, 0), U(mu, np2, 0)), U(nu, np1, 1));          // T
-            mmd_acc(x, y, U(nu, 0, 0));
-            su3<T> w = mdmd(U(mu, np1, 1), U(nu, 0, 0));  // W = U_mu(x+nu)^dag U_nu(x)^dag
-            axpby(x, c1, c0, w);
-            mm_acc(acc, U(nu, mp1, 1), x);                 // A [...]
-            y = mmd(mm(U(mu, mp1, 1), U(nu, mp2, 0)), U(mu, mp1 + np1, 0));          // E
-            scale(w, c1);
-            mm_acc(acc, y, w);                              // c1 E W
-        }
-        // ---- below the link (-nu) ----
-        {
-            su3<T> y = mm(mdm(U(mu, mm1 + nm1, 0), U(nu, mm1 + nm1, 0)), U(mu, mm1, 1));  // D'
-            su3<T> x = mdm(U(mu, nm1, 1), y);
-            y = mm(mdmd(U(nu, mp1 + nm2, 1), U(mu, nm2, 0)), U(nu, nm2, 0));             // T'
-            mm_acc(x, y, U(nu, nm1, 1));
-            su3<T> w = mdm(U(mu, nm1, 1), U(nu, nm1, 1));  // W' = U_mu(x-nu)^dag U_nu(x-nu)
-            axpby(x, c1, c0, w);
-            mdm_acc(acc, U(nu, mp1 + nm1, 0), x);          // A'^dag [...], A' = U_nu(x+mu-nu)
-            y = mmd(mmd(U(mu, mp1, 1), U(nu, mp2 + nm1, 1)), U(mu, mp1 + nm1, 0));     // E'
-            scale(w, c1);
-            mm_acc(acc, y, w);                              // c1 E' W'
+        for (int k = 1; k < 4; ++k) {
+            const int nu = (mu + k) & 3;
+            const int xn = (int)pick4(s.x[0], s.x[1], s.x[2], s.x[3], nu);
+            const int nn = (int)pick4(g.N[0], g.N[1], g.N[2], g.N[3], nu);
+            const int sn = (int)pick4(st[0], st[1], st[2], st[3], nu);
+            if (TPL == 1 || q == 0)
+                side_above(acc, U, mu, nu, mp1, mm1, mp2, lex_step(xn, 1, nn, sn),
+                           lex_step(xn, 2, nn, sn), c0, c1);
+            if (TPL == 1 || q == 1)
+                side_below(acc, U, mu, nu, mp1, mm1, mp2, lex_step(xn, -1, nn, sn),
+                           lex_step(xn, -2, nn, sn), c0, c1);
         }
     }
-
+    if (TPL == 2) {
+        if (q == 1) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) part[i * 3 + k][l] = acc.e[i][k];
+        }
+        __syncthreads();
+        if (q == 1) return;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const cpx<T> v = part[i * 3 + k][l];
+                acc.e[i][k].re += v.re;
+                acc.e[i][k].im += v.im;
+            }
+    }
+    if (!valid) return;
     const size_t base = (size_t)slot * 9 * g.Vh + h;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) st_c<T>(a.out, base + (size_t)(i * 3 + j) * g.Vh, acc.e[i][j]);
+        for (int k = 0; k < 3; ++k) st_c<T>(a.out, base + (size_t)(i * 3 + k) * g.Vh, acc.e[i][k]);
+}
+
+template <typename T, int FMT>
+int launch_tpl(const StapleArgs &a, int threads, hipStream_t stream) {
+    const dim3 grid(staple_blocks(a.geom.Vh));
+    if (threads == 1) {
+        staple_kernel<T, FMT, 1><<<grid, kStapleLinks, 0, stream>>>(a);
+        return 0;
+    }
+    if (threads == 2) {
+        staple_kernel<T, FMT, 2><<<grid, 2 * kStapleLinks, 0, stream>>>(a);
+        return 0;
+    }
+    return -1;
+}
+
+// Largest divisor of n that is at most cap and a multiple of step.
+uint32_t tile_extent(uint32_t n, uint32_t cap, uint32_t step) {
+    for (uint32_t d = cap - cap % step; d > step; d -= step)
+        if (n % d == 0) return d;
+    return step;
 }
 
 }  // namespace
 
-int launch_staples(const StapleArgs &a, int fmt, hipStream_t stream) {
-    const dim3 grid(staple_blocks(a.geom.Vh));
+StapleTile staple_tile(const Geom &g) {
+    StapleTile t;
+    const uint32_t T0 = tile_extent(g.N[0], 32, 2), T1 = tile_extent(g.N[1], 4, 1);
+    const uint32_t T2 = tile_extent(g.N[2], 2, 1);
+    t.t0h = T0 / 2;
+    t.t1 = T1;
+    t.t2 = T2;
+    t.nsl = t.t0h * T1 * T2;
+    t.np0 = g.N[0] / T0;
+    t.np1 = g.N[1] / T1;
+    return t;
+}
+
+int launch_staples(const StapleArgs &a, int fmt, int threads, hipStream_t stream) {
     switch (fmt) {
-        case FMT_C128_18:
-            staple_kernel<double, FMT_C128_18><<<grid, kStapleBlock, 0, stream>>>(a);
-            return 0;
-        case FMT_C128_12:
-            staple_kernel<double, FMT_C128_12><<<grid, kStapleBlock, 0, stream>>>(a);
-            return 0;
-        case FMT_C64_12:
-            staple_kernel<float, FMT_C64_12><<<grid, kStapleBlock, 0, stream>>>(a);
-            return 0;
-        case FMT_BF16_12:
-            staple_kernel<float, FMT_BF16_12><<<grid, kStapleBlock, 0, stream>>>(a);
-            return 0;
-        default:
-            return -1;
+        case FMT_C128_18: return launch_tpl<double, FMT_C128_18>(a, threads, stream);
+        case FMT_C128_12: return launch_tpl<double, FMT_C128_12>(a, threads, stream);
+        case FMT_C64_12: return launch_tpl<float, FMT_C64_12>(a, threads, stream);
+        case FMT_BF16_12: return launch_tpl<float, FMT_BF16_12>(a, threads, stream);
+        default: return -1;
     }
 }
 

@@ -251,6 +251,12 @@ def test_tuning_knobs(lib):
     assert lib.stg_set_tuning(3, 4) == 0
     assert lib.stg_get_tuning(3, ctypes.byref(v)) == 0 and v.value == 4
     assert lib.stg_set_tuning(3, 0) == 0
+    # threads per link of the staple kernel: 0 (automatic), 1 or 2
+    assert lib.stg_get_tuning(4, ctypes.byref(v)) == 0 and v.value == 0
+    assert lib.stg_set_tuning(4, 3) == -1 and lib.stg_set_tuning(4, -1) == -1
+    assert lib.stg_set_tuning(4, 1) == 0
+    assert lib.stg_get_tuning(4, ctypes.byref(v)) == 0 and v.value == 1
+    assert lib.stg_set_tuning(4, 0) == 0
 
 
 def test_cg_default_params(lib):

@@ -2,8 +2,10 @@
 FP64 oracle.
 
 Parity: every entry of Sigma_mu(x) for every link on small lattices (one and
-several 128-link tiles, a ragged last tile, extents of 2 where the 1x2 paths wrap
-onto themselves), and sampled links at 32^4 computed one by one by the oracle.
+several 64-link blocks, a ragged last block, several x0/x1/x2 tiles of the
+kernel's visiting order, extents of 2 where the 1x2 paths wrap onto themselves),
+with one and two threads per link, and sampled links at 32^4 computed one by one
+by the oracle.
 
 Inputs of the oracle are the links as the format holds them: FP64-18 as given;
 the 12-real formats keep rows 0 and 1 (FP64 exactly, FP32 rounded to nearest even,
@@ -69,15 +71,27 @@ def gpu_staples(dims, links, fmt, c0=C0, c1=C1):
     return s.cpu().numpy().astype(np.complex128)
 
 
+@pytest.fixture(params=[0, 1, 2], ids=["threads-auto", "threads-1", "threads-2"])
+def staple_threads(request):
+    """Threads per link of the staple kernel: automatic (2 for FP64 links, 1 for FP32
+    ones), one thread, or the two sides of the link on separate waves."""
+    key = stg._lib.STG_TUNE_STAPLE_THREADS
+    old = stg.stg_get_tuning(key)
+    stg.stg_set_tuning(key, request.param)
+    yield request.param
+    stg.stg_set_tuning(key, old)
+
+
 @pytest.mark.parametrize("fmt", FORMATS)
 @pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 4, 4), (6, 4, 2, 10), (4, 6, 8, 10),
-                                  (2, 8, 4, 6)])
-def test_staples_parity(dims, fmt):
+                                  (2, 8, 4, 6), (34, 4, 6, 2), (32, 8, 4, 6)])
+def test_staples_parity(dims, fmt, staple_threads):
     links = si.su3_links(dims, 1701, 40, sum(dims))
     got = gpu_staples(dims, links, fmt)
     want = on.staples(dims, as_stored(links, fmt))
     err = float(np.max(np.abs(got - want)))
-    say(f"staples {fmt} {dims}: max abs err {err:.3e} (tol {_tol(fmt, C0, C1):.1e})")
+    say(f"staples {fmt} {dims} threads={staple_threads}: max abs err {err:.3e} "
+        f"(tol {_tol(fmt, C0, C1):.1e})")
     assert err <= _tol(fmt, C0, C1)
 
 
@@ -103,7 +117,7 @@ def test_staples_unit_links(fmt):
 
 def test_staples_launch_shape_and_repeat_identical():
     """The XCD block order changes only which CU computes a link: bitwise equal
-    results, and two calls agree bitwise."""
+    results, and two calls agree bitwise (with the automatic threads per link)."""
     dims = (8, 4, 4, 6)
     links = si.su3_links(dims, 1701, 42, 0)
     gauge = stg.pack_gauge(dims, to_dev(links), "c128_12")
@@ -137,7 +151,7 @@ def big_links():
     return dims, si.su3_links(dims, 1701, 44, 0)
 
 
-@pytest.mark.parametrize("fmt", ["c128_12", "c64_12"])
+@pytest.mark.parametrize("fmt", ["c128_12", "c128_18", "c64_12", "bf16_12"])
 def test_staples_32_4_sampled(big_links, fmt):
     """32^4 (the size the benchmark times): every slot, sampled links including both
     ends of the half-index range, against the oracle link by link."""
@@ -151,7 +165,7 @@ def test_staples_32_4_sampled(big_links, fmt):
     err = 0.0
     for slot in range(8):
         got = s[slot][:, :, torch.from_numpy(pick).to(s.device)].cpu().numpy()
-        if fmt == "c128_12":
+        if fmt.startswith("c128"):
             want = on.staples_at(dims, links, slot, pick)
         else:
             if stored is None:
