@@ -22,6 +22,9 @@ Paper: Bonati et al., arXiv:1701.00426.
   * Sec. 2.1 (tree-level Symanzik gauge action) and Sec. 4.3 (gauge force:
     staples as products of 3 and 5 links along C-shaped paths) -- Wilson
     lines, the 1x1 and 1x2 loop sums and the staple sum of every link.
+  * Sec. 2.2 (forces of the molecular dynamics from the solutions of Eq.
+    shlineq) -- the rational pseudofermion action and its derivative with
+    respect to every link (thin links; the stout-smearing chain is not here).
 
 Everything takes the arrays as given; random inputs come from the seeded
 generators, which hold none of this arithmetic.
@@ -530,3 +533,68 @@ def staples_at(dims, links, slot: int, hs, c0=SYMANZIK_C0, c1=SYMANZIK_C1):
         for p in five:
             acc += c1 * path_product(dims, links, start, p)
     return acc
+
+
+# --------------------------------------------------------------------------
+# Fermion force of the rational pseudofermion action (Sec. 2.2: the forces of
+# the molecular dynamics come from the multi-shift solutions of Eq. shlineq;
+# Sec. 4.3: most of that step is spent in the operator).
+# --------------------------------------------------------------------------
+
+
+def rational_action(dims, links, phases, mass, shifts, coeffs, phi, solve=None):
+    """S = Re phi^dag sum_k a_k (A + sigma_k)^{-1} phi on the even sites, A the
+    normal operator of Eq. lineqeo (the a0 term of the rational function does not
+    depend on the links and is left out).  ``solve(sigma, b)`` returns
+    (A + sigma)^{-1} b; plain CG to 1e-13 when not given."""
+    s = 0.0
+    for sig, a in zip(shifts, coeffs):
+        if solve is None:
+            x, _, _ = cg(dims, links, phases, mass, phi, tol=1e-13, sigma=sig)
+        else:
+            x = solve(sig, phi)
+        s += a * float(np.real(np.vdot(phi, x)))
+    return s
+
+
+def force_from_solutions(dims, phases, coeffs, x_even, y_odd):
+    """G_mu(z), (8, 3, 3, Vh) in the gauge-field layout, from X_k (even, (n, 3, Vh))
+    and Y_k (odd, (n, 3, Vh)):
+
+      z even:  G_mu(z) =  sum_k a_k phi_mu(z) Y_k(z+mu) X_k(z)^dag
+      z odd:   G_mu(z) = -sum_k a_k phi_mu(z) X_k(z+mu) Y_k(z)^dag
+
+    With X_k = (A + sigma_k)^{-1} phi and Y_k = D_oe X_k this is the derivative of
+    the rational action: A = m^2 - D_eo D_oe gives dS = -sum_k a_k X_k^dag dA X_k
+    = sum_k a_k 2 Re(X_k^dag dD_eo Y_k) (D_eo^dag = -D_oe for any links), and a
+    link U_mu(z) enters D_eo through the forward term at an even z and the
+    backward term at z + mu for an odd z.  So S(U + E) = S(U) + Re Tr(E G) to first
+    order when one link U_mu(z) becomes U_mu(z) + E.  For arbitrary X_k, Y_k the
+    same G is the exact derivative of sum_k a_k 2 Re(X_k^dag D_eo(U) Y_k), which is
+    linear in every link."""
+    vh = half_volume(dims)
+    out = np.zeros((8, 3, 3, vh), dtype=np.complex128)
+    for parity in (0, 1):
+        z = coords(dims, parity)
+        for mu in range(4):
+            hf = half_index(dims, shifted(dims, z, mu, +1))
+            ph = phases[2 * mu + parity]
+            acc = out[2 * mu + parity]
+            for a, x, y in zip(coeffs, x_even, y_odd):
+                if parity == 0:
+                    acc += a * ph * np.einsum("an,bn->abn", y[:, hf], np.conj(x))
+                else:
+                    acc -= a * ph * np.einsum("an,bn->abn", x[:, hf], np.conj(y))
+    return out
+
+
+def fermion_force(dims, links, phases, mass, shifts, coeffs, phi, tol=1e-13):
+    """G of ``force_from_solutions`` with X_k solved by plain CG per pole and
+    Y_k = D_oe X_k.  Returns (G, X, Y)."""
+    xs, ys = [], []
+    for sig in shifts:
+        x, _, _ = cg(dims, links, phases, mass, phi, tol=tol, sigma=sig)
+        xs.append(x)
+        ys.append(d_oe(dims, links, phases, x))
+    xs, ys = np.array(xs), np.array(ys)
+    return force_from_solutions(dims, phases, coeffs, xs, ys), xs, ys

@@ -309,6 +309,133 @@ def run_staple_pins(staples_fn, first_failure=False):
     return out
 
 
+# --------------------------------------------------------------------------
+# Fermion force of the rational action (Sec. 2.2 Eq. shlineq, Eq. lineqeo).
+# Each check takes ``force_fn(dims, phases, coeffs, x_even, y_odd) -> (8,3,3,Vh)``.
+# --------------------------------------------------------------------------
+
+
+def _entries_from_response(f, links, slot, h):
+    """G[slot, :, :, h] read off f(U + E) - f(U) = Re Tr(E G) over the 18 real
+    directions E (central differences when f is not linear)."""
+    got = np.empty((3, 3), dtype=np.complex128)
+    for a in range(3):
+        for b in range(3):
+            d = []
+            for e in (1.0, 1j):
+                plus = links.copy()
+                plus[slot, a, b, h] += e
+                minus = links.copy()
+                minus[slot, a, b, h] -= e
+                d.append(0.5 * (f(plus) - f(minus)))
+            got[b, a] = d[0] - 1j * d[1]
+    return got
+
+
+def force_linear_response(force_fn, dims, seed=50, nlinks=2):
+    """For any X_k (even), Y_k (odd): f(U) = sum_k a_k 2 Re(X_k^dag D_eo(U) Y_k) is
+    linear in each link, and G must be its exact derivative."""
+    links = si.su3_links(dims, seed, 0)
+    ph = si.real_link_field(dims, seed, 1)
+    coeffs = [0.7, -0.3, 1.1]
+    xs = si.gaussian_field(dims, 3, seed, 2)
+    ys = si.gaussian_field(dims, 3, seed, 3)
+    g = force_fn(dims, ph, coeffs, xs, ys)
+
+    def f(lk):
+        return sum(a * 2 * float(np.real(np.vdot(x, on.d_eo(dims, lk, ph, y))))
+                   for a, x, y in zip(coeffs, xs, ys))
+
+    pick = si.rng(seed, 4).integers(0, on.half_volume(dims), size=(8, nlinks))
+    err = 0.0
+    for slot in range(8):
+        for h in pick[slot]:
+            err = max(err, _mat_rel(g[slot, :, :, h], _entries_from_response(f, links, slot, h)))
+    return err
+
+
+def force_action_derivative(force_fn, dims=(2, 2, 2, 4), seed=51, eps=1e-6):
+    """With X_k = (A + sigma_k)^{-1} phi and Y_k = D_oe X_k from dense solves, G is
+    the derivative of S = Re phi^dag sum_k a_k (A + sigma_k)^{-1} phi: central
+    differences of S (dense solves) in all 18 directions of one link per slot."""
+    links = si.su3_links(dims, seed, 0)
+    ph = on.standard_phases(dims)
+    mass, shifts, coeffs = 0.3, [0.0, 0.05, 0.5], [0.4, 0.8, -0.2]
+    phi = si.gaussian_field(dims, 1, seed, 1)[0]
+
+    def solver(lk):
+        _, deo, doe, _ = on.dense_blocks(dims, lk, ph)
+        a = mass * mass * np.eye(deo.shape[0]) - deo @ doe
+        return lambda sig, b: np.linalg.solve(a + sig * np.eye(a.shape[0]),
+                                              b.reshape(-1)).reshape(3, -1)
+
+    sol = solver(links)
+    xs = np.array([sol(s, phi) for s in shifts])
+    ys = np.array([on.d_oe(dims, links, ph, x) for x in xs])
+    g = force_fn(dims, ph, coeffs, xs, ys)
+
+    def f(lk):
+        return on.rational_action(dims, lk, ph, mass, shifts, coeffs, phi, solve=solver(lk))
+
+    err = 0.0
+    for slot in range(8):
+        h = slot % on.half_volume(dims)
+        got = np.empty((3, 3), dtype=np.complex128)
+        for a in range(3):
+            for b in range(3):
+                d = []
+                for e in (1.0, 1j):
+                    plus = links.copy()
+                    plus[slot, a, b, h] += eps * e
+                    minus = links.copy()
+                    minus[slot, a, b, h] -= eps * e
+                    d.append((f(plus) - f(minus)) / (2 * eps))
+                got[b, a] = d[0] - 1j * d[1]
+        err = max(err, _mat_rel(g[slot, :, :, h], got))
+    return err
+
+
+def force_gauge_covariance(force_fn, dims=(4, 2, 4, 6), seed=52):
+    """X -> g X, Y -> g Y (fields at their sites): G_mu(z) -> g(z+mu) G_mu(z) g(z)^dag."""
+    ph = si.real_link_field(dims, seed, 1)
+    coeffs = [0.5, 1.5]
+    xs = si.gaussian_field(dims, 2, seed, 2)
+    ys = si.gaussian_field(dims, 2, seed, 3)
+    g = _site_gauge(dims, seed + 100)
+    f0 = force_fn(dims, ph, coeffs, xs, ys)
+    f1 = force_fn(dims, ph, coeffs, on.site_matrices_apply(g[0], xs),
+                  on.site_matrices_apply(g[1], ys))
+    want = np.empty_like(f0)
+    for parity in (0, 1):
+        z = on.coords(dims, parity)
+        for mu in range(4):
+            gf = _g_at(dims, g, on.shifted(dims, z, mu, +1))
+            want[2 * mu + parity] = np.einsum("abn,bcn,dcn->adn", gf, f0[2 * mu + parity],
+                                              np.conj(g[parity]))
+    return _mat_rel(f1, want)
+
+
+ALL_FORCE_PINS = ("linear_response", "gauge_covariance", "action_derivative")
+
+
+def run_force_pins(force_fn, first_failure=False):
+    """{name: (error, tolerance)}, cheapest first."""
+    checks = [
+        ("gauge_covariance", lambda: force_gauge_covariance(force_fn), 1e-13),
+        ("linear_response", lambda: max(force_linear_response(force_fn, (4, 4, 2, 6)),
+                                        force_linear_response(force_fn, (2, 4, 2, 2), seed=53)),
+         1e-12),
+        ("action_derivative", lambda: force_action_derivative(force_fn), 1e-7),
+    ]
+    out = {}
+    for name, fn, tol in checks:
+        err = fn()
+        out[name] = (err, tol)
+        if first_failure and not err <= tol:
+            break
+    return out
+
+
 def rel_err(a, b):
     return _rel(a, b)
 

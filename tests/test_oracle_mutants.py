@@ -176,3 +176,53 @@ def test_unmutated_staple_copy_passes():
 def test_staple_mutant_detected(mutation):
     res = pins.run_staple_pins(make_staples(mutation), first_failure=True)
     assert _failed(res), f"planted staple mistake {mutation} passed every pin"
+
+
+# --------------------------------------------------------------------------
+# Fermion force: planted mistakes in a copy of the outer-product formula
+# --------------------------------------------------------------------------
+
+
+def make_force(mutation):
+    def force_fn(dims, phases, coeffs, x_even, y_odd):
+        out = np.zeros((8, 3, 3, on.half_volume(dims)), dtype=np.complex128)
+        for parity in (0, 1):
+            z = on.coords(dims, parity)
+            for mu in range(4):
+                step = -1 if mutation == "backward_neighbour" and mu == 2 else 1
+                hf = on.half_index(dims, on.shifted(dims, z, mu, step))
+                ph = phases[2 * mu + parity]
+                if mutation == "no_phase":
+                    ph = 1.0
+                if mutation == "phase_at_neighbour":
+                    ph = phases[2 * mu + 1 - parity][hf]
+                for a, x, y in zip(coeffs, x_even, y_odd):
+                    if parity == 0:
+                        t = np.einsum("an,bn->abn", y[:, hf], np.conj(x))
+                        if mutation == "transposed_outer":
+                            t = np.einsum("an,bn->abn", np.conj(x), y[:, hf])
+                        out[2 * mu] += a * ph * t
+                    else:
+                        t = np.einsum("an,bn->abn", x[:, hf], np.conj(y))
+                        if mutation == "conj_swapped":
+                            t = np.einsum("an,bn->abn", np.conj(x[:, hf]), y)
+                        sign = 1.0 if mutation == "odd_sign" else -1.0
+                        out[2 * mu + 1] += sign * a * ph * t
+        if mutation == "half":
+            out *= 0.5
+        return out
+    return force_fn
+
+
+FORCE_MUTANTS = ["backward_neighbour", "no_phase", "phase_at_neighbour", "transposed_outer",
+                 "conj_swapped", "odd_sign", "half"]
+
+
+def test_unmutated_force_copy_passes():
+    assert _failed(pins.run_force_pins(make_force(None))) == []
+
+
+@pytest.mark.parametrize("mutation", FORCE_MUTANTS)
+def test_force_mutant_detected(mutation):
+    res = pins.run_force_pins(make_force(mutation), first_failure=True)
+    assert _failed(res), f"planted force mistake {mutation} passed every pin"

@@ -295,3 +295,31 @@ def test_staples_at_matches_whole_lattice():
     for slot in range(8):
         part = on.staples_at(dims, links, slot, hs, 0.8, -0.3)
         assert np.array_equal(part, full[slot][:, :, hs])
+
+
+# --------------------------------------------------------------------------
+# Fermion force of the rational action (Sec. 2.2)
+# --------------------------------------------------------------------------
+
+
+def test_force_pins():
+    res = pins.run_force_pins(on.force_from_solutions)
+    for name, (err, tol) in res.items():
+        assert err <= tol, f"force pin {name} error {err:.3e} > {tol:.1e}"
+
+
+def test_fermion_force_end_to_end_matches_dense_derivative():
+    """fermion_force (its own CG solves) agrees with the force from dense solves."""
+    dims = (2, 2, 4, 2)
+    links = si.su3_links(dims, 54, 0)
+    ph = on.standard_phases(dims)
+    mass, shifts, coeffs = 0.2, [0.01, 0.3], [1.0, 0.5]
+    phi = si.gaussian_field(dims, 1, 54, 1)[0]
+    g, xs, ys = on.fermion_force(dims, links, ph, mass, shifts, coeffs, phi)
+    _, deo, doe, _ = on.dense_blocks(dims, links, ph)
+    a = mass * mass * np.eye(deo.shape[0]) - deo @ doe
+    xd = np.array([np.linalg.solve(a + s * np.eye(a.shape[0]), phi.reshape(-1)).reshape(3, -1)
+                   for s in shifts])
+    yd = np.array([on.d_oe(dims, links, ph, x) for x in xd])
+    gd = on.force_from_solutions(dims, ph, coeffs, xd, yd)
+    assert np.max(np.abs(g - gd)) <= 1e-9 * np.max(np.abs(gd))
