@@ -49,6 +49,7 @@ KERNEL_SOURCES = ["paper_1701_00426_amd/csrc/hop.hip",
 STAPLE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "staples_traffic_32x32x32x32.json")
 STAPLE_SOURCES = ["paper_1701_00426_amd/csrc/staple.hip",
                   "paper_1701_00426_amd/csrc/staple.hpp",
+                  "paper_1701_00426_amd/csrc/pencil.hpp",
                   "paper_1701_00426_amd/csrc/kernels.hpp",
                   "paper_1701_00426_amd/csrc/device_common.hpp"]
 
@@ -477,6 +478,58 @@ def bench_staples(profile=False, no_cpu=False, applies=100):
     print(json.dumps(out), flush=True)
 
 
+def bench_force(profile=False, applies=50):
+    """fermion_force at 32^4 with 16 poles (one pseudofermion of the multi-shift
+    workload): the D_oe hops of the 16 solutions plus the outer-product kernel.
+    The solutions are seeded Gaussian fields (the cost does not depend on the
+    values).  Reports the whole call, the hops alone (dirac_apply_oe on the 16
+    fields) and the difference, the force kernel, with its algorithmic GB/s."""
+    import torch
+    import paper_1701_00426_amd as stg
+    import seeded_inputs as si
+    dev = torch.device("cuda:0")
+    dims, n = (32, 32, 32, 32), 16
+    vh = stg.half_volume(dims)
+    links = torch.from_numpy(si.su3_links(dims, 1701, 8, 0)).to(dev)
+    gauge = stg.pack_gauge(dims, links, "c128_12")
+    xs = torch.from_numpy(si.gaussian_field(dims, n, 426, 8, 0)).to(dev)
+    coeffs = [1.0 / (1 + k) for k in range(n)]
+    y = torch.empty_like(xs)
+    out = torch.empty((8, 3, 3, vh), dtype=torch.complex128, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(reps):
+            fn()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / 1e3 / reps
+
+    t_all = timed(lambda: stg.fermion_force(gauge, coeffs, xs, y_odd=y, out=out), applies)
+    if profile:
+        print(json.dumps({"profile": "fermion_force 32^4 16 poles", "calls": applies,
+                          "mean_call_us": round(t_all * 1e6, 2)}), flush=True)
+        return
+    t_hop = timed(lambda: stg.dirac_apply_oe(gauge, xs, y), applies)
+    t_force = t_all - t_hop
+    force_bytes = (2 * n * 48 + 8 * 144) * vh
+    print(json.dumps({
+        "workload": "fermion force, 32^4, 16 poles, FP64-12 links: D_oe of the 16 solutions "
+                    "+ outer-product kernel",
+        "call_ms": round(t_all * 1e3, 3), "doe_16_fields_ms": round(t_hop * 1e3, 3),
+        "force_kernel_ms": round(t_force * 1e3, 3),
+        "force_kernel_algorithmic_bytes": force_bytes,
+        "force_kernel_GBs": round(force_bytes / t_force / 1e9, 1),
+        "force_kernel_frac_hbm": round(force_bytes / t_force / 1e9 / HBM_PEAK_GBS, 4),
+        "ns_per_site": round(t_all * 1e9 / (2 * vh), 3)}), flush=True)
+
+
 # Launch-shape variants of the hop compared under one kernel trace: (format, fields,
 # knob settings).  Each runs the same number of back-to-back D_eo launches.
 VARIANTS = [
@@ -545,13 +598,16 @@ def main():
     ap.add_argument("--profile-cg", action="store_true",
                     help="for rocprofv3: one FP64 CG and one mixed CG solve only")
     ap.add_argument("--workload", choices=["main", "multishift", "rational", "batch",
-                                           "batch-small", "shapes", "staples"],
+                                           "batch-small", "shapes", "staples", "force"],
                     default="main",
                     help="main: the 32^4 line; multishift: 24^3x48, 16 shifts x 8 RHS; "
                          "rational: the same shifts combined into r(A) b; "
                          "batch: 12 solves on 8^4 .. 32^4 in one cg_solve_batch; "
                          "batch-small: 48 solves on 8^4 .. 16^4; "
-                         "staples: gauge-force staples on the Table 4 shapes")
+                         "staples: gauge-force staples on the Table 4 shapes; "
+                         "force: fermion force from 16 multi-shift solutions at 32^4")
+    ap.add_argument("--profile-force", action="store_true",
+                    help="for rocprofv3: only the 32^4 fermion_force loop")
     ap.add_argument("--profile-staples", action="store_true",
                     help="for rocprofv3: only the 32^4 FP64-12 staple loop")
     ap.add_argument("--profile-variants", action="store_true",
@@ -583,6 +639,9 @@ def main():
         return
     if args.workload == "shapes":
         bench_shapes()
+        return
+    if args.workload == "force" or args.profile_force:
+        bench_force(profile=args.profile_force)
         return
     if args.workload == "staples" or args.profile_staples:
         bench_staples(profile=args.profile_staples, no_cpu=args.no_cpu)

@@ -350,6 +350,32 @@ int rational_apply(const stg_lattice *lat, const stg_gauge *hi, const stg_gauge 
 int gauge_staples(const stg_lattice *lat, const stg_gauge *gauge, double c0, double c1,
                   void *out, stg_stream_t stream);
 
+/*
+ * Derivative of the rational pseudofermion action with respect to every link, from
+ * the multi-shift solutions (Sec. 2.2: the molecular-dynamics forces come from the
+ * solutions of the shifted systems of Eq. shlineq for the rational approximation of
+ * Eq. rooting; most of that step is the operator, Sec. 4.3).  For
+ *   S = Re phi^dag sum_k a_k X_k,  X_k = (A + sigma_k)^{-1} phi  (even sites),
+ * with Y_k = D_oe X_k the call writes, for every link U_mu(z),
+ *   z even:  G_mu(z) =  phi_mu(z) sum_k a_k Y_k(z+mu) X_k(z)^dag
+ *   z odd:   G_mu(z) = -phi_mu(z) sum_k a_k X_k(z+mu) Y_k(z)^dag
+ * so that S changes by Re Tr(E G_mu(z)) to first order when U_mu(z) becomes
+ * U_mu(z) + E (phi_mu: the gauge field's phases).  The rest of the force (the
+ * projection U G -> its traceless anti-Hermitian part, smearing) is the caller's.
+ *  gauge: an FP64 format (STG_LINK_C128_18 / _12), the one the solutions belong to.
+ *  coeffs: host, nshift weights a_k (any real values; a_0 of the rational
+ *    function does not depend on the links and takes no part).
+ *  x_even: device complex128 [nshift][3][Vh], the solutions X_k (e.g. from
+ *    multishift_cg_solve with one right-hand side).
+ *  y_odd: device complex128 [nshift][3][Vh], overwritten with D_oe X_k.
+ *  out: device complex128 [8][3][3][Vh] (the link layout), written entirely.
+ * Buffers 16-byte aligned and pairwise disjoint.  Errors: STG_INVALID_ARG (nothing
+ * launched).  Asynchronous.
+ */
+int fermion_force(const stg_lattice *lat, const stg_gauge *gauge, int nshift,
+                  const double *coeffs, const void *x_even, void *y_odd, void *out,
+                  stg_stream_t stream);
+
 typedef struct {
     stg_lattice lat;
     stg_gauge hi;

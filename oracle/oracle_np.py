@@ -557,7 +557,7 @@ def rational_action(dims, links, phases, mass, shifts, coeffs, phi, solve=None):
     return s
 
 
-def force_from_solutions(dims, phases, coeffs, x_even, y_odd):
+def force_from_solutions(dims, phases, coeffs, x_even, y_odd, hs=None):
     """G_mu(z), (8, 3, 3, Vh) in the gauge-field layout, from X_k (even, (n, 3, Vh))
     and Y_k (odd, (n, 3, Vh)):
 
@@ -571,20 +571,21 @@ def force_from_solutions(dims, phases, coeffs, x_even, y_odd):
     backward term at z + mu for an odd z.  So S(U + E) = S(U) + Re Tr(E G) to first
     order when one link U_mu(z) becomes U_mu(z) + E.  For arbitrary X_k, Y_k the
     same G is the exact derivative of sum_k a_k 2 Re(X_k^dag D_eo(U) Y_k), which is
-    linear in every link."""
-    vh = half_volume(dims)
-    out = np.zeros((8, 3, 3, vh), dtype=np.complex128)
+    linear in every link.  With ``hs`` only the links at those half indices (of
+    both parities) are computed: (8, 3, 3, len(hs))."""
+    sel = np.arange(half_volume(dims)) if hs is None else np.asarray(hs, dtype=np.int64)
+    out = np.zeros((8, 3, 3, len(sel)), dtype=np.complex128)
     for parity in (0, 1):
-        z = coords(dims, parity)
+        z = coords(dims, parity)[:, sel]
         for mu in range(4):
             hf = half_index(dims, shifted(dims, z, mu, +1))
-            ph = phases[2 * mu + parity]
+            ph = phases[2 * mu + parity][sel]
             acc = out[2 * mu + parity]
             for a, x, y in zip(coeffs, x_even, y_odd):
                 if parity == 0:
-                    acc += a * ph * np.einsum("an,bn->abn", y[:, hf], np.conj(x))
+                    acc += a * ph * np.einsum("an,bn->abn", y[:, hf], np.conj(x[:, sel]))
                 else:
-                    acc -= a * ph * np.einsum("an,bn->abn", x[:, hf], np.conj(y))
+                    acc -= a * ph * np.einsum("an,bn->abn", x[:, hf], np.conj(y[:, sel]))
     return out
 
 

@@ -33,6 +33,7 @@ __all__ = [
     "multishift_cg_solve", "stg_workspace_bytes", "library", "stg_set_tuning", "stg_get_tuning",
     "cg_solve_batch", "rational_apply", "stg_rational_workspace_bytes", "stg_autotune",
     "stg_autotune_load", "stg_autotune_lookup", "gauge_staples", "SYMANZIK_C0", "SYMANZIK_C1",
+    "fermion_force",
 ]
 
 # tree-level Symanzik weights of the 1x1 and 1x2 loops: c1 = -1/12, c0 + 8 c1 = 1
@@ -212,6 +213,28 @@ def gauge_staples(gauge: Gauge, c0: float = SYMANZIK_C0, c1: float = SYMANZIK_C1
         ctypes.byref(_lib.lattice(gauge.dims)), ctypes.byref(g), float(c0), float(c1), _ptr(out),
         _stream(stream)))
     return out
+
+
+def fermion_force(gauge: Gauge, coeffs, x_even: torch.Tensor, y_odd: Optional[torch.Tensor] = None,
+                  out: Optional[torch.Tensor] = None, stream=None):
+    """Derivative G_mu(z) of S = Re phi^dag sum_k a_k X_k with respect to every link,
+    from the solutions X_k (complex128, (nshift, 3, Vh)); returns (G (8, 3, 3, Vh),
+    Y = D_oe X).  Asynchronous on the stream."""
+    vh = half_volume(gauge.dims)
+    coeffs = [float(c) for c in coeffs]
+    n = len(coeffs)
+    if x_even.dtype != torch.complex128 or tuple(x_even.shape) != (n, 3, vh) or \
+            not x_even.is_contiguous():
+        raise ValueError(f"x_even must be a contiguous complex128 tensor of shape ({n}, 3, {vh})")
+    y_odd = torch.empty_like(x_even) if y_odd is None else y_odd
+    if out is None:
+        out = torch.empty((8, 3, 3, vh), dtype=torch.complex128, device=x_even.device)
+    arr = (ctypes.c_double * max(n, 1))(*coeffs)
+    g = gauge.c()
+    _lib.check("fermion_force", library().fermion_force(
+        ctypes.byref(_lib.lattice(gauge.dims)), ctypes.byref(g), n, arr, _ptr(x_even),
+        _ptr(y_odd), _ptr(out), _stream(stream)))
+    return out, y_odd
 
 
 def stg_apply_normal(gauge: Gauge, mass: float, in_even: torch.Tensor, sigma: float = 0.0,

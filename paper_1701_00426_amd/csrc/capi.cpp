@@ -18,6 +18,7 @@
 
 #include "../../include/stagmi.h"
 #include "batch.hpp"
+#include "force.hpp"
 #include "kernels.hpp"
 #include "solver_state.hpp"
 #include "staple.hpp"
@@ -1355,7 +1356,7 @@ int gauge_staples(const stg_lattice *lat, const stg_gauge *gauge, double c0, dou
     StapleArgs a;
     std::memset(&a, 0, sizeof(a));
     a.geom = g;
-    a.tile = staple_tile(g);
+    a.tile = pencil_tile(g);
     a.links = gauge->links;
     a.out = out;
     a.c0 = c0;
@@ -1364,6 +1365,45 @@ int gauge_staples(const stg_lattice *lat, const stg_gauge *gauge, double c0, dou
     const int threads = g_staple_threads ? g_staple_threads : staple_default_threads(gauge->fmt);
     if (launch_staples(a, gauge->fmt, threads, (hipStream_t)stream))
         return invalid("unknown link format");
+    HIP_TRY(hipGetLastError());
+    return STG_OK;
+}
+
+int fermion_force(const stg_lattice *lat, const stg_gauge *gauge, int nshift,
+                  const double *coeffs, const void *x_even, void *y_odd, void *out,
+                  stg_stream_t stream) {
+    Geom g;
+    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
+    int rc = check_gauge(g, gauge, STG_C128);
+    if (rc) return rc;
+    if (nshift < 1 || !coeffs) return invalid("nshift >= 1 and coeffs non-NULL");
+    for (int k = 0; k < nshift; ++k)
+        if (!std::isfinite(coeffs[k])) return invalid("coefficients must be finite");
+    if (!aligned16(x_even) || !aligned16(y_odd) || !aligned16(out))
+        return invalid("x, y or out NULL or not 16-byte aligned");
+    const size_t fb = (size_t)3 * g.Vh * 16;
+    const size_t nb = (size_t)nshift * fb, ob = (size_t)8 * 9 * g.Vh * 16;
+    const size_t lb = link_bytes(g, gauge->fmt);
+    if (overlap(x_even, nb, y_odd, nb) || overlap(x_even, nb, out, ob) || overlap(y_odd, nb, out, ob) ||
+        overlap(gauge->links, lb, y_odd, nb) || overlap(gauge->links, lb, out, ob))
+        return invalid("x, y, out and the links must not overlap");
+    hipStream_t s = (hipStream_t)stream;
+    rc = hop_plain(g, gauge, STG_C128, nshift, x_even, y_odd, 1, s);
+    if (rc) return rc;
+    ForceArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.geom = g;
+    a.phases = reinterpret_cast<const double *>(gauge->phases);
+    a.out = out;
+    a.xcd_remap = g_xcd_remap;
+    for (int k0 = 0; k0 < nshift; k0 += kForceChunk) {
+        a.npoles = std::min(kForceChunk, nshift - k0);
+        for (int k = 0; k < a.npoles; ++k) a.coeff[k] = coeffs[k0 + k];
+        a.x = reinterpret_cast<const char *>(x_even) + (size_t)k0 * fb;
+        a.y = reinterpret_cast<const char *>(y_odd) + (size_t)k0 * fb;
+        a.accumulate = k0 > 0;
+        launch_force(a, s);
+    }
     HIP_TRY(hipGetLastError());
     return STG_OK;
 }

@@ -310,22 +310,6 @@ __device__ __forceinline__ void side_below(su3<T> &acc, const LinkAt<T, FMT> &U,
     mm_acc(acc, y, w);
 }
 
-// Half index of the j-th site of one parity in the pencil order of StapleTile.
-__device__ __forceinline__ uint32_t pencil_site(const Geom &g, const StapleTile &t, uint32_t j) {
-    const uint32_t i = j % t.nsl;
-    uint32_t r = j / t.nsl;
-    const uint32_t x3 = r % g.N[3];
-    r /= g.N[3];
-    const uint32_t p0 = r % t.np0;
-    r /= t.np0;
-    const uint32_t p1 = r % t.np1;
-    const uint32_t p2 = r / t.np1;
-    const uint32_t x0h = p0 * t.t0h + i % t.t0h;
-    const uint32_t x1 = p1 * t.t1 + (i / t.t0h) % t.t1;
-    const uint32_t x2 = p2 * t.t2 + i / (t.t0h * t.t1);
-    return x0h + g.nh0 * (x1 + g.N[1] * (x2 + g.N[2] * x3));
-}
-
 // TPL threads per link (1 or 2): a block is TPL waves over the same kStapleLinks
 // links; with 2, wave 0 sums the +nu sides and wave 1 the -nu sides, and wave 0
 // adds wave 1's sums from LDS.  Two waves per SIMD are asked of the FP64 split
@@ -418,27 +402,7 @@ int launch_tpl(const StapleArgs &a, int threads, hipStream_t stream) {
     return -1;
 }
 
-// Largest divisor of n that is at most cap and a multiple of step.
-uint32_t tile_extent(uint32_t n, uint32_t cap, uint32_t step) {
-    for (uint32_t d = cap - cap % step; d > step; d -= step)
-        if (n % d == 0) return d;
-    return step;
-}
-
 }  // namespace
-
-StapleTile staple_tile(const Geom &g) {
-    StapleTile t;
-    const uint32_t T0 = tile_extent(g.N[0], 32, 2), T1 = tile_extent(g.N[1], 4, 1);
-    const uint32_t T2 = tile_extent(g.N[2], 2, 1);
-    t.t0h = T0 / 2;
-    t.t1 = T1;
-    t.t2 = T2;
-    t.nsl = t.t0h * T1 * T2;
-    t.np0 = g.N[0] / T0;
-    t.np1 = g.N[1] / T1;
-    return t;
-}
 
 int launch_staples(const StapleArgs &a, int fmt, int threads, hipStream_t stream) {
     switch (fmt) {

@@ -291,3 +291,29 @@ def test_staple_arguments_rejected_on_host(lib):
     bad.fmt = 7
     assert call(gauge=bad) == -1
     assert b"format" in lib.stg_last_error()
+
+
+def test_force_arguments_rejected_on_host(lib):
+    """fermion_force checks its arguments before any GPU work."""
+    from paper_1701_00426_amd import _lib
+    lat = _lat((4, 4, 4, 4))
+    g = _lib.StgGauge()
+    g.links = 0x1000
+    g.fmt = 1
+    co = (ctypes.c_double * 2)(0.5, 0.25)
+
+    # every call below must fail its checks: none may reach a launch
+    def call(gauge=g, n=2, coeffs=co, x=0x1000000, y=0x2000000, out=0x3000000):
+        return lib.fermion_force(ctypes.byref(lat), ctypes.byref(gauge), n, coeffs, x, y, out,
+                                 None)
+
+    assert call(n=0) == -1
+    assert call(coeffs=None) == -1
+    assert call(coeffs=(ctypes.c_double * 2)(0.5, float("nan"))) == -1
+    assert call(x=None) == -1 and call(out=0x3000008) == -1
+    assert call(y=0x1000000 + 64) == -1               # y overlaps x
+    assert call(out=0x2000000 + 64) == -1             # out overlaps y
+    f32 = _lib.StgGauge()
+    f32.links = 0x1000
+    f32.fmt = 2                                       # FP32 links: not for the force
+    assert call(gauge=f32) == -1

@@ -323,3 +323,14 @@ def test_fermion_force_end_to_end_matches_dense_derivative():
     yd = np.array([on.d_oe(dims, links, ph, x) for x in xd])
     gd = on.force_from_solutions(dims, ph, coeffs, xd, yd)
     assert np.max(np.abs(g - gd)) <= 1e-9 * np.max(np.abs(gd))
+
+
+def test_force_sampled_matches_whole_lattice():
+    dims = (4, 2, 6, 4)
+    ph = si.real_link_field(dims, 55, 0)
+    xs = si.gaussian_field(dims, 2, 55, 1)
+    ys = si.gaussian_field(dims, 2, 55, 2)
+    full = on.force_from_solutions(dims, ph, [0.3, -1.2], xs, ys)
+    hs = [0, 7, 30, 47]
+    assert np.array_equal(on.force_from_solutions(dims, ph, [0.3, -1.2], xs, ys, hs=hs),
+                          full[:, :, :, hs])
