@@ -2,7 +2,8 @@
  * stagmi.h -- C ABI of the MI355X (gfx950) staggered-fermion library.
  *
  * The library applies the even/odd staggered Dirac operator and solves the
- * even/odd normal equations with it, on one GPU, in hand-written HIP kernels.
+ * even/odd normal equations with it, on one GPU, in hand-written HIP kernels; it
+ * also computes the gauge-force staples and the fermion force from the solutions.
  *
  * Paper: C. Bonati et al., "Design and optimization of a portable LQCD Monte
  * Carlo code using OpenACC", arXiv:1701.00426.
@@ -19,6 +20,10 @@
  *     array of 8 su3_soa), half-lattice site index of Eq. lexicographic_eo.
  *   - Sec. 4.3, deo listing: the operator reads links, an input field, a real
  *     per-link factor array ("backfield") and writes an output field.
+ *   - Sec. 2.1 and Sec. 4.3 (gauge cycle): staples of the tree-level Symanzik
+ *     gauge action, products of 3 and 5 links along C-shaped paths.
+ *   - Sec. 2.2: molecular-dynamics forces from the multi-shift solutions (the
+ *     derivative of the rational pseudofermion action with respect to the links).
  *
  * Conventions used by every call
  * ------------------------------
