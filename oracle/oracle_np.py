@@ -599,3 +599,40 @@ def fermion_force(dims, links, phases, mass, shifts, coeffs, phi, tol=1e-13):
         ys.append(d_oe(dims, links, phases, x))
     xs, ys = np.array(xs), np.array(ys)
     return force_from_solutions(dims, phases, coeffs, xs, ys), xs, ys
+
+
+# --------------------------------------------------------------------------
+# Stout smearing (Sec. 2.1: the fermion action uses stout-smeared links; Sec. 2.3:
+# the configurations of several stout levels U^(k) are kept).  The definition of
+# Morningstar and Peardon: C_mu(x) = rho * (sum of the six 3-link paths from x to
+# x + mu), Omega = C U^dag, Q = (i/2)(Omega^dag - Omega) - (i/6) Tr(Omega^dag - Omega),
+# U' = exp(iQ) U.
+# --------------------------------------------------------------------------
+
+
+def stout_q(dims, links, rho):
+    """Q_mu(x), (8, 3, 3, Vh): the traceless Hermitian generator of one stout step
+    with isotropic weight rho in all four directions."""
+    # the 3-link paths from x to x + mu are the daggers of the staple paths from
+    # x + mu back to x, so C = rho * (1x1 staple sum)^dag
+    sig = staples(dims, links, 1.0, 0.0)
+    c = rho * np.conj(np.transpose(sig, (0, 2, 1, 3)))
+    omega = np.einsum("sabn,scbn->sacn", c, np.conj(links))       # C U^dag
+    a = np.conj(np.transpose(omega, (0, 2, 1, 3))) - omega         # Omega^dag - Omega
+    tr = np.einsum("saan->sn", a)
+    q = 0.5j * a
+    for i in range(3):
+        q[:, i, i, :] -= (1j / 6.0) * tr
+    return q
+
+
+def stout_smear(dims, links, rho):
+    """U'_mu(x) = exp(i Q_mu(x)) U_mu(x) for every link (one stout level); the
+    exponential by scipy.linalg.expm, matrix by matrix."""
+    from scipy.linalg import expm
+    q = stout_q(dims, links, rho)
+    out = np.empty_like(links)
+    for s in range(8):
+        for h in range(links.shape[3]):
+            out[s, :, :, h] = expm(1j * q[s, :, :, h]) @ links[s, :, :, h]
+    return out

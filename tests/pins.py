@@ -436,6 +436,125 @@ def run_force_pins(force_fn, first_failure=False):
     return out
 
 
+# --------------------------------------------------------------------------
+# Stout smearing (Sec. 2.1 stout-improved fermion action, Sec. 2.3 stout levels).
+# Each check takes ``stout_fn(dims, links, rho) -> smeared links (8, 3, 3, Vh)``.
+# --------------------------------------------------------------------------
+
+
+def _as_mats(links):
+    return np.transpose(links, (0, 3, 1, 2)).reshape(-1, 3, 3)
+
+
+def stout_special_unitary(stout_fn, dims=(4, 4, 2, 6), rho=0.2, seed=71):
+    """exp(iQ) with Q traceless Hermitian times an SU(3) link is in SU(3)."""
+    m = _as_mats(stout_fn(dims, si.su3_links(dims, seed, 0), rho))
+    unit = np.max(np.abs(m @ np.conj(np.transpose(m, (0, 2, 1))) - np.eye(3)))
+    return max(unit, float(np.max(np.abs(np.linalg.det(m) - 1.0))))
+
+
+def stout_trivial_fields(stout_fn, dims=(4, 2, 4, 4), seed=72):
+    """rho = 0, unit links and pure-gauge links are left unchanged (on a pure-gauge
+    field every 3-link path from x to x + mu is U_mu(x), so Omega = 6 rho I, Q = 0)."""
+    links = si.su3_links(dims, seed, 0)
+    e = _mat_rel(stout_fn(dims, links, 0.0), links)
+    u = on.unit_links(dims)
+    e = max(e, _mat_rel(stout_fn(dims, u, 0.3), u))
+    pg = on.pure_gauge_links(dims, *_site_gauge(dims, seed + 1))
+    return max(e, _mat_rel(stout_fn(dims, pg, 0.3), pg))
+
+
+def stout_gauge_covariance(stout_fn, dims=(4, 4, 4, 2), rho=0.15, seed=73):
+    """smear(U^g) = smear(U)^g."""
+    links = si.su3_links(dims, seed, 0)
+    g = _site_gauge(dims, seed + 100)
+    a = stout_fn(dims, on.gauge_transform_links(dims, links, *g), rho)
+    b = on.gauge_transform_links(dims, stout_fn(dims, links, rho), *g)
+    return _mat_rel(a, b)
+
+
+def stout_abelian_closed_form(stout_fn, dims=(4, 2, 4, 6), rho=0.35, seed=74):
+    """Diagonal links diag(e^{i a}, e^{i b}, e^{-i(a+b)}): every product is diagonal,
+    entry by entry a product of phases.  With omega = (C U^dag)_cc for colour c,
+    Q_cc = Im(omega_c) - (1/3) sum_d Im(omega_d) and U'_cc = exp(i Q_cc) U_cc;
+    the phases of the 3-link paths from x to x + mu are summed here site by site."""
+    vh = on.half_volume(dims)
+    ang = si.rng(seed, 0).uniform(-np.pi, np.pi, size=(8, 2, vh))
+    ph = np.stack([ang[:, 0], ang[:, 1], -(ang[:, 0] + ang[:, 1])], axis=1)   # (8, 3, vh)
+    links = np.zeros((8, 3, 3, vh), dtype=np.complex128)
+    for c in range(3):
+        links[:, c, c, :] = np.exp(1j * ph[:, c, :])
+    got = stout_fn(dims, links, rho)
+    want = np.zeros_like(links)
+
+    def phase(d, y, c):
+        return ph[2 * d + int(on.site_parity(y)[0]), c, int(on.half_index(dims, y)[0])]
+
+    for parity in (0, 1):
+        xs = on.coords(dims, parity)
+        for h in range(vh):
+            x = xs[:, h:h + 1]
+            for mu in range(4):
+                om = np.zeros(3, dtype=np.complex128)
+                for c in range(3):
+                    tot = 0.0j
+                    xm = on.shifted(dims, x, mu, +1)
+                    for nu in range(4):
+                        if nu == mu:
+                            continue
+                        xn = on.shifted(dims, x, nu, +1)
+                        xd = on.shifted(dims, x, nu, -1)
+                        up = phase(nu, x, c) + phase(mu, xn, c) - phase(nu, xm, c)
+                        xdm = on.shifted(dims, xd, mu, +1)
+                        down = -phase(nu, xd, c) + phase(mu, xd, c) + phase(nu, xdm, c)
+                        tot += np.exp(1j * up) + np.exp(1j * down)
+                    om[c] = rho * tot * np.exp(-1j * phase(mu, x, c))
+                q = np.imag(om) - np.mean(np.imag(om))
+                for c in range(3):
+                    want[2 * mu + parity, c, c, h] = np.exp(1j * (q[c] + phase(mu, x, c)))
+    return _mat_rel(got, want)
+
+
+def stout_q_from_forward_paths(stout_q_fn, dims=(4, 4, 2, 4), rho=0.25, seed=75):
+    """Q built from the six 3-link paths from x to x + mu written as Wilson lines
+    (independent of the staple sum): C = rho sum_nu [U_nu U_mu U_nu^dag paths]."""
+    links = si.su3_links(dims, seed, 0)
+    q = stout_q_fn(dims, links, rho)
+    want = np.empty_like(q)
+    for parity in (0, 1):
+        x = on.coords(dims, parity)
+        for mu in range(4):
+            c = np.zeros((3, 3, x.shape[1]), dtype=np.complex128)
+            for nu in range(4):
+                if nu != mu:
+                    c += on.path_product(dims, links, x, [(nu, 1), (mu, 1), (nu, -1)])
+                    c += on.path_product(dims, links, x, [(nu, -1), (mu, 1), (nu, 1)])
+            om = np.einsum("abn,cbn->acn", rho * c, np.conj(links[2 * mu + parity]))
+            a = np.conj(np.transpose(om, (1, 0, 2))) - om
+            qq = 0.5j * a
+            tr = np.einsum("aan->n", a)
+            for i in range(3):
+                qq[i, i] -= (1j / 6.0) * tr
+            want[2 * mu + parity] = qq
+    return _mat_rel(q, want)
+
+
+def run_stout_pins(stout_fn, first_failure=False):
+    checks = [
+        ("special_unitary", lambda: stout_special_unitary(stout_fn), 1e-13),
+        ("trivial_fields", lambda: stout_trivial_fields(stout_fn), 1e-13),
+        ("gauge_covariance", lambda: stout_gauge_covariance(stout_fn), 1e-13),
+        ("abelian_closed_form", lambda: stout_abelian_closed_form(stout_fn), 1e-13),
+    ]
+    out = {}
+    for name, fn, tol in checks:
+        err = fn()
+        out[name] = (err, tol)
+        if first_failure and not err <= tol:
+            break
+    return out
+
+
 def rel_err(a, b):
     return _rel(a, b)
 

@@ -226,3 +226,51 @@ def test_unmutated_force_copy_passes():
 def test_force_mutant_detected(mutation):
     res = pins.run_force_pins(make_force(mutation), first_failure=True)
     assert _failed(res), f"planted force mistake {mutation} passed every pin"
+
+
+# --------------------------------------------------------------------------
+# Stout smearing: planted mistakes in a copy of the smearing step
+# --------------------------------------------------------------------------
+
+
+def make_stout(mutation):
+    from scipy.linalg import expm
+
+    def stout_fn(dims, links, rho):
+        c1 = 1.0 if mutation == "with_rectangles" else 0.0
+        sig = on.staples(dims, links, 1.0, c1)
+        c = rho * (sig if mutation == "staple_not_daggered"
+                   else np.conj(np.transpose(sig, (0, 2, 1, 3))))
+        if mutation == "omega_udag_c":
+            om = np.einsum("sban,sbcn->sacn", np.conj(links), c)
+        else:
+            om = np.einsum("sabn,scbn->sacn", c, np.conj(links))
+        a = np.conj(np.transpose(om, (0, 2, 1, 3))) - om
+        q = 0.5j * a
+        if mutation != "no_trace":
+            tr = np.einsum("saan->sn", a)
+            for i in range(3):
+                q[:, i, i, :] -= (1j / 6.0) * tr
+        sign = -1.0 if mutation == "minus_q" else 1.0
+        out = np.empty_like(links)
+        for s in range(8):
+            for h in range(links.shape[3]):
+                e = expm(sign * 1j * q[s, :, :, h])
+                u = links[s, :, :, h]
+                out[s, :, :, h] = u @ e if mutation == "right_multiply" else e @ u
+        return out
+    return stout_fn
+
+
+STOUT_MUTANTS = ["with_rectangles", "staple_not_daggered", "omega_udag_c", "no_trace", "minus_q",
+                 "right_multiply"]
+
+
+def test_unmutated_stout_copy_passes():
+    assert _failed(pins.run_stout_pins(make_stout(None))) == []
+
+
+@pytest.mark.parametrize("mutation", STOUT_MUTANTS)
+def test_stout_mutant_detected(mutation):
+    res = pins.run_stout_pins(make_stout(mutation), first_failure=True)
+    assert _failed(res), f"planted stout mistake {mutation} passed every pin"

@@ -334,3 +334,30 @@ def test_force_sampled_matches_whole_lattice():
     hs = [0, 7, 30, 47]
     assert np.array_equal(on.force_from_solutions(dims, ph, [0.3, -1.2], xs, ys, hs=hs),
                           full[:, :, :, hs])
+
+
+# --------------------------------------------------------------------------
+# Stout smearing (Sec. 2.1, Sec. 2.3)
+# --------------------------------------------------------------------------
+
+
+def test_stout_pins():
+    res = pins.run_stout_pins(on.stout_smear)
+    for name, (err, tol) in res.items():
+        assert err <= tol, f"stout pin {name} error {err:.3e} > {tol:.1e}"
+
+
+def test_stout_q_from_forward_paths():
+    assert pins.stout_q_from_forward_paths(on.stout_q) <= 1e-14
+
+
+def test_stout_q_linear_in_rho_and_small_rho():
+    """Q is linear in rho, and U'(rho) = U + i rho Q(1) U + O(rho^2)."""
+    dims = (4, 2, 4, 4)
+    links = si.su3_links(dims, 76, 0)
+    q1 = on.stout_q(dims, links, 1.0)
+    assert np.max(np.abs(on.stout_q(dims, links, 0.37) - 0.37 * q1)) <= 1e-14
+    r = 1e-5
+    d = (on.stout_smear(dims, links, r) - links) / r
+    want = 1j * np.einsum("sabn,sbcn->sacn", q1, links)
+    assert np.max(np.abs(d - want)) <= 1e-3 * np.max(np.abs(want))
