@@ -530,6 +530,61 @@ def bench_force(profile=False, applies=50):
         "ns_per_site": round(t_all * 1e9 / (2 * vh), 3)}), flush=True)
 
 
+# One stout-smearing step per link: 12 SU(3) products for the six 3-link paths
+# (2484 flop), Omega (198), Q^2 and Tr Q^3 (261), exp(iQ) = f0 + f1 Q + f2 Q^2 (189)
+# and exp(iQ) U (198), plus the weighting: about 3375 flop (trigonometric functions
+# and the row-2 reconstruction of FP64-12 links not counted).
+STOUT_FLOPS_PER_LINK = 3375
+
+
+def bench_stout(profile=False, applies=100):
+    """Two stout levels (rho = 0.15) of a 32^4 FP64-12 gauge field: level 1 reads
+    FP64-12 links, level 2 the FP64-18 output of level 1; HIP events per level."""
+    import torch
+    import paper_1701_00426_amd as stg
+    import seeded_inputs as si
+    dev = torch.device("cuda:0")
+    dims = (32, 32, 32, 32)
+    vh = stg.half_volume(dims)
+    links = torch.from_numpy(si.su3_links(dims, 1701, 9, 0)).to(dev)
+    g0 = stg.pack_gauge(dims, links, "c128_12")
+    del links
+    u1 = torch.empty((8, 3, 3, vh), dtype=torch.complex128, device=dev)
+    u2 = torch.empty_like(u1)
+    g1 = stg.pack_gauge(dims, u1, "c128_18")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(reps):
+            fn()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / 1e3 / reps
+
+    t1 = timed(lambda: stg.stout_smear(g0, 0.15, out=u1), applies)
+    if profile:
+        print(json.dumps({"profile": "stout level FP64-12 -> FP64-18, 32^4", "calls": applies,
+                          "mean_launch_us": round(t1 * 1e6, 2)}), flush=True)
+        return
+    t2 = timed(lambda: stg.stout_smear(g1, 0.15, out=u2), applies)
+    rows = []
+    for label, t, lb in (("level 1 (FP64-12 in)", t1, 96), ("level 2 (FP64-18 in)", t2, 144)):
+        tf = STOUT_FLOPS_PER_LINK * 8 * vh / t / 1e12
+        rows.append({"step": label, "launch_us": round(t * 1e6, 2),
+                     "ns_per_site": round(t * 1e9 / (2 * vh), 4), "TFLOPs": round(tf, 2),
+                     "frac_alu": round(tf / ALU_PEAK_TFLOPS, 4),
+                     "algorithmic_GBs": round((lb + 144) * 8 * vh / t / 1e9, 1),
+                     "frac_hbm": round((lb + 144) * 8 * vh / t / 1e9 / HBM_PEAK_GBS, 4)})
+    print(json.dumps({"workload": "stout smearing, 32^4, rho = 0.15, two levels",
+                      "rows": rows}), flush=True)
+
+
 # Launch-shape variants of the hop compared under one kernel trace: (format, fields,
 # knob settings).  Each runs the same number of back-to-back D_eo launches.
 VARIANTS = [
@@ -598,14 +653,18 @@ def main():
     ap.add_argument("--profile-cg", action="store_true",
                     help="for rocprofv3: one FP64 CG and one mixed CG solve only")
     ap.add_argument("--workload", choices=["main", "multishift", "rational", "batch",
-                                           "batch-small", "shapes", "staples", "force"],
+                                           "batch-small", "shapes", "staples", "force",
+                                           "stout"],
                     default="main",
                     help="main: the 32^4 line; multishift: 24^3x48, 16 shifts x 8 RHS; "
                          "rational: the same shifts combined into r(A) b; "
                          "batch: 12 solves on 8^4 .. 32^4 in one cg_solve_batch; "
                          "batch-small: 48 solves on 8^4 .. 16^4; "
                          "staples: gauge-force staples on the Table 4 shapes; "
-                         "force: fermion force from 16 multi-shift solutions at 32^4")
+                         "force: fermion force from 16 multi-shift solutions at 32^4; "
+                         "stout: two stout-smearing levels at 32^4")
+    ap.add_argument("--profile-stout", action="store_true",
+                    help="for rocprofv3: only the 32^4 level-1 stout loop")
     ap.add_argument("--profile-force", action="store_true",
                     help="for rocprofv3: only the 32^4 fermion_force loop")
     ap.add_argument("--profile-staples", action="store_true",
@@ -639,6 +698,9 @@ def main():
         return
     if args.workload == "shapes":
         bench_shapes()
+        return
+    if args.workload == "stout" or args.profile_stout:
+        bench_stout(profile=args.profile_stout)
         return
     if args.workload == "force" or args.profile_force:
         bench_force(profile=args.profile_force)

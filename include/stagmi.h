@@ -24,6 +24,7 @@
  *     gauge action, products of 3 and 5 links along C-shaped paths.
  *   - Sec. 2.2: molecular-dynamics forces from the multi-shift solutions (the
  *     derivative of the rational pseudofermion action with respect to the links).
+ *   - Sec. 2.1 and Sec. 2.3: stout-smeared links (one smearing step per call).
  *
  * Conventions used by every call
  * ------------------------------
@@ -380,6 +381,26 @@ int gauge_staples(const stg_lattice *lat, const stg_gauge *gauge, double c0, dou
 int fermion_force(const stg_lattice *lat, const stg_gauge *gauge, int nshift,
                   const double *coeffs, const void *x_even, void *y_odd, void *out,
                   stg_stream_t stream);
+
+/*
+ * One stout-smearing step of every link (Sec. 2.1: the staggered fermion action is
+ * built on stout-smeared links; Sec. 2.3: the configurations of the stout levels
+ * U^(k) are kept), by the definition of Morningstar and Peardon:
+ *   C_mu(x)  = rho * sum_{nu != mu} [ U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag
+ *                                    + U_nu(x-nu)^dag U_mu(x-nu) U_nu(x-nu+mu) ],
+ *   Omega    = C_mu(x) U_mu(x)^dag,
+ *   Q        = (i/2)(Omega^dag - Omega) - (i/6) Tr(Omega^dag - Omega),
+ *   U'_mu(x) = exp(i Q) U_mu(x).
+ * exp(iQ) is evaluated in closed form through the Cayley-Hamilton theorem (FP64).
+ *  gauge: STG_LINK_C128_18 or STG_LINK_C128_12 (links in SU(3)); phases ignored.
+ *  rho: isotropic weight, finite.
+ *  out: device complex128 [8][3][3][Vh] (the STG_LINK_C128_18 layout), 16-byte
+ *    aligned, not overlapping the links; written entirely.  Several levels: call
+ *    again with out as an STG_LINK_C128_18 gauge field (into a second buffer).
+ * Errors: STG_INVALID_ARG (nothing launched).  Asynchronous.
+ */
+int stout_smear(const stg_lattice *lat, const stg_gauge *gauge, double rho, void *out,
+                stg_stream_t stream);
 
 typedef struct {
     stg_lattice lat;

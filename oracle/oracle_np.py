@@ -636,3 +636,29 @@ def stout_smear(dims, links, rho):
         for h in range(links.shape[3]):
             out[s, :, :, h] = expm(1j * q[s, :, :, h]) @ links[s, :, :, h]
     return out
+
+
+def stout_smear_at(dims, links, slot: int, hs, rho):
+    """U' at the links of one slot at half indices hs only, (3, 3, n): the same
+    definition as ``stout_smear`` with C from the six 3-link paths from x to x + mu
+    written as Wilson lines, for spot checks on large lattices."""
+    from scipy.linalg import expm
+    mu, parity = slot // 2, slot % 2
+    hs = np.asarray(hs, dtype=np.int64)
+    x = coords(dims, parity)[:, hs]
+    c = np.zeros((3, 3, len(hs)), dtype=np.complex128)
+    for nu in range(4):
+        if nu != mu:
+            c += path_product(dims, links, x, [(nu, 1), (mu, 1), (nu, -1)])
+            c += path_product(dims, links, x, [(nu, -1), (mu, 1), (nu, 1)])
+    u = links[slot][:, :, hs]
+    om = np.einsum("abn,cbn->acn", rho * c, np.conj(u))
+    a = np.conj(np.transpose(om, (1, 0, 2))) - om
+    q = 0.5j * a
+    tr = np.einsum("aan->n", a)
+    for i in range(3):
+        q[i, i] -= (1j / 6.0) * tr
+    out = np.empty_like(u)
+    for n in range(len(hs)):
+        out[:, :, n] = expm(1j * q[:, :, n]) @ u[:, :, n]
+    return out

@@ -33,7 +33,7 @@ __all__ = [
     "multishift_cg_solve", "stg_workspace_bytes", "library", "stg_set_tuning", "stg_get_tuning",
     "cg_solve_batch", "rational_apply", "stg_rational_workspace_bytes", "stg_autotune",
     "stg_autotune_load", "stg_autotune_lookup", "gauge_staples", "SYMANZIK_C0", "SYMANZIK_C1",
-    "fermion_force",
+    "fermion_force", "stout_smear",
 ]
 
 # tree-level Symanzik weights of the 1x1 and 1x2 loops: c1 = -1/12, c0 + 8 c1 = 1
@@ -235,6 +235,23 @@ def fermion_force(gauge: Gauge, coeffs, x_even: torch.Tensor, y_odd: Optional[to
         ctypes.byref(_lib.lattice(gauge.dims)), ctypes.byref(g), n, arr, _ptr(x_even),
         _ptr(y_odd), _ptr(out), _stream(stream)))
     return out, y_odd
+
+
+def stout_smear(gauge: Gauge, rho: float, out: Optional[torch.Tensor] = None,
+                stream=None) -> torch.Tensor:
+    """One stout-smearing step of every link: complex128 (8, 3, 3, Vh), the full
+    FP64 link layout (asynchronous on the stream)."""
+    vh = half_volume(gauge.dims)
+    if out is None:
+        out = torch.empty((8, 3, 3, vh), dtype=torch.complex128, device=gauge.links.device)
+    elif out.dtype != torch.complex128 or tuple(out.shape) != (8, 3, 3, vh) or \
+            not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous complex128 tensor of shape (8, 3, 3, {vh})")
+    g = gauge.c()
+    _lib.check("stout_smear", library().stout_smear(
+        ctypes.byref(_lib.lattice(gauge.dims)), ctypes.byref(g), float(rho), _ptr(out),
+        _stream(stream)))
+    return out
 
 
 def stg_apply_normal(gauge: Gauge, mass: float, in_even: torch.Tensor, sigma: float = 0.0,

@@ -1408,6 +1408,29 @@ int fermion_force(const stg_lattice *lat, const stg_gauge *gauge, int nshift,
     return STG_OK;
 }
 
+int stout_smear(const stg_lattice *lat, const stg_gauge *gauge, double rho, void *out,
+                stg_stream_t stream) {
+    Geom g;
+    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
+    int rc = check_gauge(g, gauge, STG_C128);
+    if (rc) return rc;
+    if (!std::isfinite(rho)) return invalid("rho must be finite");
+    if (!aligned16(out)) return invalid("out NULL or not 16-byte aligned");
+    if (overlap(gauge->links, link_bytes(g, gauge->fmt), out, (size_t)8 * 9 * g.Vh * 16))
+        return invalid("links and out overlap");
+    StoutArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.geom = g;
+    a.tile = pencil_tile(g);
+    a.links = gauge->links;
+    a.out = out;
+    a.rho = rho;
+    a.xcd_remap = g_xcd_remap;
+    if (launch_stout(a, gauge->fmt, (hipStream_t)stream)) return invalid("not an FP64 link format");
+    HIP_TRY(hipGetLastError());
+    return STG_OK;
+}
+
 int dirac_apply_eo(const stg_lattice *lat, const stg_gauge *gauge, stg_field field, int nrhs,
                    const void *in_odd, void *out_even, stg_stream_t stream) {
     return apply_dirac(lat, gauge, field, nrhs, in_odd, out_even, 0, stream);

@@ -23,6 +23,12 @@
 // 11 SU(3) products instead of 14 taken path by path; below the link likewise
 // with nu -> -nu.  Products accumulate in the arithmetic type of the format
 // (FP64 for complex128 links, FP32 for the 12-real FP32 / BF16 ones).
+//
+// The same file holds one stout-smearing step (Sec. 2.1: the fermion action is
+// built on stout-smeared links; Sec. 2.3: the configurations of the stout levels
+// are kept): with C_mu(x) = rho * (the six 3-link paths from x to x + mu),
+// Omega = C U^dag and Q = (i/2)(Omega^dag - Omega) - (i/6) Tr(Omega^dag - Omega),
+// every link becomes exp(iQ) U (Morningstar and Peardon's definition).
 
 #include "device_common.hpp"
 #include "kernels.hpp"
@@ -388,6 +394,140 @@ void staple_kernel(StapleArgs a) {
         for (int k = 0; k < 3; ++k) st_c<T>(a.out, base + (size_t)(i * 3 + k) * g.Vh, acc.e[i][k]);
 }
 
+// exp(iQ) for a traceless Hermitian 3x3 matrix Q.  Cayley-Hamilton gives
+// Q^3 = c1 Q + c0 with c0 = det Q = Tr(Q^3)/3 and c1 = Tr(Q^2)/2, so
+// exp(iQ) = f0 + f1 Q + f2 Q^2.  For c1 >= 1e-3 the f_j come in closed form from the
+// eigenvalues of Q, parametrised by u and w (Morningstar and Peardon, Phys. Rev. D 69,
+// 054501 (2004), Sec. III), computed for |c0| and mapped back by
+// f_j(-c0) = (-1)^j conj(f_j(c0)).  Below that, the power series of exp, reduced by the
+// same recurrence (Q^n = a_n + b_n Q + d_n Q^2), to 16 terms.
+__device__ __forceinline__ su3<double> exp_iq(const su3<double> &q) {
+    const su3<double> q2 = mm(q, q);
+    const double c1 = 0.5 * (q2.e[0][0].re + q2.e[1][1].re + q2.e[2][2].re);
+    double tr3 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) tr3 += cmul(q.e[i][k], q2.e[k][i]).re;
+    const double c0 = tr3 / 3.0;
+    cpx<double> f0, f1, f2;
+    if (c1 < 1e-3) {
+        double an = 1.0, bn = 0.0, dn = 0.0, fact = 1.0;
+        cpx<double> ip = {1.0, 0.0};  // i^n
+        f0 = f1 = f2 = {0.0, 0.0};
+        for (int n = 0; n < 16; ++n) {
+            f0 = cadd(f0, cscale(an / fact, ip));
+            f1 = cadd(f1, cscale(bn / fact, ip));
+            f2 = cadd(f2, cscale(dn / fact, ip));
+            const double a1 = dn * c0, b1 = an + dn * c1, d1 = bn;
+            an = a1;
+            bn = b1;
+            dn = d1;
+            fact *= (double)(n + 1);
+            ip = {-ip.im, ip.re};
+        }
+    } else {
+        const double c0a = fabs(c0);
+        const double s3 = sqrt(c1 / 3.0);
+        const double c0max = 2.0 * s3 * s3 * s3;
+        const double th = acos(fmin(c0a / c0max, 1.0));
+        double st3, ct3, sw, cw, su, cu;
+        sincos(th / 3.0, &st3, &ct3);
+        const double u = s3 * ct3, w = sqrt(c1) * st3;
+        const double uu = u * u, ww = w * w;
+        sincos(w, &sw, &cw);
+        sincos(u, &su, &cu);
+        const double xi0 = fabs(w) < 0.05 ? 1.0 - ww / 6.0 * (1.0 - ww / 20.0 * (1.0 - ww / 42.0))
+                                          : sw / w;
+        const cpx<double> e2iu = {cu * cu - su * su, 2.0 * su * cu};  // exp(2iu)
+        const cpx<double> emiu = {cu, -su};                          // exp(-iu)
+        const cpx<double> h0 = cadd(cscale(uu - ww, e2iu),
+                                    cmul(emiu, cpx<double>{8.0 * uu * cw,
+                                                           2.0 * u * (3.0 * uu + ww) * xi0}));
+        const cpx<double> h1 = csub(cscale(2.0 * u, e2iu),
+                                    cmul(emiu, cpx<double>{2.0 * u * cw,
+                                                           -(3.0 * uu - ww) * xi0}));
+        const cpx<double> h2 = csub(e2iu, cmul(emiu, cpx<double>{cw, 3.0 * u * xi0}));
+        const double inv = 1.0 / (9.0 * uu - ww);
+        f0 = cscale(inv, h0);
+        f1 = cscale(inv, h1);
+        f2 = cscale(inv, h2);
+        if (c0 < 0.0) {
+            f0 = cconj(f0);
+            f1 = cscale(-1.0, cconj(f1));
+            f2 = cconj(f2);
+        }
+    }
+    su3<double> e;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            cpx<double> v = cadd(cmul(f1, q.e[i][k]), cmul(f2, q2.e[i][k]));
+            if (i == k) v = cadd(v, f0);
+            e.e[i][k] = v;
+        }
+    return e;
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kStoutBlock) void stout_kernel(StoutArgs a) {
+    const Geom &g = a.geom;
+    const uint32_t blk = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int slot = (int)(blk % 8);
+    const uint32_t j = (blk / 8) * kStoutBlock + threadIdx.x;
+    if (j >= g.Vh) return;
+    const uint32_t h = pencil_site(g, a.tile, j);
+    const int mu = slot >> 1, P = slot & 1;
+    const Site s = site_coords(g, P, h);
+    const int st[4] = {1, (int)g.N[0], (int)(g.N[0] * g.N[1]), (int)(g.N[0] * g.N[1] * g.N[2])};
+    const int L = (int)s.x[0] + st[1] * (int)s.x[1] + st[2] * (int)s.x[2] + st[3] * (int)s.x[3];
+    const LinkAt<double, FMT> U{a.links, g.Vh, L, P};
+    const int xm = (int)pick4(s.x[0], s.x[1], s.x[2], s.x[3], mu);
+    const int nm = (int)pick4(g.N[0], g.N[1], g.N[2], g.N[3], mu);
+    const int sm = (int)pick4(st[0], st[1], st[2], st[3], mu);
+    const int mp1 = lex_step(xm, 1, nm, sm);
+
+    // C / rho: the 3-link paths from x to x + mu, above and below in each plane
+    su3<double> c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) c.e[i][k] = {0.0, 0.0};
+#pragma unroll 1
+    for (int k = 1; k < 4; ++k) {
+        const int nu = (mu + k) & 3;
+        const int xn = (int)pick4(s.x[0], s.x[1], s.x[2], s.x[3], nu);
+        const int nn = (int)pick4(g.N[0], g.N[1], g.N[2], g.N[3], nu);
+        const int sn = (int)pick4(st[0], st[1], st[2], st[3], nu);
+        const int np1 = lex_step(xn, 1, nn, sn), nm1 = lex_step(xn, -1, nn, sn);
+        // U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag
+        mmd_acc(c, mm(U(nu, 0, 0), U(mu, np1, 1)), U(nu, mp1, 1));
+        // U_nu(x-nu)^dag U_mu(x-nu) U_nu(x-nu+mu)
+        mm_acc(c, mdm(U(nu, nm1, 1), U(mu, nm1, 1)), U(nu, mp1 + nm1, 0));
+    }
+    scale(c, a.rho);
+    const su3<double> u = U(mu, 0, 0);
+    const su3<double> om = mmd(c, u);  // Omega = C U^dag
+    // Q = (i/2)(Omega^dag - Omega) - (1/3) sum_i Im(Omega_ii) I
+    const double tq = (om.e[0][0].im + om.e[1][1].im + om.e[2][2].im) / 3.0;
+    su3<double> q;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const cpx<double> z = csub(cconj(om.e[k][i]), om.e[i][k]);
+            q.e[i][k] = {-0.5 * z.im, 0.5 * z.re};
+            if (i == k) q.e[i][k].re -= tq;
+        }
+    const su3<double> up = mm(exp_iq(q), u);
+    const size_t base = (size_t)slot * 9 * g.Vh + h;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) st_c<double>(a.out, base + (size_t)(i * 3 + k) * g.Vh, up.e[i][k]);
+}
+
 template <typename T, int FMT>
 int launch_tpl(const StapleArgs &a, int threads, hipStream_t stream) {
     const dim3 grid(staple_blocks(a.geom.Vh));
@@ -403,6 +543,15 @@ int launch_tpl(const StapleArgs &a, int threads, hipStream_t stream) {
 }
 
 }  // namespace
+
+int launch_stout(const StoutArgs &a, int fmt, hipStream_t stream) {
+    const dim3 grid(stout_blocks(a.geom.Vh));
+    switch (fmt) {
+        case FMT_C128_18: stout_kernel<FMT_C128_18><<<grid, kStoutBlock, 0, stream>>>(a); return 0;
+        case FMT_C128_12: stout_kernel<FMT_C128_12><<<grid, kStoutBlock, 0, stream>>>(a); return 0;
+        default: return -1;
+    }
+}
 
 int launch_staples(const StapleArgs &a, int fmt, int threads, hipStream_t stream) {
     switch (fmt) {

@@ -34,4 +34,21 @@ inline int staple_default_threads(int fmt) { return (fmt == FMT_C128_18 || fmt =
 // 0: launched; -1: unknown format or thread count (nothing launched).
 int launch_staples(const StapleArgs &a, int fmt, int threads, hipStream_t stream);
 
+// One stout-smearing step of every link (staple.hip): U' = exp(iQ) U.
+constexpr int kStoutBlock = 128;
+
+struct StoutArgs {
+    Geom geom;
+    PencilTile tile;    // visiting order of the links of a slot (pencil.hpp)
+    const void *links;  // FP64 gauge field (FMT_C128_18 or FMT_C128_12)
+    void *out;          // complex128 [8][3][3][Vh]
+    double rho;         // weight of the six 3-link paths
+    int xcd_remap;
+};
+
+inline uint32_t stout_blocks(uint32_t Vh) { return 8u * ((Vh + kStoutBlock - 1) / kStoutBlock); }
+
+// 0: launched; -1: not an FP64 format (nothing launched).
+int launch_stout(const StoutArgs &a, int fmt, hipStream_t stream);
+
 }  // namespace stg

@@ -317,3 +317,23 @@ def test_force_arguments_rejected_on_host(lib):
     f32.links = 0x1000
     f32.fmt = 2                                       # FP32 links: not for the force
     assert call(gauge=f32) == -1
+
+
+def test_stout_arguments_rejected_on_host(lib):
+    """stout_smear checks its arguments before any GPU work (every call here fails)."""
+    from paper_1701_00426_amd import _lib
+    lat = _lat((4, 4, 4, 4))
+    g = _lib.StgGauge()
+    g.links = 0x1000
+    g.fmt = 0
+
+    def call(gauge=g, rho=0.15, out=0x10000000):
+        return lib.stout_smear(ctypes.byref(lat), ctypes.byref(gauge), rho, out, None)
+
+    assert call(rho=float("nan")) == -1
+    assert call(out=None) == -1 and call(out=0x10000004) == -1
+    assert call(out=0x1000 + 4096) == -1           # overlaps the links
+    f32 = _lib.StgGauge()
+    f32.links = 0x1000
+    f32.fmt = 2
+    assert call(gauge=f32) == -1

@@ -1,0 +1,89 @@
+"""GPU stout smearing (stout_smear) against the FP64 oracle.
+
+Parity: every entry of every smeared link on small lattices (extents of 2, ragged
+last blocks, several pencils), FP64-18 and FP64-12 input, several weights rho
+including 0 and negative ones, two chained levels, sampled links at 32^4, and the
+hop on smeared links.  The oracle exponentiates with scipy.linalg.expm, the kernel
+through the Cayley-Hamilton closed form, so agreement also checks that form.
+
+Tolerance: smeared links are SU(3) (entries of modulus <= 1); the kernel's products
+and exponential in FP64 agree with the oracle's to a few 1e-15; 1e-13 absolute.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1701_00426_amd as stg  # noqa: E402
+import seeded_inputs as si  # noqa: E402
+from oracle import oracle_np as on  # noqa: E402
+
+from gpu_common import rel_max, say, to_dev  # noqa: E402
+
+TOL = 1e-13
+
+
+@pytest.mark.parametrize("fmt", ["c128_18", "c128_12"])
+@pytest.mark.parametrize("rho", [0.15, 0.0, -0.2, 1.0])
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 4, 4), (6, 4, 2, 10), (34, 4, 6, 2),
+                                  (32, 8, 4, 6)])
+def test_stout_parity(dims, rho, fmt):
+    links = si.su3_links(dims, 1701, 80, sum(dims))
+    got = stg.stout_smear(stg.pack_gauge(dims, to_dev(links), fmt), rho)
+    torch.cuda.synchronize()
+    want = on.stout_smear(dims, links, rho)
+    err = float(np.max(np.abs(got.cpu().numpy() - want)))
+    say(f"stout {fmt} {dims} rho={rho}: max abs err {err:.2e}")
+    assert err <= TOL
+
+
+def test_stout_two_levels_and_trivial_fields():
+    dims = (4, 6, 4, 2)
+    links = si.su3_links(dims, 1701, 81, 0)
+    g1 = stg.stout_smear(stg.pack_gauge(dims, to_dev(links), "c128_12"), 0.15)
+    g2 = stg.stout_smear(stg.pack_gauge(dims, g1, "c128_18"), 0.15)
+    torch.cuda.synchronize()
+    want = on.stout_smear(dims, on.stout_smear(dims, links, 0.15), 0.15)
+    assert float(np.max(np.abs(g2.cpu().numpy() - want))) <= TOL
+    g = (si.su3_site_field(dims, 82, 0), si.su3_site_field(dims, 82, 1))
+    for fixed in (on.unit_links(dims), on.pure_gauge_links(dims, *g)):
+        out = stg.stout_smear(stg.pack_gauge(dims, to_dev(fixed), "c128_18"), 0.3)
+        torch.cuda.synchronize()
+        assert float(np.max(np.abs(out.cpu().numpy() - fixed))) <= TOL
+
+
+def test_stout_32_4_sampled():
+    dims = (32, 32, 32, 32)
+    say("generating 32^4 links")
+    links = si.su3_links(dims, 1701, 83, 0)
+    out = stg.stout_smear(stg.pack_gauge(dims, to_dev(links), "c128_12"), 0.15)
+    torch.cuda.synchronize()
+    vh = on.half_volume(dims)
+    pick = np.concatenate([[0, 1, vh - 1], si.rng(84, 0).integers(0, vh, size=30)])
+    err = 0.0
+    for slot in range(8):
+        got = out[slot][:, :, torch.from_numpy(pick).to(out.device)].cpu().numpy()
+        err = max(err, float(np.max(np.abs(got - on.stout_smear_at(dims, links, slot, pick,
+                                                                      0.15)))))
+    say(f"stout 32^4 sampled: max abs err {err:.2e} over {8 * len(pick)} links")
+    assert err <= TOL
+
+
+def test_hop_on_smeared_links():
+    """D_oe on the smeared links (packed to FP64-12 and FP32-12) against the oracle's
+    operator on the oracle's smeared links."""
+    dims = (6, 4, 4, 6)
+    links = si.su3_links(dims, 1701, 85, 0)
+    sm = stg.stout_smear(stg.pack_gauge(dims, to_dev(links), "c128_18"), 0.15)
+    v = si.gaussian_field(dims, 1, 86, 0)
+    want = on.d_oe(dims, on.stout_smear(dims, links, 0.15), on.standard_phases(dims), v)
+    for fmt, tol in (("c128_12", 1e-12), ("c64_12", 2e-6)):
+        gauge = stg.pack_gauge(dims, sm, fmt)
+        vin = to_dev(v) if fmt.startswith("c128") else to_dev(v).to(torch.complex64)
+        out = stg.dirac_apply_oe(gauge, vin)
+        torch.cuda.synchronize()
+        assert rel_max(out.cpu().numpy().astype(np.complex128), want) <= tol

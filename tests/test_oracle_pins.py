@@ -361,3 +361,13 @@ def test_stout_q_linear_in_rho_and_small_rho():
     d = (on.stout_smear(dims, links, r) - links) / r
     want = 1j * np.einsum("sabn,sbcn->sacn", q1, links)
     assert np.max(np.abs(d - want)) <= 1e-3 * np.max(np.abs(want))
+
+
+def test_stout_at_matches_whole_lattice():
+    dims = (4, 2, 4, 6)
+    links = si.su3_links(dims, 77, 0)
+    full = on.stout_smear(dims, links, 0.15)
+    hs = [0, 9, 47]
+    for slot in range(8):
+        assert np.max(np.abs(on.stout_smear_at(dims, links, slot, hs, 0.15) -
+                             full[slot][:, :, hs])) <= 1e-14
