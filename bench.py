@@ -585,6 +585,55 @@ def bench_stout(profile=False, applies=100):
                       "rows": rows}), flush=True)
 
 
+def bench_tiles(applies=30):
+    """The pencil tile shapes (STG_TUNE_PENCIL_TILE 0 .. 5) at 32^4 for the kernels that
+    visit links in pencil order: staples FP64-12 (2 threads per link) and FP32-12, and
+    one stout level from FP64-12 links."""
+    import torch
+    import paper_1701_00426_amd as stg
+    import seeded_inputs as si
+    dev = torch.device("cuda:0")
+    dims = (32, 32, 32, 32)
+    vh = stg.half_volume(dims)
+    links = torch.from_numpy(si.su3_links(dims, 1701, 7, 0)).to(dev)
+    g64 = [stg.pack_gauge(dims, links if i == 0 else links.clone(), "c128_12") for i in range(2)]
+    g32 = [stg.pack_gauge(dims, links.clone(), "c64_12") for _ in range(2)]
+    del links
+    o64 = [torch.empty((8, 3, 3, vh), dtype=torch.complex128, device=dev) for _ in range(2)]
+    o32 = [torch.empty((8, 3, 3, vh), dtype=torch.complex64, device=dev) for _ in range(2)]
+    stream = torch.cuda.current_stream()
+    key = stg._lib.STG_TUNE_PENCIL_TILE
+    names = ["32x2x4", "32x4x2", "16x4x4", "16x8x4", "8x8x8", "32x8x2"]
+
+    def timed(fn):
+        for i in range(3):
+            fn(i)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for i in range(applies):
+            fn(i)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / 1e3 / applies
+
+    rows = []
+    for shape, name in enumerate(names):
+        stg.stg_set_tuning(key, shape)
+        rows.append({
+            "tile": name,
+            "staples_fp64_12_us": round(1e6 * timed(
+                lambda i: stg.gauge_staples(g64[i % 2], out=o64[i % 2])), 1),
+            "staples_fp32_12_us": round(1e6 * timed(
+                lambda i: stg.gauge_staples(g32[i % 2], out=o32[i % 2])), 1),
+            "stout_fp64_12_us": round(1e6 * timed(
+                lambda i: stg.stout_smear(g64[i % 2], 0.15, out=o64[i % 2])), 1)})
+        log(json.dumps(rows[-1]))
+    stg.stg_set_tuning(key, 0)
+    print(json.dumps({"workload": "pencil tile shapes at 32^4", "rows": rows}), flush=True)
+
+
 # Launch-shape variants of the hop compared under one kernel trace: (format, fields,
 # knob settings).  Each runs the same number of back-to-back D_eo launches.
 VARIANTS = [
@@ -654,7 +703,7 @@ def main():
                     help="for rocprofv3: one FP64 CG and one mixed CG solve only")
     ap.add_argument("--workload", choices=["main", "multishift", "rational", "batch",
                                            "batch-small", "shapes", "staples", "force",
-                                           "stout"],
+                                           "stout", "tiles"],
                     default="main",
                     help="main: the 32^4 line; multishift: 24^3x48, 16 shifts x 8 RHS; "
                          "rational: the same shifts combined into r(A) b; "
@@ -662,7 +711,8 @@ def main():
                          "batch-small: 48 solves on 8^4 .. 16^4; "
                          "staples: gauge-force staples on the Table 4 shapes; "
                          "force: fermion force from 16 multi-shift solutions at 32^4; "
-                         "stout: two stout-smearing levels at 32^4")
+                         "stout: two stout-smearing levels at 32^4; "
+                         "tiles: the pencil tile shapes of the staple and stout kernels")
     ap.add_argument("--profile-stout", action="store_true",
                     help="for rocprofv3: only the 32^4 level-1 stout loop")
     ap.add_argument("--profile-force", action="store_true",
@@ -698,6 +748,9 @@ def main():
         return
     if args.workload == "shapes":
         bench_shapes()
+        return
+    if args.workload == "tiles":
+        bench_tiles()
         return
     if args.workload == "stout" or args.profile_stout:
         bench_stout(profile=args.profile_stout)

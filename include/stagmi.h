@@ -148,6 +148,12 @@ const char *stg_last_error(void);
  *     waves and meet in LDS.  Automatic: 2 for FP64 links, 1 for FP32 / BF16
  *     ones.  Like the threads per site, it changes the order of additions.
  *     STG_TUNE_XCD_REMAP applies to gauge_staples too.
+ *   STG_TUNE_PENCIL_TILE: 0 (default) .. 5: the tile of the order in which
+ *     gauge_staples and stout_smear visit the links of a slot: tiles of
+ *     T0 x T1 x T2 sites in (x0, x1, x2), each swept along x3; the caps on
+ *     (T0, T1, T2) are 0: 32x2x4, 1: 32x4x2, 2: 16x4x4, 3: 16x8x4, 4: 8x8x8,
+ *     5: 32x8x2 (each extent the largest divisor of the lattice's within its cap).
+ *     Only the speed depends on it.
  * Returns STG_INVALID_ARG for an unknown key or value.
  */
 enum {
@@ -155,7 +161,8 @@ enum {
     STG_TUNE_SITES_PER_THREAD = 1,
     STG_TUNE_STAGE_NEIGHBOURS = 2,
     STG_TUNE_THREADS_PER_SITE = 3,
-    STG_TUNE_STAPLE_THREADS = 4
+    STG_TUNE_STAPLE_THREADS = 4,
+    STG_TUNE_PENCIL_TILE = 5
 };
 int stg_set_tuning(int key, int value);
 int stg_get_tuning(int key, int *value);

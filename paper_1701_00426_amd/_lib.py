@@ -34,6 +34,7 @@ STG_TUNE_SITES_PER_THREAD = 1
 STG_TUNE_STAGE_NEIGHBOURS = 2
 STG_TUNE_THREADS_PER_SITE = 3
 STG_TUNE_STAPLE_THREADS = 4
+STG_TUNE_PENCIL_TILE = 5
 
 # solver modes
 STG_CG_F64 = 0

@@ -36,6 +36,7 @@ int g_sites_per_thread = 1;
 int g_stage_neighbours = 0;
 int g_threads_per_site = 0;  // 0: by format and fields
 int g_staple_threads = 0;    // 0: by format
+int g_pencil_tile = 0;       // tile shape of the pencil order (pencil.hpp)
 
 int hip_fail(hipError_t e, const char *what) {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
@@ -1281,6 +1282,11 @@ int stg_set_tuning(int key, int value) {
                 return invalid("staple threads per link takes 0 (automatic), 1 or 2");
             g_staple_threads = value;
             return STG_OK;
+        case STG_TUNE_PENCIL_TILE:
+            if (value < 0 || value >= kPencilShapes)
+                return invalid("pencil tile takes 0 .. 5");
+            g_pencil_tile = value;
+            return STG_OK;
         default: return invalid("unknown tuning key");
     }
 }
@@ -1293,6 +1299,7 @@ int stg_get_tuning(int key, int *value) {
         case STG_TUNE_STAGE_NEIGHBOURS: *value = g_stage_neighbours; return STG_OK;
         case STG_TUNE_THREADS_PER_SITE: *value = g_threads_per_site; return STG_OK;
         case STG_TUNE_STAPLE_THREADS: *value = g_staple_threads; return STG_OK;
+        case STG_TUNE_PENCIL_TILE: *value = g_pencil_tile; return STG_OK;
         default: return invalid("unknown tuning key");
     }
 }
@@ -1356,7 +1363,7 @@ int gauge_staples(const stg_lattice *lat, const stg_gauge *gauge, double c0, dou
     StapleArgs a;
     std::memset(&a, 0, sizeof(a));
     a.geom = g;
-    a.tile = pencil_tile(g);
+    a.tile = pencil_tile(g, g_pencil_tile);
     a.links = gauge->links;
     a.out = out;
     a.c0 = c0;
@@ -1421,7 +1428,7 @@ int stout_smear(const stg_lattice *lat, const stg_gauge *gauge, double rho, void
     StoutArgs a;
     std::memset(&a, 0, sizeof(a));
     a.geom = g;
-    a.tile = pencil_tile(g);
+    a.tile = pencil_tile(g, g_pencil_tile);
     a.links = gauge->links;
     a.out = out;
     a.rho = rho;

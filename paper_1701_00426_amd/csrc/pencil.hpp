@@ -25,12 +25,20 @@ inline uint32_t pencil_extent(uint32_t n, uint32_t cap, uint32_t step) {
     return step;
 }
 
-// T0 the largest even divisor of N0 up to 32, T1 and T2 the largest divisors of
-// N1 and N2 up to 4 and 2.
-inline PencilTile pencil_tile(const Geom &g) {
+// Tile shapes (caps on T0 x T1 x T2) selectable by the STG_TUNE_PENCIL_TILE knob;
+// 0 is the default, 32 x 2 x 4 (the fastest of these for the staple and stout
+// kernels at 32^4; 8 x 8 x 8 is much slower: 64-byte runs along x0).
+constexpr int kPencilShapes = 6;
+constexpr uint32_t kPencilCaps[kPencilShapes][3] = {
+    {32, 2, 4}, {32, 4, 2}, {16, 4, 4}, {16, 8, 4}, {8, 8, 8}, {32, 8, 2}};
+
+// T0 the largest even divisor of N0 up to cap 0, T1 and T2 the largest divisors of
+// N1 and N2 up to caps 1 and 2 (shape: an index into kPencilCaps).
+inline PencilTile pencil_tile(const Geom &g, int shape = 0) {
     PencilTile t;
-    const uint32_t T0 = pencil_extent(g.N[0], 32, 2), T1 = pencil_extent(g.N[1], 4, 1);
-    const uint32_t T2 = pencil_extent(g.N[2], 2, 1);
+    const uint32_t *cap = kPencilCaps[(shape >= 0 && shape < kPencilShapes) ? shape : 0];
+    const uint32_t T0 = pencil_extent(g.N[0], cap[0], 2), T1 = pencil_extent(g.N[1], cap[1], 1);
+    const uint32_t T2 = pencil_extent(g.N[2], cap[2], 1);
     t.t0h = T0 / 2;
     t.t1 = T1;
     t.t2 = T2;

@@ -257,6 +257,12 @@ def test_tuning_knobs(lib):
     assert lib.stg_set_tuning(4, 1) == 0
     assert lib.stg_get_tuning(4, ctypes.byref(v)) == 0 and v.value == 1
     assert lib.stg_set_tuning(4, 0) == 0
+    # tile shape of the pencil order: 0 .. 5
+    assert lib.stg_get_tuning(5, ctypes.byref(v)) == 0 and v.value == 0
+    assert lib.stg_set_tuning(5, 6) == -1 and lib.stg_set_tuning(5, -1) == -1
+    assert lib.stg_set_tuning(5, 4) == 0
+    assert lib.stg_get_tuning(5, ctypes.byref(v)) == 0 and v.value == 4
+    assert lib.stg_set_tuning(5, 0) == 0
 
 
 def test_cg_default_params(lib):

@@ -87,3 +87,23 @@ def test_hop_on_smeared_links():
         out = stg.dirac_apply_oe(gauge, vin)
         torch.cuda.synchronize()
         assert rel_max(out.cpu().numpy().astype(np.complex128), want) <= tol
+
+
+def test_tile_shapes_change_nothing():
+    """The pencil tile shape only reorders the links across blocks: staples and stout
+    results are bitwise equal for every shape."""
+    dims = (32, 8, 4, 6)
+    links = si.su3_links(dims, 1701, 87, 0)
+    key = stg._lib.STG_TUNE_PENCIL_TILE
+    old = stg.stg_get_tuning(key)
+    try:
+        res = []
+        for shape in range(6):
+            stg.stg_set_tuning(key, shape)
+            g = stg.pack_gauge(dims, to_dev(links), "c128_12")
+            res.append((stg.gauge_staples(g).clone(), stg.stout_smear(g, 0.15).clone()))
+        torch.cuda.synchronize()
+    finally:
+        stg.stg_set_tuning(key, old)
+    for st, so in res[1:]:
+        assert torch.equal(st, res[0][0]) and torch.equal(so, res[0][1])
