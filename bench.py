@@ -38,6 +38,10 @@ TOL = 1e-10
 # algorithmic bytes per output site of one hop: 8 links + 1 input + 1 output vector
 BYTES_PER_SITE = {"c128_18": 8 * 144 + 48 + 48, "c128_12": 8 * 96 + 48 + 48,
                   "c64_12": 8 * 48 + 24 + 24, "bf16_12": 8 * 24 + 24 + 24}
+# The naive byte model of a hop: every neighbour vector read separately (8 per site),
+# no reuse through the caches.
+NAIVE_BYTES_PER_SITE = {"c128_18": 8 * 144 + 8 * 48 + 48, "c128_12": 8 * 96 + 8 * 48 + 48,
+                        "c64_12": 8 * 48 + 8 * 24 + 24, "bf16_12": 8 * 24 + 8 * 24 + 24}
 FLOPS_PER_SITE = 570  # 8 SU(3) mat-vecs (66) + 7 colour-vector sums (6); reconstruction excluded
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_traffic_32x32x32x32.json")
 KERNEL_SOURCES = ["paper_1701_00426_amd/csrc/hop.hip",
@@ -634,6 +638,70 @@ def bench_tiles(applies=30):
     print(json.dumps({"workload": "pencil tile shapes at 32^4", "rows": rows}), flush=True)
 
 
+def bench_small(reps=5):
+    """The small configuration: 8^4, m = 0.1, FP64-18 links, one RHS (latency-bound:
+    1.8 MB per hop).  Hop and normal-operator times (HIP events), FP64 CG to 1e-10:
+    wall time per solve (best of reps) and per iteration; the FP64 C oracle's CG on the
+    same inputs on the host cores as the CPU baseline."""
+    import numpy as np
+    import torch
+    import paper_1701_00426_amd as stg
+    import seeded_inputs as si
+    import oracle
+    from oracle import oracle_np as on
+    dev = torch.device("cuda:0")
+    dims, mass = (8, 8, 8, 8), 0.1
+    links_np = si.su3_links(dims, 1701, 1, 0)
+    b_np = si.gaussian_field(dims, 1, 426, 1, 0, 0)
+    gauge = stg.pack_gauge(dims, torch.from_numpy(links_np).to(dev), "c128_18")
+    b = torch.from_numpy(b_np).to(dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, n=2000):
+        for _ in range(20):
+            fn()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(n):
+            fn()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / 1e3 / n
+
+    out = torch.empty_like(b)
+    tmp = torch.empty_like(b)
+    t_eo = timed(lambda: stg.dirac_apply_eo(gauge, b, out))
+    t_n = timed(lambda: stg.stg_apply_normal(gauge, mass, b, out_even=out, tmp_odd=tmp))
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st, stats = stg.cg_solve(gauge, mass, b, tol=TOL)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if best is None or dt < best[0]:
+            best = (dt, stats[0])
+    dt, s0 = best
+    orc = oracle.COracle()
+    ph = on.standard_phases(dims)
+    t0 = time.perf_counter()
+    xc, itc, resc, stc = orc.cg(dims, links_np, ph, mass, b_np[0], tol=TOL)
+    tc = time.perf_counter() - t0
+    print(json.dumps({
+        "workload": "8^4, m = 0.1, FP64-18 links, 1 RHS: hop, normal operator, FP64 CG to 1e-10",
+        "deo_us": round(t_eo * 1e6, 2), "normal_op_us": round(t_n * 1e6, 2),
+        "deo_GBs": round(BYTES_PER_SITE["c128_18"] * stg.half_volume(dims) / t_eo / 1e9, 1),
+        "cg_ms": round(dt * 1e3, 3), "cg_iters": s0["iters"],
+        "cg_us_per_iter": round(dt * 1e6 / s0["iters"], 2),
+        "cg_true_rel_resid": s0["true_rel_resid"],
+        "cpu_baseline": {"value": round(tc * 1e3, 2), "unit": "ms per CG solve", "cores":
+                         orc.num_threads(), "kind": "oracle",
+                         "sample": f"the FP64 C oracle's CG on the same 8^4 system, {itc} "
+                                   f"iterations, true residual {resc:.2e}"}}), flush=True)
+
+
 # Launch-shape variants of the hop compared under one kernel trace: (format, fields,
 # knob settings).  Each runs the same number of back-to-back D_eo launches.
 VARIANTS = [
@@ -703,7 +771,7 @@ def main():
                     help="for rocprofv3: one FP64 CG and one mixed CG solve only")
     ap.add_argument("--workload", choices=["main", "multishift", "rational", "batch",
                                            "batch-small", "shapes", "staples", "force",
-                                           "stout", "tiles"],
+                                           "stout", "tiles", "small"],
                     default="main",
                     help="main: the 32^4 line; multishift: 24^3x48, 16 shifts x 8 RHS; "
                          "rational: the same shifts combined into r(A) b; "
@@ -712,7 +780,8 @@ def main():
                          "staples: gauge-force staples on the Table 4 shapes; "
                          "force: fermion force from 16 multi-shift solutions at 32^4; "
                          "stout: two stout-smearing levels at 32^4; "
-                         "tiles: the pencil tile shapes of the staple and stout kernels")
+                         "tiles: the pencil tile shapes of the staple and stout kernels; "
+                         "small: 8^4 FP64-18 hop and CG (latency-bound)")
     ap.add_argument("--profile-stout", action="store_true",
                     help="for rocprofv3: only the 32^4 level-1 stout loop")
     ap.add_argument("--profile-force", action="store_true",
@@ -748,6 +817,9 @@ def main():
         return
     if args.workload == "shapes":
         bench_shapes()
+        return
+    if args.workload == "small":
+        bench_small()
         return
     if args.workload == "tiles":
         bench_tiles()
@@ -799,6 +871,7 @@ def main():
             gbs = BYTES_PER_SITE[fmt] * vh / dt / 1e9
             res[name] = {"us": round(dt * 1e6, 2), "GBs": round(gbs, 1),
                          "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                         "naive_GBs": round(NAIVE_BYTES_PER_SITE[fmt] * vh / dt / 1e9, 1),
                          "GFLOPs": round(FLOPS_PER_SITE * vh / dt / 1e9, 1),
                          "ns_per_site": round(dt * 1e9 / vh, 4)}
             hop_time[(fmt, name)] = dt
