@@ -591,8 +591,9 @@ def bench_stout(profile=False, applies=100):
 
 def bench_tiles(applies=30):
     """The pencil tile shapes (STG_TUNE_PENCIL_TILE 0 .. 5) at 32^4 for the kernels that
-    visit links in pencil order: staples FP64-12 (2 threads per link) and FP32-12, and
-    one stout level from FP64-12 links."""
+    visit links or sites in pencil order: the fermion force with 16 poles (whole call),
+    staples FP64-12 (2 threads per link) and FP32-12, and one stout level from FP64-12
+    links."""
     import torch
     import paper_1701_00426_amd as stg
     import seeded_inputs as si
@@ -622,10 +623,16 @@ def bench_tiles(applies=30):
         torch.cuda.synchronize()
         return t0.elapsed_time(t1) / 1e3 / applies
 
+    xs = torch.from_numpy(si.gaussian_field(dims, 16, 426, 8, 0)).to(dev)
+    ys = torch.empty_like(xs)
+    fo = torch.empty((8, 3, 3, vh), dtype=torch.complex128, device=dev)
+    coeffs = [1.0 / (1 + k) for k in range(16)]
     rows = []
     for shape, name in enumerate(names):
         stg.stg_set_tuning(key, shape)
         rows.append({
+            "force_16_poles_us": round(1e6 * timed(
+                lambda i: stg.fermion_force(g64[i % 2], coeffs, xs, y_odd=ys, out=fo)), 1),
             "tile": name,
             "staples_fp64_12_us": round(1e6 * timed(
                 lambda i: stg.gauge_staples(g64[i % 2], out=o64[i % 2])), 1),
@@ -684,6 +691,16 @@ def bench_small(reps=5):
         if best is None or dt < best[0]:
             best = (dt, stats[0])
     dt, s0 = best
+    # the same solve through the uneven-batch runner (iterations replayed from a hipGraph)
+    bbest = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xb, stb, statsb = stg.cg_solve_batch([dict(hi=gauge, mass=mass, b=b)], tol=TOL)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        if bbest is None or tb < bbest[0]:
+            bbest = (tb, statsb[0][0])
     orc = oracle.COracle()
     ph = on.standard_phases(dims)
     t0 = time.perf_counter()
@@ -696,6 +713,8 @@ def bench_small(reps=5):
         "cg_ms": round(dt * 1e3, 3), "cg_iters": s0["iters"],
         "cg_us_per_iter": round(dt * 1e6 / s0["iters"], 2),
         "cg_true_rel_resid": s0["true_rel_resid"],
+        "batch_runner_ms": round(bbest[0] * 1e3, 3), "batch_runner_iters": bbest[1]["iters"],
+        "batch_runner_us_per_iter": round(bbest[0] * 1e6 / bbest[1]["iters"], 2),
         "cpu_baseline": {"value": round(tc * 1e3, 2), "unit": "ms per CG solve", "cores":
                          orc.num_threads(), "kind": "oracle",
                          "sample": f"the FP64 C oracle's CG on the same 8^4 system, {itc} "

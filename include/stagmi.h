@@ -149,7 +149,7 @@ const char *stg_last_error(void);
  *     ones.  Like the threads per site, it changes the order of additions.
  *     STG_TUNE_XCD_REMAP applies to gauge_staples too.
  *   STG_TUNE_PENCIL_TILE: 0 (default) .. 5: the tile of the order in which
- *     gauge_staples and stout_smear visit the links of a slot: tiles of
+ *     gauge_staples, stout_smear and fermion_force visit the sites: tiles of
  *     T0 x T1 x T2 sites in (x0, x1, x2), each swept along x3; the caps on
  *     (T0, T1, T2) are 0: 32x2x4, 1: 32x4x2, 2: 16x4x4, 3: 16x8x4, 4: 8x8x8,
  *     5: 32x8x2 (each extent the largest divisor of the lattice's within its cap).

@@ -1400,6 +1400,7 @@ int fermion_force(const stg_lattice *lat, const stg_gauge *gauge, int nshift,
     ForceArgs a;
     std::memset(&a, 0, sizeof(a));
     a.geom = g;
+    a.tile = pencil_tile(g, g_pencil_tile);
     a.phases = reinterpret_cast<const double *>(gauge->phases);
     a.out = out;
     a.xcd_remap = g_xcd_remap;

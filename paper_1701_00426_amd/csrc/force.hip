@@ -15,8 +15,10 @@
 //
 // One thread per site: it reads its own vector once per pole and the forward
 // neighbours' in the four directions, and sums the weighted outer products of its
-// four links in FP64 (the own vector serves all four).  Even and odd sites run in
-// adjacent blocks, each XCD on one contiguous range of sites.
+// four links in FP64 (the own vector serves all four).  Sites are visited in pencil
+// order (pencil.hpp), even and odd ones in adjacent blocks, each XCD on one
+// contiguous range, so a site's forward neighbours are mostly read by blocks in
+// flight at the same time.
 
 #include "device_common.hpp"
 #include "force.hpp"
@@ -30,8 +32,9 @@ __global__ __launch_bounds__(kForceBlock) void force_kernel(ForceArgs a) {
     const Geom &g = a.geom;
     const uint32_t blk = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
     const int P = (int)(blk % 2);
-    const uint32_t h = (blk / 2) * kForceBlock + threadIdx.x;
-    if (h >= g.Vh) return;
+    const uint32_t j = (blk / 2) * kForceBlock + threadIdx.x;
+    if (j >= g.Vh) return;
+    const uint32_t h = pencil_site(g, a.tile, j);
     const Site s = site_coords(g, P, h);
     uint32_t hf[4];
 #pragma unroll

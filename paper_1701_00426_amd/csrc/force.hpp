@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "device_common.hpp"
+#include "pencil.hpp"
 
 namespace stg {
 
@@ -13,6 +14,7 @@ constexpr int kForceChunk = 32;   // poles per launch (their weights travel in t
 
 struct ForceArgs {
     Geom geom;
+    PencilTile tile;        // visiting order of the sites of a parity (pencil.hpp)
     const void *x;          // complex128 [npoles][3][Vh], even sites
     const void *y;          // complex128 [npoles][3][Vh], odd sites
     const double *phases;   // real [8][Vh], or NULL for the standard phases
