@@ -10,9 +10,13 @@
 // each path a product of links leading from x + mu back to x, so U_mu(x) Sigma_mu(x)
 // is the weighted sum of the closed loops through the link.
 //
-// One thread per link; the link's (mu, parity) is uniform in a block.  Neighbour
-// half indices come from coordinate arithmetic (no index tables).  The 8 paths of
-// each side (above / below the link) share their factors:
+// One or two threads per link (with two, the paths above and below the link run
+// on separate waves of the block and meet in LDS); the link's (mu, parity) is
+// uniform in a block, the 8 slots of a group of sites run in adjacent blocks, and
+// the sites are visited in pencil order (pencil.hpp) so that a link's radius-2
+// neighbourhood is mostly in the XCD's L2.  Neighbour half indices come from
+// coordinate arithmetic (no index tables).  The 8 paths of each side (above /
+// below the link) share their factors:
 //   above:  A = U_nu(x+mu), W = U_mu(x+nu)^dag U_nu(x)^dag,
 //           D = U_mu(x-mu+nu)^dag U_nu(x-mu)^dag U_mu(x-mu),
 //           T = U_nu(x+mu+nu) U_mu(x+2nu)^dag U_nu(x+nu)^dag,
