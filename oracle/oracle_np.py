@@ -25,6 +25,9 @@ Paper: Bonati et al., arXiv:1701.00426.
   * Sec. 2.2 (forces of the molecular dynamics from the solutions of Eq.
     shlineq) -- the rational pseudofermion action and its derivative with
     respect to every link (thin links; the stout-smearing chain is not here).
+  * Sec. 2.1, Sec. 2.3 -- one stout-smearing step (Morningstar-Peardon definition).
+  * Sec. 4.3 and Table 4 -- the pure-gauge molecular dynamics: the gauge force
+    from the staples, momentum and link updates, the leapfrog and its energy.
 
 Everything takes the arrays as given; random inputs come from the seeded
 generators, which hold none of this arithmetic.
@@ -662,3 +665,67 @@ def stout_smear_at(dims, links, slot: int, hs, rho):
     for n in range(len(hs)):
         out[:, :, n] = expm(1j * q[:, :, n]) @ u[:, :, n]
     return out
+
+
+# --------------------------------------------------------------------------
+# Pure-gauge molecular dynamics (Sec. 4.3: the gauge cycle evolves momenta and
+# links with the gauge force; Table 4 times it per site).  Momenta P_mu(x) are
+# traceless Hermitian 3x3 matrices in the link layout (8, 3, 3, Vh); a link moves
+# as U -> exp(i eps P) U.
+# --------------------------------------------------------------------------
+
+
+def symanzik_action(dims, links, beta, c0=SYMANZIK_C0, c1=SYMANZIK_C1):
+    """S_g = -(beta/3) (c0 sum Re Tr(1x1 loops) + c1 sum Re Tr(1x2 loops)), the
+    link-dependent part of the tree-level Symanzik action (constants dropped)."""
+    return -(beta / 3.0) * weighted_loop_sum(dims, links, c0, c1)
+
+
+def traceless_hermitian(a):
+    """(a + a^dag)/2 minus its trace / 3, matrix by matrix, (..., 3, 3, n)."""
+    h = 0.5 * (a + np.conj(np.swapaxes(a, -3, -2)))
+    tr = np.einsum("...aan->...n", h)
+    for i in range(3):
+        h[..., i, i, :] -= tr / 3.0
+    return h
+
+
+def gauge_force(dims, links, beta, c0=SYMANZIK_C0, c1=SYMANZIK_C1):
+    """F_mu(x), traceless Hermitian, defined by dS/dt = Tr(F X) at t = 0 when the
+    link moves as U -> exp(i t X) U (X traceless Hermitian).  S depends on the link
+    through -(beta/3) Re Tr(U Sigma) (Sigma the staple sum), so
+    dS/dt = -(beta/3) Re Tr(i X U Sigma) and F = -(beta/3) traceless Hermitian
+    part of (i U Sigma)."""
+    m = np.einsum("sabn,sbcn->sacn", links, staples(dims, links, c0, c1))
+    return -(beta / 3.0) * traceless_hermitian(1j * m)
+
+
+def momentum_update(dims, links, mom, beta, eps, c0=SYMANZIK_C0, c1=SYMANZIK_C1):
+    """P -> P - eps F(U)."""
+    return mom - eps * gauge_force(dims, links, beta, c0, c1)
+
+
+def link_update(links, mom, eps):
+    """U -> exp(i eps P) U for every link (scipy.linalg.expm, matrix by matrix)."""
+    from scipy.linalg import expm
+    out = np.empty_like(links)
+    for s in range(links.shape[0]):
+        for h in range(links.shape[3]):
+            out[s, :, :, h] = expm(1j * eps * mom[s, :, :, h]) @ links[s, :, :, h]
+    return out
+
+
+def md_hamiltonian(dims, links, mom, beta, c0=SYMANZIK_C0, c1=SYMANZIK_C1):
+    """H = 1/2 sum Tr P^2 + S_g."""
+    kin = 0.5 * float(np.real(np.einsum("sabn,sban->", mom, mom)))
+    return kin + symanzik_action(dims, links, beta, c0, c1)
+
+
+def leapfrog(dims, links, mom, beta, eps, nsteps, c0=SYMANZIK_C0, c1=SYMANZIK_C1):
+    """nsteps leapfrog steps: P half step, (U full step, P full step) ..., P half step."""
+    p = momentum_update(dims, links, mom, beta, 0.5 * eps, c0, c1)
+    u = links
+    for k in range(nsteps):
+        u = link_update(u, p, eps)
+        p = momentum_update(dims, u, p, beta, eps if k < nsteps - 1 else 0.5 * eps, c0, c1)
+    return u, p

@@ -81,3 +81,17 @@ def log_shifts(n, lo=1e-4, hi=10.0):
     if n == 1:
         return np.array([lo])
     return lo * (hi / lo) ** (np.arange(n) / (n - 1))
+
+
+def traceless_hermitian_field(dims, *seed):
+    """Random traceless Hermitian 3x3 matrix per link, (8, 3, 3, Vh) complex128:
+    a Gaussian complex matrix A, (A + A^dag)/2, its trace / 3 removed (the
+    momenta of the molecular dynamics, up to normalisation)."""
+    vh = half_volume(dims)
+    z = rng(*seed).standard_normal((8, 3, 3, vh, 2))
+    a = z[..., 0] + 1j * z[..., 1]
+    h = 0.5 * (a + np.conj(np.transpose(a, (0, 2, 1, 3))))
+    tr = np.einsum("saan->sn", h)
+    for i in range(3):
+        h[:, i, i, :] -= tr / 3.0
+    return np.ascontiguousarray(h)

@@ -371,3 +371,67 @@ def test_stout_at_matches_whole_lattice():
     for slot in range(8):
         assert np.max(np.abs(on.stout_smear_at(dims, links, slot, hs, 0.15) -
                              full[slot][:, :, hs])) <= 1e-14
+
+
+# --------------------------------------------------------------------------
+# Pure-gauge molecular dynamics (Sec. 4.3, Table 4)
+# --------------------------------------------------------------------------
+
+
+def test_gauge_force_is_the_derivative_of_the_action():
+    """F traceless Hermitian, and (S(e^{itX}U) - S(e^{-itX}U)) / 2t = Tr(F X) + O(t^2)
+    for random traceless Hermitian X at links of every slot (c0, c1 tree level and
+    separately)."""
+    from scipy.linalg import expm
+    dims, beta = (4, 4, 6, 4), 5.0
+    links = si.su3_links(dims, 91, 0)
+    x = si.traceless_hermitian_field(dims, 91, 1)
+    for c0, c1 in ((on.SYMANZIK_C0, on.SYMANZIK_C1), (1.0, 0.0), (0.0, 1.0)):
+        f = on.gauge_force(dims, links, beta, c0, c1)
+        assert np.max(np.abs(f - np.conj(np.transpose(f, (0, 2, 1, 3))))) <= 1e-14
+        assert np.max(np.abs(np.einsum("saan->sn", f))) <= 1e-13
+        t = 1e-4
+        for slot in range(8):
+            h = (13 * slot + 5) % on.half_volume(dims)
+
+            def s_at(tt):
+                lk = links.copy()
+                lk[slot, :, :, h] = expm(1j * tt * x[slot, :, :, h]) @ links[slot, :, :, h]
+                return on.symanzik_action(dims, lk, beta, c0, c1)
+
+            d = (s_at(t) - s_at(-t)) / (2 * t)
+            want = float(np.real(np.trace(f[slot, :, :, h] @ x[slot, :, :, h])))
+            assert abs(d - want) <= 1e-6 * max(abs(want), 1.0)
+
+
+def test_leapfrog_energy_error_scales_as_eps_squared_and_reverses():
+    dims, beta = (4, 2, 4, 4), 5.5
+    links = si.su3_links(dims, 92, 0)
+    mom = si.traceless_hermitian_field(dims, 92, 1)
+    h0 = on.md_hamiltonian(dims, links, mom, beta)
+    dh = []
+    for eps, n in ((0.04, 4), (0.02, 8)):
+        u, p = on.leapfrog(dims, links, mom, beta, eps, n)
+        dh.append(on.md_hamiltonian(dims, u, p, beta) - h0)
+    assert 3.7 <= dh[0] / dh[1] <= 4.3, dh
+    # reversibility: flip the momenta, integrate back
+    u, p = on.leapfrog(dims, links, mom, beta, 0.02, 8)
+    ub, pb = on.leapfrog(dims, u, -p, beta, 0.02, 8)
+    assert np.max(np.abs(ub - links)) <= 1e-12 and np.max(np.abs(pb + mom)) <= 1e-12
+
+
+def test_gauge_force_covariance_and_link_update_unitary():
+    dims, beta = (4, 4, 2, 4), 6.0
+    links = si.su3_links(dims, 93, 0)
+    g = (si.su3_site_field(dims, 93, 1), si.su3_site_field(dims, 93, 2))
+    f = on.gauge_force(dims, links, beta)
+    fg = on.gauge_force(dims, on.gauge_transform_links(dims, links, *g), beta)
+    for parity in (0, 1):
+        for mu in range(4):
+            want = np.einsum("abn,bcn,dcn->adn", g[parity], f[2 * mu + parity],
+                             np.conj(g[parity]))
+            assert np.max(np.abs(fg[2 * mu + parity] - want)) <= 1e-13
+    u = on.link_update(links, si.traceless_hermitian_field(dims, 93, 3), 0.3)
+    m = np.transpose(u, (0, 3, 1, 2)).reshape(-1, 3, 3)
+    assert np.max(np.abs(m @ np.conj(np.transpose(m, (0, 2, 1))) - np.eye(3))) <= 1e-14
+    assert np.max(np.abs(np.linalg.det(m) - 1)) <= 1e-14
