@@ -721,6 +721,51 @@ def bench_small(reps=5):
                                    f"iterations, true residual {resc:.2e}"}}), flush=True)
 
 
+def bench_md(applies=50, profile=False):
+    """One pure-gauge molecular-dynamics step (momentum update with the tree-level
+    Symanzik force, then link update) on the paper's Table 4 shapes, FP64-12 links and
+    FP64 momenta; ns per site = step time / V, beside Table 4 (context)."""
+    import torch
+    import paper_1701_00426_amd as stg
+    import seeded_inputs as si
+    dev = torch.device("cuda:0")
+    beta, eps = 5.5, 0.01
+    rows = []
+    stream = torch.cuda.current_stream()
+    shapes = [(32, 32, 32, 32)] if profile else list(PAPER_TABLE4)
+    for dims in shapes:
+        vh = stg.half_volume(dims)
+        links = torch.from_numpy(si.su3_links(dims, 1701, 10, 0)).to(dev)
+        gauge = stg.pack_gauge(dims, links, "c128_12")
+        del links
+        mom = torch.from_numpy(si.traceless_hermitian_field(dims, 426, 10, 0)).to(dev)
+
+        def step():
+            stg.gauge_momentum_update(gauge, mom, beta, eps)
+            stg.gauge_link_update(gauge, mom, eps)
+
+        for _ in range(3):
+            step()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(applies):
+            step()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        dt = t0.elapsed_time(t1) / 1e3 / applies
+        rows.append({"lattice": "x".join(map(str, dims)), "step_us": round(dt * 1e6, 1),
+                     "ns_per_site": round(dt * 1e9 / (2 * vh), 3),
+                     "paper_gauge_md_ns_per_site_K80_P100": PAPER_TABLE4[dims]})
+        log(json.dumps(rows[-1]))
+        del gauge, mom
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": "pure-gauge MD step (tree-level Symanzik force, momentum + "
+                                  "link update), FP64-12 links, paper Table 4 shapes",
+                      "rows": rows}), flush=True)
+
+
 # Launch-shape variants of the hop compared under one kernel trace: (format, fields,
 # knob settings).  Each runs the same number of back-to-back D_eo launches.
 VARIANTS = [
@@ -790,7 +835,7 @@ def main():
                     help="for rocprofv3: one FP64 CG and one mixed CG solve only")
     ap.add_argument("--workload", choices=["main", "multishift", "rational", "batch",
                                            "batch-small", "shapes", "staples", "force",
-                                           "stout", "tiles", "small"],
+                                           "stout", "tiles", "small", "md"],
                     default="main",
                     help="main: the 32^4 line; multishift: 24^3x48, 16 shifts x 8 RHS; "
                          "rational: the same shifts combined into r(A) b; "
@@ -800,7 +845,10 @@ def main():
                          "force: fermion force from 16 multi-shift solutions at 32^4; "
                          "stout: two stout-smearing levels at 32^4; "
                          "tiles: the pencil tile shapes of the staple and stout kernels; "
-                         "small: 8^4 FP64-18 hop and CG (latency-bound)")
+                         "small: 8^4 FP64-18 hop and CG (latency-bound); "
+                         "md: the pure-gauge MD step on the Table 4 shapes")
+    ap.add_argument("--profile-md", action="store_true",
+                    help="for rocprofv3: only the 32^4 MD-step loop")
     ap.add_argument("--profile-stout", action="store_true",
                     help="for rocprofv3: only the 32^4 level-1 stout loop")
     ap.add_argument("--profile-force", action="store_true",
@@ -836,6 +884,9 @@ def main():
         return
     if args.workload == "shapes":
         bench_shapes()
+        return
+    if args.workload == "md" or args.profile_md:
+        bench_md(profile=args.profile_md)
         return
     if args.workload == "small":
         bench_small()

@@ -25,6 +25,8 @@
  *   - Sec. 2.2: molecular-dynamics forces from the multi-shift solutions (the
  *     derivative of the rational pseudofermion action with respect to the links).
  *   - Sec. 2.1 and Sec. 2.3: stout-smeared links (one smearing step per call).
+ *   - Sec. 4.3 and Table 4: the pure-gauge molecular-dynamics step (gauge force
+ *     from the staples, momentum and link updates).
  *
  * Conventions used by every call
  * ------------------------------
@@ -408,6 +410,35 @@ int fermion_force(const stg_lattice *lat, const stg_gauge *gauge, int nshift,
  */
 int stout_smear(const stg_lattice *lat, const stg_gauge *gauge, double rho, void *out,
                 stg_stream_t stream);
+
+/*
+ * Momentum update of the pure-gauge molecular dynamics (Sec. 4.3: the gauge cycle,
+ * whose most expensive step is the staples; Table 4 times it per site).  With the
+ * tree-level Symanzik action S = -(beta/3) (c0 sum Re Tr(1x1 loops) +
+ * c1 sum Re Tr(1x2 loops)) and the staple sum Sigma_mu(x) of gauge_staples, the
+ * force is F_mu(x) = -(beta/3) [i U_mu(x) Sigma_mu(x)]_TH ([A]_TH: the traceless
+ * Hermitian part of A), i.e. dS/dt = Tr(F X) when the link moves as
+ * U -> exp(i t X) U; the call sets P_mu(x) <- P_mu(x) - eps F_mu(x) for every link.
+ *  gauge: STG_LINK_C128_18 or STG_LINK_C128_12 (SU(3) links); phases ignored.
+ *  mom: device complex128 [8][3][3][Vh] (the link layout), traceless Hermitian
+ *    momenta, read and written; not overlapping the links.
+ *  beta, c0, c1, eps: finite.  STG_TUNE_STAPLE_THREADS and the pencil tile apply.
+ * Errors: STG_INVALID_ARG (nothing launched).  Asynchronous.
+ */
+int gauge_momentum_update(const stg_lattice *lat, const stg_gauge *gauge, double beta, double c0,
+                          double c1, double eps, void *mom, stg_stream_t stream);
+
+/*
+ * Link update of the molecular dynamics: U_mu(x) <- exp(i eps P_mu(x)) U_mu(x) for every
+ * link, in place, with exp(iQ) in the Cayley-Hamilton closed form (as in stout_smear).
+ *  fmt: STG_LINK_C128_18 or STG_LINK_C128_12 (the 12-real format keeps rows 0 and 1 of
+ *    the updated link).  links: device, that format, read and written.
+ *  mom: device complex128 [8][3][3][Vh], traceless Hermitian; not overlapping links.
+ *  eps: finite.
+ * Errors: STG_INVALID_ARG (nothing launched).  Asynchronous.
+ */
+int gauge_link_update(const stg_lattice *lat, stg_link_fmt fmt, void *links, double eps,
+                      const void *mom, stg_stream_t stream);
 
 typedef struct {
     stg_lattice lat;

@@ -33,7 +33,7 @@ __all__ = [
     "multishift_cg_solve", "stg_workspace_bytes", "library", "stg_set_tuning", "stg_get_tuning",
     "cg_solve_batch", "rational_apply", "stg_rational_workspace_bytes", "stg_autotune",
     "stg_autotune_load", "stg_autotune_lookup", "gauge_staples", "SYMANZIK_C0", "SYMANZIK_C1",
-    "fermion_force", "stout_smear",
+    "fermion_force", "stout_smear", "gauge_momentum_update", "gauge_link_update",
 ]
 
 # tree-level Symanzik weights of the 1x1 and 1x2 loops: c1 = -1/12, c0 + 8 c1 = 1
@@ -252,6 +252,34 @@ def stout_smear(gauge: Gauge, rho: float, out: Optional[torch.Tensor] = None,
         ctypes.byref(_lib.lattice(gauge.dims)), ctypes.byref(g), float(rho), _ptr(out),
         _stream(stream)))
     return out
+
+
+def _check_mom(gauge: Gauge, mom: torch.Tensor):
+    vh = half_volume(gauge.dims)
+    if mom.dtype != torch.complex128 or tuple(mom.shape) != (8, 3, 3, vh) or \
+            not mom.is_contiguous():
+        raise ValueError(f"mom must be a contiguous complex128 tensor of shape (8, 3, 3, {vh})")
+
+
+def gauge_momentum_update(gauge: Gauge, mom: torch.Tensor, beta: float, eps: float,
+                          c0: float = SYMANZIK_C0, c1: float = SYMANZIK_C1,
+                          stream=None) -> torch.Tensor:
+    """P <- P - eps F(U) in place for the tree-level Symanzik gauge force (FP64 links)."""
+    _check_mom(gauge, mom)
+    g = gauge.c()
+    _lib.check("gauge_momentum_update", library().gauge_momentum_update(
+        ctypes.byref(_lib.lattice(gauge.dims)), ctypes.byref(g), float(beta), float(c0),
+        float(c1), float(eps), _ptr(mom), _stream(stream)))
+    return mom
+
+
+def gauge_link_update(gauge: Gauge, mom: torch.Tensor, eps: float, stream=None) -> Gauge:
+    """U <- exp(i eps P) U in place on gauge.links (FP64 formats)."""
+    _check_mom(gauge, mom)
+    _lib.check("gauge_link_update", library().gauge_link_update(
+        ctypes.byref(_lib.lattice(gauge.dims)), int(gauge.fmt), _ptr(gauge.links), float(eps),
+        _ptr(mom), _stream(stream)))
+    return gauge
 
 
 def stg_apply_normal(gauge: Gauge, mass: float, in_even: torch.Tensor, sigma: float = 0.0,

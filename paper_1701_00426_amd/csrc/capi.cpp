@@ -1439,6 +1439,54 @@ int stout_smear(const stg_lattice *lat, const stg_gauge *gauge, double rho, void
     return STG_OK;
 }
 
+int gauge_momentum_update(const stg_lattice *lat, const stg_gauge *gauge, double beta, double c0,
+                          double c1, double eps, void *mom, stg_stream_t stream) {
+    Geom g;
+    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
+    int rc = check_gauge(g, gauge, STG_C128);
+    if (rc) return rc;
+    if (!std::isfinite(beta) || !std::isfinite(c0) || !std::isfinite(c1) || !std::isfinite(eps))
+        return invalid("beta, c0, c1 and eps must be finite");
+    if (!aligned16(mom)) return invalid("mom NULL or not 16-byte aligned");
+    if (overlap(gauge->links, link_bytes(g, gauge->fmt), mom, (size_t)8 * 9 * g.Vh * 16))
+        return invalid("links and mom overlap");
+    StapleArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.geom = g;
+    a.tile = pencil_tile(g, g_pencil_tile);
+    a.links = gauge->links;
+    a.out = mom;
+    a.c0 = c0;
+    a.c1 = c1;
+    a.kmom = eps * beta / 3.0;
+    a.xcd_remap = g_xcd_remap;
+    const int threads = g_staple_threads ? g_staple_threads : staple_default_threads(gauge->fmt);
+    if (launch_momentum(a, gauge->fmt, threads, (hipStream_t)stream))
+        return invalid("not an FP64 link format");
+    HIP_TRY(hipGetLastError());
+    return STG_OK;
+}
+
+int gauge_link_update(const stg_lattice *lat, stg_link_fmt fmt, void *links, double eps,
+                      const void *mom, stg_stream_t stream) {
+    Geom g;
+    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
+    if (fmt != STG_LINK_C128_18 && fmt != STG_LINK_C128_12)
+        return invalid("the link update takes FP64 link formats only");
+    if (!std::isfinite(eps)) return invalid("eps must be finite");
+    if (!aligned16(links) || !aligned16(mom)) return invalid("links or mom NULL or misaligned");
+    if (overlap(links, link_bytes(g, fmt), mom, (size_t)8 * 9 * g.Vh * 16))
+        return invalid("links and mom overlap");
+    LinkUpdateArgs a;
+    a.links = links;
+    a.mom = mom;
+    a.eps = eps;
+    a.Vh = g.Vh;
+    if (launch_link_update(a, fmt, (hipStream_t)stream)) return invalid("unknown link format");
+    HIP_TRY(hipGetLastError());
+    return STG_OK;
+}
+
 int dirac_apply_eo(const stg_lattice *lat, const stg_gauge *gauge, stg_field field, int nrhs,
                    const void *in_odd, void *out_even, stg_stream_t stream) {
     return apply_dirac(lat, gauge, field, nrhs, in_odd, out_even, 0, stream);

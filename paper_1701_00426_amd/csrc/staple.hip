@@ -324,7 +324,11 @@ __device__ __forceinline__ void side_below(su3<T> &acc, const LinkAt<T, FMT> &U,
 // links; with 2, wave 0 sums the +nu sides and wave 1 the -nu sides, and wave 0
 // adds wave 1's sums from LDS.  Two waves per SIMD are asked of the FP64 split
 // kernel (it then fits in 256 registers).
-template <typename T, int FMT, int TPL>
+// EPI 0 writes Sigma; EPI 1 (FP64 links) instead adds (eps beta / 3) times the
+// traceless Hermitian part of i U Sigma to the link's momentum: P -> P - eps F with the
+// Symanzik gauge force F = -(beta/3) [i U Sigma]_TH, the staples never leaving the
+// kernel.
+template <typename T, int FMT, int TPL, int EPI>
 __global__ __launch_bounds__(kStapleLinks * TPL)
 __attribute__((amdgpu_waves_per_eu((TPL == 2 && sizeof(T) == 8) ? 2 : 1)))
 void staple_kernel(StapleArgs a) {
@@ -392,10 +396,32 @@ void staple_kernel(StapleArgs a) {
     }
     if (!valid) return;
     const size_t base = (size_t)slot * 9 * g.Vh + h;
+    if constexpr (EPI == 0) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) st_c<T>(a.out, base + (size_t)(i * 3 + k) * g.Vh, acc.e[i][k]);
+            for (int k = 0; k < 3; ++k)
+                st_c<T>(a.out, base + (size_t)(i * 3 + k) * g.Vh, acc.e[i][k]);
+    } else {
+        // M = U Sigma; [iM]_TH = i (M - M^dag) / 2 + (sum_j Im M_jj / 3) I
+        const su3<T> u = cached_link<T, FMT>::load(a.links, g.Vh, slot, h);
+        const su3<T> m = mm(u, acc);
+        const T tr = (m.e[0][0].im + m.e[1][1].im + m.e[2][2].im) / T(3);
+        const T kf = (T)a.kmom;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const cpx<T> d = csub(m.e[i][k], cconj(m.e[k][i]));
+                cpx<T> th = {T(-0.5) * d.im, T(0.5) * d.re};
+                if (i == k) th.re += tr;
+                const size_t idx = base + (size_t)(i * 3 + k) * g.Vh;
+                cpx<T> pm = ld_c<T>(a.out, idx);
+                pm.re = fmat(kf, th.re, pm.re);
+                pm.im = fmat(kf, th.im, pm.im);
+                st_c<T>(a.out, idx, pm);
+            }
+    }
 }
 
 // exp(iQ) for a traceless Hermitian 3x3 matrix Q.  Cayley-Hamilton gives
@@ -536,14 +562,53 @@ template <typename T, int FMT>
 int launch_tpl(const StapleArgs &a, int threads, hipStream_t stream) {
     const dim3 grid(staple_blocks(a.geom.Vh));
     if (threads == 1) {
-        staple_kernel<T, FMT, 1><<<grid, kStapleLinks, 0, stream>>>(a);
+        staple_kernel<T, FMT, 1, 0><<<grid, kStapleLinks, 0, stream>>>(a);
         return 0;
     }
     if (threads == 2) {
-        staple_kernel<T, FMT, 2><<<grid, 2 * kStapleLinks, 0, stream>>>(a);
+        staple_kernel<T, FMT, 2, 0><<<grid, 2 * kStapleLinks, 0, stream>>>(a);
         return 0;
     }
     return -1;
+}
+
+template <int FMT>
+int launch_mom(const StapleArgs &a, int threads, hipStream_t stream) {
+    const dim3 grid(staple_blocks(a.geom.Vh));
+    if (threads == 1) {
+        staple_kernel<double, FMT, 1, 1><<<grid, kStapleLinks, 0, stream>>>(a);
+        return 0;
+    }
+    if (threads == 2) {
+        staple_kernel<double, FMT, 2, 1><<<grid, 2 * kStapleLinks, 0, stream>>>(a);
+        return 0;
+    }
+    return -1;
+}
+
+// U -> exp(i eps P) U in place, one thread per link, in the link's own format.
+template <int FMT>
+__global__ __launch_bounds__(kStoutBlock) void link_update_kernel(LinkUpdateArgs a) {
+    const uint32_t Vh = a.Vh;
+    const size_t n = (size_t)8 * Vh;
+    const size_t t = (size_t)blockIdx.x * kStoutBlock + threadIdx.x;
+    if (t >= n) return;
+    const int slot = (int)(t / Vh);
+    const uint32_t h = (uint32_t)(t % Vh);
+    const su3<double> u = cached_link<double, FMT>::load(a.links, Vh, slot, h);
+    su3<double> q;
+    const size_t base = (size_t)slot * 9 * Vh + h;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) q.e[i][k] = cscale(a.eps, ld_c<double>(a.mom, base + (size_t)(i * 3 + k) * Vh));
+    const su3<double> up = mm(exp_iq(q), u);
+    constexpr int rows = FMT == FMT_C128_18 ? 3 : 2;
+    const size_t lbase = (size_t)slot * rows * 3 * Vh + h;
+#pragma unroll
+    for (int i = 0; i < rows; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) st_c<double>(a.links, lbase + (size_t)(i * 3 + k) * Vh, up.e[i][k]);
 }
 
 }  // namespace
@@ -553,6 +618,23 @@ int launch_stout(const StoutArgs &a, int fmt, hipStream_t stream) {
     switch (fmt) {
         case FMT_C128_18: stout_kernel<FMT_C128_18><<<grid, kStoutBlock, 0, stream>>>(a); return 0;
         case FMT_C128_12: stout_kernel<FMT_C128_12><<<grid, kStoutBlock, 0, stream>>>(a); return 0;
+        default: return -1;
+    }
+}
+
+int launch_momentum(const StapleArgs &a, int fmt, int threads, hipStream_t stream) {
+    switch (fmt) {
+        case FMT_C128_18: return launch_mom<FMT_C128_18>(a, threads, stream);
+        case FMT_C128_12: return launch_mom<FMT_C128_12>(a, threads, stream);
+        default: return -1;
+    }
+}
+
+int launch_link_update(const LinkUpdateArgs &a, int fmt, hipStream_t stream) {
+    const dim3 grid((unsigned)(((size_t)8 * a.Vh + kStoutBlock - 1) / kStoutBlock));
+    switch (fmt) {
+        case FMT_C128_18: link_update_kernel<FMT_C128_18><<<grid, kStoutBlock, 0, stream>>>(a); return 0;
+        case FMT_C128_12: link_update_kernel<FMT_C128_12><<<grid, kStoutBlock, 0, stream>>>(a); return 0;
         default: return -1;
     }
 }

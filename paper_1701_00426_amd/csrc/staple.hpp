@@ -19,6 +19,7 @@ struct StapleArgs {
     const void *links;  // gauge field in its format, slot 2*mu + parity
     void *out;          // complex T [8][3][3][Vh], T = double or float by format
     double c0, c1;      // weights of the 3-link and 5-link paths
+    double kmom;        // momentum update only: eps * beta / 3
     int xcd_remap;      // give each XCD a contiguous range of blocks
 };
 
@@ -33,6 +34,21 @@ inline int staple_default_threads(int fmt) { return (fmt == FMT_C128_18 || fmt =
 
 // 0: launched; -1: unknown format or thread count (nothing launched).
 int launch_staples(const StapleArgs &a, int fmt, int threads, hipStream_t stream);
+
+// The momentum update of the pure-gauge molecular dynamics (staple.hip): the same
+// staples, then P -> P + kmom [i U Sigma]_TH for every link, out = the momenta
+// (complex128 [8][3][3][Vh], read and written).  FP64 formats only.
+int launch_momentum(const StapleArgs &a, int fmt, int threads, hipStream_t stream);
+
+struct LinkUpdateArgs {
+    void *links;        // FP64 gauge field, updated in place
+    const void *mom;    // complex128 [8][3][3][Vh]
+    double eps;
+    uint32_t Vh;
+};
+
+// U -> exp(i eps P) U for every link, in place (FP64 formats only).
+int launch_link_update(const LinkUpdateArgs &a, int fmt, hipStream_t stream);
 
 // One stout-smearing step of every link (staple.hip): U' = exp(iQ) U.
 constexpr int kStoutBlock = 128;

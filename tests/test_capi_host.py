@@ -343,3 +343,32 @@ def test_stout_arguments_rejected_on_host(lib):
     f32.links = 0x1000
     f32.fmt = 2
     assert call(gauge=f32) == -1
+
+
+def test_md_arguments_rejected_on_host(lib):
+    """gauge_momentum_update and gauge_link_update check their arguments before any
+    GPU work (every call here fails)."""
+    from paper_1701_00426_amd import _lib
+    lat = _lat((4, 4, 4, 4))
+    g = _lib.StgGauge()
+    g.links = 0x1000
+    g.fmt = 1
+
+    def mom_call(gauge=g, beta=5.0, eps=0.01, mom=0x10000000):
+        return lib.gauge_momentum_update(ctypes.byref(lat), ctypes.byref(gauge), beta,
+                                         5.0 / 3.0, -1.0 / 12.0, eps, mom, None)
+
+    assert mom_call(beta=float("nan")) == -1 and mom_call(eps=float("inf")) == -1
+    assert mom_call(mom=None) == -1 and mom_call(mom=0x1000 + 32) == -1
+    f32 = _lib.StgGauge()
+    f32.links = 0x1000
+    f32.fmt = 3
+    assert mom_call(gauge=f32) == -1
+
+    def link_call(fmt=0, links=0x1000, eps=0.01, mom=0x10000000):
+        return lib.gauge_link_update(ctypes.byref(lat), fmt, links, eps, mom, None)
+
+    assert link_call(fmt=2) == -1 and link_call(fmt=9) == -1
+    assert link_call(eps=float("nan")) == -1
+    assert link_call(links=None) == -1 and link_call(mom=0x1008) == -1
+    assert link_call(mom=0x1000 + 4096) == -1         # overlaps the links

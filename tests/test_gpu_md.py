@@ -1,0 +1,150 @@
+"""GPU pure-gauge molecular dynamics (gauge_momentum_update, gauge_link_update) against
+the FP64 oracle.
+
+Parity: the momentum update P - eps F(U) and the link update exp(i eps P) U entry by
+entry on small lattices (FP64-18 and FP64-12 links, one and two threads per link),
+at sampled links of 32^4, and whole leapfrog trajectories against the oracle's, with
+the energy error and reversibility measured on the GPU's own trajectory.
+
+Tolerances: F entries are bounded by (beta/3)(6|c0| + 18|c1|) (products of unitary
+matrices), and the kernel's sums agree with the oracle's to a few units of 2^-53
+per product: 64 u times that bound times eps, plus the rounding of P.  exp(i eps P) U
+agrees with scipy's expm to ~1e-15 (entries of modulus <= 1): 1e-13.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1701_00426_amd as stg  # noqa: E402
+import seeded_inputs as si  # noqa: E402
+from oracle import oracle_np as on  # noqa: E402
+
+from gpu_common import say, to_dev  # noqa: E402
+
+U53 = 2.0 ** -53
+BETA, EPS = 5.5, 0.02
+
+
+def _as_stored(links, fmt):
+    if fmt == "c128_18":
+        return links
+    out = links.copy()
+    out[:, 2] = np.conj(np.cross(links[:, 0], links[:, 1], axis=1))
+    return out
+
+
+def _mom_tol(beta, eps, c0=on.SYMANZIK_C0, c1=on.SYMANZIK_C1):
+    return 64 * U53 * (beta / 3.0) * (6 * abs(c0) + 18 * abs(c1)) * abs(eps) + 16 * U53 * 4
+
+
+@pytest.fixture(params=[0, 1, 2], ids=["threads-auto", "threads-1", "threads-2"])
+def staple_threads(request):
+    key = stg._lib.STG_TUNE_STAPLE_THREADS
+    old = stg.stg_get_tuning(key)
+    stg.stg_set_tuning(key, request.param)
+    yield request.param
+    stg.stg_set_tuning(key, old)
+
+
+@pytest.mark.parametrize("fmt", ["c128_18", "c128_12"])
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 4, 4), (6, 4, 2, 10), (32, 8, 4, 6)])
+def test_momentum_update_parity(dims, fmt, staple_threads):
+    links = si.su3_links(dims, 1701, 95, sum(dims))
+    mom = si.traceless_hermitian_field(dims, 96, sum(dims))
+    gauge = stg.pack_gauge(dims, to_dev(links), fmt)
+    p = to_dev(mom)
+    stg.gauge_momentum_update(gauge, p, BETA, EPS)
+    torch.cuda.synchronize()
+    want = on.momentum_update(dims, _as_stored(links, fmt), mom, BETA, EPS)
+    err = float(np.max(np.abs(p.cpu().numpy() - want)))
+    say(f"momentum update {fmt} {dims} threads={staple_threads}: max abs err {err:.2e}")
+    assert err <= _mom_tol(BETA, EPS)
+
+
+@pytest.mark.parametrize("fmt", ["c128_18", "c128_12"])
+@pytest.mark.parametrize("eps", [0.02, -0.5, 0.0])
+def test_link_update_parity(fmt, eps):
+    dims = (4, 6, 2, 4)
+    links = si.su3_links(dims, 1701, 97, 0)
+    mom = si.traceless_hermitian_field(dims, 98, 0)
+    gauge = stg.pack_gauge(dims, to_dev(links), fmt)
+    stg.gauge_link_update(gauge, to_dev(mom), eps)
+    torch.cuda.synchronize()
+    want = on.link_update(_as_stored(links, fmt), mom, eps)
+    got = gauge.links.cpu().numpy()
+    if fmt == "c128_12":
+        # the packed 12-real field is a raw byte buffer: rows 0 and 1 as complex128
+        got = got.view(np.complex128).reshape(8, 2, 3, -1)
+        want = want[:, :2]
+    err = float(np.max(np.abs(got - want)))
+    say(f"link update {fmt} eps={eps}: max abs err {err:.2e}")
+    assert err <= 1e-13
+
+
+def _gpu_leapfrog(gauge, p, beta, eps, n):
+    stg.gauge_momentum_update(gauge, p, beta, 0.5 * eps)
+    for k in range(n):
+        stg.gauge_link_update(gauge, p, eps)
+        stg.gauge_momentum_update(gauge, p, beta, eps if k < n - 1 else 0.5 * eps)
+
+
+def test_leapfrog_matches_oracle_conserves_and_reverses():
+    """The GPU trajectory equals the oracle's; its energy error falls by ~4 when eps
+    halves (second-order integrator; random links give large forces, so dH itself is
+    not small at these eps); flipping the momenta and integrating back returns to the
+    start."""
+    dims, n = (4, 2, 4, 4), 6
+    links = si.su3_links(dims, 1701, 99, 0)
+    mom = si.traceless_hermitian_field(dims, 100, 0)
+    h0 = on.md_hamiltonian(dims, links, mom, BETA)
+    dhs = []
+    for eps, steps in ((2 * EPS, n // 2), (EPS, n)):
+        g2 = stg.pack_gauge(dims, to_dev(links), "c128_18")
+        p2 = to_dev(mom)
+        _gpu_leapfrog(g2, p2, BETA, eps, steps)
+        torch.cuda.synchronize()
+        dhs.append(on.md_hamiltonian(dims, g2.links.cpu().numpy(), p2.cpu().numpy(), BETA) - h0)
+    gauge = stg.pack_gauge(dims, to_dev(links), "c128_18")
+    p = to_dev(mom)
+    _gpu_leapfrog(gauge, p, BETA, EPS, n)
+    torch.cuda.synchronize()
+    u1, p1 = gauge.links.cpu().numpy(), p.cpu().numpy()
+    uo, po = on.leapfrog(dims, links, mom, BETA, EPS, n)
+    eu, ep = float(np.max(np.abs(u1 - uo))), float(np.max(np.abs(p1 - po)))
+    say(f"leapfrog: |U - U_oracle| {eu:.2e}, |P - P_oracle| {ep:.2e}, dH {dhs}")
+    assert eu <= 1e-11 and ep <= 1e-11
+    assert 3.5 <= dhs[0] / dhs[1] <= 4.5
+    p.neg_()
+    _gpu_leapfrog(gauge, p, BETA, EPS, n)
+    torch.cuda.synchronize()
+    er = float(np.max(np.abs(gauge.links.cpu().numpy() - links)))
+    ep0 = float(np.max(np.abs(p.cpu().numpy() + mom)))
+    say(f"leapfrog reversed: |U - U0| {er:.2e}, |P + P0| {ep0:.2e}")
+    assert er <= 1e-11 and ep0 <= 1e-11
+
+
+def test_momentum_update_32_4_sampled():
+    dims = (32, 32, 32, 32)
+    say("generating 32^4 links and momenta")
+    links = si.su3_links(dims, 1701, 101, 0)
+    vh = on.half_volume(dims)
+    mom = np.zeros((8, 3, 3, vh), dtype=np.complex128)
+    gauge = stg.pack_gauge(dims, to_dev(links), "c128_12")
+    p = to_dev(mom)
+    stg.gauge_momentum_update(gauge, p, BETA, EPS)
+    torch.cuda.synchronize()
+    pick = np.concatenate([[0, 1, vh - 1], si.rng(102, 0).integers(0, vh, size=40)])
+    err = 0.0
+    for slot in range(8):
+        sig = on.staples_at(dims, links, slot, pick)
+        m = np.einsum("abn,bcn->acn", links[slot][:, :, pick], sig)
+        want = EPS * (BETA / 3.0) * on.traceless_hermitian(1j * m)
+        got = p[slot][:, :, torch.from_numpy(pick).to(p.device)].cpu().numpy()
+        err = max(err, float(np.max(np.abs(got - want))))
+    say(f"momentum update 32^4 sampled: max abs err {err:.2e}")
+    assert err <= _mom_tol(BETA, EPS)
