@@ -723,8 +723,9 @@ def bench_small(reps=5):
 
 def bench_md(applies=50, profile=False):
     """One pure-gauge molecular-dynamics step (momentum update with the tree-level
-    Symanzik force, then link update) on the paper's Table 4 shapes, FP64-12 links and
-    FP64 momenta; ns per site = step time / V, beside Table 4 (context)."""
+    Symanzik force, then link update) on the paper's Table 4 shapes: FP64-12 links with
+    FP64 momenta, and the single-precision variant (FP32-12 links, complex64 momenta);
+    ns per site = step time / V, beside Table 4 (context)."""
     import torch
     import paper_1701_00426_amd as stg
     import seeded_inputs as si
@@ -736,33 +737,39 @@ def bench_md(applies=50, profile=False):
     for dims in shapes:
         vh = stg.half_volume(dims)
         links = torch.from_numpy(si.su3_links(dims, 1701, 10, 0)).to(dev)
-        gauge = stg.pack_gauge(dims, links, "c128_12")
-        del links
-        mom = torch.from_numpy(si.traceless_hermitian_field(dims, 426, 10, 0)).to(dev)
+        mom64 = torch.from_numpy(si.traceless_hermitian_field(dims, 426, 10, 0)).to(dev)
+        row = {"lattice": "x".join(map(str, dims))}
+        for fmt in (("c128_12",) if profile else ("c128_12", "c64_12")):
+            gauge = stg.pack_gauge(dims, links, fmt)
+            mom = mom64 if fmt == "c128_12" else mom64.to(torch.complex64)
 
-        def step():
-            stg.gauge_momentum_update(gauge, mom, beta, eps)
-            stg.gauge_link_update(gauge, mom, eps)
+            def step():
+                stg.gauge_momentum_update(gauge, mom, beta, eps)
+                stg.gauge_link_update(gauge, mom, eps)
 
-        for _ in range(3):
-            step()
-        torch.cuda.synchronize()
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        t0.record(stream)
-        for _ in range(applies):
-            step()
-        t1.record(stream)
-        torch.cuda.synchronize()
-        dt = t0.elapsed_time(t1) / 1e3 / applies
-        rows.append({"lattice": "x".join(map(str, dims)), "step_us": round(dt * 1e6, 1),
-                     "ns_per_site": round(dt * 1e9 / (2 * vh), 3),
-                     "paper_gauge_md_ns_per_site_K80_P100": PAPER_TABLE4[dims]})
+            for _ in range(3):
+                step()
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record(stream)
+            for _ in range(applies):
+                step()
+            t1.record(stream)
+            torch.cuda.synchronize()
+            dt = t0.elapsed_time(t1) / 1e3 / applies
+            tag = "fp64" if fmt == "c128_12" else "fp32"
+            row[f"step_us_{tag}"] = round(dt * 1e6, 1)
+            row[f"ns_per_site_{tag}"] = round(dt * 1e9 / (2 * vh), 3)
+            del gauge, mom
+        row["paper_gauge_md_ns_per_site_K80_P100"] = PAPER_TABLE4[dims]
+        rows.append(row)
         log(json.dumps(rows[-1]))
-        del gauge, mom
+        del links, mom64
         torch.cuda.empty_cache()
     print(json.dumps({"workload": "pure-gauge MD step (tree-level Symanzik force, momentum + "
-                                  "link update), FP64-12 links, paper Table 4 shapes",
+                                  "link update), FP64-12 and FP32-12 links, paper Table 4 "
+                                  "shapes",
                       "rows": rows}), flush=True)
 
 

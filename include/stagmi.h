@@ -419,9 +419,11 @@ int stout_smear(const stg_lattice *lat, const stg_gauge *gauge, double rho, void
  * force is F_mu(x) = -(beta/3) [i U_mu(x) Sigma_mu(x)]_TH ([A]_TH: the traceless
  * Hermitian part of A), i.e. dS/dt = Tr(F X) when the link moves as
  * U -> exp(i t X) U; the call sets P_mu(x) <- P_mu(x) - eps F_mu(x) for every link.
- *  gauge: STG_LINK_C128_18 or STG_LINK_C128_12 (SU(3) links); phases ignored.
- *  mom: device complex128 [8][3][3][Vh] (the link layout), traceless Hermitian
- *    momenta, read and written; not overlapping the links.
+ *  gauge: STG_LINK_C128_18 or STG_LINK_C128_12 (FP64 arithmetic, complex128
+ *    momenta), or STG_LINK_C64_12 (the single-precision molecular dynamics: FP32
+ *    arithmetic, complex64 momenta); SU(3) links; phases ignored.
+ *  mom: device [8][3][3][Vh] (the link layout) of that element type, traceless
+ *    Hermitian momenta, read and written; not overlapping the links.
  *  beta, c0, c1, eps: finite.  STG_TUNE_STAPLE_THREADS and the pencil tile apply.
  * Errors: STG_INVALID_ARG (nothing launched).  Asynchronous.
  */
@@ -431,9 +433,12 @@ int gauge_momentum_update(const stg_lattice *lat, const stg_gauge *gauge, double
 /*
  * Link update of the molecular dynamics: U_mu(x) <- exp(i eps P_mu(x)) U_mu(x) for every
  * link, in place, with exp(iQ) in the Cayley-Hamilton closed form (as in stout_smear).
- *  fmt: STG_LINK_C128_18 or STG_LINK_C128_12 (the 12-real format keeps rows 0 and 1 of
- *    the updated link).  links: device, that format, read and written.
- *  mom: device complex128 [8][3][3][Vh], traceless Hermitian; not overlapping links.
+ *  fmt: STG_LINK_C128_18, STG_LINK_C128_12 or STG_LINK_C64_12 (the 12-real formats
+ *    keep rows 0 and 1 of the updated link; exp(i eps P) is formed in FP64 in every
+ *    case, the product with U in the format's precision).  links: device, that
+ *    format, read and written.
+ *  mom: device [8][3][3][Vh], complex128 (complex64 with STG_LINK_C64_12), traceless
+ *    Hermitian; not overlapping links.
  *  eps: finite.
  * Errors: STG_INVALID_ARG (nothing launched).  Asynchronous.
  */

@@ -256,15 +256,16 @@ def stout_smear(gauge: Gauge, rho: float, out: Optional[torch.Tensor] = None,
 
 def _check_mom(gauge: Gauge, mom: torch.Tensor):
     vh = half_volume(gauge.dims)
-    if mom.dtype != torch.complex128 or tuple(mom.shape) != (8, 3, 3, vh) or \
-            not mom.is_contiguous():
-        raise ValueError(f"mom must be a contiguous complex128 tensor of shape (8, 3, 3, {vh})")
+    dt = torch.complex64 if gauge.fmt == STG_LINK_C64_12 else torch.complex128
+    if mom.dtype != dt or tuple(mom.shape) != (8, 3, 3, vh) or not mom.is_contiguous():
+        raise ValueError(f"mom must be a contiguous {dt} tensor of shape (8, 3, 3, {vh})")
 
 
 def gauge_momentum_update(gauge: Gauge, mom: torch.Tensor, beta: float, eps: float,
                           c0: float = SYMANZIK_C0, c1: float = SYMANZIK_C1,
                           stream=None) -> torch.Tensor:
-    """P <- P - eps F(U) in place for the tree-level Symanzik gauge force (FP64 links)."""
+    """P <- P - eps F(U) in place for the tree-level Symanzik gauge force (FP64 links and
+    complex128 momenta, or FP32-12 links and complex64 momenta)."""
     _check_mom(gauge, mom)
     g = gauge.c()
     _lib.check("gauge_momentum_update", library().gauge_momentum_update(
@@ -274,7 +275,7 @@ def gauge_momentum_update(gauge: Gauge, mom: torch.Tensor, beta: float, eps: flo
 
 
 def gauge_link_update(gauge: Gauge, mom: torch.Tensor, eps: float, stream=None) -> Gauge:
-    """U <- exp(i eps P) U in place on gauge.links (FP64 formats)."""
+    """U <- exp(i eps P) U in place on gauge.links (FP64 formats or FP32-12)."""
     _check_mom(gauge, mom)
     _lib.check("gauge_link_update", library().gauge_link_update(
         ctypes.byref(_lib.lattice(gauge.dims)), int(gauge.fmt), _ptr(gauge.links), float(eps),

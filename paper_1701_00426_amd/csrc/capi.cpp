@@ -1443,12 +1443,16 @@ int gauge_momentum_update(const stg_lattice *lat, const stg_gauge *gauge, double
                           double c1, double eps, void *mom, stg_stream_t stream) {
     Geom g;
     if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
-    int rc = check_gauge(g, gauge, STG_C128);
+    if (!gauge) return invalid("gauge is NULL");
+    const bool fp32 = gauge->fmt == STG_LINK_C64_12;
+    int rc = check_gauge(g, gauge, fp32 ? STG_C64 : STG_C128);
     if (rc) return rc;
+    if (gauge->fmt == STG_LINK_BF16_12) return invalid("the momentum update takes no BF16 links");
     if (!std::isfinite(beta) || !std::isfinite(c0) || !std::isfinite(c1) || !std::isfinite(eps))
         return invalid("beta, c0, c1 and eps must be finite");
     if (!aligned16(mom)) return invalid("mom NULL or not 16-byte aligned");
-    if (overlap(gauge->links, link_bytes(g, gauge->fmt), mom, (size_t)8 * 9 * g.Vh * 16))
+    if (overlap(gauge->links, link_bytes(g, gauge->fmt), mom,
+                (size_t)8 * 9 * g.Vh * (fp32 ? 8 : 16)))
         return invalid("links and mom overlap");
     StapleArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -1462,7 +1466,7 @@ int gauge_momentum_update(const stg_lattice *lat, const stg_gauge *gauge, double
     a.xcd_remap = g_xcd_remap;
     const int threads = g_staple_threads ? g_staple_threads : staple_default_threads(gauge->fmt);
     if (launch_momentum(a, gauge->fmt, threads, (hipStream_t)stream))
-        return invalid("not an FP64 link format");
+        return invalid("unsupported link format for the momentum update");
     HIP_TRY(hipGetLastError());
     return STG_OK;
 }
@@ -1471,11 +1475,12 @@ int gauge_link_update(const stg_lattice *lat, stg_link_fmt fmt, void *links, dou
                       const void *mom, stg_stream_t stream) {
     Geom g;
     if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
-    if (fmt != STG_LINK_C128_18 && fmt != STG_LINK_C128_12)
-        return invalid("the link update takes FP64 link formats only");
+    if (fmt != STG_LINK_C128_18 && fmt != STG_LINK_C128_12 && fmt != STG_LINK_C64_12)
+        return invalid("the link update takes FP64 links or FP32-12 links");
     if (!std::isfinite(eps)) return invalid("eps must be finite");
     if (!aligned16(links) || !aligned16(mom)) return invalid("links or mom NULL or misaligned");
-    if (overlap(links, link_bytes(g, fmt), mom, (size_t)8 * 9 * g.Vh * 16))
+    if (overlap(links, link_bytes(g, fmt), mom,
+                (size_t)8 * 9 * g.Vh * (fmt == STG_LINK_C64_12 ? 8 : 16)))
         return invalid("links and mom overlap");
     LinkUpdateArgs a;
     a.links = links;

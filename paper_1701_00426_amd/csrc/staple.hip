@@ -324,7 +324,7 @@ __device__ __forceinline__ void side_below(su3<T> &acc, const LinkAt<T, FMT> &U,
 // links; with 2, wave 0 sums the +nu sides and wave 1 the -nu sides, and wave 0
 // adds wave 1's sums from LDS.  Two waves per SIMD are asked of the FP64 split
 // kernel (it then fits in 256 registers).
-// EPI 0 writes Sigma; EPI 1 (FP64 links) instead adds (eps beta / 3) times the
+// EPI 0 writes Sigma; EPI 1 (FP64 or FP32-12 links) instead adds (eps beta / 3) times the
 // traceless Hermitian part of i U Sigma to the link's momentum: P -> P - eps F with the
 // Symanzik gauge force F = -(beta/3) [i U Sigma]_TH, the staples never leaving the
 // kernel.
@@ -572,22 +572,24 @@ int launch_tpl(const StapleArgs &a, int threads, hipStream_t stream) {
     return -1;
 }
 
-template <int FMT>
+template <typename T, int FMT>
 int launch_mom(const StapleArgs &a, int threads, hipStream_t stream) {
     const dim3 grid(staple_blocks(a.geom.Vh));
     if (threads == 1) {
-        staple_kernel<double, FMT, 1, 1><<<grid, kStapleLinks, 0, stream>>>(a);
+        staple_kernel<T, FMT, 1, 1><<<grid, kStapleLinks, 0, stream>>>(a);
         return 0;
     }
     if (threads == 2) {
-        staple_kernel<double, FMT, 2, 1><<<grid, 2 * kStapleLinks, 0, stream>>>(a);
+        staple_kernel<T, FMT, 2, 1><<<grid, 2 * kStapleLinks, 0, stream>>>(a);
         return 0;
     }
     return -1;
 }
 
-// U -> exp(i eps P) U in place, one thread per link, in the link's own format.
-template <int FMT>
+// U -> exp(i eps P) U in place, one thread per link, in the link's own format.  The
+// exponential is formed in FP64 also for FP32 links and momenta (its cost is small
+// next to the link and momentum traffic), the product with U in the format's type.
+template <typename T, int FMT>
 __global__ __launch_bounds__(kStoutBlock) void link_update_kernel(LinkUpdateArgs a) {
     const uint32_t Vh = a.Vh;
     const size_t n = (size_t)8 * Vh;
@@ -595,20 +597,38 @@ __global__ __launch_bounds__(kStoutBlock) void link_update_kernel(LinkUpdateArgs
     if (t >= n) return;
     const int slot = (int)(t / Vh);
     const uint32_t h = (uint32_t)(t % Vh);
-    const su3<double> u = cached_link<double, FMT>::load(a.links, Vh, slot, h);
+    const su3<T> u = cached_link<T, FMT>::load(a.links, Vh, slot, h);
     su3<double> q;
     const size_t base = (size_t)slot * 9 * Vh + h;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) q.e[i][k] = cscale(a.eps, ld_c<double>(a.mom, base + (size_t)(i * 3 + k) * Vh));
-    const su3<double> up = mm(exp_iq(q), u);
-    constexpr int rows = FMT == FMT_C128_18 ? 3 : 2;
-    const size_t lbase = (size_t)slot * rows * 3 * Vh + h;
+        for (int k = 0; k < 3; ++k) {
+            const cpx<T> p = ld_c<T>(a.mom, base + (size_t)(i * 3 + k) * Vh);
+            q.e[i][k] = {a.eps * (double)p.re, a.eps * (double)p.im};
+        }
+    const su3<double> e64 = exp_iq(q);
+    su3<T> e;
 #pragma unroll
-    for (int i = 0; i < rows; ++i)
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) st_c<double>(a.links, lbase + (size_t)(i * 3 + k) * Vh, up.e[i][k]);
+        for (int k = 0; k < 3; ++k) e.e[i][k] = {(T)e64.e[i][k].re, (T)e64.e[i][k].im};
+    const su3<T> up = mm(e, u);
+    if constexpr (FMT == FMT_C64_12) {
+        // float4 chunks: (U00, U01), (U02, U10), (U11, U12)
+        float4 *p = reinterpret_cast<float4 *>(a.links) + (size_t)slot * 3 * Vh + h;
+        p[0] = make_float4(up.e[0][0].re, up.e[0][0].im, up.e[0][1].re, up.e[0][1].im);
+        p[Vh] = make_float4(up.e[0][2].re, up.e[0][2].im, up.e[1][0].re, up.e[1][0].im);
+        p[2 * (size_t)Vh] = make_float4(up.e[1][1].re, up.e[1][1].im, up.e[1][2].re, up.e[1][2].im);
+    } else {
+        constexpr int rows = FMT == FMT_C128_18 ? 3 : 2;
+        const size_t lbase = (size_t)slot * rows * 3 * Vh + h;
+#pragma unroll
+        for (int i = 0; i < rows; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                st_c<T>(a.links, lbase + (size_t)(i * 3 + k) * Vh, up.e[i][k]);
+    }
 }
 
 }  // namespace
@@ -624,8 +644,9 @@ int launch_stout(const StoutArgs &a, int fmt, hipStream_t stream) {
 
 int launch_momentum(const StapleArgs &a, int fmt, int threads, hipStream_t stream) {
     switch (fmt) {
-        case FMT_C128_18: return launch_mom<FMT_C128_18>(a, threads, stream);
-        case FMT_C128_12: return launch_mom<FMT_C128_12>(a, threads, stream);
+        case FMT_C128_18: return launch_mom<double, FMT_C128_18>(a, threads, stream);
+        case FMT_C128_12: return launch_mom<double, FMT_C128_12>(a, threads, stream);
+        case FMT_C64_12: return launch_mom<float, FMT_C64_12>(a, threads, stream);
         default: return -1;
     }
 }
@@ -633,8 +654,15 @@ int launch_momentum(const StapleArgs &a, int fmt, int threads, hipStream_t strea
 int launch_link_update(const LinkUpdateArgs &a, int fmt, hipStream_t stream) {
     const dim3 grid((unsigned)(((size_t)8 * a.Vh + kStoutBlock - 1) / kStoutBlock));
     switch (fmt) {
-        case FMT_C128_18: link_update_kernel<FMT_C128_18><<<grid, kStoutBlock, 0, stream>>>(a); return 0;
-        case FMT_C128_12: link_update_kernel<FMT_C128_12><<<grid, kStoutBlock, 0, stream>>>(a); return 0;
+        case FMT_C128_18:
+            link_update_kernel<double, FMT_C128_18><<<grid, kStoutBlock, 0, stream>>>(a);
+            return 0;
+        case FMT_C128_12:
+            link_update_kernel<double, FMT_C128_12><<<grid, kStoutBlock, 0, stream>>>(a);
+            return 0;
+        case FMT_C64_12:
+            link_update_kernel<float, FMT_C64_12><<<grid, kStoutBlock, 0, stream>>>(a);
+            return 0;
         default: return -1;
     }
 }

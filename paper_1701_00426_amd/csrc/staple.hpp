@@ -37,17 +37,17 @@ int launch_staples(const StapleArgs &a, int fmt, int threads, hipStream_t stream
 
 // The momentum update of the pure-gauge molecular dynamics (staple.hip): the same
 // staples, then P -> P + kmom [i U Sigma]_TH for every link, out = the momenta
-// (complex128 [8][3][3][Vh], read and written).  FP64 formats only.
+// (complex T [8][3][3][Vh], read and written).  FP64 formats and FP32-12.
 int launch_momentum(const StapleArgs &a, int fmt, int threads, hipStream_t stream);
 
 struct LinkUpdateArgs {
-    void *links;        // FP64 gauge field, updated in place
-    const void *mom;    // complex128 [8][3][3][Vh]
+    void *links;        // FP64 or FP32-12 gauge field, updated in place
+    const void *mom;    // complex T [8][3][3][Vh] (complex64 for FP32-12)
     double eps;
     uint32_t Vh;
 };
 
-// U -> exp(i eps P) U for every link, in place (FP64 formats only).
+// U -> exp(i eps P) U for every link, in place (FP64 formats and FP32-12).
 int launch_link_update(const LinkUpdateArgs &a, int fmt, hipStream_t stream);
 
 // One stout-smearing step of every link (staple.hip): U' = exp(iQ) U.

@@ -368,7 +368,7 @@ def test_md_arguments_rejected_on_host(lib):
     def link_call(fmt=0, links=0x1000, eps=0.01, mom=0x10000000):
         return lib.gauge_link_update(ctypes.byref(lat), fmt, links, eps, mom, None)
 
-    assert link_call(fmt=2) == -1 and link_call(fmt=9) == -1
+    assert link_call(fmt=3) == -1 and link_call(fmt=9) == -1
     assert link_call(eps=float("nan")) == -1
     assert link_call(links=None) == -1 and link_call(mom=0x1008) == -1
     assert link_call(mom=0x1000 + 4096) == -1         # overlaps the links

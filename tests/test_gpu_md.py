@@ -148,3 +148,51 @@ def test_momentum_update_32_4_sampled():
         err = max(err, float(np.max(np.abs(got - want))))
     say(f"momentum update 32^4 sampled: max abs err {err:.2e}")
     assert err <= _mom_tol(BETA, EPS)
+
+
+U24 = 2.0 ** -24
+
+
+def _as_stored_c64(links):
+    """FP32-12 links as the kernel sees them: rows 0 and 1 rounded to complex64, row 2
+    rebuilt as conj(row0 x row1) (here in FP64)."""
+    out = links.copy()
+    out[:, :2] = links[:, :2].astype(np.complex64).astype(np.complex128)
+    out[:, 2] = np.conj(np.cross(out[:, 0], out[:, 1], axis=1))
+    return out
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 10), (32, 8, 4, 6)])
+def test_momentum_update_fp32(dims, staple_threads):
+    """Single-precision molecular dynamics: FP32-12 links, complex64 momenta, FP32
+    arithmetic; tolerance 64 u (u = 2^-24) on the force term and on the momenta."""
+    links = si.su3_links(dims, 1701, 103, sum(dims))
+    mom = si.traceless_hermitian_field(dims, 104, sum(dims)).astype(np.complex64)
+    gauge = stg.pack_gauge(dims, to_dev(links), "c64_12")
+    p = to_dev(mom)
+    stg.gauge_momentum_update(gauge, p, BETA, EPS)
+    torch.cuda.synchronize()
+    want = on.momentum_update(dims, _as_stored_c64(links), mom.astype(np.complex128), BETA, EPS)
+    err = float(np.max(np.abs(p.cpu().numpy().astype(np.complex128) - want)))
+    tol = 64 * U24 * ((BETA / 3.0) * 8.5 * EPS + float(np.max(np.abs(mom))))
+    say(f"momentum update FP32 {dims} threads={staple_threads}: max abs err {err:.2e} "
+        f"(tol {tol:.1e})")
+    assert err <= tol
+
+
+def test_link_update_fp32():
+    dims = (4, 6, 2, 4)
+    links = si.su3_links(dims, 1701, 105, 0)
+    mom = si.traceless_hermitian_field(dims, 106, 0).astype(np.complex64)
+    gauge = stg.pack_gauge(dims, to_dev(links), "c64_12")
+    stg.gauge_link_update(gauge, to_dev(mom), 0.05)
+    torch.cuda.synchronize()
+    want = on.link_update(_as_stored_c64(links), mom.astype(np.complex128), 0.05)[:, :2]
+    # memory order: slot, chunk k, site, pair; chunk k holds entries 2k, 2k+1 of
+    # (U00 U01 U02 U10 U11 U12)
+    vh = on.half_volume(dims)
+    got = gauge.links.cpu().numpy().view(np.complex64).reshape(8, 3, vh, 2)
+    got = np.transpose(got, (0, 1, 3, 2)).reshape(8, 6, vh).reshape(8, 2, 3, vh)
+    err = float(np.max(np.abs(got.astype(np.complex128) - want)))
+    say(f"link update FP32: max abs err {err:.2e}")
+    assert err <= 32 * U24
