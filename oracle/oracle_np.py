@@ -25,7 +25,8 @@ Paper: Bonati et al., arXiv:1701.00426.
   * Sec. 2.2 (forces of the molecular dynamics from the solutions of Eq.
     shlineq) -- the rational pseudofermion action and its derivative with
     respect to every link (thin links; the stout-smearing chain is not here).
-  * Sec. 2.1, Sec. 2.3 -- one stout-smearing step (Morningstar-Peardon definition).
+  * Sec. 2.1, Sec. 2.3 -- one stout-smearing step (Morningstar-Peardon definition)
+    and the chain rule of a force through it.
   * Sec. 4.3 and Table 4 -- the pure-gauge molecular dynamics: the gauge force
     from the staples, momentum and link updates, the leapfrog and its energy.
 
@@ -729,3 +730,67 @@ def leapfrog(dims, links, mom, beta, eps, nsteps, c0=SYMANZIK_C0, c1=SYMANZIK_C1
         u = link_update(u, p, eps)
         p = momentum_update(dims, u, p, beta, eps if k < nsteps - 1 else 0.5 * eps, c0, c1)
     return u, p
+
+
+def stout_backprop(dims, links, rho, sig_p):
+    """The chain rule through one stout step: given Sigma'_l = dS/dU'_l for every link of
+    the smeared field U' = exp(iQ) U (convention: dS = Re Tr(dU' Sigma')), returns
+    Sigma_l = dS/dU_l for the thin links (same convention), (8, 3, 3, Vh).
+
+    Written out from the definition of the step:
+      * through U in exp(iQ) U:            Sigma'_l exp(iQ_l);
+      * through Q: with Gamma = L(iQ, U Sigma') (the Frechet derivative of exp, used
+        through Tr(L(A, E) M) = Tr(E L(A, M))), dS = Re Tr(i dQ Gamma); Q's definition
+        turns that into dS = Re Tr(dOmega G) with
+        G = (Gamma - Gamma^dag)/2 + (conj(Tr Gamma) - Tr Gamma)/6 I;
+      * Omega = C U^dag: through U^dag, C^dag G^dag; through C, Re Tr(dC U^dag G);
+      * C = rho * (3-link paths): every link of every path receives
+        rho * (product after it) (U^dag G) (product before it), daggered for a link
+        the path walks backwards.
+    Pinned by central differences of Re sum Tr(U'(U) M)."""
+    from scipy.linalg import expm_frechet
+    vh = half_volume(dims)
+    sig_s = staples(dims, links, 1.0, 0.0)
+    cmat = rho * np.conj(np.transpose(sig_s, (0, 2, 1, 3)))
+    q = stout_q(dims, links, rho)
+    out = np.zeros_like(links)
+    gc = np.empty_like(links)        # U^dag G per link
+    for s in range(8):
+        for h in range(vh):
+            u = links[s, :, :, h]
+            e, gam = expm_frechet(1j * q[s, :, :, h], u @ sig_p[s, :, :, h])
+            tg = np.trace(gam)
+            g = 0.5 * (gam - np.conj(gam.T)) + ((np.conj(tg) - tg) / 6.0) * np.eye(3)
+            c = cmat[s, :, :, h]
+            out[s, :, :, h] = sig_p[s, :, :, h] @ e + np.conj(c.T) @ np.conj(g.T)
+            gc[s, :, :, h] = np.conj(u.T) @ g
+    for parity in (0, 1):
+        x = coords(dims, parity)
+        for mu in range(4):
+            g = gc[2 * mu + parity]
+            for al in range(4):
+                if al == mu:
+                    continue
+                for steps in ([(al, 1), (mu, 1), (al, -1)], [(al, -1), (mu, 1), (al, 1)]):
+                    y = x.copy()
+                    for k, (d, sgn) in enumerate(steps):
+                        a = path_product(dims, links, x, steps[:k])
+                        if sgn > 0:
+                            site = y
+                            after = shifted(dims, y, d, +1)
+                        else:
+                            site = shifted(dims, y, d, -1)
+                            after = site
+                        dd = path_product(dims, links, after, steps[k + 1:])
+                        contrib = rho * np.einsum("abn,bcn,cdn->adn", dd, g, a)
+                        if sgn < 0:
+                            contrib = np.conj(np.transpose(contrib, (1, 0, 2)))
+                        slot = 2 * d + site_parity(site)
+                        # for fixed (mu, parity, al, path, k) the link sites are a
+                        # translate of the sites x: no index repeats
+                        hh = half_index(dims, site)
+                        for p2 in (0, 1):
+                            sel = (site_parity(site) == p2)
+                            out[2 * d + p2][:, :, hh[sel]] += contrib[:, :, sel]
+                        y = after
+    return out

@@ -435,3 +435,63 @@ def test_gauge_force_covariance_and_link_update_unitary():
     m = np.transpose(u, (0, 3, 1, 2)).reshape(-1, 3, 3)
     assert np.max(np.abs(m @ np.conj(np.transpose(m, (0, 2, 1))) - np.eye(3))) <= 1e-14
     assert np.max(np.abs(np.linalg.det(m) - 1)) <= 1e-14
+
+
+def _complex_field(dims, *seed):
+    vh = on.half_volume(dims)
+    z = si.rng(*seed).standard_normal((8, 3, 3, vh, 2))
+    return z[..., 0] + 1j * z[..., 1]
+
+
+def test_stout_backprop_is_the_chain_rule():
+    """For S(U) = Re sum_l Tr(U'_l(U) M_l) (so dS/dU' = M) the chain rule must give the
+    central differences of S in all 18 real directions, at links of every slot, on two
+    lattices and weights; rho = 0 maps Sigma' to itself."""
+    for dims, rho, seed in (((4, 2, 4, 4), 0.2, 111), ((2, 4, 4, 4), -0.35, 112)):
+        links = si.su3_links(dims, seed, 0)
+        m = _complex_field(dims, seed, 1)
+        sig = on.stout_backprop(dims, links, rho, m)
+
+        def f(lk):
+            return float(np.real(np.einsum("sabn,sban->", on.stout_smear(dims, lk, rho), m)))
+
+        eps = 1e-5
+        for slot in range(8):
+            h = (7 * slot + 3) % on.half_volume(dims)
+            got = np.empty((3, 3), dtype=np.complex128)
+            for a in range(3):
+                for b in range(3):
+                    d = []
+                    for e in (1.0, 1j):
+                        plus = links.copy()
+                        plus[slot, a, b, h] += eps * e
+                        minus = links.copy()
+                        minus[slot, a, b, h] -= eps * e
+                        d.append((f(plus) - f(minus)) / (2 * eps))
+                    got[b, a] = d[0] - 1j * d[1]
+            assert np.max(np.abs(got - sig[slot, :, :, h])) <= 1e-7 * np.max(
+                np.abs(sig[slot, :, :, h]))
+        assert np.array_equal(on.stout_backprop(dims, links, 0.0, m), m)
+
+
+def test_stout_backprop_gauge_covariance():
+    """dS = Re Tr(dU' Sigma') is gauge invariant when Sigma'_mu(x) transforms as
+    g(x+mu) Sigma' g(x)^dag; Sigma then transforms the same way."""
+    dims, rho = (4, 4, 2, 4), 0.15
+    links = si.su3_links(dims, 113, 0)
+    m = _complex_field(dims, 113, 1)
+    g = (si.su3_site_field(dims, 113, 2), si.su3_site_field(dims, 113, 3))
+
+    def tr_ends(field):
+        out = np.empty_like(field)
+        for parity in (0, 1):
+            x = on.coords(dims, parity)
+            for mu in range(4):
+                gf = pins._g_at(dims, g, on.shifted(dims, x, mu, +1))
+                out[2 * mu + parity] = np.einsum("abn,bcn,dcn->adn", gf, field[2 * mu + parity],
+                                                 np.conj(g[parity]))
+        return out
+
+    s0 = on.stout_backprop(dims, links, rho, m)
+    s1 = on.stout_backprop(dims, on.gauge_transform_links(dims, links, *g), rho, tr_ends(m))
+    assert np.max(np.abs(s1 - tr_ends(s0))) <= 1e-12 * np.max(np.abs(s0))
