@@ -773,6 +773,40 @@ def bench_md(applies=50, profile=False):
                       "rows": rows}), flush=True)
 
 
+def bench_stout_force(applies=20):
+    """The force through one stout level (stout_force_backprop) at 32^4: FP64-12 thin
+    links, rho = 0.15, a seeded Gaussian dS/dU'; two passes per call.  HIP events."""
+    import torch
+    import paper_1701_00426_amd as stg
+    import seeded_inputs as si
+    dev = torch.device("cuda:0")
+    dims = (32, 32, 32, 32)
+    vh = stg.half_volume(dims)
+    links = torch.from_numpy(si.su3_links(dims, 1701, 11, 0)).to(dev)
+    gauge = stg.pack_gauge(dims, links, "c128_12")
+    del links
+    z = si.rng(426, 11, 0).standard_normal((8, 3, 3, vh, 2))
+    sp = torch.from_numpy(z[..., 0] + 1j * z[..., 1]).to(dev)
+    del z
+    out = torch.empty_like(sp)
+    ws = torch.empty_like(sp)
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        stg.stout_force_backprop(gauge, 0.15, sp, out=out, ws=ws)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(applies):
+        stg.stout_force_backprop(gauge, 0.15, sp, out=out, ws=ws)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    dt = t0.elapsed_time(t1) / 1e3 / applies
+    print(json.dumps({"workload": "force through one stout level, 32^4, FP64-12 thin links, "
+                                  "rho = 0.15", "call_us": round(dt * 1e6, 1),
+                      "ns_per_site": round(dt * 1e9 / (2 * vh), 3)}), flush=True)
+
+
 # Launch-shape variants of the hop compared under one kernel trace: (format, fields,
 # knob settings).  Each runs the same number of back-to-back D_eo launches.
 VARIANTS = [
@@ -842,7 +876,8 @@ def main():
                     help="for rocprofv3: one FP64 CG and one mixed CG solve only")
     ap.add_argument("--workload", choices=["main", "multishift", "rational", "batch",
                                            "batch-small", "shapes", "staples", "force",
-                                           "stout", "tiles", "small", "md"],
+                                           "stout", "tiles", "small", "md",
+                                           "stoutforce"],
                     default="main",
                     help="main: the 32^4 line; multishift: 24^3x48, 16 shifts x 8 RHS; "
                          "rational: the same shifts combined into r(A) b; "
@@ -853,7 +888,8 @@ def main():
                          "stout: two stout-smearing levels at 32^4; "
                          "tiles: the pencil tile shapes of the staple and stout kernels; "
                          "small: 8^4 FP64-18 hop and CG (latency-bound); "
-                         "md: the pure-gauge MD step on the Table 4 shapes")
+                         "md: the pure-gauge MD step on the Table 4 shapes; "
+                         "stoutforce: the force through one stout level at 32^4")
     ap.add_argument("--profile-md", action="store_true",
                     help="for rocprofv3: only the 32^4 MD-step loop")
     ap.add_argument("--profile-stout", action="store_true",
@@ -891,6 +927,9 @@ def main():
         return
     if args.workload == "shapes":
         bench_shapes()
+        return
+    if args.workload == "stoutforce":
+        bench_stout_force()
         return
     if args.workload == "md" or args.profile_md:
         bench_md(profile=args.profile_md)

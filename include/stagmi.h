@@ -445,6 +445,25 @@ int gauge_momentum_update(const stg_lattice *lat, const stg_gauge *gauge, double
 int gauge_link_update(const stg_lattice *lat, stg_link_fmt fmt, void *links, double eps,
                       const void *mom, stg_stream_t stream);
 
+/*
+ * The force through one stout-smearing step (Sec. 2.2: the fermion force follows
+ * Morningstar and Peardon through the stout levels of Sec. 2.1 / Sec. 2.3): given
+ * Sigma'_l = dS/dU'_l for every link of U' = stout_smear(U, rho) (convention:
+ * dS = Re Tr(dU' Sigma'), as for fermion_force and gauge_staples), writes
+ * Sigma_l = dS/dU_l for the thin links U (same convention), the chain rule through
+ * exp(iQ) U, Q(Omega), Omega = C U^dag and the six 3-link paths of C.  Repeated calls
+ * carry a force down several levels (each with that level's thin links).
+ *  gauge: STG_LINK_C128_18 or STG_LINK_C128_12, the thin links of the level.
+ *  sigma_smeared: device complex128 [8][3][3][Vh].
+ *  sigma_thin: device complex128 [8][3][3][Vh], written entirely.
+ *  ws: device scratch, complex128 [8][3][3][Vh] (8*9*Vh*16 bytes), overwritten.
+ * The four buffers and the links are pairwise disjoint and 16-byte aligned; rho finite.
+ * Errors: STG_INVALID_ARG (nothing launched).  Asynchronous.
+ */
+int stout_force_backprop(const stg_lattice *lat, const stg_gauge *gauge, double rho,
+                         const void *sigma_smeared, void *sigma_thin, void *ws,
+                         stg_stream_t stream);
+
 typedef struct {
     stg_lattice lat;
     stg_gauge hi;

@@ -34,6 +34,7 @@ __all__ = [
     "cg_solve_batch", "rational_apply", "stg_rational_workspace_bytes", "stg_autotune",
     "stg_autotune_load", "stg_autotune_lookup", "gauge_staples", "SYMANZIK_C0", "SYMANZIK_C1",
     "fermion_force", "stout_smear", "gauge_momentum_update", "gauge_link_update",
+    "stout_force_backprop",
 ]
 
 # tree-level Symanzik weights of the 1x1 and 1x2 loops: c1 = -1/12, c0 + 8 c1 = 1
@@ -281,6 +282,27 @@ def gauge_link_update(gauge: Gauge, mom: torch.Tensor, eps: float, stream=None) 
         ctypes.byref(_lib.lattice(gauge.dims)), int(gauge.fmt), _ptr(gauge.links), float(eps),
         _ptr(mom), _stream(stream)))
     return gauge
+
+
+def stout_force_backprop(gauge: Gauge, rho: float, sigma_smeared: torch.Tensor,
+                         out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+                         stream=None) -> torch.Tensor:
+    """dS/dU for the thin links from dS/dU' of the links smeared once with weight rho
+    (complex128 (8, 3, 3, Vh) each; asynchronous on the stream)."""
+    vh = half_volume(gauge.dims)
+    shape = (8, 3, 3, vh)
+    if sigma_smeared.dtype != torch.complex128 or tuple(sigma_smeared.shape) != shape or \
+            not sigma_smeared.is_contiguous():
+        raise ValueError(f"sigma_smeared must be a contiguous complex128 tensor of shape {shape}")
+    out = torch.empty(shape, dtype=torch.complex128, device=sigma_smeared.device) \
+        if out is None else out
+    ws = torch.empty(shape, dtype=torch.complex128, device=sigma_smeared.device) \
+        if ws is None else ws
+    g = gauge.c()
+    _lib.check("stout_force_backprop", library().stout_force_backprop(
+        ctypes.byref(_lib.lattice(gauge.dims)), ctypes.byref(g), float(rho),
+        _ptr(sigma_smeared), _ptr(out), _ptr(ws), _stream(stream)))
+    return out
 
 
 def stg_apply_normal(gauge: Gauge, mass: float, in_even: torch.Tensor, sigma: float = 0.0,

@@ -1492,6 +1492,39 @@ int gauge_link_update(const stg_lattice *lat, stg_link_fmt fmt, void *links, dou
     return STG_OK;
 }
 
+int stout_force_backprop(const stg_lattice *lat, const stg_gauge *gauge, double rho,
+                         const void *sigma_smeared, void *sigma_thin, void *ws,
+                         stg_stream_t stream) {
+    Geom g;
+    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
+    int rc = check_gauge(g, gauge, STG_C128);
+    if (rc) return rc;
+    if (!std::isfinite(rho)) return invalid("rho must be finite");
+    if (!aligned16(sigma_smeared) || !aligned16(sigma_thin) || !aligned16(ws))
+        return invalid("sigma_smeared, sigma_thin or ws NULL or not 16-byte aligned");
+    const size_t mb = (size_t)8 * 9 * g.Vh * 16, lb = link_bytes(g, gauge->fmt);
+    const void *bufs[4] = {gauge->links, sigma_smeared, sigma_thin, ws};
+    const size_t sizes[4] = {lb, mb, mb, mb};
+    for (int i = 0; i < 4; ++i)
+        for (int k = i + 1; k < 4; ++k)
+            if (overlap(bufs[i], sizes[i], bufs[k], sizes[k]))
+                return invalid("links, sigma_smeared, sigma_thin and ws must not overlap");
+    StoutBackArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.geom = g;
+    a.tile = pencil_tile(g, g_pencil_tile);
+    a.links = gauge->links;
+    a.sigp = sigma_smeared;
+    a.out = sigma_thin;
+    a.ws = ws;
+    a.rho = rho;
+    a.xcd_remap = g_xcd_remap;
+    if (launch_stout_backprop(a, gauge->fmt, (hipStream_t)stream))
+        return invalid("not an FP64 link format");
+    HIP_TRY(hipGetLastError());
+    return STG_OK;
+}
+
 int dirac_apply_eo(const stg_lattice *lat, const stg_gauge *gauge, stg_field field, int nrhs,
                    const void *in_odd, void *out_even, stg_stream_t stream) {
     return apply_dirac(lat, gauge, field, nrhs, in_odd, out_even, 0, stream);

@@ -500,6 +500,217 @@ __device__ __forceinline__ su3<double> exp_iq(const su3<double> &q) {
     return e;
 }
 
+// exp(B) and the Frechet derivative L(B, M) = d/dt exp(B + t M) at t = 0 for a general
+// 3x3 complex B, M: exp of the block matrix [[B, M], [0, B]] is [[e^B, L], [0, e^B]].  With
+// T_n = B^n / n! and X_n the top-right block of the n-th term, X_n = (B X_{n-1} + M T_{n-1})/n;
+// B and M are first scaled by 2^-s so that |B|_F <= 1/4, the series taken to 14 terms
+// (remainder below 1e-20), and the pair squared back s times: (E, L) -> (E E, E L + L E).
+__device__ __forceinline__ void exp_frechet(const su3<double> &b, const su3<double> &m,
+                                            su3<double> &e, su3<double> &l) {
+    double nb = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) nb += b.e[i][k].re * b.e[i][k].re + b.e[i][k].im * b.e[i][k].im;
+    nb = sqrt(nb);
+    int sq = 0;
+    while (nb > 0.25 && sq < 40) {
+        nb *= 0.5;
+        ++sq;
+    }
+    const double sc = ldexp(1.0, -sq);
+    su3<double> bs, ms, t, x;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            bs.e[i][k] = cscale(sc, b.e[i][k]);
+            ms.e[i][k] = cscale(sc, m.e[i][k]);
+            t.e[i][k] = {i == k ? 1.0 : 0.0, 0.0};
+            x.e[i][k] = {0.0, 0.0};
+        }
+    e = t;
+    l = x;
+#pragma unroll 1
+    for (int n = 1; n <= 14; ++n) {
+        su3<double> xn = mm(bs, x);
+        mm_acc(xn, ms, t);
+        t = mm(bs, t);
+        const double inv = 1.0 / (double)n;
+        scale(xn, inv);
+        scale(t, inv);
+        x = xn;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                e.e[i][k] = cadd(e.e[i][k], t.e[i][k]);
+                l.e[i][k] = cadd(l.e[i][k], x.e[i][k]);
+            }
+    }
+#pragma unroll 1
+    for (int r = 0; r < sq; ++r) {
+        su3<double> ln = mm(e, l);
+        mm_acc(ln, l, e);
+        l = ln;
+        e = mm(e, e);
+    }
+}
+
+// Pass 1 of the force through a stout step, one thread per link l = (mu, x):
+// C = rho (3-link paths from x to x+mu), Omega = C U^dag, Q, M = U Sigma'_l,
+// Gamma = L(iQ, M); G = (Gamma - Gamma^dag)/2 + (conj(Tr Gamma) - Tr Gamma)/6;
+// out_l = Sigma'_l exp(iQ) + C^dag G^dag, ws_l = U^dag G.
+template <int FMT>
+__global__ __launch_bounds__(kStoutBlock) void stout_back1_kernel(StoutBackArgs a) {
+    const Geom &g = a.geom;
+    const uint32_t blk = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int slot = (int)(blk % 8);
+    const uint32_t j = (blk / 8) * kStoutBlock + threadIdx.x;
+    if (j >= g.Vh) return;
+    const uint32_t h = pencil_site(g, a.tile, j);
+    const int mu = slot >> 1, P = slot & 1;
+    const Site s = site_coords(g, P, h);
+    const int st[4] = {1, (int)g.N[0], (int)(g.N[0] * g.N[1]), (int)(g.N[0] * g.N[1] * g.N[2])};
+    const int L = (int)s.x[0] + st[1] * (int)s.x[1] + st[2] * (int)s.x[2] + st[3] * (int)s.x[3];
+    const LinkAt<double, FMT> U{a.links, g.Vh, L, P};
+    const int xm = (int)pick4(s.x[0], s.x[1], s.x[2], s.x[3], mu);
+    const int nm = (int)pick4(g.N[0], g.N[1], g.N[2], g.N[3], mu);
+    const int sm = (int)pick4(st[0], st[1], st[2], st[3], mu);
+    const int mp1 = lex_step(xm, 1, nm, sm);
+    su3<double> c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) c.e[i][k] = {0.0, 0.0};
+#pragma unroll 1
+    for (int k = 1; k < 4; ++k) {
+        const int nu = (mu + k) & 3;
+        const int xn = (int)pick4(s.x[0], s.x[1], s.x[2], s.x[3], nu);
+        const int nn = (int)pick4(g.N[0], g.N[1], g.N[2], g.N[3], nu);
+        const int sn = (int)pick4(st[0], st[1], st[2], st[3], nu);
+        const int np1 = lex_step(xn, 1, nn, sn), nm1 = lex_step(xn, -1, nn, sn);
+        mmd_acc(c, mm(U(nu, 0, 0), U(mu, np1, 1)), U(nu, mp1, 1));
+        mm_acc(c, mdm(U(nu, nm1, 1), U(mu, nm1, 1)), U(nu, mp1 + nm1, 0));
+    }
+    scale(c, a.rho);
+    const su3<double> u = U(mu, 0, 0);
+    const su3<double> om = mmd(c, u);
+    const double tq = (om.e[0][0].im + om.e[1][1].im + om.e[2][2].im) / 3.0;
+    su3<double> iq;  // i Q
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const cpx<double> z = csub(cconj(om.e[k][i]), om.e[i][k]);
+            cpx<double> qv = {-0.5 * z.im, 0.5 * z.re};
+            if (i == k) qv.re -= tq;
+            iq.e[i][k] = {-qv.im, qv.re};
+        }
+    const su3<double> sp = cached_link<double, FMT_C128_18>::load(a.sigp, g.Vh, slot, h);
+    su3<double> e, gam;
+    exp_frechet(iq, mm(u, sp), e, gam);
+    const cpx<double> tg = cadd(cadd(gam.e[0][0], gam.e[1][1]), gam.e[2][2]);
+    const cpx<double> dtr = cscale(1.0 / 6.0, csub(cconj(tg), tg));
+    su3<double> gg;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            cpx<double> v = cscale(0.5, csub(gam.e[i][k], cconj(gam.e[k][i])));
+            if (i == k) v = cadd(v, dtr);
+            gg.e[i][k] = v;
+        }
+    su3<double> loc = mm(sp, e);
+    // + C^dag G^dag = (G C)^dag
+    const su3<double> gcm = mm(gg, c);
+    const su3<double> ug = mdm(u, gg);  // U^dag G
+    const size_t base = (size_t)slot * 9 * g.Vh + h;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const size_t idx = base + (size_t)(i * 3 + k) * g.Vh;
+            st_c<double>(a.out, idx, cadd(loc.e[i][k], cconj(gcm.e[k][i])));
+            st_c<double>(a.ws, idx, ug.e[i][k]);
+        }
+}
+
+// Pass 2, one thread per link l = (nu, y): add rho times every product in which l
+// stands in a 3-link path of C at a neighbouring link (gc = U^dag G from pass 1):
+// for each direction b != nu,
+//   l as the middle link:  U_b(y-b+nu)^dag gc(nu, y-b) U_b(y-b),
+//                          U_b(y+nu) gc(nu, y+b) U_b(y)^dag;
+//   l as a side link:      U_b(y+nu) U_nu(y+b)^dag gc(b, y),
+//                          [gc(b, y-b) U_nu(y-b) U_b(y-b+nu)]^dag,
+//                          [U_b(y) U_nu(y+b) gc(b, y+nu)]^dag,
+//                          gc(b, y+nu-b) U_nu(y-b)^dag U_b(y-b).
+template <int FMT>
+__global__ __launch_bounds__(kStoutBlock) void stout_back2_kernel(StoutBackArgs a) {
+    const Geom &g = a.geom;
+    const uint32_t blk = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int slot = (int)(blk % 8);
+    const uint32_t j = (blk / 8) * kStoutBlock + threadIdx.x;
+    if (j >= g.Vh) return;
+    const uint32_t h = pencil_site(g, a.tile, j);
+    const int nu = slot >> 1, P = slot & 1;
+    const Site s = site_coords(g, P, h);
+    const int st[4] = {1, (int)g.N[0], (int)(g.N[0] * g.N[1]), (int)(g.N[0] * g.N[1] * g.N[2])};
+    const int L = (int)s.x[0] + st[1] * (int)s.x[1] + st[2] * (int)s.x[2] + st[3] * (int)s.x[3];
+    const LinkAt<double, FMT> U{a.links, g.Vh, L, P};
+    const LinkAt<double, FMT_C128_18> W{a.ws, g.Vh, L, P};
+    const int xv = (int)pick4(s.x[0], s.x[1], s.x[2], s.x[3], nu);
+    const int nv = (int)pick4(g.N[0], g.N[1], g.N[2], g.N[3], nu);
+    const int sv = (int)pick4(st[0], st[1], st[2], st[3], nu);
+    const int vp1 = lex_step(xv, 1, nv, sv);
+    su3<double> acc;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc.e[i][k] = {0.0, 0.0};
+#pragma unroll 1
+    for (int k = 1; k < 4; ++k) {
+        const int b = (nu + k) & 3;
+        const int xb = (int)pick4(s.x[0], s.x[1], s.x[2], s.x[3], b);
+        const int nb = (int)pick4(g.N[0], g.N[1], g.N[2], g.N[3], b);
+        const int sb = (int)pick4(st[0], st[1], st[2], st[3], b);
+        const int bp1 = lex_step(xb, 1, nb, sb), bm1 = lex_step(xb, -1, nb, sb);
+        // middle link
+        mm_acc(acc, mdm(U(b, bm1 + vp1, 0), W(nu, bm1, 1)), U(b, bm1, 1));
+        mmd_acc(acc, mm(U(b, vp1, 1), W(nu, bp1, 1)), U(b, 0, 0));
+        // side link, forward: U_b(y+nu) U_nu(y+b)^dag gc(b, y)
+        mm_acc(acc, mmd(U(b, vp1, 1), U(nu, bp1, 1)), W(b, 0, 0));
+        // side link, forward: gc(b, y+nu-b) U_nu(y-b)^dag U_b(y-b)
+        mm_acc(acc, mmd(W(b, vp1 + bm1, 0), U(nu, bm1, 1)), U(b, bm1, 1));
+        // side links walked backwards: add the daggers, one product at a time
+        {
+            const su3<double> t4 = mm(mm(W(b, bm1, 1), U(nu, bm1, 1)), U(b, bm1 + vp1, 0));
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) acc.e[i][q] = cadd(acc.e[i][q], cconj(t4.e[q][i]));
+        }
+        {
+            const su3<double> t5 = mm(mm(U(b, 0, 0), U(nu, bp1, 1)), W(b, vp1, 1));
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) acc.e[i][q] = cadd(acc.e[i][q], cconj(t5.e[q][i]));
+        }
+    }
+    const size_t base = (size_t)slot * 9 * g.Vh + h;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const size_t idx = base + (size_t)(i * 3 + k) * g.Vh;
+            cpx<double> v = ld_c<double>(a.out, idx);
+            v.re = fmat(a.rho, acc.e[i][k].re, v.re);
+            v.im = fmat(a.rho, acc.e[i][k].im, v.im);
+            st_c<double>(a.out, idx, v);
+        }
+}
+
 template <int FMT>
 __global__ __launch_bounds__(kStoutBlock) void stout_kernel(StoutArgs a) {
     const Geom &g = a.geom;
@@ -632,6 +843,21 @@ __global__ __launch_bounds__(kStoutBlock) void link_update_kernel(LinkUpdateArgs
 }
 
 }  // namespace
+
+int launch_stout_backprop(const StoutBackArgs &a, int fmt, hipStream_t stream) {
+    const dim3 grid(stout_blocks(a.geom.Vh));
+    switch (fmt) {
+        case FMT_C128_18:
+            stout_back1_kernel<FMT_C128_18><<<grid, kStoutBlock, 0, stream>>>(a);
+            stout_back2_kernel<FMT_C128_18><<<grid, kStoutBlock, 0, stream>>>(a);
+            return 0;
+        case FMT_C128_12:
+            stout_back1_kernel<FMT_C128_12><<<grid, kStoutBlock, 0, stream>>>(a);
+            stout_back2_kernel<FMT_C128_12><<<grid, kStoutBlock, 0, stream>>>(a);
+            return 0;
+        default: return -1;
+    }
+}
 
 int launch_stout(const StoutArgs &a, int fmt, hipStream_t stream) {
     const dim3 grid(stout_blocks(a.geom.Vh));

@@ -50,6 +50,23 @@ struct LinkUpdateArgs {
 // U -> exp(i eps P) U for every link, in place (FP64 formats and FP32-12).
 int launch_link_update(const LinkUpdateArgs &a, int fmt, hipStream_t stream);
 
+// The force through one stout step (staple.hip), in two passes over the links:
+// pass 1 writes Sigma' exp(iQ) + C^dag G^dag to out and U^dag G to ws; pass 2 adds
+// rho times the gathered products of ws with the links of the 3-link paths.
+struct StoutBackArgs {
+    Geom geom;
+    PencilTile tile;
+    const void *links;  // thin FP64 gauge field
+    const void *sigp;   // complex128 [8][3][3][Vh]: dS/dU' of the smeared links
+    void *out;          // complex128 [8][3][3][Vh]: dS/dU of the thin links
+    void *ws;           // complex128 [8][3][3][Vh]: U^dag G per link
+    double rho;
+    int xcd_remap;
+};
+
+// 0: both passes launched; -1: not an FP64 format (nothing launched).
+int launch_stout_backprop(const StoutBackArgs &a, int fmt, hipStream_t stream);
+
 // One stout-smearing step of every link (staple.hip): U' = exp(iQ) U.
 constexpr int kStoutBlock = 128;
 

@@ -372,3 +372,26 @@ def test_md_arguments_rejected_on_host(lib):
     assert link_call(eps=float("nan")) == -1
     assert link_call(links=None) == -1 and link_call(mom=0x1008) == -1
     assert link_call(mom=0x1000 + 4096) == -1         # overlaps the links
+
+
+def test_stout_backprop_arguments_rejected_on_host(lib):
+    """stout_force_backprop checks its arguments before any GPU work (every call fails)."""
+    from paper_1701_00426_amd import _lib
+    lat = _lat((4, 4, 4, 4))
+    g = _lib.StgGauge()
+    g.links = 0x1000
+    g.fmt = 0
+    mb = 8 * 9 * 128 * 16
+
+    def call(gauge=g, rho=0.15, sp=0x1000000, out=0x2000000, ws=0x3000000):
+        return lib.stout_force_backprop(ctypes.byref(lat), ctypes.byref(gauge), rho, sp, out, ws,
+                                        None)
+
+    assert call(rho=float("nan")) == -1
+    assert call(sp=None) == -1 and call(ws=0x3000008) == -1
+    assert call(out=0x1000000 + mb - 16) == -1      # out overlaps sigma_smeared
+    assert call(ws=0x1000 + 64) == -1               # ws overlaps the links
+    f32 = _lib.StgGauge()
+    f32.links = 0x1000
+    f32.fmt = 2
+    assert call(gauge=f32) == -1
