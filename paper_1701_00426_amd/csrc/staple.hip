@@ -636,7 +636,7 @@ __global__ __launch_bounds__(kStoutBlock) void stout_back1_kernel(StoutBackArgs 
         }
 }
 
-// Pass 2, one thread per link l = (nu, y): add rho times every product in which l
+// Pass 2, two threads per link l = (nu, y): add rho times every product in which l
 // stands in a 3-link path of C at a neighbouring link (gc = U^dag G from pass 1):
 // for each direction b != nu,
 //   l as the middle link:  U_b(y-b+nu)^dag gc(nu, y-b) U_b(y-b),
@@ -646,67 +646,91 @@ __global__ __launch_bounds__(kStoutBlock) void stout_back1_kernel(StoutBackArgs 
 //                          [U_b(y) U_nu(y+b) gc(b, y+nu)]^dag,
 //                          gc(b, y+nu-b) U_nu(y-b)^dag U_b(y-b).
 template <int FMT>
-__global__ __launch_bounds__(kStoutBlock) void stout_back2_kernel(StoutBackArgs a) {
+__global__ __launch_bounds__(2 * kStapleLinks) void stout_back2_kernel(StoutBackArgs a) {
+    // two waves over the same kStapleLinks links: wave 0 sums the first three products
+    // of each direction, wave 1 the last three; wave 1's sums meet wave 0's in LDS
+    __shared__ cpx<double> part[9][kStapleLinks];
     const Geom &g = a.geom;
     const uint32_t blk = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
     const int slot = (int)(blk % 8);
-    const uint32_t j = (blk / 8) * kStoutBlock + threadIdx.x;
-    if (j >= g.Vh) return;
-    const uint32_t h = pencil_site(g, a.tile, j);
+    const int q = (int)threadIdx.x / kStapleLinks;  // the same in a whole wave
+    const int l = (int)threadIdx.x % kStapleLinks;
+    const uint32_t j = (blk / 8) * kStapleLinks + l;
+    const bool valid = j < g.Vh;
+    const uint32_t h = valid ? pencil_site(g, a.tile, j) : 0;
     const int nu = slot >> 1, P = slot & 1;
-    const Site s = site_coords(g, P, h);
-    const int st[4] = {1, (int)g.N[0], (int)(g.N[0] * g.N[1]), (int)(g.N[0] * g.N[1] * g.N[2])};
-    const int L = (int)s.x[0] + st[1] * (int)s.x[1] + st[2] * (int)s.x[2] + st[3] * (int)s.x[3];
-    const LinkAt<double, FMT> U{a.links, g.Vh, L, P};
-    const LinkAt<double, FMT_C128_18> W{a.ws, g.Vh, L, P};
-    const int xv = (int)pick4(s.x[0], s.x[1], s.x[2], s.x[3], nu);
-    const int nv = (int)pick4(g.N[0], g.N[1], g.N[2], g.N[3], nu);
-    const int sv = (int)pick4(st[0], st[1], st[2], st[3], nu);
-    const int vp1 = lex_step(xv, 1, nv, sv);
     su3<double> acc;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int k = 0; k < 3; ++k) acc.e[i][k] = {0.0, 0.0};
+    if (valid) {
+        const Site s = site_coords(g, P, h);
+        const int st[4] = {1, (int)g.N[0], (int)(g.N[0] * g.N[1]),
+                           (int)(g.N[0] * g.N[1] * g.N[2])};
+        const int L = (int)s.x[0] + st[1] * (int)s.x[1] + st[2] * (int)s.x[2] +
+                      st[3] * (int)s.x[3];
+        const LinkAt<double, FMT> U{a.links, g.Vh, L, P};
+        const LinkAt<double, FMT_C128_18> W{a.ws, g.Vh, L, P};
+        const int xv = (int)pick4(s.x[0], s.x[1], s.x[2], s.x[3], nu);
+        const int nv = (int)pick4(g.N[0], g.N[1], g.N[2], g.N[3], nu);
+        const int sv = (int)pick4(st[0], st[1], st[2], st[3], nu);
+        const int vp1 = lex_step(xv, 1, nv, sv);
 #pragma unroll 1
-    for (int k = 1; k < 4; ++k) {
-        const int b = (nu + k) & 3;
-        const int xb = (int)pick4(s.x[0], s.x[1], s.x[2], s.x[3], b);
-        const int nb = (int)pick4(g.N[0], g.N[1], g.N[2], g.N[3], b);
-        const int sb = (int)pick4(st[0], st[1], st[2], st[3], b);
-        const int bp1 = lex_step(xb, 1, nb, sb), bm1 = lex_step(xb, -1, nb, sb);
-        // middle link
-        mm_acc(acc, mdm(U(b, bm1 + vp1, 0), W(nu, bm1, 1)), U(b, bm1, 1));
-        mmd_acc(acc, mm(U(b, vp1, 1), W(nu, bp1, 1)), U(b, 0, 0));
-        // side link, forward: U_b(y+nu) U_nu(y+b)^dag gc(b, y)
-        mm_acc(acc, mmd(U(b, vp1, 1), U(nu, bp1, 1)), W(b, 0, 0));
-        // side link, forward: gc(b, y+nu-b) U_nu(y-b)^dag U_b(y-b)
-        mm_acc(acc, mmd(W(b, vp1 + bm1, 0), U(nu, bm1, 1)), U(b, bm1, 1));
-        // side links walked backwards: add the daggers, one product at a time
-        {
-            const su3<double> t4 = mm(mm(W(b, bm1, 1), U(nu, bm1, 1)), U(b, bm1 + vp1, 0));
+        for (int k = 1; k < 4; ++k) {
+            const int b = (nu + k) & 3;
+            const int xb = (int)pick4(s.x[0], s.x[1], s.x[2], s.x[3], b);
+            const int nb = (int)pick4(g.N[0], g.N[1], g.N[2], g.N[3], b);
+            const int sb = (int)pick4(st[0], st[1], st[2], st[3], b);
+            const int bp1 = lex_step(xb, 1, nb, sb), bm1 = lex_step(xb, -1, nb, sb);
+            if (q == 0) {
+                // middle link
+                mm_acc(acc, mdm(U(b, bm1 + vp1, 0), W(nu, bm1, 1)), U(b, bm1, 1));
+                mmd_acc(acc, mm(U(b, vp1, 1), W(nu, bp1, 1)), U(b, 0, 0));
+                // side link, forward: U_b(y+nu) U_nu(y+b)^dag gc(b, y)
+                mm_acc(acc, mmd(U(b, vp1, 1), U(nu, bp1, 1)), W(b, 0, 0));
+            } else {
+                // side link, forward: gc(b, y+nu-b) U_nu(y-b)^dag U_b(y-b)
+                mm_acc(acc, mmd(W(b, vp1 + bm1, 0), U(nu, bm1, 1)), U(b, bm1, 1));
+                // side links walked backwards: add the daggers, one product at a time
+                {
+                    const su3<double> t4 =
+                        mm(mm(W(b, bm1, 1), U(nu, bm1, 1)), U(b, bm1 + vp1, 0));
 #pragma unroll
-            for (int i = 0; i < 3; ++i)
+                    for (int i = 0; i < 3; ++i)
 #pragma unroll
-                for (int q = 0; q < 3; ++q) acc.e[i][q] = cadd(acc.e[i][q], cconj(t4.e[q][i]));
-        }
-        {
-            const su3<double> t5 = mm(mm(U(b, 0, 0), U(nu, bp1, 1)), W(b, vp1, 1));
+                        for (int c = 0; c < 3; ++c)
+                            acc.e[i][c] = cadd(acc.e[i][c], cconj(t4.e[c][i]));
+                }
+                {
+                    const su3<double> t5 = mm(mm(U(b, 0, 0), U(nu, bp1, 1)), W(b, vp1, 1));
 #pragma unroll
-            for (int i = 0; i < 3; ++i)
+                    for (int i = 0; i < 3; ++i)
 #pragma unroll
-                for (int q = 0; q < 3; ++q) acc.e[i][q] = cadd(acc.e[i][q], cconj(t5.e[q][i]));
+                        for (int c = 0; c < 3; ++c)
+                            acc.e[i][c] = cadd(acc.e[i][c], cconj(t5.e[c][i]));
+                }
+            }
         }
     }
+    if (q == 1) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) part[i * 3 + k][l] = acc.e[i][k];
+    }
+    __syncthreads();
+    if (q == 1 || !valid) return;
     const size_t base = (size_t)slot * 9 * g.Vh + h;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const size_t idx = base + (size_t)(i * 3 + k) * g.Vh;
+            const cpx<double> w1 = part[i * 3 + k][l];
             cpx<double> v = ld_c<double>(a.out, idx);
-            v.re = fmat(a.rho, acc.e[i][k].re, v.re);
-            v.im = fmat(a.rho, acc.e[i][k].im, v.im);
+            v.re = fmat(a.rho, acc.e[i][k].re + w1.re, v.re);
+            v.im = fmat(a.rho, acc.e[i][k].im + w1.im, v.im);
             st_c<double>(a.out, idx, v);
         }
 }
@@ -846,14 +870,15 @@ __global__ __launch_bounds__(kStoutBlock) void link_update_kernel(LinkUpdateArgs
 
 int launch_stout_backprop(const StoutBackArgs &a, int fmt, hipStream_t stream) {
     const dim3 grid(stout_blocks(a.geom.Vh));
+    const dim3 grid2(staple_blocks(a.geom.Vh));  // kStapleLinks links per block, two waves
     switch (fmt) {
         case FMT_C128_18:
             stout_back1_kernel<FMT_C128_18><<<grid, kStoutBlock, 0, stream>>>(a);
-            stout_back2_kernel<FMT_C128_18><<<grid, kStoutBlock, 0, stream>>>(a);
+            stout_back2_kernel<FMT_C128_18><<<grid2, 2 * kStapleLinks, 0, stream>>>(a);
             return 0;
         case FMT_C128_12:
             stout_back1_kernel<FMT_C128_12><<<grid, kStoutBlock, 0, stream>>>(a);
-            stout_back2_kernel<FMT_C128_12><<<grid, kStoutBlock, 0, stream>>>(a);
+            stout_back2_kernel<FMT_C128_12><<<grid2, 2 * kStapleLinks, 0, stream>>>(a);
             return 0;
         default: return -1;
     }
