@@ -139,9 +139,10 @@ const char *stg_last_error(void);
  *     directions of a site are shared by that many threads, whose partial sums
  *     meet in LDS (with 2 or 4, sites per thread and staging do not apply; 4 is
  *     not built for FP64 links with 8 fields per launch, which then take one
- *     thread per site).  Automatic: by link format, fields per launch and
- *     epilogue (one field: 1, or 4 for the plain BF16-12 hop; two to four
- *     fields: 4; eight fields: 4 for the plain FP32 / BF16 hop, else 2).  An
+ *     thread per site).  Automatic: by link format, fields per launch, epilogue
+ *     and size (one field: 4 when Vh < 16384, else 1, or 4 for the plain BF16-12
+ *     hop; two to four fields: 4; eight fields: 4 for the plain FP32 / BF16 hop,
+ *     else 2).  An
  *     autotuned shape sets it for the plain hop only.  The choice changes the
  *     order of floating-point additions, so results may differ in the last bits
  *     between choices (each choice is deterministic).

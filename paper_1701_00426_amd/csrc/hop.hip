@@ -140,7 +140,8 @@ static int launch_ph(const HopArgs &a, int nr, int epi, hipStream_t stream) {
 int launch_hop(const HopArgs &a, int fmt, int nr, int epi, hipStream_t stream) {
     // several threads per site where that variant is built, else one
     const uint32_t tps = a.threads_per_site ? a.threads_per_site
-                                            : (uint32_t)default_threads_per_site(fmt, nr, epi);
+                                            : (uint32_t)default_threads_per_site(fmt, nr, epi,
+                                                                                 a.geom.Vh);
     if (tps > 1) {
         HopArgs b = a;
         b.threads_per_site = tps;

@@ -122,10 +122,19 @@ int launch_hop_split(const HopArgs &a, int fmt, int nr, int epi, hipStream_t str
 // and the profiled FP64-12 configuration), except the plain BF16-12 hop (4: 5 %
 // faster); two to four fields: 4; eight fields: 4 for the plain FP32 / BF16 hop,
 // else 2 (group 0 runs the whole epilogue, which for 8 fields costs more than the
-// extra waves gain, and FP64 at 4 would need 72 KB of LDS per block).
-inline int default_threads_per_site(int fmt, int nr, int epi) {
+// extra waves gain, and FP64 at 4 would need 72 KB of LDS per block).  Small
+// lattices (Vh below kSmallSites: a one-thread launch fills under a quarter of the
+// chip's CUs) take 4 threads per site for one field too: the launch is latency-bound
+// there and the shorter per-thread chains win (8^4 FP64 CG: 26.4 -> 21.9 us per
+// iteration).
+constexpr uint32_t kSmallSites = 16384;
+
+inline int default_threads_per_site(int fmt, int nr, int epi, uint32_t Vh) {
     const bool fp64 = fmt == FMT_C128_18 || fmt == FMT_C128_12;
-    if (nr == 1) return (epi == EPI_PLAIN && fmt == FMT_BF16_12) ? 4 : 1;
+    if (nr == 1) {
+        if (Vh < kSmallSites) return 4;
+        return (epi == EPI_PLAIN && fmt == FMT_BF16_12) ? 4 : 1;
+    }
     if (nr <= 4) return 4;
     return (epi == EPI_PLAIN && !fp64) ? 4 : 2;
 }
