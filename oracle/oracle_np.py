@@ -794,3 +794,67 @@ def stout_backprop(dims, links, rho, sig_p):
                             out[2 * d + p2][:, :, hh[sel]] += contrib[:, :, sel]
                         y = after
     return out
+
+
+def stout_backprop_at(dims, links, rho, sig_p, slot: int, hs):
+    """dS/dU of the thin links of one slot at half indices hs only, (3, 3, n): the
+    chain rule of ``stout_backprop`` organised per output link, for spot checks on
+    large lattices.  The link's own terms are Sigma' exp(iQ) + C^dag G^dag.  The
+    terms through C come from the 3-link paths of other links l' = (mu, x) that walk
+    across this link: 6 paths along the link's own direction (it is their middle
+    step) and 12 from links of the other directions (it is their first or last
+    step, either way); each gives rho * (product after it) (U^dag G at l')
+    (product before it), daggered where the path walks the link backwards."""
+    from scipy.linalg import expm_frechet
+    d, parity = slot // 2, slot % 2
+    hs = np.asarray(hs, dtype=np.int64)
+    z = coords(dims, parity)[:, hs]
+    eye = np.eye(3)
+
+    def terms_at(mu, x):
+        """exp(iQ), G, C, U and Sigma' of the links (mu, x), each (3, 3, n)."""
+        c = np.zeros((3, 3, x.shape[1]), dtype=np.complex128)
+        for nu in range(4):
+            if nu != mu:
+                c += path_product(dims, links, x, [(nu, 1), (mu, 1), (nu, -1)])
+                c += path_product(dims, links, x, [(nu, -1), (mu, 1), (nu, 1)])
+        c *= rho
+        u = link_matrices(dims, links, x, mu)
+        sp = np.transpose(sig_p[2 * mu + site_parity(x), :, :, half_index(dims, x)], (1, 2, 0))
+        e, g = np.empty_like(u), np.empty_like(u)
+        for i in range(x.shape[1]):
+            om = c[:, :, i] @ np.conj(u[:, :, i].T)
+            a = np.conj(om.T) - om
+            q = 0.5j * a - (1j / 6.0) * np.trace(a) * eye
+            e[:, :, i], gam = expm_frechet(1j * q, u[:, :, i] @ sp[:, :, i])
+            tg = np.trace(gam)
+            g[:, :, i] = 0.5 * (gam - np.conj(gam.T)) + ((np.conj(tg) - tg) / 6.0) * eye
+        return e, g, c, u, sp
+
+    e, g, c, u, sp = terms_at(d, z)
+    out = np.einsum("abn,bcn->acn", sp, e) + np.einsum(
+        "ban,cbn->acn", np.conj(c), np.conj(g))
+    for mu in range(4):
+        for al in range(4):
+            if al == mu:
+                continue
+            for steps in ([(al, 1), (mu, 1), (al, -1)], [(al, -1), (mu, 1), (al, 1)]):
+                for k, (dk, sk) in enumerate(steps):
+                    if dk != d:
+                        continue
+                    # the site x of the path's own link: walking steps[:k] from x
+                    # reaches y, and the link crossed next is (d, y) going forward,
+                    # (d, y - d) going backward; either must be (d, z)
+                    x = z if sk > 0 else shifted(dims, z, d, +1)
+                    for dj, sj in reversed(steps[:k]):
+                        x = shifted(dims, x, dj, -sj)
+                    _, gl, _, ul, _ = terms_at(mu, x)
+                    gc = np.einsum("ban,bcn->acn", np.conj(ul), gl)
+                    before = path_product(dims, links, x, steps[:k])
+                    after = shifted(dims, z, d, +1) if sk > 0 else z
+                    rest = path_product(dims, links, after, steps[k + 1:])
+                    contrib = rho * np.einsum("abn,bcn,cdn->adn", rest, gc, before)
+                    if sk < 0:
+                        contrib = np.conj(np.transpose(contrib, (1, 0, 2)))
+                    out += contrib
+    return out

@@ -71,3 +71,27 @@ def test_stout_backprop_two_levels():
     err = float(np.max(np.abs(s0.cpu().numpy() - want)) / np.max(np.abs(want)))
     say(f"stout backprop two levels: rel max err {err:.2e}")
     assert err <= 1e-12
+
+
+def test_stout_backprop_32_4_sampled():
+    """32^4 (the size the benchmark times), FP64-12 thin links: every slot, sampled
+    links including both ends of the half-index range, against the oracle link by
+    link."""
+    dims, rho = (32, 32, 32, 32), 0.15
+    say("generating 32^4 links and dS/dU'")
+    links = si.su3_links(dims, 1701, 124, 0)
+    sp = _complex_field(dims, 125, 0)
+    gauge = stg.pack_gauge(dims, to_dev(links), "c128_12")
+    got = stg.stout_force_backprop(gauge, rho, to_dev(sp))
+    torch.cuda.synchronize()
+    vh = on.half_volume(dims)
+    pick = np.concatenate([[0, 1, vh - 1], si.rng(126, 0).integers(0, vh, size=24)])
+    idx = torch.from_numpy(pick).to(got.device)
+    stored = _as_stored(links, "c128_12")
+    err, scale = 0.0, 0.0
+    for slot in range(8):
+        want = on.stout_backprop_at(dims, stored, rho, sp, slot, pick)
+        err = max(err, float(np.max(np.abs(got[slot][:, :, idx].cpu().numpy() - want))))
+        scale = max(scale, float(np.max(np.abs(want))))
+    say(f"stout backprop 32^4 sampled: rel max err {err / scale:.2e} over {8 * len(pick)} links")
+    assert err <= 1e-12 * scale

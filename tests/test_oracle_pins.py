@@ -495,3 +495,18 @@ def test_stout_backprop_gauge_covariance():
     s0 = on.stout_backprop(dims, links, rho, m)
     s1 = on.stout_backprop(dims, on.gauge_transform_links(dims, links, *g), rho, tr_ends(m))
     assert np.max(np.abs(s1 - tr_ends(s0))) <= 1e-12 * np.max(np.abs(s0))
+
+
+def test_stout_backprop_at_matches_whole_lattice():
+    """The per-link form of the chain rule (for spot checks at 32^4) against the whole
+    lattice one, at links of every slot, including lattices with extents of 2 where a
+    3-link path crosses the same link twice."""
+    for dims in ((4, 4, 2, 6), (2, 4, 4, 2)):
+        links = si.su3_links(dims, 114, 0)
+        m = _complex_field(dims, 114, 1)
+        full = on.stout_backprop(dims, links, 0.15, m)
+        vh = on.half_volume(dims)
+        hs = [0, 5, vh // 2, vh - 1]
+        for slot in range(8):
+            part = on.stout_backprop_at(dims, links, 0.15, m, slot, hs)
+            assert np.max(np.abs(part - full[slot][:, :, hs])) <= 1e-13 * np.max(np.abs(full))
