@@ -50,11 +50,13 @@ def test_force_parity(dims, n, fmt, std_phases):
 
 
 def test_force_32_4_sampled():
-    dims, n = (32, 32, 32, 32), 4
+    """32^4 with 16 poles, the configuration the benchmark times (the Y hops run
+    as two 8-field launches)."""
+    dims, n = (32, 32, 32, 32), 16
     say("generating 32^4 links and solutions")
     links = si.su3_links(dims, 1701, 63, 0)
     ph = on.standard_phases(dims)
-    coeffs = [0.25, 1.5, -0.75, 0.1]
+    coeffs = list(si.rng(63, 1).uniform(-1.0, 2.0, size=n))
     xs = si.gaussian_field(dims, n, 64, 0)
     gauge = stg.pack_gauge(dims, to_dev(links), "c128_12")
     g, y = stg.fermion_force(gauge, coeffs, to_dev(xs))
