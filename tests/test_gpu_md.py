@@ -196,3 +196,48 @@ def test_link_update_fp32():
     err = float(np.max(np.abs(got.astype(np.complex128) - want)))
     say(f"link update FP32: max abs err {err:.2e}")
     assert err <= 32 * U24
+
+
+@pytest.mark.parametrize("fmt", ["c128_12", "c64_12"])
+def test_md_step_32_4_sampled(fmt):
+    """One step as the benchmark times it at 32^4 (beta 5.5, eps 0.01, FP64-12 with
+    complex128 momenta or FP32-12 with complex64 ones): the momentum update from
+    nonzero momenta, then the link update with the new momenta; sampled links of every
+    slot against the oracle link by link."""
+    dims, beta, eps = (32, 32, 32, 32), 5.5, 0.01
+    say(f"generating 32^4 links and momenta ({fmt})")
+    links = si.su3_links(dims, 1701, 107, 0)
+    mom = si.traceless_hermitian_field(dims, 108, 0)
+    vh = on.half_volume(dims)
+    fp64 = fmt == "c128_12"
+    if not fp64:
+        mom = mom.astype(np.complex64).astype(np.complex128)
+    stored = _as_stored(links, fmt) if fp64 else _as_stored_c64(links)
+    gauge = stg.pack_gauge(dims, to_dev(links), fmt)
+    p = to_dev(mom if fp64 else mom.astype(np.complex64))
+    stg.gauge_momentum_update(gauge, p, beta, eps)
+    stg.gauge_link_update(gauge, p, eps)
+    torch.cuda.synchronize()
+    pick = np.concatenate([[0, 1, vh - 1], si.rng(109, 0).integers(0, vh, size=24)])
+    idx = torch.from_numpy(pick).to(p.device)
+    if fp64:
+        u_now = gauge.links.cpu().numpy().view(np.complex128).reshape(8, 2, 3, vh)
+        ptol = _mom_tol(beta, eps)
+        utol = 1e-13 + abs(eps) * 3 * ptol
+    else:
+        u_now = gauge.links.cpu().numpy().view(np.complex64).reshape(8, 3, vh, 2)
+        u_now = np.transpose(u_now, (0, 1, 3, 2)).reshape(8, 2, 3, vh)
+        ptol = 64 * U24 * ((beta / 3.0) * 8.5 * eps + float(np.max(np.abs(mom))))
+        utol = 32 * U24 + abs(eps) * 3 * ptol
+    ep = eu = 0.0
+    for slot in range(8):
+        sig = on.staples_at(dims, stored, slot, pick)
+        m = np.einsum("abn,bcn->acn", stored[slot][:, :, pick], sig)
+        p1 = mom[slot][:, :, pick] + eps * (beta / 3.0) * on.traceless_hermitian(1j * m)
+        u1 = on.link_update(stored[slot][None, :, :, pick], p1[None], eps)[0]
+        got_p = p[slot][:, :, idx].cpu().numpy().astype(np.complex128)
+        ep = max(ep, float(np.max(np.abs(got_p - p1))))
+        eu = max(eu, float(np.max(np.abs(u_now[slot][:, :, pick].astype(np.complex128) - u1[:2]))))
+    say(f"MD step 32^4 {fmt}: momenta max abs err {ep:.2e} (tol {ptol:.1e}), links {eu:.2e} "
+        f"(tol {utol:.1e})")
+    assert ep <= ptol and eu <= utol
