@@ -95,3 +95,26 @@ def test_stout_backprop_32_4_sampled():
         scale = max(scale, float(np.max(np.abs(want))))
     say(f"stout backprop 32^4 sampled: rel max err {err / scale:.2e} over {8 * len(pick)} links")
     assert err <= 1e-12 * scale
+
+
+def test_smeared_fermion_force_chain():
+    """The fermion force on stout-smeared links as a composition of library calls:
+    stout_smear, fermion_force on the smeared links, then stout_force_backprop with
+    the thin links, against the oracle's chain (the oracle pins this composition by
+    central differences of the smeared rational action)."""
+    dims, rho = (4, 6, 2, 4), 0.12
+    coeffs = [0.4, 0.8, -0.2]
+    links = si.su3_links(dims, 1701, 127, 0)
+    xs = si.gaussian_field(dims, len(coeffs), 128, 0)
+    g0 = stg.pack_gauge(dims, to_dev(links), "c128_18")
+    g1 = stg.pack_gauge(dims, stg.stout_smear(g0, rho), "c128_18")
+    gp, _ = stg.fermion_force(g1, coeffs, to_dev(xs))
+    got = stg.stout_force_backprop(g0, rho, gp)
+    torch.cuda.synchronize()
+    ph = on.standard_phases(dims)
+    sm = on.stout_smear(dims, links, rho)
+    gp_want = on.force_from_solutions(dims, ph, coeffs, xs, on.d_oe(dims, sm, ph, xs))
+    want = on.stout_backprop(dims, links, rho, gp_want)
+    err = float(np.max(np.abs(got.cpu().numpy() - want)) / np.max(np.abs(want)))
+    say(f"smeared fermion force chain: rel max err {err:.2e}")
+    assert err <= 1e-12

@@ -510,3 +510,47 @@ def test_stout_backprop_at_matches_whole_lattice():
         for slot in range(8):
             part = on.stout_backprop_at(dims, links, 0.15, m, slot, hs)
             assert np.max(np.abs(part - full[slot][:, :, hs])) <= 1e-13 * np.max(np.abs(full))
+
+
+def test_smeared_fermion_force_is_the_derivative():
+    """The force of the rational action on stout-smeared links, S(U) = Re phi^dag
+    sum_k a_k (A(U') + sigma_k)^-1 phi with U' = exp(iQ) U: the thin-link fermion force
+    on U' passed through the stout chain rule must equal the central differences of S
+    (dense solves) in all 18 directions of one link per slot.  This fixes that the two
+    pieces share one convention (dS = Re Tr(dU G)) and compose."""
+    dims, rho, eps = (2, 2, 2, 4), 0.12, 1e-6
+    links = si.su3_links(dims, 115, 0)
+    ph = on.standard_phases(dims)
+    mass, shifts, coeffs = 0.3, [0.0, 0.05, 0.5], [0.4, 0.8, -0.2]
+    phi = si.gaussian_field(dims, 1, 115, 1)[0]
+
+    def solver(lk):
+        _, deo, doe, _ = on.dense_blocks(dims, lk, ph)
+        a = mass * mass * np.eye(deo.shape[0]) - deo @ doe
+        return lambda sig, b: np.linalg.solve(a + sig * np.eye(a.shape[0]),
+                                              b.reshape(-1)).reshape(3, -1)
+
+    smeared = on.stout_smear(dims, links, rho)
+    sol = solver(smeared)
+    xs = np.array([sol(s, phi) for s in shifts])
+    ys = np.array([on.d_oe(dims, smeared, ph, x) for x in xs])
+    sig = on.stout_backprop(dims, links, rho, on.force_from_solutions(dims, ph, coeffs, xs, ys))
+
+    def f(lk):
+        sm = on.stout_smear(dims, lk, rho)
+        return on.rational_action(dims, sm, ph, mass, shifts, coeffs, phi, solve=solver(sm))
+
+    for slot in range(8):
+        h = (3 * slot + 1) % on.half_volume(dims)
+        got = np.empty((3, 3), dtype=np.complex128)
+        for a in range(3):
+            for b in range(3):
+                d = []
+                for e in (1.0, 1j):
+                    plus = links.copy()
+                    plus[slot, a, b, h] += eps * e
+                    minus = links.copy()
+                    minus[slot, a, b, h] -= eps * e
+                    d.append((f(plus) - f(minus)) / (2 * eps))
+                got[b, a] = d[0] - 1j * d[1]
+        assert np.max(np.abs(got - sig[slot, :, :, h])) <= 1e-6 * np.max(np.abs(sig[slot, :, :, h]))
