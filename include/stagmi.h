@@ -157,6 +157,11 @@ const char *stg_last_error(void);
  *     (T0, T1, T2) are 0: 32x2x4, 1: 32x4x2, 2: 16x4x4, 3: 16x8x4, 4: 8x8x8,
  *     5: 32x8x2 (each extent the largest divisor of the lattice's within its cap).
  *     Only the speed depends on it.
+ *   STG_TUNE_FIELDS_PER_LAUNCH: 0 (default: the autotuner's choice for the lattice
+ *     and link format, else 8), 1, 2, 4 or 8: the most fields one hop launch takes
+ *     when a call works on several (dirac_apply_*, stg_apply_normal, fermion_force,
+ *     the solvers); more fields share each link read, fewer keep fewer registers and
+ *     partial sums per thread.  Only the speed depends on it.
  * Returns STG_INVALID_ARG for an unknown key or value.
  */
 enum {
@@ -165,7 +170,8 @@ enum {
     STG_TUNE_STAGE_NEIGHBOURS = 2,
     STG_TUNE_THREADS_PER_SITE = 3,
     STG_TUNE_STAPLE_THREADS = 4,
-    STG_TUNE_PENCIL_TILE = 5
+    STG_TUNE_PENCIL_TILE = 5,
+    STG_TUNE_FIELDS_PER_LAUNCH = 6
 };
 int stg_set_tuning(int key, int value);
 int stg_get_tuning(int key, int *value);
@@ -181,10 +187,17 @@ int stg_get_tuning(int key, int *value);
  * the key (lattice extents, gauge format, fields per launch = the largest chunk
  * of nrhs among 8, 4, 3, 2, 1) in a process-wide table that every later hop launch
  * with that key uses, and, when cache_path is not NULL, appends it to that file as
- * one JSON object per line.  Synchronous.  stg_autotune_load reads such a file
- * into the table (later lines win) and reports the entries read in *loaded.
- * stg_autotune_lookup returns STG_OK and the stored choice, or STG_NOT_CONVERGED
- * when the key has no entry.  stg_autotune_clear empties the table.
+ * one JSON object per line.  With nrhs >= 2 it then times D_eo of all nrhs fields
+ * chunked at most 8, 4, 2 or 1 fields per launch (the RHS per block; each chunk in
+ * its stored or default shape) and keeps, per (lattice extents, gauge format), the
+ * cap with the least time per field: every later multi-field hop, normal-operator
+ * apply and solver on that lattice and format chunks its fields by it (unless
+ * STG_TUNE_FIELDS_PER_LAUNCH is set), and it is appended to the cache file too.
+ * Synchronous.  stg_autotune_load reads such a file into the tables (later lines
+ * win) and reports the entries read in *loaded.  stg_autotune_lookup returns STG_OK
+ * and the stored shape, stg_autotune_fields_lookup the stored fields per launch, or
+ * STG_NOT_CONVERGED when the key has no entry.  stg_autotune_clear empties both
+ * tables.
  */
 int stg_autotune(const stg_lattice *lat, const stg_gauge *gauge, stg_field field, int nrhs,
                  const void *in, void *out, const char *cache_path, stg_stream_t stream);
@@ -198,6 +211,7 @@ typedef struct {
 } stg_tune_choice;
 int stg_autotune_lookup(const stg_lattice *lat, stg_link_fmt fmt, int nr,
                         stg_tune_choice *choice);
+int stg_autotune_fields_lookup(const stg_lattice *lat, stg_link_fmt fmt, int *fields_per_launch);
 void stg_autotune_clear(void);
 
 /* Bytes of a gauge field of format fmt on lattice lat, written to *bytes (host). */

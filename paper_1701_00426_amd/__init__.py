@@ -32,7 +32,7 @@ __all__ = [
     "dirac_apply_eo", "dirac_apply_oe", "stg_apply_normal", "stg_dot", "cg_solve",
     "multishift_cg_solve", "stg_workspace_bytes", "library", "stg_set_tuning", "stg_get_tuning",
     "cg_solve_batch", "rational_apply", "stg_rational_workspace_bytes", "stg_autotune",
-    "stg_autotune_load", "stg_autotune_lookup", "gauge_staples", "SYMANZIK_C0", "SYMANZIK_C1",
+    "stg_autotune_load", "stg_autotune_lookup", "stg_autotune_fields_lookup", "gauge_staples", "SYMANZIK_C0", "SYMANZIK_C1",
     "fermion_force", "stout_smear", "gauge_momentum_update", "gauge_link_update",
     "stout_force_backprop",
 ]
@@ -531,7 +531,10 @@ def stg_autotune(gauge: Gauge, nrhs: int = 1, cache_path: Optional[str] = None, 
         ctypes.byref(_lib.lattice(gauge.dims)), ctypes.byref(g), int(gauge.field), int(nrhs),
         _ptr(vin), _ptr(out), cache_path.encode() if cache_path else None, _stream(stream)))
     nr = 8 if nrhs >= 8 else 4 if nrhs >= 4 else nrhs
-    return stg_autotune_lookup(gauge.dims, gauge.fmt, nr)
+    choice = stg_autotune_lookup(gauge.dims, gauge.fmt, nr)
+    if nrhs >= 2:
+        choice["fields_per_launch"] = stg_autotune_fields_lookup(gauge.dims, gauge.fmt)
+    return choice
 
 
 def stg_autotune_load(cache_path: str) -> int:
@@ -539,6 +542,17 @@ def stg_autotune_load(cache_path: str) -> int:
     _lib.check("stg_autotune_load", library().stg_autotune_load(cache_path.encode(),
                                                                 ctypes.byref(n)))
     return n.value
+
+
+def stg_autotune_fields_lookup(dims, fmt):
+    """The stored fields per launch (1, 2, 4 or 8) for (dims, fmt), or None."""
+    v = ctypes.c_int(0)
+    st = library().stg_autotune_fields_lookup(ctypes.byref(_lib.lattice(dims)), int(fmt),
+                                              ctypes.byref(v))
+    if st == _lib.STG_NOT_CONVERGED:
+        return None
+    _lib.check("stg_autotune_fields_lookup", st)
+    return v.value
 
 
 def stg_autotune_lookup(dims, fmt, nr: int = 1):

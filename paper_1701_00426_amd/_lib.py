@@ -35,6 +35,7 @@ STG_TUNE_STAGE_NEIGHBOURS = 2
 STG_TUNE_THREADS_PER_SITE = 3
 STG_TUNE_STAPLE_THREADS = 4
 STG_TUNE_PENCIL_TILE = 5
+STG_TUNE_FIELDS_PER_LAUNCH = 6
 
 # solver modes
 STG_CG_F64 = 0
@@ -95,6 +96,7 @@ SIGNATURES = {
     "stg_autotune": (_I, [_LAT, _G, _I, _I, _P, _P, ctypes.c_char_p, _P]),
     "stg_autotune_load": (_I, [ctypes.c_char_p, ctypes.POINTER(_I)]),
     "stg_autotune_lookup": (_I, [_LAT, _I, _I, ctypes.POINTER(StgTuneChoice)]),
+    "stg_autotune_fields_lookup": (_I, [_LAT, _I, ctypes.POINTER(ctypes.c_int)]),
     "stg_autotune_clear": (None, []),
     "stg_links_bytes": (_I, [_LAT, _I, ctypes.POINTER(_S)]),
     "stg_pack_links": (_I, [_LAT, _P, _I, _P, _P]),

@@ -37,6 +37,7 @@ int g_stage_neighbours = 0;
 int g_threads_per_site = 0;  // 0: by format and fields
 int g_staple_threads = 0;    // 0: by format
 int g_pencil_tile = 0;       // tile shape of the pencil order (pencil.hpp)
+int g_fields_per_launch = 0; // 0: the autotuned choice for the lattice and format, else 8
 
 int hip_fail(hipError_t e, const char *what) {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
@@ -150,11 +151,20 @@ int hop(HopArgs a, int fmt, int nr, int epi, hipStream_t stream) {
 }
 
 // Largest supported chunk of fields for one kernel launch (8, 4, 3, 2 or 1: each
-// launch reads the links once for all its fields).
-int chunk_of(int remaining) {
-    if (remaining >= 8) return 8;
-    if (remaining >= 4) return 4;
-    return remaining;
+// launch reads the links once for all its fields), at most cap (1, 2, 4 or 8).
+int chunk_of(int remaining, int cap = 8) {
+    const int c = std::min(remaining, cap);
+    if (c >= 8) return 8;
+    if (c >= 4) return 4;
+    return c;
+}
+
+// Fields per launch for hops on this lattice and link format: the caller's setting,
+// else the autotuner's choice, else 8.
+int field_cap(const Geom &g, int fmt) {
+    if (g_fields_per_launch) return g_fields_per_launch;
+    int cap;
+    return fields_lookup(g, fmt, cap) ? cap : 8;
 }
 
 int hop_plain(const Geom &g, const stg_gauge *gauge, int field, int nrhs, const void *in,
@@ -163,8 +173,9 @@ int hop_plain(const Geom &g, const stg_gauge *gauge, int field, int nrhs, const 
     HopArgs a = base_hop(g, gauge);
     a.out_parity = out_parity;
     a.op = OP_NONE;
+    const int cap = field_cap(g, gauge->fmt);
     for (int j0 = 0; j0 < nrhs;) {
-        int nr = chunk_of(nrhs - j0);
+        int nr = chunk_of(nrhs - j0, cap);
         a.in = reinterpret_cast<const char *>(in) + j0 * fb;
         a.out = reinterpret_cast<char *>(out) + j0 * fb;
         if (hop(a, gauge->fmt, nr, EPI_PLAIN, stream)) return invalid("unsupported hop");
@@ -276,9 +287,10 @@ struct CgProblem {
     std::vector<double> diag;  // m^2 + sigma per system
     stg_cg_params prm;
     int group = 0;     // systems s share b[s % group] (multi-shift refinement); 0: group = nsys
+    int cap = 8;       // fields per launch (field_cap of the inner links)
     int chunk(int j0) const {
         const int g = group > 0 ? group : nsys;
-        return chunk_of(std::min(nsys - j0, g - j0 % g));
+        return chunk_of(std::min(nsys - j0, g - j0 % g), cap);
     }
     const void *b_at(int j0, size_t fb64) const {
         const int g = group > 0 ? group : nsys;
@@ -678,8 +690,9 @@ size_t ms_workspace(const Geom &g, int nrhs, int nshift, int mode) {
 int enqueue_ms_iteration(const Geom &g, const stg_gauge *gg, int f64, int nrhs, int nshift,
                          const MsWork &w, hipStream_t s) {
     const size_t fb = (size_t)3 * g.Vh * (f64 ? 16 : 8);
+    const int cap = field_cap(g, gg->fmt);
     for (int j0 = 0; j0 < nrhs;) {
-        const int nr = chunk_of(nrhs - j0);
+        const int nr = chunk_of(nrhs - j0, cap);
         const size_t o = j0 * fb;
         HopArgs a = base_hop(g, gg);
         a.gate_running = 1;
@@ -864,6 +877,7 @@ int run_mscg(const Geom &g, const stg_gauge *hi, const stg_gauge *lo, double mas
     P.b = b;
     P.x = x;
     P.group = nrhs;
+    P.cap = field_cap(g, mode == STG_CG_F64 ? hi->fmt : lo->fmt);
     P.diag.resize(P.nsys);
     for (int k = 0; k < nshift; ++k)
         for (int j = 0; j < nrhs; ++j) P.diag[(size_t)k * nrhs + j] = mass * mass + shifts[k];
@@ -1287,6 +1301,11 @@ int stg_set_tuning(int key, int value) {
                 return invalid("pencil tile takes 0 .. 5");
             g_pencil_tile = value;
             return STG_OK;
+        case STG_TUNE_FIELDS_PER_LAUNCH:
+            if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
+                return invalid("fields per launch takes 0 (automatic), 1, 2, 4 or 8");
+            g_fields_per_launch = value;
+            return STG_OK;
         default: return invalid("unknown tuning key");
     }
 }
@@ -1300,6 +1319,7 @@ int stg_get_tuning(int key, int *value) {
         case STG_TUNE_THREADS_PER_SITE: *value = g_threads_per_site; return STG_OK;
         case STG_TUNE_STAPLE_THREADS: *value = g_staple_threads; return STG_OK;
         case STG_TUNE_PENCIL_TILE: *value = g_pencil_tile; return STG_OK;
+        case STG_TUNE_FIELDS_PER_LAUNCH: *value = g_fields_per_launch; return STG_OK;
         default: return invalid("unknown tuning key");
     }
 }
@@ -1558,8 +1578,9 @@ int stg_apply_normal(const stg_lattice *lat, const stg_gauge *gauge, stg_field f
     a.out_parity = 0;
     a.op = OP_NONE;
     a.diag = mass * mass + sigma;
+    const int cap = field_cap(g, gauge->fmt);
     for (int j0 = 0; j0 < nrhs;) {
-        int nr = chunk_of(nrhs - j0);
+        int nr = chunk_of(nrhs - j0, cap);
         a.in = (const char *)tmp_odd + j0 * f1;
         a.out = (char *)out_even + j0 * f1;
         a.aux0 = (const char *)in_even + j0 * f1;
@@ -1641,6 +1662,7 @@ int cg_solve(const stg_lattice *lat, const stg_gauge *hi, const stg_gauge *lo, d
     P.b = b_even;
     P.x = x_even;
     P.diag.assign(nrhs, mass * mass);
+    P.cap = field_cap(g, mode == STG_CG_F64 ? hi->fmt : lo->fmt);
     P.prm = *params;
     CgWork w = carve_cg(g, nrhs, mode, ws);
     return run_cg(P, w, stats, (hipStream_t)stream);
@@ -1819,12 +1841,63 @@ int stg_autotune(const stg_lattice *lat, const stg_gauge *gauge, stg_field field
     TuneChoice best{1, 1, 0, 1, 1e300};
     for (const TuneChoice &c : cand)
         if (c.us < best.us) best = c;
+    if (rc2 == STG_OK) tune_store(g, gauge->fmt, nr, best);
+
+    // fields per launch: with several fields, time D_eo of all nrhs of them chunked
+    // at most 8, 4, 2 or 1 per launch (each chunk in its tuned or default shape) and
+    // keep the chunking with the least time per field
+    int best_cap = 0;
+    double best_us = 1e300;
+    if (rc2 == STG_OK && nrhs >= 2) {
+        const size_t f1 = (size_t)3 * g.Vh * field_elem(field);
+        HopArgs b = base_hop(g, gauge);
+        b.out_parity = 0;
+        b.op = OP_NONE;
+        auto apply_all = [&](int cap) {
+            for (int j0 = 0; j0 < nrhs;) {
+                const int c = chunk_of(nrhs - j0, cap);
+                b.in = (const char *)in + j0 * f1;
+                b.out = (char *)out + j0 * f1;
+                if (hop(b, gauge->fmt, c, EPI_PLAIN, s)) return false;
+                j0 += c;
+            }
+            return true;
+        };
+        const int caps[4] = {8, 4, 2, 1};
+        const int reps_all = std::max(3, reps * nr / nrhs);
+        for (int pass = 0; pass < 2 && rc2 == STG_OK; ++pass)
+            for (int ci = 0; ci < 4 && rc2 == STG_OK; ++ci) {
+                const int cap = caps[ci];
+                // a cap at or above the largest chunk of nrhs changes nothing
+                if (cap != 8 && cap >= nr) continue;
+                for (int w = 0; w < 2; ++w) apply_all(cap);
+                hipError_t e = hipEventRecord(e0, s);
+                for (int r = 0; r < reps_all && e == hipSuccess; ++r)
+                    if (!apply_all(cap)) e = hipErrorInvalidValue;
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) {
+                    rc2 = hip_fail(e, "autotune timing (fields per launch)");
+                    break;
+                }
+                const double us = 1e3 * ms / reps_all / nrhs;
+                if (us < best_us) {
+                    best_us = us;
+                    best_cap = cap;
+                }
+            }
+        if (rc2 == STG_OK) fields_store(g, gauge->fmt, best_cap);
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc2 != STG_OK) return rc2;
     HIP_TRY(hipGetLastError());
-    tune_store(g, gauge->fmt, nr, best);
     if (cache_path && tune_append_file(cache_path, g, gauge->fmt, nr, best))
+        return invalid("cannot append to the autotune cache file");
+    if (cache_path && best_cap &&
+        fields_append_file(cache_path, g, gauge->fmt, best_cap, best_us))
         return invalid("cannot append to the autotune cache file");
     return STG_OK;
 }
@@ -1848,6 +1921,16 @@ int stg_autotune_lookup(const stg_lattice *lat, stg_link_fmt fmt, int nr,
         choice->threads_per_site = c.threads_per_site;
         choice->us = c.us;
     }
+    return STG_OK;
+}
+
+int stg_autotune_fields_lookup(const stg_lattice *lat, stg_link_fmt fmt, int *fields_per_launch) {
+    Geom g;
+    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
+    if (!fields_per_launch) return invalid("fields_per_launch is NULL");
+    int cap;
+    if (!fields_lookup(g, fmt, cap)) return STG_NOT_CONVERGED;
+    *fields_per_launch = cap;
     return STG_OK;
 }
 

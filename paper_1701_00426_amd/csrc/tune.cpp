@@ -6,7 +6,10 @@
 // format, fields-per-launch) key the autotuner times every candidate shape on the
 // caller's buffers with HIP events, keeps the fastest in a process-wide table that
 // every hop launch consults, and appends it to a cache file (one JSON object per
-// line) that a later process can load.  Results never depend on the shape.
+// line) that a later process can load.  A second table holds, per (lattice, link
+// format), how many fields one launch takes at most (the RHS per block): the
+// chunking of several fields into launches with the least time per field.  Results
+// never depend on either choice.
 
 #include <hip/hip_runtime.h>
 
@@ -27,6 +30,7 @@ using Key = std::tuple<uint32_t, uint32_t, uint32_t, uint32_t, int, int>;
 
 std::mutex g_mu;
 std::map<Key, TuneChoice> g_table;
+std::map<Key, int> g_fields;  // key with nr = 0
 
 Key make_key(const Geom &g, int fmt, int nr) {
     return Key(g.N[0], g.N[1], g.N[2], g.N[3], fmt, nr);
@@ -47,9 +51,34 @@ void tune_store(const Geom &g, int fmt, int nr, const TuneChoice &c) {
     g_table[make_key(g, fmt, nr)] = c;
 }
 
+bool fields_lookup(const Geom &g, int fmt, int &cap) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_fields.find(make_key(g, fmt, 0));
+    if (it == g_fields.end()) return false;
+    cap = it->second;
+    return true;
+}
+
+void fields_store(const Geom &g, int fmt, int cap) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_fields[make_key(g, fmt, 0)] = cap;
+}
+
 void tune_clear() {
     std::lock_guard<std::mutex> lk(g_mu);
     g_table.clear();
+    g_fields.clear();
+}
+
+int fields_append_file(const char *path, const Geom &g, int fmt, int cap, double us_per_field) {
+    FILE *f = std::fopen(path, "a");
+    if (!f) return -1;
+    std::fprintf(f,
+                 "{\"arch\": \"gfx950\", \"dims\": [%u, %u, %u, %u], \"fmt\": %d, "
+                 "\"fields_per_launch\": %d, \"us_per_field\": %.3f}\n",
+                 g.N[0], g.N[1], g.N[2], g.N[3], fmt, cap, us_per_field);
+    std::fclose(f);
+    return 0;
 }
 
 int tune_append_file(const char *path, const Geom &g, int fmt, int nr, const TuneChoice &c) {
@@ -100,6 +129,18 @@ int tune_load_file(const char *path, int *loaded) {
         const char *dims = std::strstr(line, "\"dims\": [");
         if (!dims || std::sscanf(dims, "\"dims\": [%u, %u, %u, %u]", &d[0], &d[1], &d[2], &d[3]) != 4)
             continue;
+        Geom g;
+        std::memset(&g, 0, sizeof g);
+        for (int k = 0; k < 4; ++k) g.N[k] = d[k];
+        if (std::strstr(line, "\"fields_per_launch\"")) {
+            int cap;
+            if (!find_int(line, "fmt", fmt) || !find_int(line, "fields_per_launch", cap) ||
+                (cap != 1 && cap != 2 && cap != 4 && cap != 8))
+                continue;
+            fields_store(g, fmt, cap);  // later lines win
+            ++n;
+            continue;
+        }
         if (!find_int(line, "fmt", fmt) || !find_int(line, "nr", nr) ||
             !find_int(line, "xcd_remap", xcd) || !find_int(line, "sites_per_thread", spt) ||
             !find_num(line, "us", us))
@@ -112,9 +153,6 @@ int tune_load_file(const char *path, int *loaded) {
         if ((xcd != 0 && xcd != 1) || (spt != 1 && spt != 2 && spt != 4 && spt != 8) ||
             (stage != 0 && stage != 1) || (tps != 1 && tps != 2 && tps != 4))
             continue;
-        Geom g;
-        std::memset(&g, 0, sizeof g);
-        for (int k = 0; k < 4; ++k) g.N[k] = d[k];
         tune_store(g, fmt, nr, TuneChoice{xcd, spt, stage, tps, us});  // later lines win
         ++n;
     }

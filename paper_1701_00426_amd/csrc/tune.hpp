@@ -15,8 +15,16 @@ struct TuneChoice {
 
 bool tune_lookup(const Geom &g, int fmt, int nr, TuneChoice &c);
 void tune_store(const Geom &g, int fmt, int nr, const TuneChoice &c);
-void tune_clear();
 int tune_append_file(const char *path, const Geom &g, int fmt, int nr, const TuneChoice &c);
+
+// Fields per launch (the RHS per block): the largest number of fields one hop launch
+// takes for a (lattice, link format), 1, 2, 4 or 8, chosen by the autotuner from
+// the time per field of each chunking.
+bool fields_lookup(const Geom &g, int fmt, int &cap);
+void fields_store(const Geom &g, int fmt, int cap);
+int fields_append_file(const char *path, const Geom &g, int fmt, int cap, double us_per_field);
+
+void tune_clear();  // empties both tables
 int tune_load_file(const char *path, int *loaded);
 
 }  // namespace stg

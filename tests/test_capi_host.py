@@ -231,6 +231,44 @@ def test_autotune_cache_roundtrip(lib, tmp_path):
     assert lib.stg_autotune_lookup(ctypes.byref(lat), 1, 1, ctypes.byref(c)) == 1
 
 
+def test_autotune_fields_cache_roundtrip(lib, tmp_path):
+    """Fields-per-launch lines of the cache: read into their own table (later lines
+    win, caps other than 1, 2, 4, 8 skipped), looked up per (lattice, format), and
+    emptied by stg_autotune_clear together with the shapes."""
+    lat = _lat((32, 32, 32, 32))
+    lat8 = _lat((8, 8, 8, 8))
+    lib.stg_autotune_clear()
+    v = ctypes.c_int(-1)
+    assert lib.stg_autotune_fields_lookup(ctypes.byref(lat), 2, ctypes.byref(v)) == 1
+    assert lib.stg_autotune_fields_lookup(ctypes.byref(lat), 2, None) == -1
+    assert lib.stg_autotune_fields_lookup(None, 2, ctypes.byref(v)) == -1
+    bad = _lat((8, 8, 8, 7))
+    assert lib.stg_autotune_fields_lookup(ctypes.byref(bad), 2, ctypes.byref(v)) == -1
+    head = '{"arch": "gfx950", "dims": '
+    f = tmp_path / "fields.jsonl"
+    f.write_text(
+        head + '[32, 32, 32, 32], "fmt": 2, "fields_per_launch": 4, "us_per_field": 9.5}\n'
+        + head + '[32, 32, 32, 32], "fmt": 2, "fields_per_launch": 8, "us_per_field": 9.1}\n'
+        + head + '[8, 8, 8, 8], "fmt": 1, "fields_per_launch": 3, "us_per_field": 1.0}\n'
+        + head + '[8, 8, 8, 8], "fmt": 3, "fields_per_launch": 2, "us_per_field": 1.5}\n'
+        + head + '[8, 8, 8, 8], "fmt": 3, "nr": 1, "xcd_remap": 0, '
+        '"sites_per_thread": 1, "us": 2.0}\n')
+    n = ctypes.c_int(0)
+    assert lib.stg_autotune_load(str(f).encode(), ctypes.byref(n)) == 0
+    assert n.value == 4  # the cap of 3 is skipped
+    assert lib.stg_autotune_fields_lookup(ctypes.byref(lat), 2, ctypes.byref(v)) == 0
+    assert v.value == 8
+    assert lib.stg_autotune_fields_lookup(ctypes.byref(lat8), 3, ctypes.byref(v)) == 0
+    assert v.value == 2
+    assert lib.stg_autotune_fields_lookup(ctypes.byref(lat8), 1, ctypes.byref(v)) == 1
+    from paper_1701_00426_amd import _lib
+    c = _lib.StgTuneChoice()
+    assert lib.stg_autotune_lookup(ctypes.byref(lat8), 3, 1, ctypes.byref(c)) == 0
+    lib.stg_autotune_clear()
+    assert lib.stg_autotune_fields_lookup(ctypes.byref(lat8), 3, ctypes.byref(v)) == 1
+    assert lib.stg_autotune_lookup(ctypes.byref(lat8), 3, 1, ctypes.byref(c)) == 1
+
+
 def test_tuning_knobs(lib):
     v = ctypes.c_int(-1)
     assert lib.stg_get_tuning(0, ctypes.byref(v)) == 0 and v.value == 1
@@ -238,7 +276,7 @@ def test_tuning_knobs(lib):
     assert lib.stg_set_tuning(1, 2) == 0
     assert lib.stg_get_tuning(1, ctypes.byref(v)) == 0 and v.value == 2
     assert lib.stg_set_tuning(1, 1) == 0
-    assert lib.stg_set_tuning(7, 1) == -1
+    assert lib.stg_set_tuning(7, 1) == -1 and lib.stg_set_tuning(6 + 2, 1) == -1
     # neighbour staging: 0 or 1, off by default
     assert lib.stg_get_tuning(2, ctypes.byref(v)) == 0 and v.value == 0
     assert lib.stg_set_tuning(2, 2) == -1
@@ -263,6 +301,14 @@ def test_tuning_knobs(lib):
     assert lib.stg_set_tuning(5, 4) == 0
     assert lib.stg_get_tuning(5, ctypes.byref(v)) == 0 and v.value == 4
     assert lib.stg_set_tuning(5, 0) == 0
+    # fields per launch: 0 (automatic), 1, 2, 4 or 8
+    assert lib.stg_get_tuning(6, ctypes.byref(v)) == 0 and v.value == 0
+    for bad in (3, 5, 16, -1):
+        assert lib.stg_set_tuning(6, bad) == -1
+    for good in (1, 2, 4, 8):
+        assert lib.stg_set_tuning(6, good) == 0
+        assert lib.stg_get_tuning(6, ctypes.byref(v)) == 0 and v.value == good
+    assert lib.stg_set_tuning(6, 0) == 0
 
 
 def test_cg_default_params(lib):

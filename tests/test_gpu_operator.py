@@ -210,6 +210,31 @@ def test_hop_multi_rhs(nrhs, fmt, tps, corc, tuning):
         (1e-14 if fmt == "c128_12" else 1e-6)
 
 
+@pytest.mark.parametrize("cap", [1, 2, 4, 8])
+@pytest.mark.parametrize("fmt", ["c128_12", "c64_12"])
+def test_fields_per_launch(fmt, cap, corc, tuning):
+    """11 fields chunked at most 1, 2, 4 or 8 per launch: D_oe, D_eo and the normal
+    operator of every field match the oracle."""
+    dims, nrhs = (6, 4, 2, 10), 11
+    say(f"fields per launch {cap} {fmt}")
+    tuning(stg._lib.STG_TUNE_FIELDS_PER_LAUNCH, cap)
+    links = si.su3_links(dims, 13, 0)
+    phases = on.standard_phases(dims)
+    g = stg.pack_gauge(dims, to_dev(links), fmt)
+    cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
+    v = si.gaussian_field(dims, nrhs, 13, 1)
+    dv = to_dev(v).to(cdt)
+    oe = stg.dirac_apply_oe(g, dv).cpu().numpy().astype(np.complex128)
+    eo = stg.dirac_apply_eo(g, dv).cpu().numpy().astype(np.complex128)
+    nm = stg.stg_apply_normal(g, 0.2, dv).cpu().numpy().astype(np.complex128)
+    want_oe = corc.dslash(dims, links, phases, 1, v)
+    want_eo = corc.dslash(dims, links, phases, 0, v)
+    for j in range(nrhs):
+        assert rel_max(oe[j], want_oe[j]) <= TOL[fmt]
+        assert rel_max(eo[j], want_eo[j]) <= TOL[fmt]
+        assert rel_max(nm[j], corc.apply_normal(dims, links, phases, 0.2, v[j])) <= TOL[fmt]
+
+
 @pytest.mark.parametrize("fmt", ["c128_12", "c64_12", "bf16_12"])
 def test_apply_normal(fmt, corc):
     dims = (4, 6, 4, 6)
@@ -324,11 +349,12 @@ def test_deterministic_hop_and_dot():
 
 
 @pytest.mark.parametrize("fmt,nrhs", [("c64_12", 1), ("c64_12", 3), ("c128_12", 2),
-                                      ("bf16_12", 1)])
+                                      ("bf16_12", 1), ("c64_12", 8), ("c128_12", 5)])
 def test_autotune_choice_and_parity(fmt, nrhs, corc, tmp_path):
     """stg_autotune times the launch shapes on the caller's buffers, keeps a valid
     choice in the process-wide table and the cache file (read back by
-    stg_autotune_load), and the hop launched with that shape matches the oracle."""
+    stg_autotune_load), with several fields also the fields per launch, and the hop
+    launched with those choices matches the oracle."""
     dims = (8, 6, 4, 10)
     say(f"autotune {fmt} nrhs={nrhs}")
     links = si.su3_links(dims, 1701, 12, 0)
@@ -348,6 +374,8 @@ def test_autotune_choice_and_parity(fmt, nrhs, corc, tmp_path):
         assert choice["us"] > 0
         if choice["threads_per_site"] > 1:
             assert choice["sites_per_thread"] == 1 and choice["stage_neighbours"] == 0
+        if nrhs >= 2:
+            assert choice["fields_per_launch"] in (1, 2, 4, 8)
         v = si.gaussian_field(dims, nrhs, 426, 12, 1)
         got = stg.dirac_apply_eo(g, to_dev(v).to(cdt)).cpu().numpy().astype(np.complex128)
         want = corc.dslash(dims, links, phases, 0, v)
@@ -355,11 +383,14 @@ def test_autotune_choice_and_parity(fmt, nrhs, corc, tmp_path):
             assert rel_max(got[j], want[j]) <= TOL[fmt]
         lib.stg_autotune_clear()
         assert stg.stg_autotune_lookup(dims, g.fmt, choice_nr(nrhs)) is None
-        assert stg.stg_autotune_load(str(cache)) == 1
+        assert stg.stg_autotune_fields_lookup(dims, g.fmt) is None
+        assert stg.stg_autotune_load(str(cache)) == (2 if nrhs >= 2 else 1)
         again = stg.stg_autotune_lookup(dims, g.fmt, choice_nr(nrhs))
-        assert {k: again[k] for k in choice if k != "us"} == {k: choice[k] for k in choice
-                                                               if k != "us"}
+        shape_keys = [k for k in choice if k not in ("us", "fields_per_launch")]
+        assert {k: again[k] for k in shape_keys} == {k: choice[k] for k in shape_keys}
         assert abs(again["us"] - choice["us"]) <= 1e-3
+        if nrhs >= 2:
+            assert stg.stg_autotune_fields_lookup(dims, g.fmt) == choice["fields_per_launch"]
     finally:
         lib.stg_autotune_clear()
 

@@ -69,13 +69,24 @@ def test_cg_mixed(lofmt, corc):
     _check(corc, dims, links, phases, 0.1, b, x.cpu().numpy(), stats, label=lofmt)
 
 
+@pytest.fixture(params=[0, 1, 2, 4], ids=["fields-auto", "fields-1", "fields-2", "fields-4"])
+def fields_per_launch(request):
+    """The most fields one hop launch takes (0: automatic, 8 without a tuned choice)."""
+    key = stg._lib.STG_TUNE_FIELDS_PER_LAUNCH
+    old = stg.stg_get_tuning(key)
+    stg.stg_set_tuning(key, request.param)
+    yield request.param
+    stg.stg_set_tuning(key, old)
+
+
 @pytest.mark.parametrize("nrhs", [5, 8])
 @pytest.mark.parametrize("mode", ["f64", "c64_12"])
-def test_cg_multi_rhs(mode, nrhs, corc):
+def test_cg_multi_rhs(mode, nrhs, corc, fields_per_launch):
     """Chunks of 4 + 1 and 8 fields per launch, with the default launch shapes
-    (several threads per site: the most blocks, so the most reduction partials)."""
+    (several threads per site: the most blocks, so the most reduction partials), and
+    the same systems chunked at most 1, 2 or 4 fields per launch."""
     dims = (4, 6, 4, 8)
-    say(f"cg multi-rhs {mode} nrhs={nrhs}")
+    say(f"cg multi-rhs {mode} nrhs={nrhs} fields per launch {fields_per_launch}")
     links, phases, b = _problem(dims, (2, 0), nrhs)
     dl = to_dev(links)
     hi = stg.pack_gauge(dims, dl, "c128_12")
@@ -149,7 +160,7 @@ def test_cg_bitwise_reproducible():
 
 
 @pytest.mark.parametrize("mode", ["f64", "c64_12"])
-def test_multishift(mode, corc):
+def test_multishift(mode, corc, fields_per_launch):
     dims = (4, 6, 4, 8)
     nrhs = 2
     shifts = si.log_shifts(6, 1e-4, 10.0)
