@@ -398,3 +398,28 @@ def test_autotune_choice_and_parity(fmt, nrhs, corc, tmp_path):
 def choice_nr(nrhs):
     """Fields per launch of the first chunk of nrhs fields (8, 4, or nrhs below 4)."""
     return 8 if nrhs >= 8 else 4 if nrhs >= 4 else nrhs
+
+
+def test_hop_sampled_links_above_4gib():
+    """The largest buffers: FP64-18 links on 48^3 x 72 take 4.59 GB, so the byte
+    offsets of the last sites' links do not fit in 32 bits.  D_eo and D_oe at sampled
+    output sites, the last 64 half-sites included, against the oracle site by site."""
+    dims = (48, 48, 48, 72)
+    vh = on.half_volume(dims)
+    assert 8 * 9 * 16 * vh > 2 ** 32
+    say(f"generating {dims} links ({8 * 9 * 16 * vh / 1e9:.2f} GB)")
+    links = si.su3_links(dims, 1701, 14, 0)
+    phases = on.standard_phases(dims)
+    g = stg.pack_gauge(dims, to_dev(links), "c128_18")
+    rng = np.random.default_rng(14)
+    hs = np.concatenate([rng.choice(vh, 2000, replace=False), np.arange(32),
+                         vh - 1 - np.arange(64)])
+    for par in (0, 1):
+        v = si.gaussian_field(dims, 1, 14, 1, par)
+        fn = stg.dirac_apply_eo if par == 0 else stg.dirac_apply_oe
+        out = fn(g, to_dev(v))
+        got = out[..., torch.from_numpy(hs).to(out.device)].cpu().numpy()
+        want = on.dslash(dims, links, phases, par, v, hs=hs)
+        err = rel_max(got, want)
+        say(f"  parity {par}: sampled max rel err {err:.2e}")
+        assert err <= TOL["c128_18"]
