@@ -160,8 +160,9 @@ const char *stg_last_error(void);
  *   STG_TUNE_FIELDS_PER_LAUNCH: 0 (default: the autotuner's choice for the lattice
  *     and link format, else 8), 1, 2, 4 or 8: the most fields one hop launch takes
  *     when a call works on several (dirac_apply_*, stg_apply_normal, fermion_force,
- *     the solvers); more fields share each link read, fewer keep fewer registers and
- *     partial sums per thread.  Only the speed depends on it.
+ *     cg_solve, multishift_cg_solve, rational_apply; cg_solve_batch keeps its own
+ *     tiles of at most 4 fields); more fields share each link read, fewer keep fewer
+ *     registers and partial sums per thread.  Only the speed depends on it.
  * Returns STG_INVALID_ARG for an unknown key or value.
  */
 enum {
@@ -191,8 +192,9 @@ int stg_get_tuning(int key, int *value);
  * chunked at most 8, 4, 2 or 1 fields per launch (the RHS per block; each chunk in
  * its stored or default shape) and keeps, per (lattice extents, gauge format), the
  * cap with the least time per field: every later multi-field hop, normal-operator
- * apply and solver on that lattice and format chunks its fields by it (unless
- * STG_TUNE_FIELDS_PER_LAUNCH is set), and it is appended to the cache file too.
+ * apply and solver on that lattice and format (cg_solve_batch aside) chunks its
+ * fields by it (unless STG_TUNE_FIELDS_PER_LAUNCH is set), and it is appended to the
+ * cache file too.
  * Synchronous.  stg_autotune_load reads such a file into the tables (later lines
  * win) and reports the entries read in *loaded.  stg_autotune_lookup returns STG_OK
  * and the stored shape, stg_autotune_fields_lookup the stored fields per launch, or
