@@ -100,6 +100,26 @@ def time_applies(stg, torch, gauges, fields, outs, parity, n):
     return t0.elapsed_time(t1) * 1e-3 / n
 
 
+def time_pack(stg, torch, links, dims, fmt, reps=20):
+    """stg_pack_links from full complex128 links into one compressed format: HIP-event
+    mean over reps calls after one warm-up; GB/s of the bytes read (144 B per link)
+    plus the bytes written (the packed field)."""
+    stg.stg_pack_links(dims, links, fmt)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(reps):
+        out = stg.stg_pack_links(dims, links, fmt)
+    t1.record(stream)
+    t1.synchronize()
+    dt = t0.elapsed_time(t1) * 1e-3 / reps
+    nbytes = links.numel() * links.element_size() + out.numel()
+    return {"us": round(dt * 1e6, 2), "GBs": round(nbytes / dt / 1e9, 1),
+            "bytes": int(nbytes)}
+
+
 def cpu_baseline(links, b, vh, seconds=10.0):
     """The FP64 C oracle's D_eo on the host cores: bounded sample of applies."""
     import numpy as np
@@ -1023,6 +1043,13 @@ def main():
         del gauges, fields, outs
         torch.cuda.empty_cache()
 
+    # ---- link packing (once per gauge configuration, timed apart from the steps) -------
+    pack = {}
+    if not args.profile and not args.profile_cg:
+        for fmt in ("c128_12", "c64_12", "bf16_12"):
+            pack[fmt] = time_pack(stg, torch, links, DIMS, fmt)
+        log("pack: " + ", ".join(f"{k} {v['us']} us {v['GBs']} GB/s" for k, v in pack.items()))
+
     if args.profile:
         dt = hop_time[("c128_12", "D_eo")]
         print(json.dumps({"profile": "hop D_eo FP64-12 32^4", "applies": args.applies,
@@ -1144,6 +1171,7 @@ def main():
         "cg_mixed": {"iters": stmx["iters"], "true_rel_resid": stmx["true_rel_resid"],
                      "reliable_updates": stmx["reliable_updates"]},
         "operator_variants": variants,
+        "pack_links": pack,
         "roofline": roofline,
     }
     if not args.no_cpu and not args.profile:
