@@ -280,3 +280,29 @@ def test_rational_apply_free_field_and_identity():
     bd = to_dev(b)
     y0, st, _ = stg.rational_apply(g, mass, [0.5], [0.0], 0.75, bd, tol=1e-10)
     assert torch.equal(y0, 0.75 * bd)
+
+
+def test_tuned_fields_per_launch_reaches_the_solvers(corc, tmp_path):
+    """A fields-per-launch choice in the autotuner's table (here read from a cache
+    line: at most 2 fields per launch for this lattice and FP64-12) is what the
+    solver chunks by when no setting overrides it; the solutions still meet the
+    oracle-recomputed residual."""
+    dims, nrhs = (4, 6, 4, 8), 5
+    key = stg._lib.STG_TUNE_FIELDS_PER_LAUNCH
+    old = stg.stg_get_tuning(key)
+    stg.stg_set_tuning(key, 0)
+    cache = tmp_path / "fields.jsonl"
+    cache.write_text('{"arch": "gfx950", "dims": [4, 6, 4, 8], "fmt": 1, '
+                     '"fields_per_launch": 2, "us_per_field": 1.0}\n')
+    lib = stg.library()
+    lib.stg_autotune_clear()
+    try:
+        assert stg.stg_autotune_load(str(cache)) == 1
+        assert stg.stg_autotune_fields_lookup(dims, stg.STG_LINK_C128_12) == 2
+        links, phases, b = _problem(dims, (3, 0), nrhs)
+        hi = stg.pack_gauge(dims, to_dev(links), "c128_12")
+        x, st, stats = stg.cg_solve(hi, 0.05, to_dev(b), tol=TOL)
+        _check(corc, dims, links, phases, 0.05, b, x.cpu().numpy(), stats, label="tuned cap 2")
+    finally:
+        lib.stg_autotune_clear()
+        stg.stg_set_tuning(key, old)
