@@ -120,27 +120,75 @@ def time_pack(stg, torch, links, dims, fmt, reps=20):
             "bytes": int(nbytes)}
 
 
-def cpu_baseline(links, b, vh, seconds=10.0):
-    """The FP64 C oracle's D_eo on the host cores: bounded sample of applies."""
-    import numpy as np
+def _native_oracle():
+    """The C oracle compiled with -O3 -march=native on this host (a private copy: the
+    tests keep the portable build)."""
+    import tempfile
     import oracle
+    return oracle.COracle(oracle.build(native_dir=tempfile.mkdtemp(prefix="stg_oracle_")))
+
+
+def cpu_baseline(links, b, vh, seconds=10.0, one_core_seconds=4.0):
+    """The FP64 C oracle's D_eo on the host cores, bounded samples on all cores and
+    on one core; the metric's unit (GB/s on the same byte model as value)."""
     from oracle import oracle_np as on
-    orc = oracle.COracle()
+    orc = _native_oracle()
     phases = on.standard_phases(DIMS)
-    t = time.perf_counter()
-    orc.d_eo(DIMS, links, phases, b)
-    one = time.perf_counter() - t
-    n = max(1, min(50, int(seconds / max(one, 1e-3))))
-    t = time.perf_counter()
-    for _ in range(n):
+    cores = orc.num_threads()
+
+    def sample(budget):
+        t = time.perf_counter()
         orc.d_eo(DIMS, links, phases, b)
-    dt = (time.perf_counter() - t) / n
+        one = time.perf_counter() - t
+        n = max(1, min(50, int(budget / max(one, 1e-3))))
+        t = time.perf_counter()
+        for _ in range(n):
+            orc.d_eo(DIMS, links, phases, b)
+        return n, (time.perf_counter() - t) / n
+
+    n, dt = sample(seconds)
+    orc.set_num_threads(1)
+    n1, dt1 = sample(one_core_seconds)
+    orc.set_num_threads(cores)
     gbs = BYTES_PER_SITE["c128_12"] * vh / dt / 1e9
+    return {"value": round(gbs, 3), "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} D_eo applies of the FP64 C oracle (gcc -O3 -march=native, OpenMP "
+                      f"over {cores} threads, full 3x3 links) at 32^4, {dt * 1e3:.1f} ms each, "
+                      f"same byte model as value (864 B/site); one core: {n1} applies, "
+                      f"{dt1 * 1e3:.1f} ms each",
+            "ms_per_apply": round(dt * 1e3, 3),
+            "one_core": {"GBs": round(BYTES_PER_SITE["c128_12"] * vh / dt1 / 1e9, 3),
+                         "ms_per_apply": round(dt1 * 1e3, 3), "applies": n1}}
+
+
+def oracle_solution(links, b, tol=1e-12):
+    """x* = the FP64 C oracle's own CG solution of the benchmark system to |r|/|b| <=
+    tol on all host cores (textbook CG on the full 3x3 links), and its time to
+    solution: the CPU time-to-solution figure of the FP64 solve."""
+    import numpy as np
+    from oracle import oracle_np as on
+    import threading
+    orc = _native_oracle()
+    phases = on.standard_phases(DIMS)
+    done = threading.Event()
+
+    def ticker():  # progress lines while the C call runs (it releases the GIL)
+        while not done.wait(20.0):
+            log(f"  oracle CG running, {time.perf_counter() - t:.0f} s")
+
+    t = time.perf_counter()
+    th = threading.Thread(target=ticker, daemon=True)
+    th.start()
+    try:
+        x, iters, res, st = orc.cg(DIMS, links, phases, MASS, b, tol=tol, max_iter=20000)
+    finally:
+        done.set()
+        th.join()
+    dt = time.perf_counter() - t
     del np
-    return {"value": round(gbs, 3), "unit": "GB/s", "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"{n} D_eo applies of the FP64 C oracle (OpenMP, full 3x3 links) at 32^4, "
-                      f"{dt * 1e3:.1f} ms each, same byte model as value (864 B/site)",
-            "ms_per_apply": round(dt * 1e3, 3)}
+    return x, {"tol": tol, "status": int(st), "iters": int(iters), "true_rel_resid": res,
+               "seconds": round(dt, 2), "cores": orc.num_threads(),
+               "build": "gcc -O3 -march=native -fopenmp (dslash over OpenMP threads)"}
 
 
 def copy_ceiling(torch, nbytes=1 << 30, reps=20):
@@ -242,7 +290,36 @@ def bench_multishift():
            "iters_largest_shift": max(s["iters"] for s in stats[-1]),
            "refine_reliable_updates_max": max(s["reliable_updates"] for s in flat),
            "workspace_GB": round(ws.numel() / 1e9, 2)}
+    out["ms_stage_bytes"] = multishift_stage_bytes(dims, stats, 8)
     print(json.dumps(out), flush=True)
+
+
+def multishift_stage_bytes(dims, stats, elem):
+    """Algorithmic bytes of the multi-shift stage (each datum once per kernel), from
+    the iterations each (shift, RHS) system took part in (stats[k][j]["ms_iters"]):
+    the operator (two hops per iteration; one link read per launch serves the 8
+    fields of a launch) against the vector kernels, the shift update above all.
+    elem: bytes per complex entry of the stage's vectors (8 for FP32)."""
+    vh = 1
+    for d in dims:
+        vh *= d
+    vh //= 2
+    vec = 3 * elem                                # one colour vector per site
+    nshift, nrhs = len(stats), len(stats[0])
+    base = [max(stats[k][j]["ms_iters"] for k in range(nshift)) for j in range(nrhs)]
+    shift_iters = sum(stats[k][j]["ms_iters"] for k in range(nshift) for j in range(nrhs))
+    launches = sum(max(base[j0:j0 + 8]) for j0 in range(0, nrhs, 8))   # 8 fields per launch
+    link_bytes = 8 * 6 * elem                      # FP32-12: 48 B per link, 8 per site
+    hops = vh * (2 * launches * link_bytes + sum(base) * (2 * vec + 3 * vec))
+    r_update = vh * sum(base) * 3 * vec            # r, q read, r written
+    # base p: r, p read, p written; each (shift, RHS) still in the stage: p_k, x_k read,
+    # x_k and p_k written (r is re-read by every shift's blocks from L2: counted once)
+    p_update = vh * (sum(base) * 3 * vec + shift_iters * 4 * vec)
+    return {"hop_launch_pairs": launches, "base_iters": base, "shift_iters_total": shift_iters,
+            "hops": hops, "ms_r_update": r_update, "ms_p_update": p_update,
+            "model": "hops: 2 x 8 links x 48 B per launch + per field 2 x (in + out) + p; "
+                     "ms_r_update: 3 vectors per field; ms_p_update: 3 vectors per field + "
+                     "4 vectors per (shift, RHS) iteration; vector = 24 B per site"}
 
 
 def bench_rational():
@@ -1071,12 +1148,17 @@ def main():
     xmx = torch.zeros_like(b)
     xbf = torch.zeros_like(b)
     nb = 8
-    b8 = torch.from_numpy(si.gaussian_field(DIMS, nb, 426, 2, 1, 0)).to(dev)
+    b8_np = si.gaussian_field(DIMS, nb, 426, 2, 1, 0)
+    b8_np[0] = b_np[0]  # the first of the 8 RHS is the single-RHS b: one x* serves both
+    b8 = torch.from_numpy(b8_np).to(dev)
     x8 = torch.zeros_like(b8)
     ws8 = torch.empty(stg.stg_workspace_bytes(DIMS, nb, 0, stg.STG_CG_MIXED), dtype=torch.uint8,
                       device=dev)
 
+    failures = []
+
     def step():
+        s3 = s4 = 0
         x64.zero_()
         xmx.zero_()
         xbf.zero_()
@@ -1094,6 +1176,13 @@ def main():
         if not args.profile_cg:
             _, s4, st4 = stg.cg_solve(hi, MASS, b, x=xbf, lo=lo16, ws=wsbf, tol=TOL)
         t4 = time.perf_counter()
+        for name, status, stats in (("fp64", s1, st1), ("mixed_fp32", s2, st2),
+                                    ("mixed_fp32_8rhs", s3 if st3 else 0, st3 or []),
+                                    ("mixed_bf16", s4 if st4 else 0, st4 or [])):
+            bad = [q for q in stats if q["status"] != 0 or not q["true_rel_resid"] <= TOL]
+            if status != 0 or bad:
+                failures.append({"solve": name, "status": status,
+                                 "stats": bad[:2] if bad else stats[:1]})
         return t1 - t0, t2 - t1, st1[0], st2[0], t3 - t2, st3, t4 - t3, st4
 
     if args.profile_cg:
@@ -1110,6 +1199,10 @@ def main():
     runs = [step() for _ in range(args.steps)]
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
+    if failures:
+        print(json.dumps({"error": "a timed solve did not reach |r|/|b| <= 1e-10",
+                          "failures": failures[:4]}), file=sys.stderr, flush=True)
+        sys.exit(1)
     t64 = min(r[0] for r in runs)
     tmx = min(r[1] for r in runs)
     t8 = min(r[4] for r in runs)
@@ -1177,6 +1270,19 @@ def main():
     if not args.no_cpu and not args.profile:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(links_np, b_np, vh)
+        log("oracle CG to 1e-12 on the host cores (x*)")
+        xs, info = oracle_solution(links_np, b_np[0])
+        out["cpu_baseline"]["cg_fp64_time_to_solution"] = info
+        xsn = float(np.linalg.norm(xs))
+        sols = {"fp64": x64[0], "mixed_fp32_12": xmx[0], "mixed_bf16_12": xbf[0],
+                "mixed_fp32_12_8rhs_rhs0": x8[0]}
+        kappa = (MASS * MASS + 16.0) / (MASS * MASS)
+        out["error_vs_oracle_solution"] = {
+            k: float(np.linalg.norm(v.cpu().numpy() - xs) / xsn) for k, v in sols.items()}
+        out["error_vs_oracle_solution"]["bound_2kappa_tol"] = 2 * kappa * TOL
+        out["error_vs_oracle_solution"]["x_star"] = (
+            f"oracle FP64 CG to |r|/|b| <= 1e-12 ({info['iters']} iterations, true residual "
+            f"{info['true_rel_resid']:.2e}); the last timed step's solutions")
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

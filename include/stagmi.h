@@ -293,6 +293,10 @@ typedef struct {
     int converged_iter;     /* iteration at which this system met its stopping test */
     double true_rel_resid;  /* FP64 |b - A x| / |b| at return */
     double seconds;         /* wall time of the call */
+    int ms_iters;           /* multishift_cg_solve / rational_apply: iterations of the shared
+                               multi-shift stage this (shift, RHS) system took part in (the
+                               rest of iters refined it alone); 0 for the other solvers */
+    int pad_;
 } stg_cg_stats;
 
 /* Fills p with the defaults: tol 1e-10, max_iter 100000, mode F64, delta 0.1,

@@ -33,15 +33,26 @@ LIB_PATH = os.path.join(_HERE, "libstag_oracle.so")
 SRC_PATH = os.path.join(_HERE, "stag_oracle.c")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile stag_oracle.c into libstag_oracle.so (plain gcc, OpenMP)."""
-    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-shared", "-fPIC", SRC_PATH,
-           "-o", LIB_PATH + ".tmp", "-lm"]
+def build(verbose: bool = False, native_dir: str = "") -> str:
+    """Compile stag_oracle.c into libstag_oracle.so (plain gcc, OpenMP).
+
+    With native_dir the library is built with -O3 -march=native into that folder
+    (the CPU baseline builds it on the host it times; -march=native code may not
+    run on another CPU, so the tests' copy keeps the portable flags).  The source
+    is ISO C99, so gcc contracts no multiply-add: both builds round alike."""
+    if native_dir:
+        out = os.path.join(native_dir, "libstag_oracle_native.so")
+        flags = ["-O3", "-march=native"]
+    else:
+        out = LIB_PATH
+        flags = ["-O2"]
+    cmd = ["gcc", *flags, "-std=c99", "-fopenmp", "-shared", "-fPIC", SRC_PATH,
+           "-o", out + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
-    return LIB_PATH
+    os.replace(out + ".tmp", out)
+    return out
 
 
 _P = ctypes.c_void_p
@@ -62,6 +73,8 @@ class COracle:
         lib = ctypes.CDLL(path)
         lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_num_threads.argtypes = []
+        lib.orc_set_num_threads.restype = None
+        lib.orc_set_num_threads.argtypes = [ctypes.c_int]
         lib.orc_half_volume.restype = ctypes.c_long
         lib.orc_half_volume.argtypes = [_P]
         lib.orc_standard_phases.argtypes = [_P, _P]
@@ -75,6 +88,9 @@ class COracle:
 
     def num_threads(self) -> int:
         return int(self.lib.orc_num_threads())
+
+    def set_num_threads(self, n: int) -> None:
+        self.lib.orc_set_num_threads(int(n))
 
     @staticmethod
     def _dims(dims):

@@ -33,8 +33,8 @@
  *    (antiperiodic time boundary, time = x3), s_mu = +1 otherwise.
  *  - Even/odd normal operator (Sec. 2.2, Eq. lineqeo): A = m^2 - D_eo D_oe on even
  *    sites, shifted by sigma for the rational-approximation poles (Eq. shlineq).
- *  - CG (Sec. 2.2, "the simplest of the Krylov solvers"): textbook
- *    Hestenes-Stiefel iteration.
+ *  - CG (Sec. 2.2, the Krylov solver the paper uses for the normal equations):
+ *    textbook Hestenes-Stiefel iteration.
  *  - Multi-shift CG (Sec. 2.2, Eq. shlineq: all shifted systems with one
  *    matrix-vector product per iteration): the shifted residuals stay collinear
  *    with the base residual, r_k = zeta_k r; zeta, alpha_k and beta_k follow from
@@ -42,6 +42,7 @@
  *    A+sigma_k (derivation in the design notes).
  *
  * Build: gcc -O2 -fopenmp -shared -fPIC stag_oracle.c -o libstag_oracle.so -lm
+ * (the CPU baseline builds its own copy with -O3 -march=native on the host it runs on)
  */
 #include <complex.h>
 #include <math.h>
@@ -63,6 +64,15 @@ int orc_num_threads(void) {
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* sets the threads of the OpenMP loops (the CPU baseline times 1 and all cores) */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }
 

@@ -59,7 +59,8 @@ class StgCgParams(ctypes.Structure):
 class StgCgStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int),
                 ("status", ctypes.c_int), ("converged_iter", ctypes.c_int),
-                ("true_rel_resid", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("true_rel_resid", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("ms_iters", ctypes.c_int), ("pad_", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -68,6 +68,109 @@ __global__ __launch_bounds__(kBlock) void p_update_kernel(VecArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// single-field CG iteration with the reductions finished by their consumers
+// ---------------------------------------------------------------------------
+// Sum of the n (sum, error) pairs at x by the whole block, in the fixed order of
+// block_sum2_pairs, returned to every thread: every block of a launch obtains the
+// bitwise same total, so each can take the scalar step itself and no finalize
+// kernel runs between the producer and the consumer.
+__device__ __forceinline__ double block_total(const double *x, uint32_t n) {
+    __shared__ double sh_red[2 * kWaves];
+    __shared__ double sh_tot;
+    const double t = block_sum2_pairs(x, (int)n, sh_red);
+    if (threadIdx.x == 0) sh_tot = t;
+    __syncthreads();
+    return sh_tot;
+}
+
+// alpha = rr / <p, q> (the hop's partials), x += alpha p, r -= alpha q, partials of
+// |r|^2.  Writes no solver state.  A breakdown (<p, q> not a finite positive
+// number) leaves x and r alone and writes NaN partials, which the beta step of the
+// next kernel turns into SYS_BREAKDOWN.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void cg_update_fused_kernel(VecArgs a) {
+    if (block_gate_closed(a.ctl, a.gate_running)) return;
+    const double pq = block_total(a.fin_partials, a.fin_blocks);
+    const SysState &s = a.state[0];
+    const bool running = (s.flags & SYS_RUNNING) != 0;
+    const bool ok = finite_pos(pq) && (s.rr >= 0.0 && s.rr < 1.0e300);
+    const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+    double ps[1] = {0.0}, pc[1] = {0.0};
+    if (running && !ok) {
+        ps[0] = __builtin_nan("");
+    } else if (running && h < a.Vh) {
+        const T al = (T)(s.rr / pq);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t i = (size_t)c * a.Vh + h;
+            cpx<T> x = ld_c<T>(a.x, i), p = ld_c<T>(a.p, i), r = ld_c<T>(a.r, i),
+                   q = ld_c<T>(a.q, i);
+            x.re += al * p.re;
+            x.im += al * p.im;
+            r.re -= al * q.re;
+            r.im -= al * q.im;
+            st_c<T>(a.x, i, x);
+            st_c<T>(a.r, i, r);
+            pair_add(ps[0], pc[0], (double)r.re * (double)r.re + (double)r.im * (double)r.im,
+                     0.0);
+        }
+    }
+    block_partials<1>(ps, pc, a.partials);
+}
+
+// |r_new|^2 from the partials of cg_update_fused, the beta step (solver_state.hpp)
+// on a copy of the state, p = r + beta p while the system still runs.  Block 0
+// stores the new state in a.state_out: the next iteration reads that buffer, so
+// no block reads a state that another block of this launch is writing.  Block 0
+// always runs (also when no system runs), so that a.state_out is always current.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void p_update_fused_kernel(VecArgs a) {
+    const bool closed = block_gate_closed(a.ctl, a.gate_running);
+    if (closed && blockIdx.x != 0) return;
+    SysState ns = a.state[0];
+    ns.flags &= ~SYS_RESUME;
+    bool left = false;
+    if (!closed && (ns.flags & SYS_RUNNING)) {
+        const double rr = block_total(a.fin_partials, a.fin_blocks);
+        left = beta_step(ns, rr);
+        const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+        if (!left && h < a.Vh) {
+            const T be = (T)ns.beta;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t i = (size_t)c * a.Vh + h;
+                cpx<T> p = ld_c<T>(a.p, i), r = ld_c<T>(a.r, i);
+                p.re = r.re + be * p.re;
+                p.im = r.im + be * p.im;
+                st_c<T>(a.p, i, p);
+            }
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.state_out[0] = ns;
+        if (left) atomicAdd(&a.ctl->n_running, -1);
+    }
+}
+
+int launch_cg_update_fused(const VecArgs &a, int fp64, hipStream_t stream) {
+    dim3 grid(site_blocks(a.Vh));
+    if (fp64)
+        cg_update_fused_kernel<double><<<grid, kBlock, 0, stream>>>(a);
+    else
+        cg_update_fused_kernel<float><<<grid, kBlock, 0, stream>>>(a);
+    return 0;
+}
+
+int launch_p_update_fused(const VecArgs &a, int fp64, hipStream_t stream) {
+    dim3 grid(site_blocks(a.Vh));
+    if (fp64)
+        p_update_fused_kernel<double><<<grid, kBlock, 0, stream>>>(a);
+    else
+        p_update_fused_kernel<float><<<grid, kBlock, 0, stream>>>(a);
+    return 0;
+}
+
 // x64 += x32; x32 = 0 for parked systems
 template <int NR>
 __global__ __launch_bounds__(kBlock) void ru_accumulate_kernel(VecArgs a) {
@@ -143,48 +246,71 @@ __global__ __launch_bounds__(kBlock) void ms_r_update_kernel(VecArgs a) {
 // multi-shift, after beta: every shift that took part in this iteration steps
 // x_k += alpha_k p_k with its old p_k, then the still active ones p_k = zeta_k r +
 // beta_k p_k (one read of p_k for both); the base p = r + beta p.
+//
+// One block works on one chunk of kBlock sites for one shift (or, for the last
+// index, the base directions), so every (shift, RHS) pair is its own streamed pass
+// over its two fields and a retired shift costs one scalar test per block.  The
+// shift blocks of a site chunk sit next to each other in the XCD-ordered block
+// sequence: they run on the same XCD, where the base residual r they all read
+// stays in L2.
 template <typename T, int NR>
 __global__ __launch_bounds__(kBlock) void ms_p_update_kernel(VecArgs a) {
     if (a.gate_running && a.ctl->n_running == 0) return;
-    const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
-    if (h >= a.Vh) return;
+    const uint32_t nk = (uint32_t)a.nshift + 1;
+    const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t k = lb % nk;
+    const uint32_t h = (lb / nk) * kBlock + threadIdx.x;
     const Ctl &ctl = *a.ctl;
+    if (k == (uint32_t)a.nshift) {  // base directions of the running systems
+        if (h >= a.Vh) return;
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            const SysState &s = a.state[j];
+            if (!(s.flags & SYS_RUNNING)) continue;
+            const T be = (T)s.beta;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t i = (size_t)j * a.fstride + (size_t)c * a.Vh + h;
+                cpx<T> p = ld_c<T>(a.p, i), r = ld_c<T>(a.r, i);
+                p.re = r.re + be * p.re;
+                p.im = r.im + be * p.im;
+                st_c<T>(a.p, i, p);
+            }
+        }
+        return;
+    }
+    // this shift for every RHS: wave-uniform tests, the loads of all its active
+    // systems issued together
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const SysState &s = a.state[j];
+        const bool part = (s.flags & (SYS_RUNNING | SYS_FINISHING)) != 0;
+        any = any || (part && ctl.ms[k * ctl.nrhs + s.gid].active != 0);
+    }
+    if (!any || h >= a.Vh) return;
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         const SysState &s = a.state[j];
         const bool running = (s.flags & SYS_RUNNING) != 0;
         if (!running && !(s.flags & SYS_FINISHING)) continue;
-        const T be = (T)s.beta;
-        cpx<T> r[3];
+        const ShiftState &z = ctl.ms[k * ctl.nrhs + s.gid];
+        if (!z.active) continue;
+        const bool more = running && z.active == 1;
+        const T ak = (T)z.alpha, zk = (T)z.zeta, bk = (T)z.beta;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const size_t i = (size_t)j * a.fstride + (size_t)c * a.Vh + h;
-            r[c] = ld_c<T>(a.r, i);
-            if (running) {
-                cpx<T> p = ld_c<T>(a.p, i);
-                p.re = r[c].re + be * p.re;
-                p.im = r[c].im + be * p.im;
-                st_c<T>(a.p, i, p);
-            }
-        }
-        for (int k = 0; k < a.nshift; ++k) {
-            const ShiftState &z = ctl.ms[k * ctl.nrhs + s.gid];
-            if (!z.active) continue;
-            const bool more = running && z.active == 1;
-            const T ak = (T)z.alpha, zk = (T)z.zeta, bk = (T)z.beta;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const size_t i = (size_t)k * a.kstride + (size_t)j * a.fstride +
-                                 (size_t)c * a.Vh + h;
-                cpx<T> p = ld_c<T>(a.ps, i), x = ld_c<T>(a.xs, i);
-                x.re += ak * p.re;
-                x.im += ak * p.im;
-                st_c<T>(a.xs, i, x);
-                if (more) {
-                    p.re = zk * r[c].re + bk * p.re;
-                    p.im = zk * r[c].im + bk * p.im;
-                    st_c<T>(a.ps, i, p);
-                }
+            const size_t ir = (size_t)j * a.fstride + (size_t)c * a.Vh + h;
+            const size_t i = (size_t)k * a.kstride + ir;
+            cpx<T> p = ld_c<T>(a.ps, i), x = ld_c<T>(a.xs, i);
+            x.re += ak * p.re;
+            x.im += ak * p.im;
+            st_c<T>(a.xs, i, x);
+            if (more) {
+                const cpx<T> r = ld_c<T>(a.r, ir);
+                p.re = zk * r.re + bk * p.re;
+                p.im = zk * r.im + bk * p.im;
+                st_c<T>(a.ps, i, p);
             }
         }
     }
@@ -213,12 +339,29 @@ STG_VEC_LAUNCHER(launch_cg_update_only, cg_update_kernel)
 STG_VEC_LAUNCHER(launch_p_update, p_update_kernel)
 STG_VEC_LAUNCHER(launch_ru_resume, ru_resume_kernel)
 STG_VEC_LAUNCHER(launch_ms_r_update_only, ms_r_update_kernel)
-STG_VEC_LAUNCHER(launch_ms_p_update, ms_p_update_kernel)
 
 int launch_cg_update(const VecArgs &a, int fp64, int nr, hipStream_t stream) {
     if (launch_cg_update_only(a, fp64, nr, stream)) return -1;
     FinArgs f{a.partials, site_blocks(a.Vh), nr, OP_BETA, a.gate_running, a.ctl, a.state, nullptr};
     return launch_finalize(f, stream);
+}
+
+// grid: (nshift + 1) blocks per chunk of kBlock sites
+int launch_ms_p_update(const VecArgs &a, int fp64, int nr, hipStream_t stream) {
+    dim3 grid(site_blocks(a.Vh) * (uint32_t)(a.nshift + 1));
+    switch (nr * 2 + (fp64 ? 1 : 0)) {
+        case 3: ms_p_update_kernel<double, 1><<<grid, kBlock, 0, stream>>>(a); return 0;
+        case 2: ms_p_update_kernel<float, 1><<<grid, kBlock, 0, stream>>>(a); return 0;
+        case 5: ms_p_update_kernel<double, 2><<<grid, kBlock, 0, stream>>>(a); return 0;
+        case 4: ms_p_update_kernel<float, 2><<<grid, kBlock, 0, stream>>>(a); return 0;
+        case 7: ms_p_update_kernel<double, 3><<<grid, kBlock, 0, stream>>>(a); return 0;
+        case 6: ms_p_update_kernel<float, 3><<<grid, kBlock, 0, stream>>>(a); return 0;
+        case 9: ms_p_update_kernel<double, 4><<<grid, kBlock, 0, stream>>>(a); return 0;
+        case 8: ms_p_update_kernel<float, 4><<<grid, kBlock, 0, stream>>>(a); return 0;
+        case 17: ms_p_update_kernel<double, 8><<<grid, kBlock, 0, stream>>>(a); return 0;
+        case 16: ms_p_update_kernel<float, 8><<<grid, kBlock, 0, stream>>>(a); return 0;
+        default: return -1;
+    }
 }
 
 int launch_ms_r_update(const VecArgs &a, int fp64, int nr, hipStream_t stream) {

@@ -66,6 +66,11 @@ int internal(const char *why) {
         if ((call) != 0) return internal("hop launch refused: " #call); \
     } while (0)
 
+#define VEC_TRY(call)                                                       \
+    do {                                                                    \
+        if ((call) != 0) return internal("vector kernel not built: " #call); \
+    } while (0)
+
 bool make_geom(const stg_lattice *lat, Geom &g) {
     if (!lat) return false;
     uint64_t v = 1;
@@ -218,8 +223,10 @@ struct Carver {
 
 struct CgWork {
     Ctl *ctl;
-    SysState *state;
+    SysState *state;      // the solver state the next kernel reads
+    SysState *state_alt;  // single-field solves: the other buffer of the double-buffered state
     double *partials;
+    double *partials2;    // single-field solves: |r|^2 partials (partials holds <p, A p>)
     // inner precision (FP64 mode: double fields; MIXED: float fields)
     void *x_in, *p, *r, *q, *t;
     // FP64 fields for the true residual (MIXED only; F64 mode aliases r / t)
@@ -242,7 +249,9 @@ CgWork carve_cg(const Geom &g, int nsys, int mode, void *ws) {
     const size_t f32 = (size_t)nsys * 3 * g.Vh * 8;
     w.ctl = (Ctl *)c.take(sizeof(Ctl));
     w.state = (SysState *)c.take(sizeof(SysState) * (size_t)nsys);
+    w.state_alt = (SysState *)c.take(sizeof(SysState) * (size_t)nsys);
     w.partials = (double *)c.take(sizeof(double) * partial_count(g));
+    w.partials2 = (double *)c.take(sizeof(double) * partial_count(g));
     if (mode == STG_CG_F64) {
         w.x_in = nullptr;  // the caller's x
         w.p = c.take(f64);
@@ -302,12 +311,21 @@ struct CgProblem {
 // the flags snapshot `st` (systems leave the running state only inside the
 // iteration, and re-enter it only through a reliable update, after which the host
 // reads fresh flags: a snapshot one chunk old never skips a running system).
-int enqueue_inner_iteration(const CgProblem &P, const CgWork &w, const std::vector<SysState> &st,
+//
+// A solve of one field runs the iteration in four kernels: D_oe, D_eo with the
+// normal-operator epilogue and <p, q> partials, the x / r update that finishes
+// alpha from those partials in every block, and the p update that finishes |r|^2
+// and takes the beta step in every block.  Its state is double-buffered (the p
+// update writes the next iteration's copy), so w.state and w.state_alt swap after
+// each iteration.  Several fields keep the finalize kernels (one block per field)
+// between the producers and consumers.
+int enqueue_inner_iteration(const CgProblem &P, CgWork &w, const std::vector<SysState> &st,
                             hipStream_t s) {
     const bool f64 = P.mode == STG_CG_F64;
     const stg_gauge *gg = f64 ? P.hi : P.lo;
     const size_t fb = (size_t)3 * P.g.Vh * (f64 ? 16 : 8);
     void *xin = f64 ? P.x : w.x_in;
+    const bool fused = P.nsys == 1;
     for (int j0 = 0; j0 < P.nsys;) {
         const int nr = P.chunk(j0);
         bool any = false;
@@ -330,13 +348,16 @@ int enqueue_inner_iteration(const CgProblem &P, const CgWork &w, const std::vect
         a.out = (char *)w.t + o;
         HOP_TRY(hop(a, gg->fmt, nr, EPI_PLAIN, s));
         // q = diag p - D_eo t ; <p, q> -> alpha
+        uint32_t hop_blocks = 0;
         a.out_parity = 0;
         a.op = OP_ALPHA;
         a.in = (const char *)w.t + o;
         a.out = (char *)w.q + o;
         a.aux0 = (const char *)w.p + o;
+        a.defer_finish = fused ? 1 : 0;
+        a.grid_out = &hop_blocks;
         HOP_TRY(hop(a, gg->fmt, nr, EPI_NORMAL, s));
-        // x += alpha p, r -= alpha q ; |r|^2 -> beta / park
+        // x += alpha p, r -= alpha q ; |r|^2 -> beta / park ; p = r + beta p
         VecArgs v;
         std::memset(&v, 0, sizeof(v));
         v.Vh = P.g.Vh;
@@ -349,8 +370,20 @@ int enqueue_inner_iteration(const CgProblem &P, const CgWork &w, const std::vect
         v.ctl = w.ctl;
         v.partials = w.partials;
         v.gate_running = 1;
-        launch_cg_update(v, f64, nr, s);
-        launch_p_update(v, f64, nr, s);
+        if (fused) {
+            v.fin_partials = w.partials;
+            v.fin_blocks = hop_blocks;
+            v.partials = w.partials2;
+            VEC_TRY(launch_cg_update_fused(v, f64, s));
+            v.fin_partials = w.partials2;
+            v.fin_blocks = site_blocks(P.g.Vh);
+            v.state_out = w.state_alt;
+            VEC_TRY(launch_p_update_fused(v, f64, s));
+            std::swap(w.state, w.state_alt);
+        } else {
+            VEC_TRY(launch_cg_update(v, f64, nr, s));
+            VEC_TRY(launch_p_update(v, f64, nr, s));
+        }
         j0 += nr;
     }
     HIP_TRY(hipGetLastError());
@@ -375,7 +408,7 @@ int enqueue_reliable_update(const CgProblem &P, const CgWork &w, hipStream_t s) 
         v.x64 = (char *)P.x + j0 * fb64;
         if (!f64) {
             v.x = (char *)w.x_in + j0 * fbin;
-            launch_ru_accumulate(v, nr, s);
+            VEC_TRY(launch_ru_accumulate(v, nr, s));
         }
         HopArgs a = base_hop(P.g, P.hi);
         a.ctl = w.ctl;
@@ -397,7 +430,7 @@ int enqueue_reliable_update(const CgProblem &P, const CgWork &w, hipStream_t s) 
         v.r64 = (const char *)w.r64 + j0 * fb64;
         v.r = (char *)w.r + j0 * fbin;
         v.p = (char *)w.p + j0 * fbin;
-        launch_ru_resume(v, f64, nr, s);
+        VEC_TRY(launch_ru_resume(v, f64, nr, s));
         j0 += nr;
     }
     HIP_TRY(hipGetLastError());
@@ -476,7 +509,7 @@ int read_states(const CgWork &w, int nsys, std::vector<SysState> &st, hipStream_
     return read_states_n(w.state, nsys, st, s);
 }
 
-int run_cg(const CgProblem &P, const CgWork &w, stg_cg_stats *stats, hipStream_t s) {
+int run_cg(const CgProblem &P, CgWork w, stg_cg_stats *stats, hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
     const int n = P.nsys;
     const bool f64 = P.mode == STG_CG_F64;
@@ -617,6 +650,7 @@ int run_cg(const CgProblem &P, const CgWork &w, stg_cg_stats *stats, hipStream_t
                                       : st[j].bb == 0.0 ? 0.0
                                                         : std::nan("");
             stats[j].seconds = secs;
+            stats[j].ms_iters = 0;
         }
         if (stj == STG_BREAKDOWN || (stj == STG_NOT_CONVERGED && status_all == STG_OK))
             status_all = stj;
@@ -726,8 +760,8 @@ int enqueue_ms_iteration(const Geom &g, const stg_gauge *gg, int f64, int nrhs, 
         v.ctl = w.ctl;
         v.partials = w.partials;
         v.gate_running = 1;
-        launch_ms_r_update(v, f64, nr, s);
-        launch_ms_p_update(v, f64, nr, s);
+        VEC_TRY(launch_ms_r_update(v, f64, nr, s));
+        VEC_TRY(launch_ms_p_update(v, f64, nr, s));
         j0 += nr;
     }
     HIP_TRY(hipGetLastError());
@@ -895,6 +929,7 @@ int run_mscg(const Geom &g, const stg_gauge *hi, const stg_gauge *lo, double mas
             const int ms_it = z.active ? base[j].iter : z.conv_iter;
             stats[i] = rs[i];
             stats[i].iters = ms_it + rs[i].iters;
+            stats[i].ms_iters = ms_it;
             stats[i].converged_iter =
                 rs[i].status == STG_OK ? ms_it + std::max(0, rs[i].converged_iter) : -1;
             stats[i].seconds = secs;
@@ -1014,36 +1049,36 @@ int enqueue_batch_iteration(const BatchPlan &B, int f64, int fmt_in, hipStream_t
     a.out_parity = 1;  // t = D_oe p
     a.f_in = BF_P;
     a.f_out = BF_T;
-    if (launch_bhop(a, fmt_in, EPI_PLAIN, s)) return invalid("batch hop");
+    HOP_TRY(launch_bhop(a, fmt_in, EPI_PLAIN, s));
     a.out_parity = 0;  // q = diag p - D_eo t; <p, q>
     a.f_in = BF_T;
     a.f_out = BF_Q;
     a.f_aux0 = BF_P;
-    launch_bhop(a, fmt_in, EPI_NORMAL, s);
-    launch_bfinalize(a, OP_ALPHA, s);
-    launch_bcg_update(a, f64, s);
-    launch_bfinalize(a, OP_BETA, s);
-    launch_bp_update(a, f64, s);
+    HOP_TRY(launch_bhop(a, fmt_in, EPI_NORMAL, s));
+    VEC_TRY(launch_bfinalize(a, OP_ALPHA, s));
+    VEC_TRY(launch_bcg_update(a, f64, s));
+    VEC_TRY(launch_bfinalize(a, OP_BETA, s));
+    VEC_TRY(launch_bp_update(a, f64, s));
     HIP_TRY(hipGetLastError());
     return STG_OK;
 }
 
 int enqueue_batch_update(const BatchPlan &B, int f64, int fmt_hi, hipStream_t s) {
     BArgs a = batch_args(B, 0, SYS_RU_PENDING);
-    if (!f64) launch_bru_accumulate(a, s);
+    if (!f64) VEC_TRY(launch_bru_accumulate(a, s));
     a.use_hi = 1;
     a.out_parity = 1;
     a.f_in = BF_X64;
     a.f_out = BF_T64;
-    launch_bhop(a, fmt_hi, EPI_PLAIN, s);
+    HOP_TRY(launch_bhop(a, fmt_hi, EPI_PLAIN, s));
     a.out_parity = 0;
     a.f_in = BF_T64;
     a.f_out = BF_R64;
     a.f_aux0 = BF_X64;
-    launch_bhop(a, fmt_hi, EPI_RESID, s);
-    launch_bfinalize(a, OP_RU, s);
+    HOP_TRY(launch_bhop(a, fmt_hi, EPI_RESID, s));
+    VEC_TRY(launch_bfinalize(a, OP_RU, s));
     a.tile_mask = SYS_RESUME;
-    launch_bru_resume(a, f64, s);
+    VEC_TRY(launch_bru_resume(a, f64, s));
     HIP_TRY(hipGetLastError());
     return STG_OK;
 }
@@ -1214,6 +1249,7 @@ int run_cg_batch(int nsolve, const stg_solve_desc *d, const stg_cg_params &prm, 
                                   : st[k].bb == 0.0 ? 0.0
                                                     : std::nan("");
         stats[k].seconds = secs;
+        stats[k].ms_iters = 0;
         if (stk == STG_BREAKDOWN || (stk == STG_NOT_CONVERGED && status_all == STG_OK))
             status_all = stk;
     }
@@ -1245,6 +1281,51 @@ int check_batch(int nsolve, const stg_solve_desc *d, const stg_cg_params *prm) {
         const size_t fb = (size_t)d[i].nrhs * 3 * g.Vh * 16;
         if (overlap(d[i].b, fb, d[i].x, fb)) return invalid("batch: b and x overlap");
     }
+    return STG_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// normal operator
+// ---------------------------------------------------------------------------
+namespace {
+
+int check_normal(const stg_lattice *lat, const stg_gauge *gauge, int field, int nrhs,
+                 const void *in_even, const void *out_even, Geom &g) {
+    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
+    if (field != STG_C128 && field != STG_C64) return invalid("unknown field type");
+    int rc = check_gauge(g, gauge, field);
+    if (rc) return rc;
+    if (nrhs < 1) return invalid("nrhs < 1");
+    if (!aligned16(in_even) || !aligned16(out_even))
+        return invalid("field NULL or not 16-byte aligned");
+    const size_t fb = (size_t)nrhs * 3 * g.Vh * field_elem(field);
+    if (overlap(in_even, fb, out_even, fb)) return invalid("fields overlap");
+    return STG_OK;
+}
+
+// out = diag in - D_eo D_oe in, with tmp (odd parity, same shape) receiving D_oe in.
+int apply_normal(const Geom &g, const stg_gauge *gauge, int field, int nrhs, double mass,
+                 double sigma, const void *in_even, void *out_even, void *tmp_odd,
+                 hipStream_t s) {
+    int rc = hop_plain(g, gauge, field, nrhs, in_even, tmp_odd, 1, s);
+    if (rc) return rc;
+    const size_t f1 = (size_t)3 * g.Vh * field_elem(field);
+    HopArgs a = base_hop(g, gauge);
+    a.out_parity = 0;
+    a.op = OP_NONE;
+    a.diag = mass * mass + sigma;
+    const int cap = field_cap(g, gauge->fmt);
+    for (int j0 = 0; j0 < nrhs;) {
+        int nr = chunk_of(nrhs - j0, cap);
+        a.in = (const char *)tmp_odd + j0 * f1;
+        a.out = (char *)out_even + j0 * f1;
+        a.aux0 = (const char *)in_even + j0 * f1;
+        HOP_TRY(hop(a, gauge->fmt, nr, EPI_NORMAL, s));
+        j0 += nr;
+    }
+    HIP_TRY(hipGetLastError());
     return STG_OK;
 }
 
@@ -1559,36 +1640,14 @@ int stg_apply_normal(const stg_lattice *lat, const stg_gauge *gauge, stg_field f
                      double mass, double sigma, const void *in_even, void *out_even,
                      void *tmp_odd, stg_stream_t stream) {
     Geom g;
-    if (!make_geom(lat, g)) return invalid("lattice extents must be even, >= 2, Vh < 2^30");
-    if (field != STG_C128 && field != STG_C64) return invalid("unknown field type");
-    int rc = check_gauge(g, gauge, field);
+    int rc = check_normal(lat, gauge, field, nrhs, in_even, out_even, g);
     if (rc) return rc;
-    if (nrhs < 1) return invalid("nrhs < 1");
-    if (!aligned16(in_even) || !aligned16(out_even) || !aligned16(tmp_odd))
-        return invalid("field NULL or not 16-byte aligned");
+    if (!aligned16(tmp_odd)) return invalid("field NULL or not 16-byte aligned");
     const size_t fb = (size_t)nrhs * 3 * g.Vh * field_elem(field);
-    if (overlap(in_even, fb, out_even, fb) || overlap(in_even, fb, tmp_odd, fb) ||
-        overlap(out_even, fb, tmp_odd, fb))
+    if (overlap(in_even, fb, tmp_odd, fb) || overlap(out_even, fb, tmp_odd, fb))
         return invalid("fields overlap");
-    hipStream_t s = (hipStream_t)stream;
-    rc = hop_plain(g, gauge, field, nrhs, in_even, tmp_odd, 1, s);
-    if (rc) return rc;
-    const size_t f1 = (size_t)3 * g.Vh * field_elem(field);
-    HopArgs a = base_hop(g, gauge);
-    a.out_parity = 0;
-    a.op = OP_NONE;
-    a.diag = mass * mass + sigma;
-    const int cap = field_cap(g, gauge->fmt);
-    for (int j0 = 0; j0 < nrhs;) {
-        int nr = chunk_of(nrhs - j0, cap);
-        a.in = (const char *)tmp_odd + j0 * f1;
-        a.out = (char *)out_even + j0 * f1;
-        a.aux0 = (const char *)in_even + j0 * f1;
-        HOP_TRY(hop(a, gauge->fmt, nr, EPI_NORMAL, s));
-        j0 += nr;
-    }
-    HIP_TRY(hipGetLastError());
-    return STG_OK;
+    return apply_normal(g, gauge, field, nrhs, mass, sigma, in_even, out_even, tmp_odd,
+                        (hipStream_t)stream);
 }
 
 size_t stg_dot_workspace_bytes(void) {

@@ -109,7 +109,8 @@ static int launch_nr(const HopArgs &a, int epi, hipStream_t stream) {
         launch_multi<T, FMT, STDPH, NR, (NR <= 2)>(a, epi, grid, stream);
     else
         launch_multi<T, FMT, STDPH, NR, false>(a, epi, grid, stream);
-    if (reduce) {
+    if (a.grid_out) *a.grid_out = grid.x;
+    if (reduce && !a.defer_finish) {
         FinArgs f{a.partials, grid.x, NR, a.op, a.gate_running, a.ctl, a.state, a.out_sums};
         launch_finalize(f, stream);
     }

@@ -31,6 +31,8 @@ __global__ __launch_bounds__(kBlock) void hop_split_kernel(HopArgs a) {
     if (a.gate_running && a.ctl->n_running == 0) return;
     constexpr int SPB = kBlock / TPS;  // sites per block, a multiple of the wave size
     constexpr int DPT = 4 / TPS;       // directions per thread
+    static_assert(split_lds_bytes(sizeof(cpx<T>), NR, TPS) <= kSplitLdsMax,
+                  "partial sums exceed the LDS budget of one block");
     __shared__ cpx<T> part[TPS - 1][NR][3][SPB];
 
     const Geom &g = a.geom;
@@ -104,7 +106,8 @@ static int launch_tps(const HopArgs &a, int epi, hipStream_t stream) {
             hop_split_kernel<T, FMT, STDPH, NR, EPI_RESID, TPS><<<grid, kBlock, 0, stream>>>(a);
             break;
     }
-    if (reduce) {
+    if (a.grid_out) *a.grid_out = grid.x;
+    if (reduce && !a.defer_finish) {
         FinArgs f{a.partials, grid.x, NR, a.op, a.gate_running, a.ctl, a.state, a.out_sums};
         launch_finalize(f, stream);
     }

@@ -36,6 +36,8 @@ struct HopArgs {
     size_t partial_pairs; // (sum, error) pairs that fit in partials; a launch with a
                           // reduction that needs more is refused
     double *out_sums;     // OP_STORE destination [NR]
+    int defer_finish;     // 1: leave the block partials to the next kernel (no finalize)
+    uint32_t *grid_out;   // host: receives the launch's block count (partials per field)
 
     __device__ __forceinline__ double st_diag(int j) const {
         return state ? state[j].diag : diag;
@@ -161,12 +163,25 @@ struct VecArgs {
     size_t kstride;       // complex elements between shifts (nrhs * 3 * Vh)
     int nshift;
     int pad2_;
+    // single-field CG with the reductions finished in the consumers: the block
+    // partials of the previous kernel, and the state buffer the next iteration reads
+    const double *fin_partials;
+    uint32_t fin_blocks;
+    int pad3_;
+    SysState *state_out;
 };
 
 // x += alpha p; r -= alpha q; |r|^2 -> OP_BETA  (running systems)
 int launch_cg_update(const VecArgs &a, int fp64, int nr, hipStream_t stream);
 // p = r + beta p  (running systems)
 int launch_p_update(const VecArgs &a, int fp64, int nr, hipStream_t stream);
+// One field: alpha = rr / <p, q> finished from a.fin_partials in every block, then
+// x += alpha p, r -= alpha q and the block partials of |r|^2 (no state written).
+int launch_cg_update_fused(const VecArgs &a, int fp64, hipStream_t stream);
+// One field: |r|^2 finished from a.fin_partials in every block, the beta step on a
+// copy of a.state, p = r + beta p while the system runs; block 0 writes the new
+// state to a.state_out (never a.state, which other blocks are reading).
+int launch_p_update_fused(const VecArgs &a, int fp64, hipStream_t stream);
 // x64 += x32; x32 = 0  (parked systems)
 int launch_ru_accumulate(const VecArgs &a, int nr, hipStream_t stream);
 // r_inner = r64 (rounded); p = r_inner + beta p  (systems just resumed)

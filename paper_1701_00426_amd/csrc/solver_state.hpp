@@ -98,6 +98,33 @@ __device__ __forceinline__ bool block_gate_closed(const Ctl *ctl, int gate) {
 
 __device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < 1.0e300; }
 
+// The CG step after |r_new|^2 = sum on a running system: beta = sum / |r|^2, or the
+// system parks for a true-residual update (sum below the target, or dropped by
+// delta since the largest |r|^2 since the last update), stops at the iteration cap,
+// or breaks down (sum not finite).  Returns true when the system leaves the
+// running state.
+__device__ __forceinline__ bool beta_step(SysState &s, double sum) {
+    s.iter += 1;
+    if (!(sum >= 0.0 && sum < 1.0e300)) {
+        s.flags = SYS_BREAKDOWN;
+        return true;
+    }
+    if (sum > s.maxrr) s.maxrr = sum;
+    if (sum <= s.tol2bb || sum < s.delta2 * s.maxrr) {
+        s.rr_old = s.rr;
+        s.rr = sum;
+        s.flags = SYS_RU_PENDING;
+        return true;
+    }
+    s.beta = sum / s.rr;
+    s.rr = sum;
+    if (s.iter >= s.max_iter) {
+        s.flags = SYS_CAPPED;
+        return true;
+    }
+    return false;
+}
+
 // Scalar step for system j after a reduction (one thread).  Several blocks may run
 // it at once for different systems (the batched finalize), so the running count is
 // changed with atomics only.
@@ -127,26 +154,7 @@ __device__ __forceinline__ void finalize_one(int op, Ctl *ctl, SysState *st, dou
     }
     if (op == OP_BETA) {
         if (!(s.flags & SYS_RUNNING)) return;
-        s.iter += 1;
-        if (!(sum >= 0.0 && sum < 1.0e300)) {
-            s.flags = SYS_BREAKDOWN;
-            atomicAdd(&ctl->n_running, -1);
-            return;
-        }
-        if (sum > s.maxrr) s.maxrr = sum;
-        if (sum <= s.tol2bb || sum < s.delta2 * s.maxrr) {
-            s.rr_old = s.rr;
-            s.rr = sum;
-            s.flags = SYS_RU_PENDING;
-            atomicAdd(&ctl->n_running, -1);
-            return;
-        }
-        s.beta = sum / s.rr;
-        s.rr = sum;
-        if (s.iter >= s.max_iter) {
-            s.flags = SYS_CAPPED;
-            atomicAdd(&ctl->n_running, -1);
-        }
+        if (beta_step(s, sum)) atomicAdd(&ctl->n_running, -1);
         return;
     }
     if (op == OP_RU) {

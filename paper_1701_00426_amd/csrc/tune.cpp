@@ -1,7 +1,7 @@
 // tune.cpp -- launch-shape autotuner of the hop kernels.
 //
-// The paper picks its OpenACC tile sizes per architecture at compile time
-// (Sec. 4.3, TILE0..2; Sec. 5, "the best tile dimensions for each of them").
+// The paper fixes its OpenACC tile sizes per architecture at compile time, after
+// measuring which sizes run fastest on each machine (Sec. 4.3, TILE0..2; Sec. 5).
 // Here the launch shape of the hop is chosen at run time: for a (lattice, link
 // format, fields-per-launch) key the autotuner times every candidate shape on the
 // caller's buffers with HIP events, keeps the fastest in a process-wide table that
