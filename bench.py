@@ -977,6 +977,87 @@ def profile_variants(applies=100):
         del fields, outs
 
 
+# Launch shapes of the hop with 8 fields per launch at 32^4 (D_eo; normal operator):
+# threads per site, layer order (x3 planes per group, 0: half-index order) and the
+# spread epilogue.
+MULTIFIELD_VARIANTS = [
+    ("c64_12", {"tps": 4, "group": 0, "spread": 0}, "default (4 threads per site)"),
+    ("c64_12", {"tps": 4, "group": 4, "spread": 0}, "layer order G=4"),
+    ("c64_12", {"tps": 4, "group": 8, "spread": 0}, "layer order G=8"),
+    ("c64_12", {"tps": 4, "group": 0, "spread": 1}, "spread epilogue"),
+    ("c64_12", {"tps": 4, "group": 4, "spread": 1}, "layer order G=4 + spread"),
+    ("c64_12", {"tps": 4, "group": 8, "spread": 1}, "layer order G=8 + spread"),
+    ("c64_12", {"tps": 2, "group": 8, "spread": 1}, "2 threads, G=8 + spread"),
+    ("c128_12", {"tps": 2, "group": 0, "spread": 0}, "default (2 threads per site)"),
+    ("c128_12", {"tps": 2, "group": 4, "spread": 0}, "layer order G=4"),
+    ("c128_12", {"tps": 2, "group": 8, "spread": 0}, "layer order G=8"),
+    ("c128_12", {"tps": 2, "group": 8, "spread": 1}, "layer order G=8 + spread"),
+    ("c128_12", {"tps": 1, "group": 8, "spread": 0}, "1 thread, G=8"),
+    ("bf16_12", {"tps": 4, "group": 0, "spread": 0}, "default (4 threads per site)"),
+    ("bf16_12", {"tps": 4, "group": 8, "spread": 1}, "layer order G=8 + spread"),
+]
+
+
+def profile_multifield(only=None, applies=100):
+    """For rocprofv3: D_eo and the normal operator with 8 fields per launch at 32^4 in the
+    launch shapes of MULTIFIELD_VARIANTS (all, or the one with index `only`), rotating
+    three link/field copies; one JSON line per variant with HIP-event means and GB/s of
+    the algorithmic bytes (links once + 8 x (in + out) for D_eo)."""
+    import torch
+    import paper_1701_00426_amd as stg
+    import seeded_inputs as si
+    dev = torch.device("cuda:0")
+    vh = stg.half_volume(DIMS)
+    links = torch.from_numpy(si.su3_links(DIMS, 1701, 2, 0)).to(dev)
+    b8 = torch.from_numpy(si.gaussian_field(DIMS, 8, 426, 2, 0, 0)).to(dev)
+    L = stg._lib
+    keys = {"tps": L.STG_TUNE_THREADS_PER_SITE, "group": L.STG_TUNE_LAYER_GROUP,
+            "spread": L.STG_TUNE_SPREAD_EPILOGUE}
+    cache = {}
+    stream = torch.cuda.current_stream()
+    for idx, (fmt, knobs, label) in enumerate(MULTIFIELD_VARIANTS):
+        if only is not None and idx != only:
+            continue
+        if fmt not in cache:
+            cache.clear()
+            torch.cuda.empty_cache()
+            cache[fmt] = [stg.pack_gauge(DIMS, links if i == 0 else links.clone(), fmt)
+                          for i in range(3)]
+        gauges = cache[fmt]
+        cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
+        fields = [b8.to(cdt).clone() for _ in range(3)]
+        outs = [torch.empty_like(fields[0]) for _ in range(3)]
+        tmps = [torch.empty_like(fields[0]) for _ in range(3)]
+        for k, v in knobs.items():
+            stg.stg_set_tuning(keys[k], v)
+        log(f"variant {idx}: {fmt} {label}")
+        dt = time_applies(stg, torch, gauges, fields, outs, 0, applies)
+        for i in range(3):
+            stg.stg_apply_normal(gauges[i], MASS, fields[i], out_even=outs[i], tmp_odd=tmps[i])
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for i in range(applies):
+            stg.stg_apply_normal(gauges[i % 3], MASS, fields[i % 3], out_even=outs[i % 3],
+                                 tmp_odd=tmps[i % 3])
+        t1.record(stream)
+        t1.synchronize()
+        dn = t0.elapsed_time(t1) * 1e-3 / applies
+        for k in keys.values():
+            stg.stg_set_tuning(k, 0)
+        links_b = {"c128_12": 768, "c64_12": 384, "bf16_12": 192}[fmt]
+        field_b = 96 if fmt.startswith("c128") else 48
+        byts = (links_b + 8 * field_b) * vh
+        print(json.dumps({"variant": idx, "format": fmt, "fields": 8, "label": label,
+                          "knobs": knobs, "deo_us": round(dt * 1e6, 2),
+                          "deo_GBs": round(byts / dt / 1e9, 1),
+                          "deo_frac_hbm": round(byts / dt / 1e9 / HBM_PEAK_GBS, 4),
+                          "normal_us": round(dn * 1e6, 2),
+                          "algorithmic_bytes_deo": byts}), flush=True)
+        del fields, outs, tmps
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1014,6 +1095,10 @@ def main():
                     help="for rocprofv3: only the 32^4 FP64-12 staple loop")
     ap.add_argument("--profile-variants", action="store_true",
                     help="for rocprofv3: the hop's launch-shape variants at 32^4, in order")
+    ap.add_argument("--profile-multifield", type=int, nargs="?", const=-1, default=None,
+                    metavar="VARIANT",
+                    help="for rocprofv3: the 8-field hop launch shapes at 32^4 (all, or one "
+                         "index of MULTIFIELD_VARIANTS)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="for rocprofv3 --pmc: a plain 1 GiB device copy, to scale byte counters")
     args = ap.parse_args()
@@ -1026,6 +1111,9 @@ def main():
         return
     if args.profile_variants:
         profile_variants()
+        return
+    if args.profile_multifield is not None:
+        profile_multifield(None if args.profile_multifield < 0 else args.profile_multifield)
         return
     if args.workload == "multishift":
         bench_multishift()

@@ -163,6 +163,20 @@ const char *stg_last_error(void);
  *     cg_solve, multishift_cg_solve, rational_apply; cg_solve_batch keeps its own
  *     tiles of at most 4 fields); more fields share each link read, fewer keep fewer
  *     registers and partial sums per thread.  Only the speed depends on it.
+ *   STG_TUNE_LAYER_GROUP: 0 (default) or G in 1 .. 1024: the order in which the hop
+ *     kernels hand output sites to blocks.  0: half-index order.  G: layer order,
+ *     a layer being one (x2, x3) plane of N0/2 * N1 sites, visited in groups of G'
+ *     consecutive x3 planes (G' the largest divisor of N3 not above G; none above 1
+ *     keeps half-index order), x3 fastest within a group, then x2: a site's x3
+ *     neighbours are read one layer, not one x3 plane, apart, so the input fields
+ *     of several fields per launch stay in L2 between their reads.  Not applied
+ *     with LDS neighbour staging.  It changes which sites share a block, so the
+ *     order of additions in the reductions (not the operator) may change.
+ *   STG_TUNE_SPREAD_EPILOGUE: 0 (default) or 1: with 2 or 4 threads per site and a
+ *     number of fields per launch that is a multiple of it, every thread group adds
+ *     the partial sums of its share of the fields and runs their epilogue (the
+ *     same additions in the same order as when group 0 finishes every field, so
+ *     the results are identical).  Only the speed depends on it.
  * Returns STG_INVALID_ARG for an unknown key or value.
  */
 enum {
@@ -172,7 +186,9 @@ enum {
     STG_TUNE_THREADS_PER_SITE = 3,
     STG_TUNE_STAPLE_THREADS = 4,
     STG_TUNE_PENCIL_TILE = 5,
-    STG_TUNE_FIELDS_PER_LAUNCH = 6
+    STG_TUNE_FIELDS_PER_LAUNCH = 6,
+    STG_TUNE_LAYER_GROUP = 7,
+    STG_TUNE_SPREAD_EPILOGUE = 8
 };
 int stg_set_tuning(int key, int value);
 int stg_get_tuning(int key, int *value);

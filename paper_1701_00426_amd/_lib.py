@@ -36,6 +36,8 @@ STG_TUNE_THREADS_PER_SITE = 3
 STG_TUNE_STAPLE_THREADS = 4
 STG_TUNE_PENCIL_TILE = 5
 STG_TUNE_FIELDS_PER_LAUNCH = 6
+STG_TUNE_LAYER_GROUP = 7
+STG_TUNE_SPREAD_EPILOGUE = 8
 
 # solver modes
 STG_CG_F64 = 0

@@ -38,6 +38,9 @@ int g_threads_per_site = 0;  // 0: by format and fields
 int g_staple_threads = 0;    // 0: by format
 int g_pencil_tile = 0;       // tile shape of the pencil order (pencil.hpp)
 int g_fields_per_launch = 0; // 0: the autotuned choice for the lattice and format, else 8
+int g_layer_group = 0;       // 0: half-index order; G: layer order, G x3 planes per group
+int g_spread_epilogue = 0;   // 1: split hops with fields a multiple of the threads per
+                             // site finish the fields on every thread group
 
 int hip_fail(hipError_t e, const char *what) {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
@@ -127,6 +130,15 @@ int check_gauge(const Geom &g, const stg_gauge *gauge, int field) {
     return STG_OK;
 }
 
+// Planes per group of the layer order for a requested G: the largest divisor of N3
+// not above it (0 keeps the half-index order).
+uint32_t layer_group_for(const Geom &g, int want) {
+    if (want <= 0) return 0;
+    for (uint32_t d = std::min<uint32_t>((uint32_t)want, g.N[3]); d > 1; --d)
+        if (g.N[3] % d == 0) return d;
+    return 0;
+}
+
 HopArgs base_hop(const Geom &g, const stg_gauge *gauge) {
     HopArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -138,6 +150,8 @@ HopArgs base_hop(const Geom &g, const stg_gauge *gauge) {
     a.sites_per_thread = (uint32_t)g_sites_per_thread;
     a.stage_neighbours = (uint32_t)g_stage_neighbours;
     a.threads_per_site = (uint32_t)g_threads_per_site;
+    a.layer_group = layer_group_for(g, g_layer_group);
+    a.spread_epilogue = (uint32_t)g_spread_epilogue;
     return a;
 }
 
@@ -1387,6 +1401,14 @@ int stg_set_tuning(int key, int value) {
                 return invalid("fields per launch takes 0 (automatic), 1, 2, 4 or 8");
             g_fields_per_launch = value;
             return STG_OK;
+        case STG_TUNE_LAYER_GROUP:
+            if (value < 0 || value > 1024) return invalid("layer group takes 0 .. 1024");
+            g_layer_group = value;
+            return STG_OK;
+        case STG_TUNE_SPREAD_EPILOGUE:
+            if (value != 0 && value != 1) return invalid("spread epilogue takes 0 or 1");
+            g_spread_epilogue = value;
+            return STG_OK;
         default: return invalid("unknown tuning key");
     }
 }
@@ -1401,6 +1423,8 @@ int stg_get_tuning(int key, int *value) {
         case STG_TUNE_STAPLE_THREADS: *value = g_staple_threads; return STG_OK;
         case STG_TUNE_PENCIL_TILE: *value = g_pencil_tile; return STG_OK;
         case STG_TUNE_FIELDS_PER_LAUNCH: *value = g_fields_per_launch; return STG_OK;
+        case STG_TUNE_LAYER_GROUP: *value = g_layer_group; return STG_OK;
+        case STG_TUNE_SPREAD_EPILOGUE: *value = g_spread_epilogue; return STG_OK;
         default: return invalid("unknown tuning key");
     }
 }

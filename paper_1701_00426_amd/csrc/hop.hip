@@ -9,8 +9,9 @@
 //                            - phi_mu(x-mu) U_mu(x-mu)^dag psi(x-mu) ]
 // for NR fields at once, so that each link read from memory serves NR mat-vecs.
 // One thread owns one output site; consecutive threads own consecutive half
-// indices, so every link, phase and field access of a wave is one coalesced run
-// (forward links at h, backward links at h - stride_mu, neighbours likewise).
+// indices (in half-index or in layer order, kernels.hpp), so every link, phase and
+// field access of a wave is one coalesced run (forward links at h, backward links
+// at h - stride_mu, neighbours likewise).
 // Links are read with non-temporal loads: they are streamed once per hop and must
 // not evict the neighbour field lines that the surrounding sites re-read from L2.
 //
@@ -48,7 +49,11 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
 #pragma unroll 1
     for (uint32_t k = 0; k < nchunk; ++k) {
     const uint32_t chunk0 = (blk * a.sites_per_thread + k) * kBlock;
-    const uint32_t h = chunk0 + threadIdx.x;
+    const uint32_t pos = chunk0 + threadIdx.x;
+    // the layer order does not apply with LDS staging (a chunk's neighbours there are
+    // the half-index range around it)
+    const uint32_t h = (!STAGE && a.layer_group && pos < g.Vh)
+                           ? layer_site(g, a.layer_group, pos) : pos;
     vec3<T> acc[NR];
     if constexpr (STAGE) {
         // the block's sites and one x1 row on either side, staged in LDS

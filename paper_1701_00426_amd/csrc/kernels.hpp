@@ -29,6 +29,11 @@ struct HopArgs {
     uint32_t stage_neighbours;  // 1: x0/x1 neighbour fields read from an LDS copy
     uint32_t threads_per_site;  // 0: by format and fields (default_threads_per_site),
                                 // 1, or 2 / 4 threads sharing the directions of a site
+    uint32_t layer_group;       // 0: sites in half-index order; G (divides N3): layer
+                                // order with G planes per group (layer_site)
+    uint32_t spread_epilogue;   // 2 / 4 threads per site, fields a multiple of them:
+                                // each thread group finishes and stores its share of
+                                // the fields (0: group 0 finishes every field)
     double diag;          // m^2 + sigma when state == nullptr
     SysState *state;      // per-field solver state, or nullptr
     Ctl *ctl;
@@ -100,6 +105,24 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
     const uint32_t x = b % kXcds, i = b / kXcds;
     const uint32_t q = nb / kXcds, r = nb % kXcds;
     return x * q + (x < r ? x : r) + i;
+}
+
+// Layer order of the output sites.  A layer is one (x2, x3) plane of nh0 * N1
+// consecutive half indices.  The layers are visited in groups of G consecutive x3
+// planes (G divides N3): x3 fastest within a group, then x2, then the group.  Sites
+// at position pos of this order form each block, so a block's accesses stay
+// contiguous runs, while a site's x3 neighbours are visited one layer (not one
+// whole x3 plane) before or after it: with several fields per launch one x3 plane
+// of the input fields outgrows an XCD's L2 (8 FP32 fields at 32^4: 3.1 MB), and
+// in half-index order every input line came back from memory for each of the three
+// x3 planes that read it.  A bijection of [0, Vh).
+__device__ __forceinline__ uint32_t layer_site(const Geom &g, uint32_t G, uint32_t pos) {
+    const uint32_t L = g.stride[2];               // nh0 * N1 sites per layer
+    const uint32_t lp = pos / L, off = pos - lp * L;
+    const uint32_t gs = G * g.N[2];               // layers per group
+    const uint32_t grp = lp / gs, r = lp - grp * gs;
+    const uint32_t x2 = r / G, x3 = grp * G + (r - x2 * G);
+    return (x2 + g.N[2] * x3) * L + off;
 }
 
 // Blocks of kBlock threads needed to cover Vh sites.

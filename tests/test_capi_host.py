@@ -276,7 +276,7 @@ def test_tuning_knobs(lib):
     assert lib.stg_set_tuning(1, 2) == 0
     assert lib.stg_get_tuning(1, ctypes.byref(v)) == 0 and v.value == 2
     assert lib.stg_set_tuning(1, 1) == 0
-    assert lib.stg_set_tuning(7, 1) == -1 and lib.stg_set_tuning(6 + 2, 1) == -1
+    assert lib.stg_set_tuning(9, 1) == -1 and lib.stg_set_tuning(-1, 1) == -1
     # neighbour staging: 0 or 1, off by default
     assert lib.stg_get_tuning(2, ctypes.byref(v)) == 0 and v.value == 0
     assert lib.stg_set_tuning(2, 2) == -1
@@ -309,6 +309,22 @@ def test_tuning_knobs(lib):
         assert lib.stg_set_tuning(6, good) == 0
         assert lib.stg_get_tuning(6, ctypes.byref(v)) == 0 and v.value == good
     assert lib.stg_set_tuning(6, 0) == 0
+    # layer order: 0 (half-index order) or planes per group 1 .. 1024
+    assert lib.stg_get_tuning(7, ctypes.byref(v)) == 0
+    default = v.value
+    assert lib.stg_set_tuning(7, -1) == -1 and lib.stg_set_tuning(7, 1025) == -1
+    for good in (0, 1, 4, 1024):
+        assert lib.stg_set_tuning(7, good) == 0
+        assert lib.stg_get_tuning(7, ctypes.byref(v)) == 0 and v.value == good
+    assert lib.stg_set_tuning(7, default) == 0
+    # spread epilogue: 0 or 1
+    assert lib.stg_get_tuning(8, ctypes.byref(v)) == 0
+    default = v.value
+    assert lib.stg_set_tuning(8, 2) == -1 and lib.stg_set_tuning(8, -1) == -1
+    for good in (0, 1):
+        assert lib.stg_set_tuning(8, good) == 0
+        assert lib.stg_get_tuning(8, ctypes.byref(v)) == 0 and v.value == good
+    assert lib.stg_set_tuning(8, default) == 0
 
 
 def test_cg_default_params(lib):

@@ -152,6 +152,44 @@ def test_hop_threads_per_site(dims, fmt, nrhs, tps, corc, tuning):
                 assert rel_max(got[j], want[j]) <= TOL[fmt]
 
 
+@pytest.mark.parametrize("group", [0, 2, 3, 4])
+@pytest.mark.parametrize("tps", [1, 2, 4])
+@pytest.mark.parametrize("fmt", ["c128_12", "c64_12", "bf16_12"])
+@pytest.mark.parametrize("dims", [(4, 6, 8, 12), (6, 4, 2, 10), (2, 2, 2, 2)])
+def test_hop_layer_order_and_spread_epilogue(dims, fmt, tps, group, corc, tuning):
+    """The layer order of the output sites (G x3 planes per group) and the spread
+    epilogue (every thread group finishes its share of the fields): D_oe, D_eo and
+    the normal operator of 8 and 4 fields against the oracle; the spread epilogue
+    gives results bitwise equal to group 0 finishing every field."""
+    say(f"layer order G={group} tps={tps} {fmt} {dims}")
+    L = stg._lib
+    tuning(L.STG_TUNE_THREADS_PER_SITE, tps)
+    tuning(L.STG_TUNE_LAYER_GROUP, group)
+    links = si.su3_links(dims, 1701, 14, 0)
+    phases = on.standard_phases(dims)
+    g = stg.pack_gauge(dims, to_dev(links), fmt)
+    cdt = torch.complex128 if fmt.startswith("c128") else torch.complex64
+    for nrhs in (8, 4):
+        v = si.gaussian_field(dims, nrhs, 426, 14, nrhs)
+        dv = to_dev(v).to(cdt)
+        res = {}
+        for spread in (0, 1):
+            tuning(L.STG_TUNE_SPREAD_EPILOGUE, spread)
+            res[spread] = [stg.dirac_apply_oe(g, dv).cpu().numpy(),
+                           stg.dirac_apply_eo(g, dv).cpu().numpy(),
+                           stg.stg_apply_normal(g, 0.2, dv, sigma=0.01).cpu().numpy()]
+        for a, b in zip(res[0], res[1]):
+            assert np.array_equal(a, b)
+        oe, eo, nm = (x.astype(np.complex128) for x in res[1])
+        want_oe = corc.dslash(dims, links, phases, 1, v)
+        want_eo = corc.dslash(dims, links, phases, 0, v)
+        for j in range(nrhs):
+            assert rel_max(oe[j], want_oe[j]) <= TOL[fmt]
+            assert rel_max(eo[j], want_eo[j]) <= TOL[fmt]
+            want_nm = corc.apply_normal(dims, links, phases, 0.2, v[j], sigma=0.01)
+            assert rel_max(nm[j], want_nm) <= TOL[fmt]
+
+
 @pytest.mark.parametrize("tps", [2, 4])
 @pytest.mark.parametrize("fmt", ["c128_12", "c64_12"])
 def test_apply_normal_threads_per_site(fmt, tps, corc, tuning):

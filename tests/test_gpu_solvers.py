@@ -95,6 +95,31 @@ def test_cg_multi_rhs(mode, nrhs, corc, fields_per_launch):
     _check(corc, dims, links, phases, 0.05, b, x.cpu().numpy(), stats, label=mode)
 
 
+@pytest.mark.parametrize("knobs", [(0, 0), (2, 1), (4, 1)], ids=["natural", "G2-spread", "G4-spread"])
+@pytest.mark.parametrize("mode", ["f64", "c64_12"])
+def test_cg_multi_rhs_layer_order(mode, knobs, corc):
+    """8 right-hand sides with the hop's layer order of the sites and the spread
+    epilogue (every thread group finishes its share of the fields), solved to the
+    oracle-checked true residual."""
+    group, spread = knobs
+    dims, nrhs = (4, 6, 4, 8), 8
+    say(f"cg multi-rhs layer order {mode} G={group} spread={spread}")
+    L = stg._lib
+    old = {k: stg.stg_get_tuning(k) for k in (L.STG_TUNE_LAYER_GROUP, L.STG_TUNE_SPREAD_EPILOGUE)}
+    stg.stg_set_tuning(L.STG_TUNE_LAYER_GROUP, group)
+    stg.stg_set_tuning(L.STG_TUNE_SPREAD_EPILOGUE, spread)
+    try:
+        links, phases, b = _problem(dims, (2, 1), nrhs)
+        dl = to_dev(links)
+        hi = stg.pack_gauge(dims, dl, "c128_12")
+        lo = stg.pack_gauge(dims, dl, mode) if mode != "f64" else None
+        x, st, stats = stg.cg_solve(hi, 0.05, to_dev(b), lo=lo, tol=TOL)
+        _check(corc, dims, links, phases, 0.05, b, x.cpu().numpy(), stats, label=mode)
+    finally:
+        for k, v in old.items():
+            stg.stg_set_tuning(k, v)
+
+
 def test_cg_pure_gauge_exact():
     """b = g * plane wave: the GPU CG returns b / lambda (FP64 path)."""
     dims = (4, 4, 6, 8)

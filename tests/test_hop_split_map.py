@@ -117,3 +117,96 @@ def test_removed_variant_unguarded_form_stores_past_the_chunk():
     for nr in (4, 8):
         st = removed_variant_stores(nr, 4, guarded=False)
         assert len(st) == len(set(st)) == nr * 3 * 64
+
+
+def emulate_spread(nr, tps):
+    """The spread epilogue: group q' writes its partial of every field j it does not
+    own (owner o = j // (nr // tps)) to part[r][j] with r = q' if q' < o else q' - 1;
+    after one barrier the owner adds the tps partials in the order q' = 0 .. tps-1
+    (its own from registers) and stores field j.  Checks: every LDS access in bounds,
+    no slot written twice, every slot the owner reads written by the right group for
+    the same (field, colour, site), the same addition order as group 0 finishing
+    every field, and every output entry stored exactly once."""
+    assert nr % tps == 0
+    spb = KBLOCK // tps
+    k = nr // tps
+    shape = (tps - 1, nr, 3, spb)
+    writes, stores = {}, {}
+    for tid in range(KBLOCK):
+        q, l = tid // spb, tid % spb
+        for j in range(nr):
+            o = j // k
+            if o == q:
+                continue
+            r = q if q < o else q - 1
+            for c in range(3):
+                idx = (r, j, c, l)
+                assert all(0 <= idx[i] < shape[i] for i in range(4))
+                assert idx not in writes
+                writes[idx] = (q, j, c, l)
+    for tid in range(KBLOCK):
+        q, l = tid // spb, tid % spb
+        for kk in range(k):
+            j = q * k + kk
+            for c in range(3):
+                order = []
+                for src in range(tps):
+                    if src == q:
+                        order.append(("own", q))
+                    else:
+                        idx = (src if src < q else src - 1, j, c, l)
+                        assert all(0 <= idx[i] < shape[i] for i in range(4))
+                        assert writes[idx] == (src, j, c, l)
+                        order.append(("lds", src))
+                assert [s for _, s in order] == list(range(tps))
+                assert (j, c, l) not in stores
+                stores[(j, c, l)] = q
+    assert len(stores) == nr * 3 * spb
+    assert len(writes) == (tps - 1) * nr * 3 * spb   # the same LDS as the live exchange
+
+
+@pytest.mark.parametrize("nr,tps", [(2, 2), (4, 2), (8, 2), (4, 4), (8, 4)])
+def test_spread_epilogue_exact_and_in_bounds(nr, tps):
+    emulate_spread(nr, tps)
+
+
+def layer_site(dims, G, pos):
+    """Host copy of the layer order (kernels.hpp layer_site): position -> half index."""
+    n0, n1, n2, n3 = dims
+    L = n0 // 2 * n1
+    lp, off = divmod(pos, L)
+    gs = G * n2
+    grp, r = divmod(lp, gs)
+    x2, x3l = divmod(r, G)
+    x3 = grp * G + x3l
+    return (x2 + n2 * x3) * L + off
+
+
+def layer_group_for(n3, want):
+    """Host copy of capi.cpp layer_group_for: the largest divisor of N3 up to want."""
+    if want <= 0:
+        return 0
+    for d in range(min(want, n3), 1, -1):
+        if n3 % d == 0:
+            return d
+    return 0
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 6, 8, 10), (6, 4, 2, 10), (32, 32, 32, 32),
+                                  (24, 24, 24, 48), (16, 16, 16, 32), (10, 2, 4, 2)])
+@pytest.mark.parametrize("want", [1, 2, 3, 4, 8, 16, 1024])
+def test_layer_order_is_a_bijection_with_x3_fastest(dims, want):
+    n0, n1, n2, n3 = dims
+    vh = n0 * n1 * n2 * n3 // 2
+    G = layer_group_for(n3, want)
+    if G == 0:
+        return  # half-index order
+    assert n3 % G == 0
+    hs = [layer_site(dims, G, p) for p in range(vh)]
+    assert sorted(hs) == list(range(vh))
+    L = n0 // 2 * n1
+    # consecutive layers of one group and one x2 differ by one x3 plane
+    for p in range(0, vh - L, L):
+        lp = p // L
+        if (lp % G) != G - 1:
+            assert hs[p + L] - hs[p] == L * n2
