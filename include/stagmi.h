@@ -61,8 +61,9 @@
  *    STG_LINK_C64_12 / STG_LINK_BF16_12 with STG_C64 fields (compute in FP32).
  *
  * Memory ownership: every buffer argument marked "device" is a device pointer
- * owned by the caller; the library allocates no device memory and keeps no
- * pointer after a call returns.  Solvers take a caller-owned device workspace
+ * owned by the caller; the library allocates no device memory (apart from the
+ * fixed scratch array of stg_apply_normal_noalloc, loaded with its code object)
+ * and keeps no pointer after a call returns.  Solvers take a caller-owned device workspace
  * whose size comes from stg_workspace_bytes.  Arguments marked "host" are host
  * memory.  Device buffers must be 16-byte aligned; an input and an output
  * buffer of one call must not overlap.
@@ -270,6 +271,26 @@ int dirac_apply_oe(const stg_lattice *lat, const stg_gauge *gauge, stg_field fie
 int stg_apply_normal(const stg_lattice *lat, const stg_gauge *gauge, stg_field field, int nrhs,
                      double mass, double sigma, const void *in_even, void *out_even,
                      void *tmp_odd, stg_stream_t stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops that forbid allocation): stg_apply_normal without the tmp_odd
+ * argument.  out_even = (mass^2 + sigma) in_even - D_eo D_oe in_even as in
+ * stg_apply_normal (the same kernels, bitwise the same result); the odd-site
+ * intermediate D_oe in_even goes to a device array of fixed size that the library
+ * holds on each GPU it runs on, from its first call there until the process ends
+ * (stg_noalloc_scratch_bytes: 64 MiB).  The call makes no hipMalloc, hipFree or
+ * other allocating call; its first call on a device looks up that device's copy of
+ * the array.  The array keeps the last call's contents (each call overwrites what it
+ * reads), and it is shared by every call on one GPU: calls that overlap in time on
+ * one GPU (other streams, other host threads) race on it and must be serialised by
+ * the caller.  Errors: as stg_apply_normal; STG_WORKSPACE_TOO_SMALL (nothing
+ * launched) when nrhs * 3 * Vh * element size exceeds the array.  Asynchronous.
+ */
+size_t stg_noalloc_scratch_bytes(void);
+int stg_apply_normal_noalloc(const stg_lattice *lat, const stg_gauge *gauge, stg_field field,
+                             int nrhs, double mass, double sigma, const void *in_even,
+                             void *out_even, stg_stream_t stream);
 
 /* Device workspace bytes needed by stg_dot. */
 size_t stg_dot_workspace_bytes(void);

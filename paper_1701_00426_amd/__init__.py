@@ -29,7 +29,8 @@ from ._lib import (STG_C64, STG_C128, STG_CG_F64, STG_CG_MIXED, STG_LINK_BF16_12
 
 __all__ = [
     "Gauge", "pack_gauge", "stg_links_bytes", "stg_pack_links", "stg_pack_phases",
-    "dirac_apply_eo", "dirac_apply_oe", "stg_apply_normal", "stg_dot", "cg_solve",
+    "dirac_apply_eo", "dirac_apply_oe", "stg_apply_normal", "stg_apply_normal_noalloc",
+    "stg_dot", "cg_solve",
     "multishift_cg_solve", "stg_workspace_bytes", "library", "stg_set_tuning", "stg_get_tuning",
     "cg_solve_batch", "rational_apply", "stg_rational_workspace_bytes", "stg_autotune",
     "stg_autotune_load", "stg_autotune_lookup", "stg_autotune_fields_lookup", "gauge_staples", "SYMANZIK_C0", "SYMANZIK_C1",
@@ -317,6 +318,20 @@ def stg_apply_normal(gauge: Gauge, mass: float, in_even: torch.Tensor, sigma: fl
     _lib.check("stg_apply_normal", library().stg_apply_normal(
         ctypes.byref(_lib.lattice(gauge.dims)), ctypes.byref(g), _field_type(in_even), nrhs,
         float(mass), float(sigma), _ptr(in_even), _ptr(out_even), _ptr(tmp_odd), _stream(stream)))
+    return out_even
+
+
+def stg_apply_normal_noalloc(gauge: Gauge, mass: float, in_even: torch.Tensor,
+                             out_even: torch.Tensor, sigma: float = 0.0,
+                             stream=None) -> torch.Tensor:
+    """out = (mass^2 + sigma) in - D_eo D_oe in, the odd intermediate in the library's
+    fixed device scratch array (no allocation by the call; out_even is the caller's)."""
+    vh = half_volume(gauge.dims)
+    nrhs = _nrhs(in_even, vh)
+    g = gauge.c()
+    _lib.check("stg_apply_normal_noalloc", library().stg_apply_normal_noalloc(
+        ctypes.byref(_lib.lattice(gauge.dims)), ctypes.byref(g), _field_type(in_even), nrhs,
+        float(mass), float(sigma), _ptr(in_even), _ptr(out_even), _stream(stream)))
     return out_even
 
 

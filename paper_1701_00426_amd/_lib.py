@@ -113,6 +113,8 @@ SIGNATURES = {
     "gauge_link_update": (_I, [_LAT, _I, _P, _D, _P, _P]),
     "stout_force_backprop": (_I, [_LAT, _G, _D, _P, _P, _P, _P]),
     "stg_apply_normal": (_I, [_LAT, _G, _I, _I, _D, _D, _P, _P, _P, _P]),
+    "stg_noalloc_scratch_bytes": (ctypes.c_size_t, []),
+    "stg_apply_normal_noalloc": (_I, [_LAT, _G, _I, _I, _D, _D, _P, _P, _P]),
     "stg_dot_workspace_bytes": (_S, []),
     "stg_dot": (_I, [_I, _I, _S, _P, _P, ctypes.POINTER(_D), _P, _S, _P]),
     "stg_cg_default_params": (None, [ctypes.POINTER(StgCgParams)]),

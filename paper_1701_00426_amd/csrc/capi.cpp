@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1671,6 +1672,63 @@ int stg_apply_normal(const stg_lattice *lat, const stg_gauge *gauge, stg_field f
     if (overlap(in_even, fb, tmp_odd, fb) || overlap(out_even, fb, tmp_odd, fb))
         return invalid("fields overlap");
     return apply_normal(g, gauge, field, nrhs, mass, sigma, in_even, out_even, tmp_odd,
+                        (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free normal operator
+// ---------------------------------------------------------------------------
+namespace {
+
+// The odd-site intermediate D_oe in of stg_apply_normal_noalloc lives in this
+// array: every GPU the library runs on holds its own copy, from the loading of the
+// library's code object on that device until the process ends.  On the host the
+// name is only a stand-in for the device symbol; host code passes the address that
+// hipGetSymbolAddress returned for the current device, never the name itself.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];  // device address of scratch, per device ordinal
+
+// Device address of scratch on the current device, looked up once per device.
+int noalloc_scratch(void **ptr) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return internal("device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return internal("hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return STG_OK;
+}
+
+}  // namespace
+
+size_t stg_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
+
+int stg_apply_normal_noalloc(const stg_lattice *lat, const stg_gauge *gauge, stg_field field,
+                             int nrhs, double mass, double sigma, const void *in_even,
+                             void *out_even, stg_stream_t stream) {
+    Geom g;
+    int rc = check_normal(lat, gauge, field, nrhs, in_even, out_even, g);
+    if (rc) return rc;
+    const size_t fb = (size_t)nrhs * 3 * g.Vh * field_elem(field);
+    if (fb > kNoAllocScratchBytes) {
+        g_last_error = "stg_apply_normal_noalloc: the odd-site intermediate needs " +
+                       std::to_string(fb) + " bytes, above the library's fixed scratch of " +
+                       std::to_string(kNoAllocScratchBytes) + " bytes";
+        return STG_WORKSPACE_TOO_SMALL;
+    }
+    void *tmp = nullptr;
+    rc = noalloc_scratch(&tmp);
+    if (rc) return rc;
+    return apply_normal(g, gauge, field, nrhs, mass, sigma, in_even, out_even, tmp,
                         (hipStream_t)stream);
 }
 
