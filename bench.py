@@ -779,6 +779,8 @@ def bench_small(reps=5):
     t_eo = timed(lambda: stg.dirac_apply_eo(gauge, b, out))
     t_n = timed(lambda: stg.stg_apply_normal(gauge, mass, b, out_even=out, tmp_odd=tmp))
     best = None
+    key = stg._lib.STG_TUNE_CG_FORM
+    stg.stg_set_tuning(key, 1)  # the classic form first
     for _ in range(reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -788,6 +790,18 @@ def bench_small(reps=5):
         if best is None or dt < best[0]:
             best = (dt, stats[0])
     dt, s0 = best
+    # the same solve in the single-reduction form of CG (the default for one field)
+    stg.stg_set_tuning(key, 2)
+    cbest = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xg, stg_, statsg = stg.cg_solve(gauge, mass, b, tol=TOL)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t0
+        if cbest is None or tg < cbest[0]:
+            cbest = (tg, statsg[0])
+    stg.stg_set_tuning(key, 0)
     # the same solve through the uneven-batch runner (iterations replayed from a hipGraph)
     bbest = None
     for _ in range(reps):
@@ -820,9 +834,13 @@ def bench_small(reps=5):
         "workload": "8^4, m = 0.1, FP64-18 links, 1 RHS: hop, normal operator, FP64 CG to 1e-10",
         "deo_us": round(t_eo * 1e6, 2), "normal_op_us": round(t_n * 1e6, 2),
         "deo_GBs": round(BYTES_PER_SITE["c128_18"] * stg.half_volume(dims) / t_eo / 1e9, 1),
-        "cg_ms": round(dt * 1e3, 3), "cg_iters": s0["iters"],
-        "cg_us_per_iter": round(dt * 1e6 / s0["iters"], 2),
-        "cg_true_rel_resid": s0["true_rel_resid"],
+        "cg_classic_ms": round(dt * 1e3, 3), "cg_classic_iters": s0["iters"],
+        "cg_classic_us_per_iter": round(dt * 1e6 / s0["iters"], 2),
+        "cg_classic_true_rel_resid": s0["true_rel_resid"],
+        "cg_single_reduction_ms": round(cbest[0] * 1e3, 3),
+        "cg_single_reduction_iters": cbest[1]["iters"],
+        "cg_single_reduction_us_per_iter": round(cbest[0] * 1e6 / cbest[1]["iters"], 2),
+        "cg_single_reduction_true_rel_resid": cbest[1]["true_rel_resid"],
         "tuned_shape": {k: v for k, v in choice.items() if k != "us"},
         "deo_us_tuned": round(t_eo_tuned * 1e6, 2),
         "cg_ms_tuned": round(tbest[0] * 1e3, 3),
@@ -993,14 +1011,27 @@ MULTIFIELD_VARIANTS = [
     ("c128_12", {"tps": 2, "group": 8, "spread": 0}, "layer order G=8"),
     ("c128_12", {"tps": 2, "group": 8, "spread": 1}, "layer order G=8 + spread"),
     ("c128_12", {"tps": 1, "group": 8, "spread": 0}, "1 thread, G=8"),
+    ("c64_12", {}, "automatic"),
+    ("c64_12", {"fsplit": 1, "group": 0}, "fields split, 1 per wave"),
+    ("c64_12", {"fsplit": 2, "group": 0}, "fields split, 2 per wave"),
+    ("c64_12", {"fsplit": 1, "group": 4}, "fields split, 1 per wave, G=4"),
+    ("c64_12", {"fsplit": 2, "group": 4}, "fields split, 2 per wave, G=4"),
+    ("c128_12", {"fsplit": 1, "group": 0}, "fields split, 1 per wave"),
+    ("c128_12", {"fsplit": 1, "group": 4}, "fields split, 1 per wave, G=4"),
+    ("c128_12", {"fsplit": 2, "group": 0}, "fields split, 2 per wave"),
     ("bf16_12", {"tps": 4, "group": 0, "spread": 0}, "default (4 threads per site)"),
     ("bf16_12", {"tps": 4, "group": 8, "spread": 1}, "layer order G=8 + spread"),
+    ("bf16_12", {"fsplit": 1, "group": 0}, "fields split, 1 per wave"),
+    ("bf16_12", {"fsplit": 2, "group": 0}, "fields split, 2 per wave"),
+    ("bf16_12", {"fsplit": 1, "group": 4}, "fields split, 1 per wave, G=4"),
+    ("c128_12", {}, "automatic"),
+    ("bf16_12", {}, "automatic"),
 ]
 
 
 def profile_multifield(only=None, applies=100):
     """For rocprofv3: D_eo and the normal operator with 8 fields per launch at 32^4 in the
-    launch shapes of MULTIFIELD_VARIANTS (all, or the one with index `only`), rotating
+    launch shapes of MULTIFIELD_VARIANTS (all, or the indices in the set `only`), rotating
     three link/field copies; one JSON line per variant with HIP-event means and GB/s of
     the algorithmic bytes (links once + 8 x (in + out) for D_eo)."""
     import torch
@@ -1012,11 +1043,11 @@ def profile_multifield(only=None, applies=100):
     b8 = torch.from_numpy(si.gaussian_field(DIMS, 8, 426, 2, 0, 0)).to(dev)
     L = stg._lib
     keys = {"tps": L.STG_TUNE_THREADS_PER_SITE, "group": L.STG_TUNE_LAYER_GROUP,
-            "spread": L.STG_TUNE_SPREAD_EPILOGUE}
+            "spread": L.STG_TUNE_SPREAD_EPILOGUE, "fsplit": L.STG_TUNE_FIELD_SPLIT}
     cache = {}
     stream = torch.cuda.current_stream()
     for idx, (fmt, knobs, label) in enumerate(MULTIFIELD_VARIANTS):
-        if only is not None and idx != only:
+        if only is not None and idx not in only:
             continue
         if fmt not in cache:
             cache.clear()
@@ -1095,10 +1126,13 @@ def main():
                     help="for rocprofv3: only the 32^4 FP64-12 staple loop")
     ap.add_argument("--profile-variants", action="store_true",
                     help="for rocprofv3: the hop's launch-shape variants at 32^4, in order")
-    ap.add_argument("--profile-multifield", type=int, nargs="?", const=-1, default=None,
-                    metavar="VARIANT",
-                    help="for rocprofv3: the 8-field hop launch shapes at 32^4 (all, or one "
-                         "index of MULTIFIELD_VARIANTS)")
+    ap.add_argument("--profile-multifield", nargs="?", const="all", default=None,
+                    metavar="VARIANTS",
+                    help="for rocprofv3: the 8-field hop launch shapes at 32^4 (all, or "
+                         "comma-separated indices of MULTIFIELD_VARIANTS)")
+    ap.add_argument("--cg-form", type=int, default=0, choices=[0, 1, 2],
+                    help="STG_TUNE_CG_FORM for the solves: 0 automatic, 1 classic (two "
+                         "reductions per iteration), 2 single reduction")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="for rocprofv3 --pmc: a plain 1 GiB device copy, to scale byte counters")
     args = ap.parse_args()
@@ -1113,7 +1147,8 @@ def main():
         profile_variants()
         return
     if args.profile_multifield is not None:
-        profile_multifield(None if args.profile_multifield < 0 else args.profile_multifield)
+        pm = args.profile_multifield
+        profile_multifield(None if pm == "all" else {int(v) for v in pm.split(",")})
         return
     if args.workload == "multishift":
         bench_multishift()
@@ -1166,6 +1201,7 @@ def main():
     b_np = si.gaussian_field(DIMS, 1, 426, 2, 0, 0)
     links = torch.from_numpy(links_np).to(dev)
     b = torch.from_numpy(b_np).to(dev)
+    stg.stg_set_tuning(stg._lib.STG_TUNE_CG_FORM, args.cg_form)
 
     # ---- operator bandwidth (value + roofline) ----------------------------------------
     variants = {}
@@ -1275,7 +1311,8 @@ def main():
 
     if args.profile_cg:
         r = step()
-        print(json.dumps({"profile": "CG 32^4", "fp64_s": round(r[0], 4), "mixed_s": round(r[1], 4),
+        print(json.dumps({"profile": "CG 32^4", "cg_form": args.cg_form,
+                          "fp64_s": round(r[0], 4), "mixed_s": round(r[1], 4),
                           "fp64_iters": r[2]["iters"], "mixed_iters": r[3]["iters"]}), flush=True)
         return
     copy_gbs = copy_ceiling(torch)

@@ -172,12 +172,34 @@ const char *stg_last_error(void);
  *     neighbours are read one layer, not one x3 plane, apart, so the input fields
  *     of several fields per launch stay in L2 between their reads.  Not applied
  *     with LDS neighbour staging.  It changes which sites share a block, so the
- *     order of additions in the reductions (not the operator) may change.
+ *     order of additions in the reductions (not the operator) may change.  With 0,
+ *     launches that take the field split automatically (STG_TUNE_FIELD_SPLIT) use
+ *     G = 4.
  *   STG_TUNE_SPREAD_EPILOGUE: 0 (default) or 1: with 2 or 4 threads per site and a
  *     number of fields per launch that is a multiple of it, every thread group adds
  *     the partial sums of its share of the fields and runs their epilogue (the
  *     same additions in the same order as when group 0 finishes every field, so
  *     the results are identical).  Only the speed depends on it.
+ *   STG_TUNE_FIELD_SPLIT: 0 (default: automatic), -1 (off) or F in 1, 2: a hop
+ *     launch with 2, 3, 4 or 8 fields and 12-real links runs with the fields split
+ *     over the waves of a block, F fields per wave (F must divide the fields of the
+ *     launch), 64 sites per block: each wave sums all four directions of its fields,
+ *     and the block reads its sites' links from memory once into LDS, where every
+ *     wave reads them.  F takes precedence over STG_TUNE_THREADS_PER_SITE for such
+ *     launches.  Automatic, when STG_TUNE_THREADS_PER_SITE is automatic too: launches
+ *     of 8 fields take F = 1 with FP64-12 links and F = 2 with FP32-12 / BF16-12
+ *     links; other launches keep the threads per site.  It changes the order of
+ *     additions, so results may differ in the last bits.
+ *   STG_TUNE_CG_FORM: 0 (default: automatic: form 2 for a solve of one field, else
+ *     form 1), 1 or 2: the form of
+ *     the CG iteration of cg_solve and of the refinement stage of
+ *     multishift_cg_solve / rational_apply.  1: the classic iteration of Sec. 2.2
+ *     (<p, A p> -> alpha, then |r|^2 -> beta: two global reductions per iteration).
+ *     2: the single-reduction form of Chronopoulos and Gear (w = A r; |r|^2 and
+ *     <r, w> -> alpha and beta together; s = A p kept by recurrence), the same
+ *     iterates in exact arithmetic with one reduction and fewer launches per
+ *     iteration; the convergence test of an update runs one iteration later.
+ *     Results differ from form 1 by rounding; both reach the requested true residual.
  * Returns STG_INVALID_ARG for an unknown key or value.
  */
 enum {
@@ -189,7 +211,9 @@ enum {
     STG_TUNE_PENCIL_TILE = 5,
     STG_TUNE_FIELDS_PER_LAUNCH = 6,
     STG_TUNE_LAYER_GROUP = 7,
-    STG_TUNE_SPREAD_EPILOGUE = 8
+    STG_TUNE_SPREAD_EPILOGUE = 8,
+    STG_TUNE_FIELD_SPLIT = 9,
+    STG_TUNE_CG_FORM = 10
 };
 int stg_set_tuning(int key, int value);
 int stg_get_tuning(int key, int *value);

@@ -38,6 +38,8 @@ STG_TUNE_PENCIL_TILE = 5
 STG_TUNE_FIELDS_PER_LAUNCH = 6
 STG_TUNE_LAYER_GROUP = 7
 STG_TUNE_SPREAD_EPILOGUE = 8
+STG_TUNE_FIELD_SPLIT = 9
+STG_TUNE_CG_FORM = 10
 
 # solver modes
 STG_CG_F64 = 0

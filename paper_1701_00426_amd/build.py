@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libstagmi.so")
-SOURCES = ["hop.hip", "hop_split.hip", "blas.hip", "batch.hip", "staple.hip", "force.hip",
+SOURCES = ["hop.hip", "hop_split.hip", "hop_fsplit.hip", "blas.hip", "batch.hip", "staple.hip", "force.hip",
            "capi.cpp", "tune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -99,8 +99,13 @@ __device__ void bhop_tile(const BArgs &a, const BSolve &S, const BTile &t) {
 #pragma unroll
     for (int j = 0; j < NR; ++j) ps[j] = pc[j] = 0.0;
     if (h < g.Vh) {
+        // one direction at a time: the persistent kernel holds the registers of its
+        // largest tile variant for every tile, so no variant may unroll all four
         vec3<T> acc[NR];
-        hop_site<T, FMT, STDPH, NR>(g, a.out_parity, h, links, phases, in, fs, acc);
+        const Site s = site_coords(g, a.out_parity, h);
+        zero_acc<T, NR>(acc);
+        hop_dirs<T, FMT, STDPH, NR, 0, 4, 1>(g, a.out_parity, h, s, links, phases,
+                                             GlobalNb<T>{in, fs, g.Vh}, acc);
         bhop_epilogue<T, NR, EPI>(a, S, t, h, acc, ps, pc);
     }
     if (EPI != EPI_PLAIN) {
@@ -117,23 +122,127 @@ __device__ void bhop_tile(const BArgs &a, const BSolve &S, const BTile &t) {
     }
 }
 
+// The tile with TPS threads per site: in each of TPS passes the block covers
+// SPB = kBlock / TPS sites, thread group q (whole waves) sums directions
+// q * 4/TPS .. (q + 1) * 4/TPS - 1 of every site, the groups' partial sums meet in
+// LDS (lds: [TPS - 1][NR][3][SPB] entries) and group 0 adds them in the order
+// q = 1, 2, 3 and runs the epilogue.
+template <typename T, int FMT, bool STDPH, int NR, int EPI, int TPS, int Q>
+__device__ __forceinline__ void bgroup_dirs(const Geom &g, int P, uint32_t h, const Site &s,
+                                            const void *links, const void *phases,
+                                            const GlobalNb<T> &nb, vec3<T> (&acc)[NR]) {
+    constexpr int DPT = 4 / TPS;
+    hop_dirs<T, FMT, STDPH, NR, Q * DPT, DPT, 1>(g, P, h, s, links, phases, nb, acc);
+}
+
+template <typename T, int FMT, bool STDPH, int NR, int EPI, int TPS>
+__device__ void bhop_tile_split(const BArgs &a, const BSolve &S, const BTile &t, void *lds) {
+    constexpr int SPB = kBlock / TPS;
+    auto part = reinterpret_cast<cpx<T>(*)[NR][3][SPB]>(lds);
+    const Geom &g = S.g;
+    const int P = a.out_parity;
+    const size_t fs = (size_t)3 * g.Vh;
+    const size_t e = sizeof(T) * 2;
+    const bool hi = a.use_hi;
+    const void *links = hi ? S.hi_links : S.lo_links;
+    const void *phases = hi ? S.hi_phases : S.lo_phases;
+    const char *in = (const char *)a.field(S, a.f_in) + t.j0 * fs * e;
+    const GlobalNb<T> nb{in, fs, g.Vh};
+    const int q = threadIdx.x / SPB;  // the same in a whole wave
+    const int l = threadIdx.x % SPB;
+    double ps[NR], pc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) ps[j] = pc[j] = 0.0;
+#pragma unroll 1
+    for (int sub = 0; sub < TPS; ++sub) {
+        const uint32_t h = t.blk * kBlock + sub * SPB + l;
+        const bool live = h < g.Vh;
+        vec3<T> acc[NR];
+        zero_acc<T, NR>(acc);
+        if (live) {
+            const Site s = site_coords(g, P, h);
+            if (q == 0)
+                bgroup_dirs<T, FMT, STDPH, NR, EPI, TPS, 0>(g, P, h, s, links, phases, nb, acc);
+            else if (q == 1)
+                bgroup_dirs<T, FMT, STDPH, NR, EPI, TPS, 1>(g, P, h, s, links, phases, nb, acc);
+            else if (TPS == 4 && q == 2)
+                bgroup_dirs<T, FMT, STDPH, NR, EPI, TPS, (TPS == 4 ? 2 : 0)>(g, P, h, s, links,
+                                                                              phases, nb, acc);
+            else if (TPS == 4)
+                bgroup_dirs<T, FMT, STDPH, NR, EPI, TPS, (TPS == 4 ? 3 : 0)>(g, P, h, s, links,
+                                                                              phases, nb, acc);
+        }
+        if (q > 0) {
+#pragma unroll
+            for (int j = 0; j < NR; ++j)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) part[q - 1][j][c][l] = acc[j].c[c];
+        }
+        __syncthreads();
+        if (q == 0 && live) {
+#pragma unroll
+            for (int r = 0; r < TPS - 1; ++r)
+#pragma unroll
+                for (int j = 0; j < NR; ++j)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const cpx<T> v = part[r][j][c][l];
+                        acc[j].c[c].re += v.re;
+                        acc[j].c[c].im += v.im;
+                    }
+            bhop_epilogue<T, NR, EPI>(a, S, t, h, acc, ps, pc);
+        }
+        __syncthreads();  // the next pass overwrites the partial sums
+    }
+    if (EPI != EPI_PLAIN) {
+        __shared__ double sh_red[2 * kWaves];
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            block_sum_pair(ps[j], pc[j], sh_red);
+            if (threadIdx.x == 0) {
+                double *pj = a.partials + 2 * ((size_t)S.part0 + (size_t)(t.j0 + j) * S.nblk + t.blk);
+                pj[0] = ps[j];
+                pj[1] = pc[j];
+            }
+        }
+    }
+}
+
+// LDS of the split tiles: the largest is 4 fields with 4 threads per site
+template <typename T>
+constexpr size_t bhop_lds_bytes() {
+    return (size_t)3 * 4 * 3 * (kBlock / 4) * sizeof(cpx<T>);
+}
+
+template <typename T, int FMT, bool STDPH, int NR, int EPI>
+__device__ __forceinline__ void bhop_tile_any(const BArgs &a, const BSolve &S, const BTile &t,
+                                              void *lds) {
+    if (t.tps == 4)
+        bhop_tile_split<T, FMT, STDPH, NR, EPI, 4>(a, S, t, lds);
+    else if (t.tps == 2)
+        bhop_tile_split<T, FMT, STDPH, NR, EPI, 2>(a, S, t, lds);
+    else
+        bhop_tile<T, FMT, STDPH, NR, EPI>(a, S, t);
+}
+
 template <typename T, int FMT, int EPI>
 __global__ __launch_bounds__(kBlock) void bhop_kernel(BArgs a) {
     if (a.gate_running && a.ctl->n_running == 0) return;
+    __shared__ __align__(16) char lds[bhop_lds_bytes<T>()];
     FOR_EACH_TILE(a, ti) {
         const BTile t = a.tiles[ti];
         const BSolve &S = a.solves[t.solve];
         if (!tile_active(a, S, t)) continue;
         const bool stdph = (a.use_hi ? S.hi_phases : S.lo_phases) == nullptr;
         switch (t.nr * 2 + (stdph ? 1 : 0)) {
-            case 3: bhop_tile<T, FMT, true, 1, EPI>(a, S, t); break;
-            case 2: bhop_tile<T, FMT, false, 1, EPI>(a, S, t); break;
-            case 5: bhop_tile<T, FMT, true, 2, EPI>(a, S, t); break;
-            case 4: bhop_tile<T, FMT, false, 2, EPI>(a, S, t); break;
-            case 7: bhop_tile<T, FMT, true, 3, EPI>(a, S, t); break;
-            case 6: bhop_tile<T, FMT, false, 3, EPI>(a, S, t); break;
-            case 9: bhop_tile<T, FMT, true, 4, EPI>(a, S, t); break;
-            default: bhop_tile<T, FMT, false, 4, EPI>(a, S, t); break;
+            case 3: bhop_tile_any<T, FMT, true, 1, EPI>(a, S, t, lds); break;
+            case 2: bhop_tile_any<T, FMT, false, 1, EPI>(a, S, t, lds); break;
+            case 5: bhop_tile_any<T, FMT, true, 2, EPI>(a, S, t, lds); break;
+            case 4: bhop_tile_any<T, FMT, false, 2, EPI>(a, S, t, lds); break;
+            case 7: bhop_tile_any<T, FMT, true, 3, EPI>(a, S, t, lds); break;
+            case 6: bhop_tile_any<T, FMT, false, 3, EPI>(a, S, t, lds); break;
+            case 9: bhop_tile_any<T, FMT, true, 4, EPI>(a, S, t, lds); break;
+            default: bhop_tile_any<T, FMT, false, 4, EPI>(a, S, t, lds); break;
         }
     }
 }

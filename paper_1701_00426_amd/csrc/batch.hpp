@@ -27,12 +27,15 @@ struct BSolve {
     uint32_t nrhs;
 };
 
-// kBlock consecutive sites (block blk) of one solve for systems j0 .. j0+nr-1.
+// kBlock consecutive sites (block blk) of one solve for systems j0 .. j0+nr-1.  The
+// hop kernel works on a tile with tps threads per site (1, 2 or 4; the directions of
+// a site shared as in hop_split.hip), in tps passes of kBlock / tps sites each.
 struct BTile {
     uint32_t solve;
     uint32_t blk;
     uint16_t j0;
-    uint16_t nr;  // 1 to 4
+    uint8_t nr;   // 1 to 4
+    uint8_t tps;  // threads per site of the hop
 };
 
 struct BSysRef {

@@ -171,6 +171,95 @@ int launch_p_update_fused(const VecArgs &a, int fp64, hipStream_t stream) {
     return 0;
 }
 
+// ---------------------------------------------------------------------------
+// single-reduction CG (Chronopoulos and Gear; solver_state.hpp cgcg_step)
+// ---------------------------------------------------------------------------
+// One site's update of one system: p = r + beta p; s = w + beta s; x += alpha p;
+// r -= alpha s; returns the site's |r_new|^2 in FP64.
+template <typename T>
+__device__ __forceinline__ double cgcg_site(const VecArgs &a, size_t o, uint32_t h, T al, T be) {
+    double rr = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const size_t i = o + (size_t)c * a.Vh + h;
+        cpx<T> r = ld_c<T>(a.r, i), w = ld_c<T>(a.w, i), p = ld_c<T>(a.p, i),
+               sv = ld_c<T>(a.s, i), x = ld_c<T>(a.x, i);
+        p.re = r.re + be * p.re;
+        p.im = r.im + be * p.im;
+        sv.re = w.re + be * sv.re;
+        sv.im = w.im + be * sv.im;
+        x.re += al * p.re;
+        x.im += al * p.im;
+        r.re -= al * sv.re;
+        r.im -= al * sv.im;
+        st_c<T>(a.p, i, p);
+        st_c<T>(a.s, i, sv);
+        st_c<T>(a.x, i, x);
+        st_c<T>(a.r, i, r);
+        rr = fmat((double)r.re, (double)r.re, rr);
+        rr = fmat((double)r.im, (double)r.im, rr);
+    }
+    return rr;
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(kBlock) void cgcg_update_kernel(VecArgs a) {
+    if (a.gate_running && a.ctl->n_running == 0) return;
+    const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+    double ps[NR], pc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        ps[j] = 0.0;
+        pc[j] = 0.0;
+        const SysState &st = a.state[j];
+        if (!(st.flags & SYS_RUNNING) || h >= a.Vh) continue;
+        pair_add(ps[j], pc[j], cgcg_site<T>(a, (size_t)j * a.fstride, h, (T)st.alpha, (T)st.beta),
+                 0.0);
+    }
+    block_partials<NR>(ps, pc, a.partials);
+}
+
+// One field, no finalize kernel: every block sums the hop's <r, w> partials and the
+// previous update's |r|^2 partials in the same fixed order (bitwise the same totals),
+// takes the scalar step on a copy of the state, and updates its sites; block 0 stores
+// the new state in a.state_out (the next iteration's buffer, never a.state, which the
+// other blocks are reading).  Block 0 always runs, so that a.state_out stays current.
+// A breakdown or a system that parks leaves the vectors alone.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void cgcg_update_fused_kernel(VecArgs a) {
+    const bool closed = block_gate_closed(a.ctl, a.gate_running);
+    if (closed && blockIdx.x != 0) return;
+    SysState ns = a.state[0];
+    bool left = false, step = false;
+    double ps[1] = {0.0}, pc[1] = {0.0};
+    if (!closed && (ns.flags & SYS_RUNNING)) {
+        const double delta = block_total(a.fin_partials, a.fin_blocks);
+        // just resumed: gamma comes from the state, the partials are stale
+        const double gamma = (ns.flags & SYS_RESUME) ? 0.0
+                                                     : block_total(a.fin_partials2, a.fin_blocks2);
+        left = cgcg_step(ns, delta, gamma);
+        step = !left;
+        const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+        if (step && h < a.Vh)
+            pair_add(ps[0], pc[0], cgcg_site<T>(a, 0, h, (T)ns.alpha, (T)ns.beta), 0.0);
+    }
+    if (!closed) block_partials<1>(ps, pc, a.partials);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.state_out[0] = ns;
+        if (left) atomicAdd(&a.ctl->n_running, -1);
+    }
+}
+
+int launch_cgcg_update(const VecArgs &a, int fp64, int nr, hipStream_t stream);
+int launch_cgcg_update_fused(const VecArgs &a, int fp64, hipStream_t stream) {
+    dim3 grid(site_blocks(a.Vh));
+    if (fp64)
+        cgcg_update_fused_kernel<double><<<grid, kBlock, 0, stream>>>(a);
+    else
+        cgcg_update_fused_kernel<float><<<grid, kBlock, 0, stream>>>(a);
+    return 0;
+}
+
 // x64 += x32; x32 = 0 for parked systems
 template <int NR>
 __global__ __launch_bounds__(kBlock) void ru_accumulate_kernel(VecArgs a) {
@@ -208,6 +297,7 @@ __global__ __launch_bounds__(kBlock) void ru_resume_kernel(VecArgs a) {
             cpx<double> rd = ld_c<double>(a.r64, i);
             cpx<T> r{(T)rd.re, (T)rd.im};
             if (a.r != a.r64) st_c<T>(a.r, i, r);
+            if (a.skip_p) continue;
             cpx<T> p = ld_c<T>(a.p, i);
             p.re = r.re + be * p.re;
             p.im = r.im + be * p.im;
@@ -339,6 +429,7 @@ STG_VEC_LAUNCHER(launch_cg_update_only, cg_update_kernel)
 STG_VEC_LAUNCHER(launch_p_update, p_update_kernel)
 STG_VEC_LAUNCHER(launch_ru_resume, ru_resume_kernel)
 STG_VEC_LAUNCHER(launch_ms_r_update_only, ms_r_update_kernel)
+STG_VEC_LAUNCHER(launch_cgcg_update, cgcg_update_kernel)
 
 int launch_cg_update(const VecArgs &a, int fp64, int nr, hipStream_t stream) {
     if (launch_cg_update_only(a, fp64, nr, stream)) return -1;
@@ -379,10 +470,13 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(FinArgs f) {
     if (block_gate_closed(f.ctl, f.gate_running)) return;
     const int j = blockIdx.x;
     double tot = block_sum2_pairs(f.partials + 2 * (size_t)j * f.nblocks, (int)f.nblocks, sh_red);
+    double tot2 = 0.0;
+    if (f.op == OP_CGCG)
+        tot2 = block_sum2_pairs(f.partials2 + 2 * (size_t)j * f.nblocks2, (int)f.nblocks2, sh_red);
     if (f.op == OP_MS_ALPHA || f.op == OP_MS_BETA)
         finalize_ms_block(f.op, f.ctl, f.state, j, tot);
     else if (threadIdx.x == 0)
-        finalize_one(f.op, f.ctl, f.state, f.out, j, tot);
+        finalize_one(f.op, f.ctl, f.state, f.out, j, tot, tot2);
 }
 
 int launch_finalize(const FinArgs &f, hipStream_t stream) {

@@ -42,6 +42,10 @@ int g_fields_per_launch = 0; // 0: the autotuned choice for the lattice and form
 int g_layer_group = 0;       // 0: half-index order; G: layer order, G x3 planes per group
 int g_spread_epilogue = 0;   // 1: split hops with fields a multiple of the threads per
                              // site finish the fields on every thread group
+int g_cg_form = 0;           // CG iteration: 0 automatic, 1 two reductions (classic),
+                             // 2 one reduction (Chronopoulos-Gear)
+int g_field_split = 0;       // several fields per launch split over the waves of a block:
+                             // 1 or 2 fields per wave, 0: automatic, -1: off
 
 int hip_fail(hipError_t e, const char *what) {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
@@ -152,7 +156,9 @@ HopArgs base_hop(const Geom &g, const stg_gauge *gauge) {
     a.stage_neighbours = (uint32_t)g_stage_neighbours;
     a.threads_per_site = (uint32_t)g_threads_per_site;
     a.layer_group = layer_group_for(g, g_layer_group);
+    a.layer_group_auto = g_layer_group == 0 ? layer_group_for(g, 4) : 0;
     a.spread_epilogue = (uint32_t)g_spread_epilogue;
+    a.fields_per_wave = g_field_split;
     return a;
 }
 
@@ -242,8 +248,12 @@ struct CgWork {
     SysState *state_alt;  // single-field solves: the other buffer of the double-buffered state
     double *partials;
     double *partials2;    // single-field solves: |r|^2 partials (partials holds <p, A p>)
-    // inner precision (FP64 mode: double fields; MIXED: float fields)
-    void *x_in, *p, *r, *q, *t;
+    double *rr_partials;  // single-reduction CG: |r|^2 partials of the last update, per
+                          // system, [2 buffers][nsys][site blocks][2]
+    int rr_cur = 0;       // buffer of rr_partials the next update reads (one-field fused)
+    // inner precision (FP64 mode: double fields; MIXED: float fields); s = A p of the
+    // single-reduction CG
+    void *x_in, *p, *r, *q, *t, *s;
     // FP64 fields for the true residual (MIXED only; F64 mode aliases r / t)
     void *r64, *t64;
     size_t bytes;
@@ -267,12 +277,14 @@ CgWork carve_cg(const Geom &g, int nsys, int mode, void *ws) {
     w.state_alt = (SysState *)c.take(sizeof(SysState) * (size_t)nsys);
     w.partials = (double *)c.take(sizeof(double) * partial_count(g));
     w.partials2 = (double *)c.take(sizeof(double) * partial_count(g));
+    w.rr_partials = (double *)c.take(sizeof(double) * 2 * 2 * (size_t)nsys * site_blocks(g.Vh));
     if (mode == STG_CG_F64) {
         w.x_in = nullptr;  // the caller's x
         w.p = c.take(f64);
         w.r = c.take(f64);
         w.q = c.take(f64);
         w.t = c.take(f64);
+        w.s = c.take(f64);
         w.r64 = w.r;
         w.t64 = w.t;
     } else {
@@ -281,6 +293,7 @@ CgWork carve_cg(const Geom &g, int nsys, int mode, void *ws) {
         w.r = c.take(f32);
         w.q = c.take(f32);
         w.t = c.take(f32);
+        w.s = c.take(f32);
         w.r64 = c.take(f64);
         w.t64 = c.take(f64);
     }
@@ -300,6 +313,13 @@ int resolve_restart(int restart, int mode, const stg_gauge *lo) {
     return (mode == STG_CG_MIXED && lo && lo->fmt == STG_LINK_BF16_12) ? 1 : 0;
 }
 
+// The form of the CG iteration (STG_TUNE_CG_FORM).  Automatic: the single-reduction
+// form for a solve of one field, where it saves a finalize kernel and a vector pass
+// launch per iteration (measured on MI355X: 8^4 FP64 20.6 -> 17.2 us per iteration;
+// 32^4 FP32-12 inner iteration 116.6 -> 111.6 us), the classic one for several fields,
+// where it measured no faster.
+bool cg_single_reduction(int nsys) { return g_cg_form == 2 || (g_cg_form == 0 && nsys == 1); }
+
 struct CgProblem {
     Geom g;
     const stg_gauge *hi;
@@ -312,6 +332,7 @@ struct CgProblem {
     stg_cg_params prm;
     int group = 0;     // systems s share b[s % group] (multi-shift refinement); 0: group = nsys
     int cap = 8;       // fields per launch (field_cap of the inner links)
+    bool cgcg = false; // the single-reduction form of the iteration
     int chunk(int j0) const {
         const int g = group > 0 ? group : nsys;
         return chunk_of(std::min(nsys - j0, g - j0 % g), cap);
@@ -327,20 +348,110 @@ struct CgProblem {
 // iteration, and re-enter it only through a reliable update, after which the host
 // reads fresh flags: a snapshot one chunk old never skips a running system).
 //
-// A solve of one field runs the iteration in four kernels: D_oe, D_eo with the
-// normal-operator epilogue and <p, q> partials, the x / r update that finishes
-// alpha from those partials in every block, and the p update that finishes |r|^2
-// and takes the beta step in every block.  Its state is double-buffered (the p
+// A solve of one field on a small lattice runs the iteration in four kernels: D_oe,
+// D_eo with the normal-operator epilogue and <p, q> partials, the x / r update that
+// finishes alpha from those partials in every block, and the p update that finishes
+// |r|^2 and takes the beta step in every block.  Its state is double-buffered (the p
 // update writes the next iteration's copy), so w.state and w.state_alt swap after
-// each iteration.  Several fields keep the finalize kernels (one block per field)
-// between the producers and consumers.
-int enqueue_inner_iteration(const CgProblem &P, CgWork &w, const std::vector<SysState> &st,
-                            hipStream_t s) {
+// each iteration.  Several fields, and one field on a large lattice, keep the
+// finalize kernels (one block per field) between the producers and consumers: there
+// every block of a consumer would re-read all the producer's partials before its
+// first vector load (measured at 32^4 on MI355X, one field: the p update took 21.0 us
+// in FP32 and 24.4 us in FP64 that way, against about 7 and 14 us plus a 4.6 us
+// finalize), while on a small lattice every kernel sits at the launch floor and the
+// saved launches win (8^4 FP64: 19.6 us per iteration against 21.9-26.1 with six).
+constexpr uint32_t kFusedFinishMaxVh = 32768;  // half sites: 16^4 and below
+
+// The single-reduction form (Chronopoulos and Gear, solver_state.hpp cgcg_step) runs
+// the iteration in four kernels: t = D_oe r, w = A r with the <r, w> partials (the
+// normal-operator epilogue on r), the finalize kernel (alpha and beta from <r, w> and
+// the |r|^2 partials of the previous update), and one vector update (p, s = A p, x,
+// r) that leaves the |r|^2 partials for the next iteration; a field on a small lattice
+// finishes both sums in the update's blocks instead, three kernels per iteration.
+int enqueue_cgcg_iteration(const CgProblem &P, CgWork &w, const std::vector<SysState> &st,
+                           hipStream_t s) {
     const bool f64 = P.mode == STG_CG_F64;
     const stg_gauge *gg = f64 ? P.hi : P.lo;
     const size_t fb = (size_t)3 * P.g.Vh * (f64 ? 16 : 8);
     void *xin = f64 ? P.x : w.x_in;
-    const bool fused = P.nsys == 1;
+    const bool fused = P.nsys == 1 && P.g.Vh <= kFusedFinishMaxVh;
+    const uint32_t nbu = site_blocks(P.g.Vh);                 // blocks of the update kernel
+    const size_t rr_buf = (size_t)2 * P.nsys * nbu;           // doubles per rr_partials buffer
+    for (int j0 = 0; j0 < P.nsys;) {
+        const int nr = P.chunk(j0);
+        bool any = false;
+        for (int j = j0; j < j0 + nr; ++j) any = any || (st[j].flags & SYS_RUNNING);
+        if (!any) {
+            j0 += nr;
+            continue;
+        }
+        const size_t o = j0 * fb;
+        HopArgs a = base_hop(P.g, gg);
+        a.gate_running = 1;
+        a.ctl = w.ctl;
+        a.state = w.state + j0;
+        a.partials = w.partials;
+        a.partial_pairs = partial_count(P.g) / 2;
+        // t = D_oe r
+        a.out_parity = 1;
+        a.op = OP_NONE;
+        a.in = (const char *)w.r + o;
+        a.out = (char *)w.t + o;
+        HOP_TRY(hop(a, gg->fmt, nr, EPI_PLAIN, s));
+        // w = diag r - D_eo t (into q) ; <r, w> partials
+        uint32_t hop_blocks = 0;
+        a.out_parity = 0;
+        a.op = OP_CGCG;
+        a.in = (const char *)w.t + o;
+        a.out = (char *)w.q + o;
+        a.aux0 = (const char *)w.r + o;
+        a.defer_finish = 1;
+        a.grid_out = &hop_blocks;
+        HOP_TRY(hop(a, gg->fmt, nr, EPI_NORMAL, s));
+        VecArgs v;
+        std::memset(&v, 0, sizeof(v));
+        v.Vh = P.g.Vh;
+        v.fstride = (size_t)3 * P.g.Vh;
+        v.x = (char *)xin + o;
+        v.p = (char *)w.p + o;
+        v.r = (char *)w.r + o;
+        v.w = (const char *)w.q + o;
+        v.s = (char *)w.s + o;
+        v.state = w.state + j0;
+        v.ctl = w.ctl;
+        v.gate_running = 1;
+        if (fused) {
+            v.fin_partials = w.partials;
+            v.fin_blocks = hop_blocks;
+            v.fin_partials2 = w.rr_partials + (size_t)w.rr_cur * rr_buf;
+            v.fin_blocks2 = nbu;
+            v.partials = w.rr_partials + (size_t)(w.rr_cur ^ 1) * rr_buf;
+            v.state_out = w.state_alt;
+            VEC_TRY(launch_cgcg_update_fused(v, f64, s));
+            std::swap(w.state, w.state_alt);
+            w.rr_cur ^= 1;
+        } else {
+            double *rrp = w.rr_partials + (size_t)2 * j0 * nbu;
+            FinArgs f{w.partials, hop_blocks, nr, OP_CGCG, 1, w.ctl, w.state + j0, nullptr,
+                      rrp, nbu};
+            VEC_TRY(launch_finalize(f, s));
+            v.partials = rrp;
+            VEC_TRY(launch_cgcg_update(v, f64, nr, s));
+        }
+        j0 += nr;
+    }
+    HIP_TRY(hipGetLastError());
+    return STG_OK;
+}
+
+int enqueue_inner_iteration(const CgProblem &P, CgWork &w, const std::vector<SysState> &st,
+                            hipStream_t s) {
+    if (P.cgcg) return enqueue_cgcg_iteration(P, w, st, s);
+    const bool f64 = P.mode == STG_CG_F64;
+    const stg_gauge *gg = f64 ? P.hi : P.lo;
+    const size_t fb = (size_t)3 * P.g.Vh * (f64 ? 16 : 8);
+    void *xin = f64 ? P.x : w.x_in;
+    const bool fused = P.nsys == 1 && P.g.Vh <= kFusedFinishMaxVh;
     for (int j0 = 0; j0 < P.nsys;) {
         const int nr = P.chunk(j0);
         bool any = false;
@@ -445,7 +556,10 @@ int enqueue_reliable_update(const CgProblem &P, const CgWork &w, hipStream_t s) 
         v.r64 = (const char *)w.r64 + j0 * fb64;
         v.r = (char *)w.r + j0 * fbin;
         v.p = (char *)w.p + j0 * fbin;
-        VEC_TRY(launch_ru_resume(v, f64, nr, s));
+        // the single-reduction update applies beta itself: only the inner r is rebuilt
+        // (nothing to do in FP64, where r is the true residual already)
+        v.skip_p = P.cgcg ? 1 : 0;
+        if (!(P.cgcg && f64)) VEC_TRY(launch_ru_resume(v, f64, nr, s));
         j0 += nr;
     }
     HIP_TRY(hipGetLastError());
@@ -550,6 +664,7 @@ int run_cg(const CgProblem &P, CgWork w, stg_cg_stats *stats, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(w.ctl, &ctl0, sizeof(Ctl), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(w.state, st.data(), sizeof(SysState) * n, hipMemcpyHostToDevice, s));
     launch_zero(w.p, (size_t)n * fbin, s);
+    if (P.cgcg) launch_zero(w.s, (size_t)n * fbin, s);
     if (!f64) launch_zero(w.x_in, (size_t)n * fbin, s);
     for (int j = 0; j < n; ++j) {
         const void *bj = P.b_at(j, fb64);
@@ -927,6 +1042,7 @@ int run_mscg(const Geom &g, const stg_gauge *hi, const stg_gauge *lo, double mas
     P.x = x;
     P.group = nrhs;
     P.cap = field_cap(g, mode == STG_CG_F64 ? hi->fmt : lo->fmt);
+    P.cgcg = cg_single_reduction(P.nsys);
     P.diag.resize(P.nsys);
     for (int k = 0; k < nshift; ++k)
         for (int j = 0; j < nrhs; ++j) P.diag[(size_t)k * nrhs + j] = mass * mass + shifts[k];
@@ -974,6 +1090,18 @@ struct BatchPlan {
 // Persistent grid: enough blocks for 8 resident per CU on 256 CUs.
 constexpr uint32_t kBatchGrid = 2048;
 
+// Threads per site of a batch tile's hop for a solve's lattice, inner link format and
+// chunk of fields: the autotuner's choice when it has timed that key, else the
+// library's default for the normal-operator hop (several for several fields or a
+// small lattice, else one).
+uint8_t batch_tile_tps(const Geom &g, int fmt, int nr) {
+    TuneChoice c;
+    int tps = tune_lookup(g, fmt, nr, c) ? c.threads_per_site
+                                         : default_threads_per_site(fmt, nr, EPI_NORMAL, g.Vh);
+    if (g_threads_per_site) tps = g_threads_per_site;  // the caller's process-wide choice
+    return (uint8_t)((tps == 2 || tps == 4) ? tps : 1);
+}
+
 // Lays out the batch in ws (ws == nullptr: size only).  Tiles follow the solve
 // order, then the RHS chunks (4 while at least 4 remain, then the rest) of each
 // solve, then the site blocks.
@@ -997,11 +1125,13 @@ int plan_batch(int nsolve, const stg_solve_desc *d, int mode, void *ws, BatchPla
         pairs += S.nblk * S.nrhs;
         for (int j = 0; j < d[i].nrhs; ++j) B.sysref.push_back(BSysRef{(uint32_t)i, (uint32_t)j});
         sys += S.nrhs;
+        const int fmt_in = f64 ? d[i].hi.fmt : d[i].lo.fmt;
         for (int j0 = 0; j0 < d[i].nrhs;) {
             int rem = d[i].nrhs - j0;
             int nr = rem >= 4 ? 4 : rem;
+            const uint8_t tps = batch_tile_tps(g, fmt_in, nr);
             for (uint32_t blk = 0; blk < S.nblk; ++blk)
-                B.tiles.push_back(BTile{(uint32_t)i, blk, (uint16_t)j0, (uint16_t)nr});
+                B.tiles.push_back(BTile{(uint32_t)i, blk, (uint16_t)j0, (uint8_t)nr, tps});
             j0 += nr;
         }
     }
@@ -1410,6 +1540,16 @@ int stg_set_tuning(int key, int value) {
             if (value != 0 && value != 1) return invalid("spread epilogue takes 0 or 1");
             g_spread_epilogue = value;
             return STG_OK;
+        case STG_TUNE_CG_FORM:
+            if (value < 0 || value > 2)
+                return invalid("CG form takes 0 (automatic), 1 (two reductions) or 2 (one)");
+            g_cg_form = value;
+            return STG_OK;
+        case STG_TUNE_FIELD_SPLIT:
+            if (value < -1 || value > 2)
+                return invalid("field split takes -1 (off), 0 (automatic), 1 or 2 fields per wave");
+            g_field_split = value;
+            return STG_OK;
         default: return invalid("unknown tuning key");
     }
 }
@@ -1426,6 +1566,8 @@ int stg_get_tuning(int key, int *value) {
         case STG_TUNE_FIELDS_PER_LAUNCH: *value = g_fields_per_launch; return STG_OK;
         case STG_TUNE_LAYER_GROUP: *value = g_layer_group; return STG_OK;
         case STG_TUNE_SPREAD_EPILOGUE: *value = g_spread_epilogue; return STG_OK;
+        case STG_TUNE_FIELD_SPLIT: *value = g_field_split; return STG_OK;
+        case STG_TUNE_CG_FORM: *value = g_cg_form; return STG_OK;
         default: return invalid("unknown tuning key");
     }
 }
@@ -1804,6 +1946,7 @@ int cg_solve(const stg_lattice *lat, const stg_gauge *hi, const stg_gauge *lo, d
     P.x = x_even;
     P.diag.assign(nrhs, mass * mass);
     P.cap = field_cap(g, mode == STG_CG_F64 ? hi->fmt : lo->fmt);
+    P.cgcg = cg_single_reduction(P.nsys);
     P.prm = *params;
     CgWork w = carve_cg(g, nrhs, mode, ws);
     return run_cg(P, w, stats, (hipStream_t)stream);

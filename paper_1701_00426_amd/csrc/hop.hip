@@ -144,6 +144,18 @@ static int launch_ph(const HopArgs &a, int nr, int epi, hipStream_t stream) {
 // launching for an unsupported combination (checked by the caller beforehand) or
 // when a reduction needs more (sum, error) pairs than a.partial_pairs.
 int launch_hop(const HopArgs &a, int fmt, int nr, int epi, hipStream_t stream) {
+    // fields split over the waves where asked for (or by default, when the threads
+    // per site are left open too) and built
+    int fpw = a.fields_per_wave;
+    const bool automatic = fpw == 0;
+    if (automatic) fpw = a.threads_per_site ? 0 : default_fields_per_wave(fmt, nr);
+    if (fpw > 0 && nr >= 2) {
+        HopArgs b = a;
+        b.fields_per_wave = fpw;
+        if (automatic && b.layer_group == 0) b.layer_group = a.layer_group_auto;
+        const int rc = launch_hop_fsplit(b, fmt, nr, epi, stream);
+        if (rc != -1) return rc;  // launched, or refused for lack of partials
+    }
     // several threads per site where that variant is built, else one
     const uint32_t tps = a.threads_per_site ? a.threads_per_site
                                             : (uint32_t)default_threads_per_site(fmt, nr, epi,

@@ -75,29 +75,71 @@ __device__ __forceinline__ void stage_fill(cpx<T> (*tile)[3][kStageMax], const v
     __syncthreads();
 }
 
+// Neighbour half indices of site h along direction MU and the phases of its forward
+// and backward link.
+template <typename T, bool STDPH, int MU>
+__device__ __forceinline__ void dir_sites(const Geom &g, const Site &s, uint32_t h, int P,
+                                          const void *phases, uint32_t &hf, uint32_t &hb,
+                                          T &pf, T &pb) {
+    hf = nb_fwd(g, s, h, MU);
+    hb = nb_bwd(g, s, h, MU);
+    if (STDPH) {
+        pf = (T)std_phase(g, s, MU, false);
+        pb = (T)std_phase(g, s, MU, true);
+    } else {
+        const T *ph = reinterpret_cast<const T *>(phases);
+        pf = ph[(size_t)(2 * MU + P) * g.Vh + h];
+        pb = ph[(size_t)(2 * MU + 1 - P) * g.Vh + hb];
+    }
+}
+
+// The same for a direction known only at run time: compile-time arms, so that a loop
+// over directions that is not unrolled indexes no per-thread array (the site's
+// coordinates would otherwise go to scratch memory).
+template <typename T, bool STDPH>
+__device__ __forceinline__ void dir_sites_rt(int mu, const Geom &g, const Site &s, uint32_t h,
+                                             int P, const void *phases, uint32_t &hf,
+                                             uint32_t &hb, T &pf, T &pb) {
+    switch (mu) {
+        case 0: dir_sites<T, STDPH, 0>(g, s, h, P, phases, hf, hb, pf, pb); break;
+        case 1: dir_sites<T, STDPH, 1>(g, s, h, P, phases, hf, hb, pf, pb); break;
+        case 2: dir_sites<T, STDPH, 2>(g, s, h, P, phases, hf, hb, pf, pb); break;
+        default: dir_sites<T, STDPH, 3>(g, s, h, P, phases, hf, hb, pf, pb); break;
+    }
+}
+
 // Adds the terms of directions MU0 .. MU0 + ND - 1 at output site h (parity P) to
 // acc[j] for the NR fields: forward link U_mu(x) and neighbour x + mu, backward
-// link U_mu(x - mu)^dag and neighbour x - mu, each times its phase.
-template <typename T, int FMT, bool STDPH, int NR, int MU0, int ND, typename NB>
+// link U_mu(x - mu)^dag and neighbour x - mu, each times its phase.  UNR directions
+// are unrolled (0: HopUnroll's choice).
+template <typename T, int FMT, bool STDPH, int NR, int MU0, int ND, int UNR = 0, typename NB>
 __device__ __forceinline__ void hop_dirs(const Geom &g, int P, uint32_t h, const Site &s,
                                          const void *links, const void *phases, const NB &nb,
                                          vec3<T> (&acc)[NR]) {
-    constexpr int kUnroll = HopUnroll<T, NR>::value < ND ? HopUnroll<T, NR>::value : ND;
+    constexpr int kU = UNR > 0 ? UNR : HopUnroll<T, NR>::value;
+    constexpr int kUnroll = kU < ND ? kU : ND;
 #pragma unroll kUnroll
     for (int d = 0; d < ND; ++d) {
         const int mu = MU0 + d;
-        const uint32_t hf = nb_fwd(g, s, h, mu);
-        const uint32_t hb = nb_bwd(g, s, h, mu);
         const int sf = 2 * mu + P;        // U_mu(x) starts at x
         const int sb = 2 * mu + (1 - P);  // U_mu(x - mu) starts at x - mu
+        uint32_t hf, hb;
         T pf, pb;
-        if (STDPH) {
-            pf = (T)std_phase(g, s, mu, false);
-            pb = (T)std_phase(g, s, mu, true);
+        if constexpr (kUnroll >= ND) {
+            // fully unrolled: mu is a constant in every copy, and the loads of all the
+            // directions are scheduled together
+            hf = nb_fwd(g, s, h, mu);
+            hb = nb_bwd(g, s, h, mu);
+            if (STDPH) {
+                pf = (T)std_phase(g, s, mu, false);
+                pb = (T)std_phase(g, s, mu, true);
+            } else {
+                const T *ph = reinterpret_cast<const T *>(phases);
+                pf = ph[(size_t)sf * g.Vh + h];
+                pb = ph[(size_t)sb * g.Vh + hb];
+            }
         } else {
-            const T *ph = reinterpret_cast<const T *>(phases);
-            pf = ph[(size_t)sf * g.Vh + h];
-            pb = ph[(size_t)sb * g.Vh + hb];
+            dir_sites_rt<T, STDPH>(mu, g, s, h, P, phases, hf, hb, pf, pb);
         }
         su3<T> uf = link_loader<T, FMT>::load(links, g.Vh, sf, h);
 #pragma unroll

@@ -34,6 +34,11 @@ struct HopArgs {
     uint32_t spread_epilogue;   // 2 / 4 threads per site, fields a multiple of them:
                                 // each thread group finishes and stores its share of
                                 // the fields (0: group 0 finishes every field)
+    uint32_t layer_group_auto;  // layer order of automatic field-split launches when
+                                // the caller leaves layer_group at 0 (0: none)
+    int32_t fields_per_wave;    // several fields per launch on the field-split hop
+                                // (hop_fsplit.hip): 1 or 2 fields per wave, 0: by
+                                // format and fields (default_fields_per_wave), -1: off
     double diag;          // m^2 + sigma when state == nullptr
     SysState *state;      // per-field solver state, or nullptr
     Ctl *ctl;
@@ -83,6 +88,8 @@ struct FinArgs {
     Ctl *ctl;
     SysState *state;
     double *out;
+    const double *partials2;  // OP_CGCG: the |r|^2 partials, [nr][nblocks2][2]
+    uint32_t nblocks2;
 };
 int launch_finalize(const FinArgs &f, hipStream_t stream);
 
@@ -142,6 +149,27 @@ constexpr size_t split_lds_bytes(size_t elem_bytes, int nr, int tps) {
 }
 int launch_hop_split(const HopArgs &a, int fmt, int nr, int epi, hipStream_t stream);  // -1: not built, -2: partials too small
 
+// The hop with the fields of a launch split over the waves of a block and the
+// block's links shared through LDS (hop_fsplit.hip): a.fields_per_wave fields per
+// wave, 64 sites per block.  -1: not built for (format, fields, fields per wave),
+// -2: partials too small.
+int launch_hop_fsplit(const HopArgs &a, int fmt, int nr, int epi, hipStream_t stream);
+
+// Fields per wave of the field-split hop when the caller leaves both it and the
+// threads per site open, from 32^4 timings on MI355X with 8 fields (rotating copies):
+// FP64-12 one field per wave (D_eo 206.6 us, normal operator 441.5 us, against 251.1
+// and 537.9 with 2 threads per site), FP32-12 and BF16-12 two (113.8 / 227.7 against
+// 121.9 / 273.8, and 101.7 / 205.8 against 104.1 / 263.9 with 4 threads per site).
+// Other field counts keep the direction-split hop (0).  Such automatic launches also
+// take the layer order with 4 x3 planes per group unless the caller set an order
+// (HopArgs::layer_group_auto): at 32^4 it cut their reads from 1.7 to 1.2 times the
+// algorithmic bytes (FP64-12 D_eo 206.6 -> 192.7 us; FP32-12 about 1 % faster).
+inline int default_fields_per_wave(int fmt, int nr) {
+    if (nr != 8) return 0;
+    if (fmt == FMT_C128_12) return 1;
+    return (fmt == FMT_C64_12 || fmt == FMT_BF16_12) ? 2 : 0;
+}
+
 // Threads per site when the caller leaves the choice open, from hop timings at 32^4
 // on MI355X: one field: one thread per site (the same speed or faster inside CG,
 // and the profiled FP64-12 configuration), except the plain BF16-12 hop (4: 5 %
@@ -192,6 +220,13 @@ struct VecArgs {
     uint32_t fin_blocks;
     int pad3_;
     SysState *state_out;
+    // single-reduction CG: w = A r (from the hop), s = A p (kept by recurrence), and
+    // the |r|^2 partials of the previous update (read by the fused update)
+    const void *w;
+    void *s;
+    const double *fin_partials2;
+    uint32_t fin_blocks2;
+    int skip_p;           // ru_resume: rebuild r only (the update kernel applies beta)
 };
 
 // x += alpha p; r -= alpha q; |r|^2 -> OP_BETA  (running systems)
@@ -205,6 +240,15 @@ int launch_cg_update_fused(const VecArgs &a, int fp64, hipStream_t stream);
 // copy of a.state, p = r + beta p while the system runs; block 0 writes the new
 // state to a.state_out (never a.state, which other blocks are reading).
 int launch_p_update_fused(const VecArgs &a, int fp64, hipStream_t stream);
+// Single-reduction CG (solver_state.hpp cgcg_step), after the scalar step of the
+// finalize kernel: p = r + beta p; s = w + beta s; x += alpha p; r -= alpha s;
+// block partials of |r|^2  (running systems)
+int launch_cgcg_update(const VecArgs &a, int fp64, int nr, hipStream_t stream);
+// One field, the reductions finished in every block: delta from a.fin_partials (the
+// hop's), gamma from a.fin_partials2 (the previous update's), the scalar step on a
+// copy of a.state, the update, |r|^2 partials into a.partials; block 0 writes the new
+// state to a.state_out.
+int launch_cgcg_update_fused(const VecArgs &a, int fp64, hipStream_t stream);
 // x64 += x32; x32 = 0  (parked systems)
 int launch_ru_accumulate(const VecArgs &a, int nr, hipStream_t stream);
 // r_inner = r64 (rounded); p = r_inner + beta p  (systems just resumed)

@@ -82,7 +82,8 @@ enum FinOp {
     OP_BETA = 4,     // sums = |r_new|^2 -> beta, convergence / park test
     OP_RU = 5,       // sums = |b - A x|^2 of parked systems -> done or resume
     OP_MS_ALPHA = 6, // multi-shift: base alpha, then zeta_next and alpha_k of every shift
-    OP_MS_BETA = 7   // multi-shift: base beta, then beta_k, zeta shift and retirement
+    OP_MS_BETA = 7,  // multi-shift: base beta, then beta_k, zeta shift and retirement
+    OP_CGCG = 8      // single-reduction CG: sums = <r, A r>, sums2 = |r|^2 -> alpha, beta
 };
 
 // Gate of the kernels that finish reductions: other blocks of the same launch may
@@ -125,11 +126,57 @@ __device__ __forceinline__ bool beta_step(SysState &s, double sum) {
     return false;
 }
 
+// The scalar step of the single-reduction form of CG (Chronopoulos and Gear): with
+// w = A r, gamma = |r|^2 and delta = <r, w> from one pass,
+//   beta = gamma / gamma_prev,  alpha = gamma / (delta - beta gamma / alpha_prev),
+// then p = r + beta p, s = w + beta s (s = A p by recurrence), x += alpha p,
+// r -= alpha s: the iterates of CG (Sec. 2.2) in exact arithmetic, with one global
+// reduction per iteration instead of two.  gamma is the |r|^2 of the update of the
+// previous iteration, so the convergence and reliable-update tests of that update
+// happen here; just after a true-residual update (SYS_RESUME) gamma and beta come
+// from the update (rr, beta) instead.  Returns true when the system leaves the
+// running state (parked, capped or broken down); alpha and beta are then unused.
+__device__ __forceinline__ bool cgcg_step(SysState &s, double delta, double gamma) {
+    double beta;
+    if (s.flags & SYS_RESUME) {
+        s.flags &= ~SYS_RESUME;
+        gamma = s.rr;
+        beta = s.beta;
+    } else {
+        s.iter += 1;
+        if (!(gamma >= 0.0 && gamma < 1.0e300)) {
+            s.flags = SYS_BREAKDOWN;
+            return true;
+        }
+        if (gamma > s.maxrr) s.maxrr = gamma;
+        if (gamma <= s.tol2bb || gamma < s.delta2 * s.maxrr) {
+            s.rr_old = s.rr;
+            s.rr = gamma;
+            s.flags = SYS_RU_PENDING;
+            return true;
+        }
+        beta = gamma / s.rr;
+        s.rr = gamma;
+        if (s.iter >= s.max_iter) {
+            s.flags = SYS_CAPPED;
+            return true;
+        }
+    }
+    const double den = beta == 0.0 ? delta : delta - beta * gamma / s.alpha;
+    if (!finite_pos(den) || !finite_pos(gamma)) {
+        s.flags = SYS_BREAKDOWN;
+        return true;
+    }
+    s.alpha = gamma / den;
+    s.beta = beta;
+    return false;
+}
+
 // Scalar step for system j after a reduction (one thread).  Several blocks may run
 // it at once for different systems (the batched finalize), so the running count is
 // changed with atomics only.
 __device__ __forceinline__ void finalize_one(int op, Ctl *ctl, SysState *st, double *out, int j,
-                                             double sum) {
+                                             double sum, double sum2 = 0.0) {
     if (op == OP_STORE) {
         out[j] = sum;
         return;
@@ -155,6 +202,11 @@ __device__ __forceinline__ void finalize_one(int op, Ctl *ctl, SysState *st, dou
     if (op == OP_BETA) {
         if (!(s.flags & SYS_RUNNING)) return;
         if (beta_step(s, sum)) atomicAdd(&ctl->n_running, -1);
+        return;
+    }
+    if (op == OP_CGCG) {
+        if (!(s.flags & SYS_RUNNING)) return;
+        if (cgcg_step(s, sum, sum2)) atomicAdd(&ctl->n_running, -1);
         return;
     }
     if (op == OP_RU) {

@@ -276,7 +276,7 @@ def test_tuning_knobs(lib):
     assert lib.stg_set_tuning(1, 2) == 0
     assert lib.stg_get_tuning(1, ctypes.byref(v)) == 0 and v.value == 2
     assert lib.stg_set_tuning(1, 1) == 0
-    assert lib.stg_set_tuning(9, 1) == -1 and lib.stg_set_tuning(-1, 1) == -1
+    assert lib.stg_set_tuning(11, 1) == -1 and lib.stg_set_tuning(-1, 1) == -1
     # neighbour staging: 0 or 1, off by default
     assert lib.stg_get_tuning(2, ctypes.byref(v)) == 0 and v.value == 0
     assert lib.stg_set_tuning(2, 2) == -1
@@ -325,6 +325,18 @@ def test_tuning_knobs(lib):
         assert lib.stg_set_tuning(8, good) == 0
         assert lib.stg_get_tuning(8, ctypes.byref(v)) == 0 and v.value == good
     assert lib.stg_set_tuning(8, default) == 0
+    # field split: 0 (automatic, the default), -1 (off), 1 or 2 fields per wave
+    assert lib.stg_get_tuning(9, ctypes.byref(v)) == 0 and v.value == 0
+    assert lib.stg_set_tuning(9, 3) == -1 and lib.stg_set_tuning(9, -2) == -1
+    for good in (1, 2, -1, 0):
+        assert lib.stg_set_tuning(9, good) == 0
+        assert lib.stg_get_tuning(9, ctypes.byref(v)) == 0 and v.value == good
+    # CG form: 0 (automatic, the default), 1 (two reductions) or 2 (one reduction)
+    assert lib.stg_get_tuning(10, ctypes.byref(v)) == 0 and v.value == 0
+    assert lib.stg_set_tuning(10, 3) == -1 and lib.stg_set_tuning(10, -1) == -1
+    for good in (2, 1, 0):
+        assert lib.stg_set_tuning(10, good) == 0
+        assert lib.stg_get_tuning(10, ctypes.byref(v)) == 0 and v.value == good
 
 
 def test_cg_default_params(lib):
