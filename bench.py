@@ -1031,7 +1031,8 @@ MULTIFIELD_VARIANTS = [
 
 def profile_multifield(only=None, applies=100):
     """For rocprofv3: D_eo and the normal operator with 8 fields per launch at 32^4 in the
-    launch shapes of MULTIFIELD_VARIANTS (all, or the indices in the set `only`), rotating
+    launch shapes of MULTIFIELD_VARIANTS (all, or the indices in the list `only`, in its order
+    and with its repeats), rotating
     three link/field copies; one JSON line per variant with HIP-event means and GB/s of
     the algorithmic bytes (links once + 8 x (in + out) for D_eo)."""
     import torch
@@ -1046,9 +1047,9 @@ def profile_multifield(only=None, applies=100):
             "spread": L.STG_TUNE_SPREAD_EPILOGUE, "fsplit": L.STG_TUNE_FIELD_SPLIT}
     cache = {}
     stream = torch.cuda.current_stream()
-    for idx, (fmt, knobs, label) in enumerate(MULTIFIELD_VARIANTS):
-        if only is not None and idx not in only:
-            continue
+    order = range(len(MULTIFIELD_VARIANTS)) if only is None else only
+    for idx in order:
+        fmt, knobs, label = MULTIFIELD_VARIANTS[idx]
         if fmt not in cache:
             cache.clear()
             torch.cuda.empty_cache()
@@ -1148,7 +1149,7 @@ def main():
         return
     if args.profile_multifield is not None:
         pm = args.profile_multifield
-        profile_multifield(None if pm == "all" else {int(v) for v in pm.split(",")})
+        profile_multifield(None if pm == "all" else [int(v) for v in pm.split(",")])
         return
     if args.workload == "multishift":
         bench_multishift()
