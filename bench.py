@@ -1338,17 +1338,25 @@ def main():
     # ---- dominant kernel roofline --------------------------------------------------
     dt = hop_time[("c128_12", "D_eo")]
     achieved = BYTES_PER_SITE["c128_12"] * vh / dt / 1e9
-    traffic = None
+    traffic = trace_us = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
         if tr.get("kernel_hash") == kernel_hash():
             traffic = tr.get("bytes_per_launch")
+            trace_us = tr.get("trace_mean_launch_us")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "hop_kernel<double, FMT_C128_12, std phases, NR=1, EPI_PLAIN> (D_eo)",
                 "algorithmic_bytes_per_launch": BYTES_PER_SITE["c128_12"] * vh,
-                "mean_launch_us": round(dt * 1e6, 2)}
+                "mean_launch_us": round(dt * 1e6, 2),
+                "timing": f"HIP events on the library's stream around {args.applies} back-to-back "
+                          "launches rotating three link/field copies, in this run",
+                # the rocprofv3 kernel-trace average of the same kernel in the committed
+                # profile (same sources), and the fraction it gives
+                "trace_mean_launch_us": trace_us,
+                "trace_frac": (round(BYTES_PER_SITE["c128_12"] * vh / (trace_us * 1e3)
+                                     / HBM_PEAK_GBS, 4) if trace_us else None)}
 
     out = {
         "metric": METRIC,
