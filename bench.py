@@ -1029,19 +1029,19 @@ MULTIFIELD_VARIANTS = [
 ]
 
 
-def profile_multifield(only=None, applies=100):
-    """For rocprofv3: D_eo and the normal operator with 8 fields per launch at 32^4 in the
+def profile_multifield(only=None, applies=100, nfields=8):
+    """For rocprofv3: D_eo and the normal operator with `nfields` fields per launch at 32^4 in the
     launch shapes of MULTIFIELD_VARIANTS (all, or the indices in the list `only`, in its order
     and with its repeats), rotating
     three link/field copies; one JSON line per variant with HIP-event means and GB/s of
-    the algorithmic bytes (links once + 8 x (in + out) for D_eo)."""
+    the algorithmic bytes (links once + nfields x (in + out) for D_eo)."""
     import torch
     import paper_1701_00426_amd as stg
     import seeded_inputs as si
     dev = torch.device("cuda:0")
     vh = stg.half_volume(DIMS)
     links = torch.from_numpy(si.su3_links(DIMS, 1701, 2, 0)).to(dev)
-    b8 = torch.from_numpy(si.gaussian_field(DIMS, 8, 426, 2, 0, 0)).to(dev)
+    b8 = torch.from_numpy(si.gaussian_field(DIMS, nfields, 426, 2, 0, 0)).to(dev)
     L = stg._lib
     keys = {"tps": L.STG_TUNE_THREADS_PER_SITE, "group": L.STG_TUNE_LAYER_GROUP,
             "spread": L.STG_TUNE_SPREAD_EPILOGUE, "fsplit": L.STG_TUNE_FIELD_SPLIT}
@@ -1080,8 +1080,8 @@ def profile_multifield(only=None, applies=100):
             stg.stg_set_tuning(k, 0)
         links_b = {"c128_12": 768, "c64_12": 384, "bf16_12": 192}[fmt]
         field_b = 96 if fmt.startswith("c128") else 48
-        byts = (links_b + 8 * field_b) * vh
-        print(json.dumps({"variant": idx, "format": fmt, "fields": 8, "label": label,
+        byts = (links_b + nfields * field_b) * vh
+        print(json.dumps({"variant": idx, "format": fmt, "fields": nfields, "label": label,
                           "knobs": knobs, "deo_us": round(dt * 1e6, 2),
                           "deo_GBs": round(byts / dt / 1e9, 1),
                           "deo_frac_hbm": round(byts / dt / 1e9 / HBM_PEAK_GBS, 4),
@@ -1131,6 +1131,8 @@ def main():
                     metavar="VARIANTS",
                     help="for rocprofv3: the 8-field hop launch shapes at 32^4 (all, or "
                          "comma-separated indices of MULTIFIELD_VARIANTS)")
+    ap.add_argument("--mf-fields", type=int, default=8, choices=[2, 3, 4, 8],
+                    help="fields per launch of --profile-multifield")
     ap.add_argument("--cg-form", type=int, default=0, choices=[0, 1, 2],
                     help="STG_TUNE_CG_FORM for the solves: 0 automatic, 1 classic (two "
                          "reductions per iteration), 2 single reduction")
@@ -1149,7 +1151,8 @@ def main():
         return
     if args.profile_multifield is not None:
         pm = args.profile_multifield
-        profile_multifield(None if pm == "all" else [int(v) for v in pm.split(",")])
+        profile_multifield(None if pm == "all" else [int(v) for v in pm.split(",")],
+                           nfields=args.mf_fields)
         return
     if args.workload == "multishift":
         bench_multishift()

@@ -4,11 +4,14 @@
 // paper fixes the lattice extents at compile time (Sec. 4.1 LNH_N0..), so one
 // launch serves one lattice.  Here every kernel of a CG step walks a table of
 // tiles that spans all lattices of the batch: a tile is kBlock consecutive sites of
-// one lattice for a chunk of 1 to 4 right-hand sides.  One launch per step
-// therefore serves every solve, small lattices ride along with large ones, and
-// the launch count does not grow with the number of solves.  A persistent grid
-// deals the tiles round-robin in XCD-aware order; each kernel only touches tiles
-// holding a system in the state it acts on (running, parked or resumed).
+// one lattice for a chunk of 1 to 4 right-hand sides.  One launch per step (per tile
+// class for the hop) therefore serves every solve, small lattices ride along with
+// large ones, and the launch count does not grow with the number of solves.  Each
+// tile (each pass of a tile, for the hop) has a block of its own, in XCD-aware
+// order, so no block carries a second tile's latency; a block whose tile holds no
+// system in the state its kernel acts on (running, parked or resumed) exits.
+
+#include <algorithm>
 
 #include "batch.hpp"
 #include "device_common.hpp"
@@ -26,13 +29,26 @@ __device__ __forceinline__ bool tile_active(const BArgs &a, const BSolve &S, con
     return false;
 }
 
-// Tiles are dealt to the blocks round-robin from the XCD-ordered logical block
-// index: in every round the blocks of one XCD take one contiguous run of tiles
-// (neighbour lines meet in that XCD's L2), and every block gets about the same
-// share of every solve, so the work stays balanced as solves finish.
-#define FOR_EACH_TILE(a, ti)                                              \
-    for (uint32_t ti = xcd_block(blockIdx.x, gridDim.x); ti < (a).ntiles; \
-         ti += gridDim.x)
+// Thread 0 stores the block's (sum, error) pair of system js in slot `slot` of tile
+// t; the writer of slot 0 also clears the slots used .. kTileSlots - 1 that no block
+// of its launch writes.
+__device__ __forceinline__ void put_tile_partial(const BArgs &a, const BSolve &S, const BTile &t,
+                                                 int js, int slot, int used, double sum,
+                                                 double err) {
+    double *pj = a.partials + 2 * (((size_t)S.part0 + (size_t)js * S.nblk + t.blk) * kTileSlots);
+    pj[2 * slot] = sum;
+    pj[2 * slot + 1] = err;
+    if (slot == 0)
+        for (int k = used; k < kTileSlots; ++k) pj[2 * k] = pj[2 * k + 1] = 0.0;
+}
+
+// Tile ti of the vector kernels is block ti: these kernels reuse nothing between
+// tiles, and the hardware deals consecutive blocks to the XCDs in turn, so every
+// XCD gets its share of each solve's tiles however few solves still run.  The
+// launches give every tile a block of its own; the loop only guards a grid smaller
+// than the range.
+#define FOR_EACH_TILE(a, ti) \
+    for (uint32_t ti = (a).tile0 + blockIdx.x; ti < (a).ntiles; ti += gridDim.x)
 
 // Epilogue of a tile's fields at site h (acc = twice the hop): plain, normal
 // operator with Re<p, q> partials, or true residual with |r|^2 partials.
@@ -113,20 +129,16 @@ __device__ void bhop_tile(const BArgs &a, const BSolve &S, const BTile &t) {
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             block_sum_pair(ps[j], pc[j], sh_red);
-            if (threadIdx.x == 0) {
-                double *pj = a.partials + 2 * ((size_t)S.part0 + (size_t)(t.j0 + j) * S.nblk + t.blk);
-                pj[0] = ps[j];
-                pj[1] = pc[j];
-            }
+            if (threadIdx.x == 0) put_tile_partial(a, S, t, t.j0 + j, 0, 1, ps[j], pc[j]);
         }
     }
 }
 
-// The tile with TPS threads per site: in each of TPS passes the block covers
-// SPB = kBlock / TPS sites, thread group q (whole waves) sums directions
-// q * 4/TPS .. (q + 1) * 4/TPS - 1 of every site, the groups' partial sums meet in
-// LDS (lds: [TPS - 1][NR][3][SPB] entries) and group 0 adds them in the order
-// q = 1, 2, 3 and runs the epilogue.
+// Pass `sub` of the tile with TPS threads per site: the block covers the SPB =
+// kBlock / TPS sites sub * SPB .. of the tile, thread group q (whole waves) sums
+// directions q * 4/TPS .. (q + 1) * 4/TPS - 1 of every site, the groups' partial
+// sums meet in LDS (lds: [TPS - 1][NR][3][SPB] entries) and group 0 adds them in the
+// order q = 1, 2, 3 and runs the epilogue.
 template <typename T, int FMT, bool STDPH, int NR, int EPI, int TPS, int Q>
 __device__ __forceinline__ void bgroup_dirs(const Geom &g, int P, uint32_t h, const Site &s,
                                             const void *links, const void *phases,
@@ -136,7 +148,8 @@ __device__ __forceinline__ void bgroup_dirs(const Geom &g, int P, uint32_t h, co
 }
 
 template <typename T, int FMT, bool STDPH, int NR, int EPI, int TPS>
-__device__ void bhop_tile_split(const BArgs &a, const BSolve &S, const BTile &t, void *lds) {
+__device__ void bhop_tile_split(const BArgs &a, const BSolve &S, const BTile &t, int sub,
+                                void *lds) {
     constexpr int SPB = kBlock / TPS;
     auto part = reinterpret_cast<cpx<T>(*)[NR][3][SPB]>(lds);
     const Geom &g = S.g;
@@ -153,8 +166,7 @@ __device__ void bhop_tile_split(const BArgs &a, const BSolve &S, const BTile &t,
     double ps[NR], pc[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) ps[j] = pc[j] = 0.0;
-#pragma unroll 1
-    for (int sub = 0; sub < TPS; ++sub) {
+    {
         const uint32_t h = t.blk * kBlock + sub * SPB + l;
         const bool live = h < g.Vh;
         vec3<T> acc[NR];
@@ -192,59 +204,37 @@ __device__ void bhop_tile_split(const BArgs &a, const BSolve &S, const BTile &t,
                     }
             bhop_epilogue<T, NR, EPI>(a, S, t, h, acc, ps, pc);
         }
-        __syncthreads();  // the next pass overwrites the partial sums
     }
     if (EPI != EPI_PLAIN) {
         __shared__ double sh_red[2 * kWaves];
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             block_sum_pair(ps[j], pc[j], sh_red);
-            if (threadIdx.x == 0) {
-                double *pj = a.partials + 2 * ((size_t)S.part0 + (size_t)(t.j0 + j) * S.nblk + t.blk);
-                pj[0] = ps[j];
-                pj[1] = pc[j];
-            }
+            if (threadIdx.x == 0) put_tile_partial(a, S, t, t.j0 + j, sub, TPS, ps[j], pc[j]);
         }
     }
 }
 
-// LDS of the split tiles: the largest is 4 fields with 4 threads per site
-template <typename T>
-constexpr size_t bhop_lds_bytes() {
-    return (size_t)3 * 4 * 3 * (kBlock / 4) * sizeof(cpx<T>);
-}
-
-template <typename T, int FMT, bool STDPH, int NR, int EPI>
-__device__ __forceinline__ void bhop_tile_any(const BArgs &a, const BSolve &S, const BTile &t,
-                                              void *lds) {
-    if (t.tps == 4)
-        bhop_tile_split<T, FMT, STDPH, NR, EPI, 4>(a, S, t, lds);
-    else if (t.tps == 2)
-        bhop_tile_split<T, FMT, STDPH, NR, EPI, 2>(a, S, t, lds);
-    else
-        bhop_tile<T, FMT, STDPH, NR, EPI>(a, S, t);
-}
-
-template <typename T, int FMT, int EPI>
-__global__ __launch_bounds__(kBlock) void bhop_kernel(BArgs a) {
+// One launch per tile class: every tile of the range has NR fields, TPS threads per
+// site and standard (STDPH) or stored phases on the gauge field of the launch, so the
+// kernel carries only that shape.  Block L
+// of the XCD order takes pass L % TPS of tile tile0 + L / TPS: the grid is TPS
+// blocks per tile, and a block whose tile has no system in the masked state exits.
+template <typename T, int FMT, int EPI, int NR, int TPS, bool STDPH>
+__global__ __launch_bounds__(kBlock) void bhop_class_kernel(BArgs a) {
     if (a.gate_running && a.ctl->n_running == 0) return;
-    __shared__ __align__(16) char lds[bhop_lds_bytes<T>()];
-    FOR_EACH_TILE(a, ti) {
-        const BTile t = a.tiles[ti];
-        const BSolve &S = a.solves[t.solve];
-        if (!tile_active(a, S, t)) continue;
-        const bool stdph = (a.use_hi ? S.hi_phases : S.lo_phases) == nullptr;
-        switch (t.nr * 2 + (stdph ? 1 : 0)) {
-            case 3: bhop_tile_any<T, FMT, true, 1, EPI>(a, S, t, lds); break;
-            case 2: bhop_tile_any<T, FMT, false, 1, EPI>(a, S, t, lds); break;
-            case 5: bhop_tile_any<T, FMT, true, 2, EPI>(a, S, t, lds); break;
-            case 4: bhop_tile_any<T, FMT, false, 2, EPI>(a, S, t, lds); break;
-            case 7: bhop_tile_any<T, FMT, true, 3, EPI>(a, S, t, lds); break;
-            case 6: bhop_tile_any<T, FMT, false, 3, EPI>(a, S, t, lds); break;
-            case 9: bhop_tile_any<T, FMT, true, 4, EPI>(a, S, t, lds); break;
-            default: bhop_tile_any<T, FMT, false, 4, EPI>(a, S, t, lds); break;
-        }
-    }
+    constexpr int NP = TPS > 1 ? TPS - 1 : 1;
+    __shared__ cpx<T> part[NP][NR][3][kBlock / TPS];
+    const uint32_t L = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t ti = a.tile0 + L / TPS;
+    if (ti >= a.ntiles) return;
+    const BTile t = a.tiles[ti];
+    const BSolve &S = a.solves[t.solve];
+    if (!tile_active(a, S, t)) return;
+    if constexpr (TPS == 1)
+        bhop_tile<T, FMT, STDPH, NR, EPI>(a, S, t);
+    else
+        bhop_tile_split<T, FMT, STDPH, NR, EPI, TPS>(a, S, t, (int)(L % TPS), part);
 }
 
 // ---------------------------------------------------------------------------
@@ -287,11 +277,7 @@ __device__ void bcg_update_tile(const BArgs &a, const BSolve &S, const BTile &t,
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         block_sum_pair(ps[j], pc[j], sh_red);
-        if (threadIdx.x == 0) {
-            double *pj = a.partials + 2 * ((size_t)S.part0 + (size_t)(t.j0 + j) * S.nblk + t.blk);
-            pj[0] = ps[j];
-            pj[1] = pc[j];
-        }
+        if (threadIdx.x == 0) put_tile_partial(a, S, t, t.j0 + j, 0, 1, ps[j], pc[j]);
     }
 }
 
@@ -421,11 +407,7 @@ __global__ __launch_bounds__(kBlock) void bnorm_b_kernel(BArgs a) {
                     pair_add(ps, pc, v.im * v.im, 0.0);
                 }
             block_sum_pair(ps, pc, sh_red);
-            if (threadIdx.x == 0) {
-                double *pj = a.partials + 2 * ((size_t)S.part0 + (size_t)js * S.nblk + t.blk);
-                pj[0] = ps;
-                pj[1] = pc;
-            }
+            if (threadIdx.x == 0) put_tile_partial(a, S, t, js, 0, 1, ps, pc);
         }
     }
 }
@@ -437,39 +419,75 @@ __global__ __launch_bounds__(kBlock) void bfinalize_kernel(BArgs a, int op) {
     const uint32_t sys = blockIdx.x;
     const BSysRef ref = a.sysref[sys];
     const BSolve &S = a.solves[ref.solve];
-    double tot = block_sum2_pairs(a.partials + 2 * ((size_t)S.part0 + (size_t)ref.j * S.nblk),
-                                  (int)S.nblk, sh_red);
+    double tot = block_sum2_pairs(
+        a.partials + 2 * (((size_t)S.part0 + (size_t)ref.j * S.nblk) * kTileSlots),
+        (int)(S.nblk * kTileSlots), sh_red);
     if (threadIdx.x == 0) finalize_one(op, a.ctl, a.state, nullptr, (int)sys, tot);
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename T, int FMT>
-static void bhop_launch(const BArgs &a, int epi, hipStream_t s) {
-    dim3 grid(a.grid);
-    if (epi == EPI_PLAIN)
-        bhop_kernel<T, FMT, EPI_PLAIN><<<grid, kBlock, 0, s>>>(a);
-    else if (epi == EPI_NORMAL)
-        bhop_kernel<T, FMT, EPI_NORMAL><<<grid, kBlock, 0, s>>>(a);
+template <typename T, int FMT, int EPI, int NR, bool STDPH>
+static void bhop_launch_ph(const BArgs &a, int tps, hipStream_t s) {
+    const dim3 grid(a.grid);
+    if (tps == 4)
+        bhop_class_kernel<T, FMT, EPI, NR, 4, STDPH><<<grid, kBlock, 0, s>>>(a);
+    else if (tps == 2)
+        bhop_class_kernel<T, FMT, EPI, NR, 2, STDPH><<<grid, kBlock, 0, s>>>(a);
     else
-        bhop_kernel<T, FMT, EPI_RESID><<<grid, kBlock, 0, s>>>(a);
+        bhop_class_kernel<T, FMT, EPI, NR, 1, STDPH><<<grid, kBlock, 0, s>>>(a);
 }
 
-int launch_bhop(const BArgs &a, int fmt, int epi, hipStream_t s) {
-    switch (fmt) {
-        case FMT_C128_18: bhop_launch<double, FMT_C128_18>(a, epi, s); return 0;
-        case FMT_C128_12: bhop_launch<double, FMT_C128_12>(a, epi, s); return 0;
-        case FMT_C64_12:
-            if (epi == EPI_RESID) return -1;
-            bhop_launch<float, FMT_C64_12>(a, epi, s);
-            return 0;
-        case FMT_BF16_12:
-            if (epi == EPI_RESID) return -1;
-            bhop_launch<float, FMT_BF16_12>(a, epi, s);
-            return 0;
-        default: return -1;
+template <typename T, int FMT, int EPI, int NR>
+static void bhop_launch_nr(const BArgs &a, int tps, bool stdph, hipStream_t s) {
+    if (stdph)
+        bhop_launch_ph<T, FMT, EPI, NR, true>(a, tps, s);
+    else
+        bhop_launch_ph<T, FMT, EPI, NR, false>(a, tps, s);
+}
+
+template <typename T, int FMT, int EPI>
+static void bhop_launch(const BArgs &a, int nr, int tps, bool stdph, hipStream_t s) {
+    switch (nr) {
+        case 1: bhop_launch_nr<T, FMT, EPI, 1>(a, tps, stdph, s); return;
+        case 2: bhop_launch_nr<T, FMT, EPI, 2>(a, tps, stdph, s); return;
+        case 3: bhop_launch_nr<T, FMT, EPI, 3>(a, tps, stdph, s); return;
+        default: bhop_launch_nr<T, FMT, EPI, 4>(a, tps, stdph, s); return;
     }
+}
+
+template <typename T, int FMT>
+static void bhop_launch_epi(const BArgs &a, int epi, int nr, int tps, bool stdph, hipStream_t s) {
+    if (epi == EPI_PLAIN)
+        bhop_launch<T, FMT, EPI_PLAIN>(a, nr, tps, stdph, s);
+    else if (epi == EPI_NORMAL)
+        bhop_launch<T, FMT, EPI_NORMAL>(a, nr, tps, stdph, s);
+    else
+        bhop_launch<T, FMT, EPI_RESID>(a, nr, tps, stdph, s);
+}
+
+// Kernel boundary stays the synchronisation point: the classes' launches follow one
+// another on the stream, and the finalize kernel after them sees every tile's partials.
+int launch_bhop(const BArgs &a, const BClass *cls, int ncls, int fmt, int epi, hipStream_t s) {
+    if ((fmt == FMT_C64_12 || fmt == FMT_BF16_12) && epi == EPI_RESID) return -1;
+    if (fmt < FMT_C128_18 || fmt > FMT_BF16_12) return -1;
+    for (int c = 0; c < ncls; ++c) {
+        BArgs b = a;
+        b.tile0 = cls[c].begin;
+        b.ntiles = cls[c].end;
+        b.grid = (cls[c].end - cls[c].begin) * (uint32_t)cls[c].tps;
+        if (b.grid == 0) continue;
+        const int nr = cls[c].nr, tps = cls[c].tps;
+        const bool ph = a.use_hi ? cls[c].std_hi : cls[c].std_lo;
+        switch (fmt) {
+            case FMT_C128_18: bhop_launch_epi<double, FMT_C128_18>(b, epi, nr, tps, ph, s); break;
+            case FMT_C128_12: bhop_launch_epi<double, FMT_C128_12>(b, epi, nr, tps, ph, s); break;
+            case FMT_C64_12: bhop_launch_epi<float, FMT_C64_12>(b, epi, nr, tps, ph, s); break;
+            default: bhop_launch_epi<float, FMT_BF16_12>(b, epi, nr, tps, ph, s); break;
+        }
+    }
+    return 0;
 }
 
 int launch_bfinalize(const BArgs &a, int op, hipStream_t s) {

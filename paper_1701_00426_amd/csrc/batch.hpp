@@ -23,13 +23,20 @@ struct BSolve {
     void *r64, *t64;      // FP64 residual and odd temporary (aliases in FP64 mode)
     uint32_t sys0;   // global index of its first system
     uint32_t nblk;   // blocks of kBlock sites
-    uint32_t part0;  // first partial pair of this solve: system j uses part0 + j*nblk
+    uint32_t part0;  // first partial slot group of this solve (see kTileSlots)
     uint32_t nrhs;
 };
 
+// Partial sums: every tile holds kTileSlots (sum, error) pairs per system, pair
+// ((part0 + j * nblk + blk) * kTileSlots + slot).  The hop launches a tile as tps
+// blocks, one per pass of kBlock / tps sites, and pass k writes slot k; the vector
+// kernels write slot 0.  The writer of slot 0 also zeroes the slots no block of its
+// launch owns, so the finalize sums all kTileSlots * nblk pairs of a system.
+constexpr int kTileSlots = 4;
+
 // kBlock consecutive sites (block blk) of one solve for systems j0 .. j0+nr-1.  The
 // hop kernel works on a tile with tps threads per site (1, 2 or 4; the directions of
-// a site shared as in hop_split.hip), in tps passes of kBlock / tps sites each.
+// a site shared as in hop_split.hip), as tps blocks of kBlock / tps sites each.
 struct BTile {
     uint32_t solve;
     uint32_t blk;
@@ -52,9 +59,10 @@ struct BArgs {
     SysState *state;  // [nsys]
     Ctl *ctl;
     double *partials;
-    uint32_t ntiles;
+    uint32_t ntiles;  // end of the tile range the kernel walks
+    uint32_t tile0;   // its first tile (the hop launches one range per tile class)
     uint32_t nsys;
-    uint32_t grid;    // persistent grid size
+    uint32_t grid;    // blocks of the launch (at most one per tile, or per tile pass)
     int out_parity;
     int use_hi;       // hop on the FP64 gauge field (true residual) or the inner one
     int gate_running;     // exit at once when ctl->n_running == 0
@@ -76,7 +84,16 @@ struct BArgs {
     }
 };
 
-int launch_bhop(const BArgs &a, int fmt, int epi, hipStream_t s);
+// Tiles of one class (fields per tile, threads per site, standard or stored phases
+// on the inner and on the FP64 gauge field) sit in one contiguous range of the tile
+// table; the hop runs one launch per class, so each launch holds only the registers
+// its own tile shape needs.
+struct BClass {
+    uint32_t begin, end;
+    int nr, tps;
+    int std_lo, std_hi;  // 1: the class's solves have standard phases (no phase array)
+};
+int launch_bhop(const BArgs &a, const BClass *cls, int ncls, int fmt, int epi, hipStream_t s);
 int launch_bfinalize(const BArgs &a, int op, hipStream_t s);
 int launch_bcg_update(const BArgs &a, int fp64, hipStream_t s);
 int launch_bp_update(const BArgs &a, int fp64, hipStream_t s);

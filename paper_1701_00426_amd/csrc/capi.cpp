@@ -1074,7 +1074,9 @@ int run_mscg(const Geom &g, const stg_gauge *hi, const stg_gauge *lo, double mas
 // ---------------------------------------------------------------------------
 struct BatchPlan {
     std::vector<BSolve> solves;
-    std::vector<BTile> tiles;
+    std::vector<BTile> sorted;    // every tile, grouped by class
+    std::vector<BTile> tiles;     // the tiles launched: grouped by class, see classes
+    std::vector<BClass> classes;  // contiguous tile ranges of one (fields, threads per site)
     std::vector<BSysRef> sysref;
     uint32_t nsys = 0, npairs = 0;
     // device tables and state (in the workspace)
@@ -1086,9 +1088,6 @@ struct BatchPlan {
     double *partials = nullptr;
     size_t bytes = 0;
 };
-
-// Persistent grid: enough blocks for 8 resident per CU on 256 CUs.
-constexpr uint32_t kBatchGrid = 2048;
 
 // Threads per site of a batch tile's hop for a solve's lattice, inner link format and
 // chunk of fields: the autotuner's choice when it has timed that key, else the
@@ -1102,9 +1101,86 @@ uint8_t batch_tile_tps(const Geom &g, int fmt, int nr) {
     return (uint8_t)((tps == 2 || tps == 4) ? tps : 1);
 }
 
-// Lays out the batch in ws (ws == nullptr: size only).  Tiles follow the solve
-// order, then the RHS chunks (4 while at least 4 remain, then the rest) of each
-// solve, then the site blocks.
+// Lays out the batch in ws (ws == nullptr: size only).  Tiles are grouped by class
+// (fields per tile, threads per site: one hop launch each); within a class they follow
+// the solve order, then the RHS chunks (4 while at least 4 remain, then the rest) of
+// each solve, then the site blocks.
+// The hop gives each XCD one contiguous run of a class's tiles (xcd_block).  Reorder
+// the class range [begin, end) so that run x holds the x-th eighth of every group of
+// tiles with one solve and chunk of fields: every XCD then works on every solve as
+// long as it runs, and its share of a solve is consecutive sites, whose neighbour
+// lines meet in that XCD's L2.
+void deal_over_xcds(std::vector<BTile> &tiles, uint32_t begin, uint32_t end) {
+    std::vector<std::pair<uint32_t, uint32_t>> groups;
+    for (uint32_t k = begin; k < end;) {
+        uint32_t e = k + 1;
+        while (e < end && tiles[e].solve == tiles[k].solve && tiles[e].j0 == tiles[k].j0) ++e;
+        groups.emplace_back(k, e);
+        k = e;
+    }
+    std::vector<BTile> out;
+    out.reserve(end - begin);
+    for (uint32_t x = 0; x < kXcds; ++x)
+        for (const auto &gr : groups) {
+            const uint64_t m = gr.second - gr.first;
+            for (uint64_t k = gr.first + m * x / kXcds; k < gr.first + m * (x + 1) / kXcds; ++k)
+                out.push_back(tiles[k]);
+        }
+    std::copy(out.begin(), out.end(), tiles.begin() + begin);
+}
+
+// A system that converged or broke down never runs again.
+bool system_final(const SysState &q) {
+    return (q.flags & (SYS_DONE | SYS_BREAKDOWN)) &&
+           !(q.flags & (SYS_RUNNING | SYS_RU_PENDING | SYS_RESUME));
+}
+
+bool tile_finished(const BatchPlan &B, const BTile &t, const std::vector<SysState> &st) {
+    const uint32_t k0 = B.solves[t.solve].sys0 + t.j0;
+    for (uint32_t j = 0; j < t.nr; ++j)
+        if (!system_final(st[k0 + j])) return false;
+    return true;
+}
+
+// The launched tile table: the tiles of B.sorted (all of them, or with st the ones
+// holding a system that is not final), in classes, each class dealt over the XCDs.
+void arrange_tiles(BatchPlan &B, const std::vector<SysState> *st) {
+    B.tiles.clear();
+    for (const BTile &t : B.sorted)
+        if (!st || !tile_finished(B, t, *st)) B.tiles.push_back(t);
+    B.classes.clear();
+    for (uint32_t k = 0; k < (uint32_t)B.tiles.size(); ++k) {
+        const BTile &t = B.tiles[k];
+        const BSolve &S = B.solves[t.solve];
+        const int lo = S.lo_phases == nullptr, hi = S.hi_phases == nullptr;
+        const BClass *c = B.classes.empty() ? nullptr : &B.classes.back();
+        if (!c || c->nr != t.nr || c->tps != t.tps || c->std_lo != lo || c->std_hi != hi)
+            B.classes.push_back(BClass{k, k, t.nr, t.tps, lo, hi});
+        B.classes.back().end = k + 1;
+    }
+    for (const BClass &cl : B.classes) deal_over_xcds(B.tiles, cl.begin, cl.end);
+}
+
+// Class order of the tiles: fields, threads per site, then the phase kinds.
+int tile_class_key(const BatchPlan &B, const BTile &t) {
+    const BSolve &S = B.solves[t.solve];
+    return ((t.nr * 8 + t.tps) * 2 + (S.lo_phases == nullptr)) * 2 + (S.hi_phases == nullptr);
+}
+
+// Whether dropping the finished tiles pays for a new graph: a quarter of the launched
+// tiles, or a whole class (two hop launches per iteration), would go.
+bool prune_pays(const BatchPlan &B, const std::vector<SysState> &st) {
+    size_t live = 0;
+    size_t live_classes = 0;
+    for (const BClass &cl : B.classes) {
+        size_t n = 0;
+        for (uint32_t k = cl.begin; k < cl.end; ++k) n += tile_finished(B, B.tiles[k], st) ? 0 : 1;
+        live += n;
+        live_classes += n ? 1 : 0;
+    }
+    return live > 0 && (4 * live <= 3 * B.tiles.size() || live_classes < B.classes.size());
+}
+
 int plan_batch(int nsolve, const stg_solve_desc *d, int mode, void *ws, BatchPlan &B) {
     const bool f64 = mode == STG_CG_F64;
     Carver c{reinterpret_cast<char *>(ws)};
@@ -1122,6 +1198,8 @@ int plan_batch(int nsolve, const stg_solve_desc *d, int mode, void *ws, BatchPla
         S.sys0 = sys;
         S.nblk = site_blocks(g.Vh);
         S.part0 = pairs;
+        S.hi_phases = d[i].hi.phases;  // the tile classes depend on the phase kinds
+        S.lo_phases = f64 ? nullptr : d[i].lo.phases;
         pairs += S.nblk * S.nrhs;
         for (int j = 0; j < d[i].nrhs; ++j) B.sysref.push_back(BSysRef{(uint32_t)i, (uint32_t)j});
         sys += S.nrhs;
@@ -1135,6 +1213,12 @@ int plan_batch(int nsolve, const stg_solve_desc *d, int mode, void *ws, BatchPla
             j0 += nr;
         }
     }
+    // group the tiles by class, keeping their order within a class
+    std::stable_sort(B.tiles.begin(), B.tiles.end(), [&B](const BTile &x, const BTile &y) {
+        return tile_class_key(B, x) < tile_class_key(B, y);
+    });
+    B.sorted = B.tiles;
+    arrange_tiles(B, nullptr);
     B.nsys = sys;
     B.npairs = pairs;
     B.ctl = (Ctl *)c.take(sizeof(Ctl));
@@ -1142,15 +1226,13 @@ int plan_batch(int nsolve, const stg_solve_desc *d, int mode, void *ws, BatchPla
     B.d_solves = (BSolve *)c.take(sizeof(BSolve) * nsolve);
     B.d_tiles = (BTile *)c.take(sizeof(BTile) * B.tiles.size());
     B.d_sysref = (BSysRef *)c.take(sizeof(BSysRef) * sys);
-    B.partials = (double *)c.take(sizeof(double) * 2 * (size_t)pairs);
+    B.partials = (double *)c.take(sizeof(double) * 2 * kTileSlots * (size_t)pairs);
     for (int i = 0; i < nsolve; ++i) {
         BSolve &S = B.solves[i];
         const size_t n1 = (size_t)S.nrhs * 3 * S.g.Vh;
         const size_t fin = n1 * (f64 ? 16 : 8);
         S.hi_links = d[i].hi.links;
-        S.hi_phases = d[i].hi.phases;
         S.lo_links = f64 ? nullptr : d[i].lo.links;
-        S.lo_phases = f64 ? nullptr : d[i].lo.phases;
         S.b = d[i].b;
         S.x64 = d[i].x;
         S.p = c.take(fin);
@@ -1182,7 +1264,7 @@ BArgs batch_args(const BatchPlan &B, int gate, int tile_mask) {
     a.partials = B.partials;
     a.ntiles = (uint32_t)B.tiles.size();
     a.nsys = B.nsys;
-    a.grid = std::min<uint32_t>(kBatchGrid, a.ntiles);
+    a.grid = a.ntiles;  // one block per tile
     a.gate_running = gate;
     a.tile_mask = tile_mask;
     return a;
@@ -1194,12 +1276,12 @@ int enqueue_batch_iteration(const BatchPlan &B, int f64, int fmt_in, hipStream_t
     a.out_parity = 1;  // t = D_oe p
     a.f_in = BF_P;
     a.f_out = BF_T;
-    HOP_TRY(launch_bhop(a, fmt_in, EPI_PLAIN, s));
+    HOP_TRY(launch_bhop(a, B.classes.data(), (int)B.classes.size(), fmt_in, EPI_PLAIN, s));
     a.out_parity = 0;  // q = diag p - D_eo t; <p, q>
     a.f_in = BF_T;
     a.f_out = BF_Q;
     a.f_aux0 = BF_P;
-    HOP_TRY(launch_bhop(a, fmt_in, EPI_NORMAL, s));
+    HOP_TRY(launch_bhop(a, B.classes.data(), (int)B.classes.size(), fmt_in, EPI_NORMAL, s));
     VEC_TRY(launch_bfinalize(a, OP_ALPHA, s));
     VEC_TRY(launch_bcg_update(a, f64, s));
     VEC_TRY(launch_bfinalize(a, OP_BETA, s));
@@ -1215,12 +1297,12 @@ int enqueue_batch_update(const BatchPlan &B, int f64, int fmt_hi, hipStream_t s)
     a.out_parity = 1;
     a.f_in = BF_X64;
     a.f_out = BF_T64;
-    HOP_TRY(launch_bhop(a, fmt_hi, EPI_PLAIN, s));
+    HOP_TRY(launch_bhop(a, B.classes.data(), (int)B.classes.size(), fmt_hi, EPI_PLAIN, s));
     a.out_parity = 0;
     a.f_in = BF_T64;
     a.f_out = BF_R64;
     a.f_aux0 = BF_X64;
-    HOP_TRY(launch_bhop(a, fmt_hi, EPI_RESID, s));
+    HOP_TRY(launch_bhop(a, B.classes.data(), (int)B.classes.size(), fmt_hi, EPI_RESID, s));
     VEC_TRY(launch_bfinalize(a, OP_RU, s));
     a.tile_mask = SYS_RESUME;
     VEC_TRY(launch_bru_resume(a, f64, s));
@@ -1229,6 +1311,33 @@ int enqueue_batch_update(const BatchPlan &B, int f64, int fmt_hi, hipStream_t s)
 }
 
 thread_local hipStream_t g_capture_stream = nullptr;
+
+// K inner iterations of the whole batch, captured into one executable graph.
+int capture_batch(const BatchPlan &B, int f64, int fmt_in, int K, hipGraph_t &graph,
+                  hipGraphExec_t &exec) {
+    graph = nullptr;
+    exec = nullptr;
+    if (!g_capture_stream) HIP_TRY(hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < K; ++i) {
+        const int rc = enqueue_batch_iteration(B, f64, fmt_in, g_capture_stream);
+        if (rc) {
+            hipGraph_t junk = nullptr;
+            (void)hipStreamEndCapture(g_capture_stream, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            return rc;
+        }
+    }
+    HIP_TRY(hipStreamEndCapture(g_capture_stream, &graph));
+    hipError_t ge = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ge != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        graph = nullptr;
+        exec = nullptr;
+        return hip_fail(ge, "hipGraphInstantiate");
+    }
+    return STG_OK;
+}
 
 int run_cg_batch(int nsolve, const stg_solve_desc *d, const stg_cg_params &prm, void *ws,
                  stg_cg_stats *stats, hipStream_t s) {
@@ -1297,27 +1406,13 @@ int run_cg_batch(int nsolve, const stg_solve_desc *d, const stg_cg_params &prm, 
     rc = enqueue_batch_update(B, f64, fmt_hi, s);
     if (rc) return rc;
 
-    // K inner iterations of the whole batch, captured once and replayed
+    // K inner iterations of the whole batch, captured and replayed; captured again
+    // over the remaining tiles when finished solves leave enough of them idle
     int K = prm.poll_every > 0 ? prm.poll_every : 16;
-    if (!g_capture_stream) HIP_TRY(hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    HIP_TRY(hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < K; ++i) {
-        rc = enqueue_batch_iteration(B, f64, fmt_in, g_capture_stream);
-        if (rc) {
-            hipGraph_t junk;
-            (void)hipStreamEndCapture(g_capture_stream, &junk);
-            if (junk) (void)hipGraphDestroy(junk);
-            return rc;
-        }
-    }
-    HIP_TRY(hipStreamEndCapture(g_capture_stream, &graph));
-    hipError_t ge = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (ge != hipSuccess) {
-        (void)hipGraphDestroy(graph);
-        return hip_fail(ge, "hipGraphInstantiate");
-    }
+    rc = capture_batch(B, f64, fmt_in, K, graph, exec);
+    if (rc) return rc;
     int replays = 0;
     rc = snapshots_ready(n);
     if (!rc) rc = read_states_n(B.state, n, st, s);
@@ -1344,6 +1439,30 @@ int run_cg_batch(int nsolve, const stg_solve_desc *d, const stg_cg_params &prm, 
             rc = stall_error();
             break;
         }
+        if (prune_pays(B, st)) {
+            // the replay in flight still reads the old tile table
+            hipError_t e = hipStreamSynchronize(s);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "hipStreamSynchronize");
+                break;
+            }
+            if (pend >= 0) {
+                rc = snapshot_wait(n, pend, st);
+                if (rc) break;
+                pend = -1;
+            }
+            arrange_tiles(B, &st);
+            e = hipMemcpyAsync(B.d_tiles, B.tiles.data(), sizeof(BTile) * B.tiles.size(),
+                               hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "hipMemcpyAsync");
+                break;
+            }
+            (void)hipGraphExecDestroy(exec);
+            (void)hipGraphDestroy(graph);
+            rc = capture_batch(B, f64, fmt_in, K, graph, exec);
+            if (rc) break;
+        }
         hipError_t le = hipGraphLaunch(exec, s);
         if (le != hipSuccess) {
             rc = hip_fail(le, "hipGraphLaunch");
@@ -1360,8 +1479,8 @@ int run_cg_batch(int nsolve, const stg_solve_desc *d, const stg_cg_params &prm, 
         hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
     }
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     if (rc) return rc;
     rc = read_states_n(B.state, n, st, s);
     if (rc) return rc;

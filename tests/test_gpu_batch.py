@@ -93,3 +93,48 @@ def test_batch_not_converged_and_zero_rhs():
         for s in sts:
             assert s["iters"] <= 25
     assert any(s["status"] == 1 for sts in stats for s in sts)
+
+
+def test_batch_independent_of_poll_interval():
+    """The host drops finished solves' tiles and captures a new graph at a poll; how
+    often it polls moves those points but changes no arithmetic: the solutions and
+    iteration counts with a poll after every iteration equal those with one after
+    every 16, bit for bit."""
+    inp = _inputs("c64_12")
+    solves = [dict(hi=v["hi"], lo=v["lo"], mass=v["mass"], b=v["b"]) for v in inp]
+    xs1, st1, s1 = stg.cg_solve_batch(solves, tol=TOL, poll_every=1)
+    xs16, st16, s16 = stg.cg_solve_batch(solves, tol=TOL, poll_every=16)
+    assert st1 == 0 and st16 == 0
+    for x, y in zip(xs1, xs16):
+        assert torch.equal(x, y)
+    for a, c in zip(s1, s16):
+        assert [q["iters"] for q in a] == [q["iters"] for q in c]
+
+
+@pytest.mark.parametrize("lofmt", [None, "c64_12"])
+def test_batch_stored_phases(lofmt):
+    """Solves with arbitrary real per-link phases read from memory next to solves with
+    the standard staggered phases: the hop launches one class per phase kind, and
+    every system meets the oracle's FP64 true residual."""
+    cases = [((4, 4, 4, 4), 0.1, 2, True), ((6, 4, 2, 8), 0.05, 1, False),
+             ((8, 8, 8, 8), 0.1, 3, True), ((4, 6, 4, 4), 0.2, 1, False)]
+    solves, ref = [], []
+    for i, (dims, m, nrhs, stored) in enumerate(cases):
+        say(f"batch stored phases {lofmt or 'f64'}: {dims} nrhs={nrhs} stored={stored}")
+        links = si.su3_links(dims, 1701, 41, i)
+        ph = si.real_link_field(dims, 41, i) if stored else on.standard_phases(dims)
+        b = si.gaussian_field(dims, nrhs, 426, 41, i)
+        dl = to_dev(links)
+        kw = dict(phases_f64=to_dev(ph)) if stored else {}
+        hi = stg.pack_gauge(dims, dl, "c128_12", **kw)
+        lo = stg.pack_gauge(dims, dl, lofmt, **kw) if lofmt else None
+        solves.append(dict(hi=hi, lo=lo, mass=m, b=to_dev(b)))
+        ref.append((dims, links, ph, m, b))
+    xs, st, stats = stg.cg_solve_batch(solves, tol=TOL)
+    assert st == 0
+    for (dims, links, ph, m, b), x, sts in zip(ref, xs, stats):
+        xn = x.cpu().numpy()
+        for j in range(xn.shape[0]):
+            res = on.true_relative_residual(dims, links, ph, m, b[j], xn[j])
+            say(f"  {dims} rhs {j}: iters {sts[j]['iters']} oracle resid {res:.2e}")
+            assert sts[j]["status"] == 0 and res <= TOL
