@@ -358,9 +358,10 @@ def bench_rational():
     print(json.dumps(out), flush=True)
 
 
-def _batch_run(shapes_masses, label):
-    """One cg_solve_batch (mixed FP32-12) over the solves, against the same solves
-    launched one after another with cg_solve; nrhs_i = 1 + (i mod 4)."""
+def _batch_run(shapes_masses, label, form=0):
+    """One cg_solve_batch (mixed FP32-12; STG_TUNE_CG_FORM `form` for the batch) over the
+    solves, against the same solves launched one after another with cg_solve in the
+    automatic form; nrhs_i = 1 + (i mod 4)."""
     import torch
     import paper_1701_00426_amd as stg
     import seeded_inputs as si
@@ -374,10 +375,12 @@ def _batch_run(shapes_masses, label):
                            lo=stg.pack_gauge(dims, links, "c64_12"), mass=m, b=b))
         del links
     torch.cuda.synchronize()
+    stg.stg_set_tuning(stg._lib.STG_TUNE_CG_FORM, form)
     t0 = time.perf_counter()
     xs, st, stats = stg.cg_solve_batch(solves, tol=TOL)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    stg.stg_set_tuning(stg._lib.STG_TUNE_CG_FORM, 0)
     t1 = time.perf_counter()
     worst_single = 0.0
     for sv in solves:
@@ -386,7 +389,7 @@ def _batch_run(shapes_masses, label):
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t1
     flat = [q for row in stats for q in row]
-    out = {"workload": label, "status": st, "makespan_s": round(t_batch, 3),
+    out = {"workload": label, "cg_form": form, "status": st, "makespan_s": round(t_batch, 3),
            "sequential_cg_solve_s": round(t_seq, 3),
            "speedup_vs_sequential": round(t_seq / t_batch, 3),
            "worst_true_rel_resid": max(q["true_rel_resid"] for q in flat),
@@ -395,22 +398,22 @@ def _batch_run(shapes_masses, label):
     print(json.dumps(out), flush=True)
 
 
-def bench_batch():
+def bench_batch(form=0):
     """12 solves: two each on 8^4, 12^4, 16^4, 16^3x32, 24^4, 32^4 at m = 0.01 and 0.05."""
     shapes = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16), (16, 16, 16, 32),
               (24, 24, 24, 24), (32, 32, 32, 32)]
     _batch_run([(d, m) for d in shapes for m in (0.01, 0.05)],
                "uneven batch: 12 solves (8^4, 12^4, 16^4, 16^3x32, 24^4, 32^4 x m in "
-               "{0.01, 0.05}), 30 RHS, FP32-12 + FP64 reliable updates, tol 1e-10")
+               "{0.01, 0.05}), 30 RHS, FP32-12 + FP64 reliable updates, tol 1e-10", form)
 
 
-def bench_batch_small():
+def bench_batch_small(form=0):
     """48 small solves: 16 each on 8^4, 12^4 and 16^4 at m in {0.05, 0.1}: the regime the
     batch is for, where one launch per kernel and solve is all overhead."""
     shapes = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16)]
     _batch_run([(d, (0.05, 0.1)[k % 2]) for d in shapes for k in range(16)],
                "uneven batch of small lattices: 48 solves (16 each on 8^4, 12^4, 16^4, m in "
-               "{0.05, 0.1}), 120 RHS, FP32-12 + FP64 reliable updates, tol 1e-10")
+               "{0.05, 0.1}), 120 RHS, FP32-12 + FP64 reliable updates, tol 1e-10", form)
 
 
 # The paper's Table 3 lattices, written N0 x N1 x N2 x N3 with time last, and its
@@ -1161,10 +1164,10 @@ def main():
         bench_rational()
         return
     if args.workload == "batch":
-        bench_batch()
+        bench_batch(args.cg_form)
         return
     if args.workload == "batch-small":
-        bench_batch_small()
+        bench_batch_small(args.cg_form)
         return
     if args.workload == "shapes":
         bench_shapes()

@@ -192,7 +192,7 @@ const char *stg_last_error(void);
  *     additions, so results may differ in the last bits.
  *   STG_TUNE_CG_FORM: 0 (default: automatic: form 2 for a solve of one field, else
  *     form 1), 1 or 2: the form of
- *     the CG iteration of cg_solve and of the refinement stage of
+ *     the CG iteration of cg_solve, cg_solve_batch and of the refinement stage of
  *     multishift_cg_solve / rational_apply.  1: the classic iteration of Sec. 2.2
  *     (<p, A p> -> alpha, then |r|^2 -> beta: two global reductions per iteration).
  *     2: the single-reduction form of Chronopoulos and Gear (w = A r; |r|^2 and

@@ -32,10 +32,10 @@ __device__ __forceinline__ bool tile_active(const BArgs &a, const BSolve &S, con
 // Thread 0 stores the block's (sum, error) pair of system js in slot `slot` of tile
 // t; the writer of slot 0 also clears the slots used .. kTileSlots - 1 that no block
 // of its launch writes.
-__device__ __forceinline__ void put_tile_partial(const BArgs &a, const BSolve &S, const BTile &t,
+__device__ __forceinline__ void put_tile_partial(double *partials, const BSolve &S, const BTile &t,
                                                  int js, int slot, int used, double sum,
                                                  double err) {
-    double *pj = a.partials + 2 * (((size_t)S.part0 + (size_t)js * S.nblk + t.blk) * kTileSlots);
+    double *pj = partials + 2 * (((size_t)S.part0 + (size_t)js * S.nblk + t.blk) * kTileSlots);
     pj[2 * slot] = sum;
     pj[2 * slot + 1] = err;
     if (slot == 0)
@@ -129,7 +129,7 @@ __device__ void bhop_tile(const BArgs &a, const BSolve &S, const BTile &t) {
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             block_sum_pair(ps[j], pc[j], sh_red);
-            if (threadIdx.x == 0) put_tile_partial(a, S, t, t.j0 + j, 0, 1, ps[j], pc[j]);
+            if (threadIdx.x == 0) put_tile_partial(a.partials, S, t, t.j0 + j, 0, 1, ps[j], pc[j]);
         }
     }
 }
@@ -210,7 +210,7 @@ __device__ void bhop_tile_split(const BArgs &a, const BSolve &S, const BTile &t,
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             block_sum_pair(ps[j], pc[j], sh_red);
-            if (threadIdx.x == 0) put_tile_partial(a, S, t, t.j0 + j, sub, TPS, ps[j], pc[j]);
+            if (threadIdx.x == 0) put_tile_partial(a.partials, S, t, t.j0 + j, sub, TPS, ps[j], pc[j]);
         }
     }
 }
@@ -257,27 +257,30 @@ __device__ void bcg_update_tile(const BArgs &a, const BSolve &S, const BTile &t,
         const SysState &st = a.state[S.sys0 + js];
         if (!(st.flags & SYS_RUNNING) || h >= S.g.Vh) continue;
         const T al = (T)st.alpha;
+        // the site's twelve loads first (the stores may alias them as far as the
+        // compiler knows, so loads issued per colour would wait for the stores)
+        vec3<T> x = ld_v<T>(S.xin, fs, S.g.Vh, js, h);
+        const vec3<T> p = ld_v<T>(S.p, fs, S.g.Vh, js, h);
+        vec3<T> r = ld_v<T>(S.r, fs, S.g.Vh, js, h);
+        const vec3<T> q = ld_v<T>(S.q, fs, S.g.Vh, js, h);
         double site = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const size_t i = js * fs + (size_t)c * S.g.Vh + h;
-            cpx<T> x = ld_c<T>(S.xin, i), p = ld_c<T>(S.p, i), r = ld_c<T>(S.r, i),
-                   q = ld_c<T>(S.q, i);
-            x.re += al * p.re;
-            x.im += al * p.im;
-            r.re -= al * q.re;
-            r.im -= al * q.im;
-            st_c<T>(S.xin, i, x);
-            st_c<T>(S.r, i, r);
-            site = fmat((double)r.re, (double)r.re, site);
-            site = fmat((double)r.im, (double)r.im, site);
+            x.c[c].re += al * p.c[c].re;
+            x.c[c].im += al * p.c[c].im;
+            r.c[c].re -= al * q.c[c].re;
+            r.c[c].im -= al * q.c[c].im;
+            site = fmat((double)r.c[c].re, (double)r.c[c].re, site);
+            site = fmat((double)r.c[c].im, (double)r.c[c].im, site);
         }
+        st_v<T>(S.xin, fs, S.g.Vh, js, h, x);
+        st_v<T>(S.r, fs, S.g.Vh, js, h, r);
         pair_add(ps[j], pc[j], site, 0.0);
     }
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         block_sum_pair(ps[j], pc[j], sh_red);
-        if (threadIdx.x == 0) put_tile_partial(a, S, t, t.j0 + j, 0, 1, ps[j], pc[j]);
+        if (threadIdx.x == 0) put_tile_partial(a.partials, S, t, t.j0 + j, 0, 1, ps[j], pc[j]);
     }
 }
 
@@ -310,14 +313,14 @@ __device__ __forceinline__ void bp_update_tile(const BArgs &a, const BSolve &S, 
         const SysState &st = a.state[S.sys0 + js];
         if (!(st.flags & SYS_RUNNING)) continue;
         const T be = (T)st.beta;
+        vec3<T> p = ld_v<T>(S.p, fs, S.g.Vh, js, h);  // loads first, as above
+        const vec3<T> r = ld_v<T>(S.r, fs, S.g.Vh, js, h);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const size_t i = js * fs + (size_t)c * S.g.Vh + h;
-            cpx<T> p = ld_c<T>(S.p, i), r = ld_c<T>(S.r, i);
-            p.re = r.re + be * p.re;
-            p.im = r.im + be * p.im;
-            st_c<T>(S.p, i, p);
+            p.c[c].re = r.c[c].re + be * p.c[c].re;
+            p.c[c].im = r.c[c].im + be * p.c[c].im;
         }
+        st_v<T>(S.p, fs, S.g.Vh, js, h, p);
     }
 }
 
@@ -333,6 +336,73 @@ __global__ __launch_bounds__(kBlock) void bp_update_kernel(BArgs a) {
             case 2: bp_update_tile<T, 2>(a, S, t); break;
             case 3: bp_update_tile<T, 3>(a, S, t); break;
             default: bp_update_tile<T, 4>(a, S, t); break;
+        }
+    }
+}
+
+// Single-reduction form (Chronopoulos and Gear, solver_state.hpp cgcg_step), running
+// systems: p = r + beta p, s = w + beta s (s = A p by recurrence; w = A r is in q),
+// x += alpha p, r -= alpha s, and the new |r|^2 partials into partials2 for the next
+// step's finalize.
+template <typename T, int NR>
+__device__ void bcgcg_update_tile(const BArgs &a, const BSolve &S, const BTile &t,
+                                  double *sh_red) {
+    const size_t fs = (size_t)3 * S.g.Vh;
+    const uint32_t h = t.blk * kBlock + threadIdx.x;
+    double ps[NR], pc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        ps[j] = pc[j] = 0.0;
+        const int js = t.j0 + j;
+        const SysState &st = a.state[S.sys0 + js];
+        if (!(st.flags & SYS_RUNNING) || h >= S.g.Vh) continue;
+        const T al = (T)st.alpha, be = (T)st.beta;
+        // the site's fifteen loads first, as in the x/r update
+        vec3<T> r = ld_v<T>(S.r, fs, S.g.Vh, js, h);
+        const vec3<T> w = ld_v<T>(S.q, fs, S.g.Vh, js, h);
+        vec3<T> p = ld_v<T>(S.p, fs, S.g.Vh, js, h);
+        vec3<T> sv = ld_v<T>(S.s, fs, S.g.Vh, js, h);
+        vec3<T> x = ld_v<T>(S.xin, fs, S.g.Vh, js, h);
+        double site = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            p.c[c].re = r.c[c].re + be * p.c[c].re;
+            p.c[c].im = r.c[c].im + be * p.c[c].im;
+            sv.c[c].re = w.c[c].re + be * sv.c[c].re;
+            sv.c[c].im = w.c[c].im + be * sv.c[c].im;
+            x.c[c].re += al * p.c[c].re;
+            x.c[c].im += al * p.c[c].im;
+            r.c[c].re -= al * sv.c[c].re;
+            r.c[c].im -= al * sv.c[c].im;
+            site = fmat((double)r.c[c].re, (double)r.c[c].re, site);
+            site = fmat((double)r.c[c].im, (double)r.c[c].im, site);
+        }
+        st_v<T>(S.p, fs, S.g.Vh, js, h, p);
+        st_v<T>(S.s, fs, S.g.Vh, js, h, sv);
+        st_v<T>(S.xin, fs, S.g.Vh, js, h, x);
+        st_v<T>(S.r, fs, S.g.Vh, js, h, r);
+        pair_add(ps[j], pc[j], site, 0.0);
+    }
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        block_sum_pair(ps[j], pc[j], sh_red);
+        if (threadIdx.x == 0) put_tile_partial(a.partials2, S, t, t.j0 + j, 0, 1, ps[j], pc[j]);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void bcgcg_update_kernel(BArgs a) {
+    if (block_gate_closed(a.ctl, a.gate_running)) return;
+    __shared__ double sh_red[2 * kWaves];
+    FOR_EACH_TILE(a, ti) {
+        const BTile t = a.tiles[ti];
+        const BSolve &S = a.solves[t.solve];
+        if (!tile_active(a, S, t)) continue;
+        switch (t.nr) {
+            case 1: bcgcg_update_tile<T, 1>(a, S, t, sh_red); break;
+            case 2: bcgcg_update_tile<T, 2>(a, S, t, sh_red); break;
+            case 3: bcgcg_update_tile<T, 3>(a, S, t, sh_red); break;
+            default: bcgcg_update_tile<T, 4>(a, S, t, sh_red); break;
         }
     }
 }
@@ -380,6 +450,7 @@ __global__ __launch_bounds__(kBlock) void bru_resume_kernel(BArgs a) {
                 cpx<double> rd = ld_c<double>(S.r64, i);
                 cpx<T> r{(T)rd.re, (T)rd.im};
                 if (S.r != S.r64) st_c<T>(S.r, i, r);
+                if (a.skip_p) continue;
                 cpx<T> p = ld_c<T>(S.p, i);
                 p.re = r.re + be * p.re;
                 p.im = r.im + be * p.im;
@@ -407,7 +478,7 @@ __global__ __launch_bounds__(kBlock) void bnorm_b_kernel(BArgs a) {
                     pair_add(ps, pc, v.im * v.im, 0.0);
                 }
             block_sum_pair(ps, pc, sh_red);
-            if (threadIdx.x == 0) put_tile_partial(a, S, t, js, 0, 1, ps, pc);
+            if (threadIdx.x == 0) put_tile_partial(a.partials, S, t, js, 0, 1, ps, pc);
         }
     }
 }
@@ -419,10 +490,12 @@ __global__ __launch_bounds__(kBlock) void bfinalize_kernel(BArgs a, int op) {
     const uint32_t sys = blockIdx.x;
     const BSysRef ref = a.sysref[sys];
     const BSolve &S = a.solves[ref.solve];
-    double tot = block_sum2_pairs(
-        a.partials + 2 * (((size_t)S.part0 + (size_t)ref.j * S.nblk) * kTileSlots),
-        (int)(S.nblk * kTileSlots), sh_red);
-    if (threadIdx.x == 0) finalize_one(op, a.ctl, a.state, nullptr, (int)sys, tot);
+    const size_t first = ((size_t)S.part0 + (size_t)ref.j * S.nblk) * kTileSlots;
+    double tot = block_sum2_pairs(a.partials + 2 * first, (int)(S.nblk * kTileSlots), sh_red);
+    double tot2 = 0.0;
+    if (op == OP_CGCG)
+        tot2 = block_sum2_pairs(a.partials2 + 2 * first, (int)(S.nblk * kTileSlots), sh_red);
+    if (threadIdx.x == 0) finalize_one(op, a.ctl, a.state, nullptr, (int)sys, tot, tot2);
 }
 
 // ---------------------------------------------------------------------------
@@ -500,6 +573,14 @@ int launch_bcg_update(const BArgs &a, int fp64, hipStream_t s) {
         bcg_update_kernel<double><<<dim3(a.grid), kBlock, 0, s>>>(a);
     else
         bcg_update_kernel<float><<<dim3(a.grid), kBlock, 0, s>>>(a);
+    return 0;
+}
+
+int launch_bcgcg_update(const BArgs &a, int fp64, hipStream_t s) {
+    if (fp64)
+        bcgcg_update_kernel<double><<<dim3(a.grid), kBlock, 0, s>>>(a);
+    else
+        bcgcg_update_kernel<float><<<dim3(a.grid), kBlock, 0, s>>>(a);
     return 0;
 }
 

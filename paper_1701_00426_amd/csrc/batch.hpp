@@ -19,7 +19,8 @@ struct BSolve {
     const void *b;   // complex128 [nrhs][3][Vh]
     void *x64;       // complex128 [nrhs][3][Vh]: the caller's x
     void *xin;       // inner-precision solution (the caller's x in FP64 mode)
-    void *p, *r, *q, *t;  // inner precision
+    void *p, *r, *q, *t;  // inner precision (q holds w = A r in the single-reduction form)
+    void *s;              // inner precision: s = A p of the single-reduction form
     void *r64, *t64;      // FP64 residual and odd temporary (aliases in FP64 mode)
     uint32_t sys0;   // global index of its first system
     uint32_t nblk;   // blocks of kBlock sites
@@ -59,6 +60,7 @@ struct BArgs {
     SysState *state;  // [nsys]
     Ctl *ctl;
     double *partials;
+    double *partials2;  // single-reduction form: the update's |r|^2, same slot layout
     uint32_t ntiles;  // end of the tile range the kernel walks
     uint32_t tile0;   // its first tile (the hop launches one range per tile class)
     uint32_t nsys;
@@ -68,6 +70,8 @@ struct BArgs {
     int gate_running;     // exit at once when ctl->n_running == 0
     int tile_mask;        // work on a tile only when one of its systems has one of these flags
     int f_in, f_out, f_aux0;  // BField selectors of the hop operands
+    int skip_p;           // resume kernel: rebuild r only (the single-reduction update applies
+                          // beta to p and s itself)
 
     __device__ __forceinline__ const void *field(const BSolve &S, int f) const {
         switch (f) {
@@ -97,6 +101,9 @@ int launch_bhop(const BArgs &a, const BClass *cls, int ncls, int fmt, int epi, h
 int launch_bfinalize(const BArgs &a, int op, hipStream_t s);
 int launch_bcg_update(const BArgs &a, int fp64, hipStream_t s);
 int launch_bp_update(const BArgs &a, int fp64, hipStream_t s);
+// single-reduction form: p = r + beta p, s = w + beta s, x += alpha p, r -= alpha s and
+// the |r|^2 partials (into partials2) of every running system
+int launch_bcgcg_update(const BArgs &a, int fp64, hipStream_t s);
 int launch_bru_accumulate(const BArgs &a, hipStream_t s);
 int launch_bru_resume(const BArgs &a, int fp64, hipStream_t s);
 int launch_bnorm_b(const BArgs &a, hipStream_t s);
