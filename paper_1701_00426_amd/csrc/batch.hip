@@ -115,8 +115,8 @@ __device__ void bhop_tile(const BArgs &a, const BSolve &S, const BTile &t) {
 #pragma unroll
     for (int j = 0; j < NR; ++j) ps[j] = pc[j] = 0.0;
     if (h < g.Vh) {
-        // one direction at a time: the persistent kernel holds the registers of its
-        // largest tile variant for every tile, so no variant may unroll all four
+        // one direction at a time: the loads of one direction in flight per thread
+        // (76 to 105 VGPRs for the FP32 one-thread-per-site classes of 1 to 4 fields)
         vec3<T> acc[NR];
         const Site s = site_coords(g, a.out_parity, h);
         zero_acc<T, NR>(acc);
