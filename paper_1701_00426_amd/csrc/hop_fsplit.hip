@@ -151,7 +151,16 @@ __global__ __launch_bounds__(64 * (NR / FPG)) void hop_fsplit_kernel(HopArgs a) 
     vec3<T> acc[FPG];
     zero_acc<T, FPG>(acc);
     if (live) {
-        const int j0 = f * FPG;
+        // neighbour loads on the wave's scalar field bases with 32-bit byte offsets, as
+        // in the decoded-tile kernel below
+        const int j0 = __builtin_amdgcn_readfirstlane(f) * FPG;
+        const char *fb[FPG][3];
+#pragma unroll
+        for (int jj = 0; jj < FPG; ++jj)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                fb[jj][c] = reinterpret_cast<const char *>(a.in) +
+                            ((size_t)(j0 + jj) * a.fstride + (size_t)c * g.Vh) * sizeof(cpx<T>);
         // one direction at a time (the loads of one direction in flight per wave keep
         // the registers low enough for many waves); the direction's neighbour indices
         // and phases come from compile-time arms, so no per-thread array is indexed
@@ -165,17 +174,31 @@ __global__ __launch_bounds__(64 * (NR / FPG)) void hop_fsplit_kernel(HopArgs a) 
 #pragma unroll
             for (int k = 0; k < W; ++k) w[k] = tile[2 * d][k][l];
             const su3<T> uf = LinkWords<T, FMT>::decode(w);
+            const uint32_t of = hf * (uint32_t)sizeof(cpx<T>);
 #pragma unroll
             for (int jj = 0; jj < FPG; ++jj) {
-                const vec3<T> v = ld_v<T>(a.in, a.fstride, g.Vh, j0 + jj, hf);
+                vec3<T> v;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    using Pr = typename field_traits<T>::pair;
+                    const Pr w = *reinterpret_cast<const Pr *>(fb[jj][c] + of);
+                    v.c[c] = {w.x, w.y};
+                }
                 acc_mv(acc[jj], pf, uf, v);
             }
 #pragma unroll
             for (int k = 0; k < W; ++k) w[k] = tile[2 * d + 1][k][l];
             const su3<T> ub = LinkWords<T, FMT>::decode(w);
+            const uint32_t ob = hb * (uint32_t)sizeof(cpx<T>);
 #pragma unroll
             for (int jj = 0; jj < FPG; ++jj) {
-                const vec3<T> v = ld_v<T>(a.in, a.fstride, g.Vh, j0 + jj, hb);
+                vec3<T> v;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    using Pr = typename field_traits<T>::pair;
+                    const Pr w = *reinterpret_cast<const Pr *>(fb[jj][c] + ob);
+                    v.c[c] = {w.x, w.y};
+                }
                 acc_mdv(acc[jj], -pb, ub, v);
             }
         }
@@ -347,8 +370,8 @@ static int launch_fpg(const HopArgs &a, int epi, hipStream_t stream) {
     if constexpr (NR % FPG != 0 || fsplit_lds_bytes<T, FMT>() > kSplitLdsMax) {
         return -1;
     } else {
-        // the decoded-tile kernel addresses neighbours by 32-bit byte offsets
-        if (sizeof(T) == 4 && a.geom.Vh >= (1u << 29)) return -1;
+        // both kernels address neighbours by 32-bit byte offsets (8 or 16 B per entry)
+        if ((size_t)a.geom.Vh * sizeof(cpx<T>) >= ((size_t)1 << 32)) return -1;
         dim3 grid((a.geom.Vh + kFsSites - 1) / kFsSites);
         const dim3 block(64 * (NR / FPG));
         const bool reduce = epi != EPI_PLAIN && a.op != OP_NONE;
